@@ -1,0 +1,285 @@
+/*
+ * lw_oracle.c -- plain FP64 CPU oracle for radiation spectral synthesis.
+ *
+ * TEST INFRASTRUCTURE.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py load this library.  The product path (the HIP
+ * library under paper_1003_1140_amd/) never calls it, links it or shares code
+ * with it.
+ *
+ * What it computes (paper, Section 2.2 "Radiation Spectral Synthesis"): the
+ * discretised form of the standard expression for the energy radiated per
+ * unit frequency and solid angle by an accelerated charge (Rybicki & Lightman;
+ * Jackson eq. 14.67), accumulated over the stored trajectory of each
+ * synthetic particle and reduced over particles.  In the paper's PIC units
+ * c = m_e = q_e = 1:
+ *
+ *   kappa_k = 1 - n.beta_k
+ *   g_k     = n x ((n - beta_k) x betadot_k) / kappa_k^2        (3-vector)
+ *   phi'_k  = t_k - n.r_k          (the paper's retarded phase, c = 1)
+ *   A_p(n,w)= sum_k g_k exp(i w phi'_k) dt_p                     (complex 3-vector)
+ *   S(s,n,w)= sum_{p in species s} w_p q_p^2 |A_p(n,w)|^2 / (4 pi^2)
+ *
+ * Readings of the paper (it prints only a proportionality with E_ret under
+ * the time integral):
+ *   - the emission-time integrand carries 1/kappa^2 (one power of kappa is
+ *     the Jacobian dt/dt' of the retarded time), as in Rybicki & Lightman;
+ *   - the prefactor is e^2/(4 pi^2 c) -> q^2/(4 pi^2), the positive-frequency
+ *     convention;
+ *   - the quadrature is the left Riemann sum with weight dt on every sample;
+ *   - the synthesis here is incoherent (sum of |A_p|^2), one of the two
+ *     options the paper offers; lwo_amplitude exposes A_p itself so that
+ *     coherent sums can be formed from it.
+ *
+ * Pins: tests/test_oracle_pins.py checks this file against closed forms
+ * (Bessel-harmonic synchrotron lines, the Doppler-shifted line of a driven
+ * oscillator, discrete and continuous Parseval sums, the Larmor/Lienard total,
+ * zero emission from straight motion) and invariances.
+ *
+ * Build: gcc -O2 -fopenmp -shared -fPIC (no -ffast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define LWO_OK 0
+#define LWO_EINVAL (-1)
+#define LWO_ENOMEM (-2)
+#define LWO_ERANGE (-5)
+
+static void cross3(const double a[3], const double b[3], double out[3]) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Unit vector along d; returns 0 for a zero or non-finite vector. */
+static int unit3(const double d[3], double n[3]) {
+  double len = sqrt(dot3(d, d));
+  if (!(len > 0.0) || !isfinite(len)) return 0;
+  n[0] = d[0] / len;
+  n[1] = d[1] / len;
+  n[2] = d[2] / len;
+  return 1;
+}
+
+/*
+ * Complex amplitude A(n, w) of one particle for one direction, all
+ * frequencies.  Samples k = 0..len-1 sit at t_k = t0 + k dt.
+ * A_out[j][c][0/1] = Re/Im of component c (x,y,z) at frequency omega[j].
+ * Returns LWO_OK, or LWO_ERANGE if some sample has |beta| >= 1 or a
+ * non-finite value (then *bad_sample holds the first such k).
+ */
+int lwo_amplitude(int64_t len, const double* x, const double* y, const double* z,
+                  const double* bx, const double* by, const double* bz,
+                  const double* ax, const double* ay, const double* az, double t0,
+                  double dt, const double dir[3], int32_t nw, const double* omega,
+                  double* A_out, int64_t* bad_sample) {
+  double n[3];
+  if (len < 0 || nw < 0 || !unit3(dir, n)) return LWO_EINVAL;
+  memset(A_out, 0, sizeof(double) * (size_t)nw * 6);
+  if (len == 0 || nw == 0) return LWO_OK;
+
+  double* g = (double*)malloc(sizeof(double) * 3 * (size_t)len);
+  double* phase = (double*)malloc(sizeof(double) * (size_t)len);
+  if (!g || !phase) {
+    free(g);
+    free(phase);
+    return LWO_ENOMEM;
+  }
+  /* Per sample: the integrand vector g_k and the retarded time phi'_k. */
+  for (int64_t k = 0; k < len; ++k) {
+    double beta[3] = {bx[k], by[k], bz[k]};
+    double bdot[3] = {ax[k], ay[k], az[k]};
+    double r[3] = {x[k], y[k], z[k]};
+    double b2 = dot3(beta, beta);
+    int finite = isfinite(b2) && isfinite(dot3(bdot, bdot)) && isfinite(dot3(r, r)) &&
+                 isfinite(t0 + (double)k * dt);
+    if (!finite || !(b2 < 1.0)) {
+      if (bad_sample) *bad_sample = k;
+      free(g);
+      free(phase);
+      return LWO_ERANGE;
+    }
+    double kappa = 1.0 - dot3(n, beta);
+    double nmb[3] = {n[0] - beta[0], n[1] - beta[1], n[2] - beta[2]};
+    double inner[3], outer[3];
+    cross3(nmb, bdot, inner);
+    cross3(n, inner, outer);
+    for (int c = 0; c < 3; ++c) g[3 * k + c] = outer[c] / (kappa * kappa);
+    double t = t0 + (double)k * dt;
+    phase[k] = t - dot3(n, r);
+  }
+  /* Riemann sum over emission time for every frequency. */
+  for (int32_t j = 0; j < nw; ++j) {
+    double w = omega[j];
+    double re[3] = {0, 0, 0}, im[3] = {0, 0, 0};
+    for (int64_t k = 0; k < len; ++k) {
+      double c = cos(w * phase[k]);
+      double s = sin(w * phase[k]);
+      for (int q = 0; q < 3; ++q) {
+        re[q] += g[3 * k + q] * c * dt;
+        im[q] += g[3 * k + q] * s * dt;
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      A_out[(size_t)j * 6 + 2 * q + 0] = re[q];
+      A_out[(size_t)j * 6 + 2 * q + 1] = im[q];
+    }
+  }
+  free(g);
+  free(phase);
+  return LWO_OK;
+}
+
+/*
+ * Incoherent spectrum of a batch of particles.
+ *
+ * Particle p owns samples offsets[p] .. offsets[p+1]-1 of the SoA arrays
+ * x..az.  species may be NULL (all species 0).  dirs is [nd][3] (normalised
+ * here), omega is [nw].
+ * S_out[s][d][j] receives sum_p w_p q_p^2 |A_p|^2 / (4 pi^2)  (overwritten).
+ * per_particle (may be NULL) receives the particle's own term, [P][nd][nw].
+ * nthreads <= 0 means the OpenMP default.
+ * On LWO_ERANGE, *bad_particle holds the lowest offending particle index.
+ */
+int lwo_spectrum(int64_t n_particles, const int64_t* offsets, const double* x,
+                 const double* y, const double* z, const double* bx, const double* by,
+                 const double* bz, const double* ax, const double* ay, const double* az,
+                 const double* t0, const double* dt, const double* charge,
+                 const double* weight, const int32_t* species, int32_t n_species,
+                 const double* dirs, int32_t nd, const double* omega, int32_t nw,
+                 double* S_out, double* per_particle, int nthreads,
+                 int64_t* bad_particle) {
+  if (n_particles < 0 || nd <= 0 || nw <= 0 || n_species <= 0) return LWO_EINVAL;
+  for (int32_t d = 0; d < nd; ++d) {
+    double tmp[3];
+    if (!unit3(dirs + 3 * d, tmp)) return LWO_EINVAL;
+  }
+  for (int64_t p = 0; p < n_particles; ++p) {
+    if (offsets[p + 1] < offsets[p]) return LWO_EINVAL;
+    if (species && (species[p] < 0 || species[p] >= n_species)) return LWO_EINVAL;
+  }
+  size_t per = (size_t)nd * (size_t)nw;
+  double* own = per_particle;
+  if (!own) {
+    own = (double*)malloc(sizeof(double) * per * (size_t)(n_particles > 0 ? n_particles : 1));
+    if (!own) return LWO_ENOMEM;
+  }
+  int64_t first_bad = -1;
+  int status = LWO_OK;
+  const double four_pi2 = 4.0 * M_PI * M_PI;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * 6 * (size_t)nw);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t task = 0; task < n_particles * (int64_t)nd; ++task) {
+      int64_t p = task / nd;
+      int32_t d = (int32_t)(task % nd);
+      int64_t o = offsets[p], len = offsets[p + 1] - offsets[p];
+      double* row = own + (size_t)p * per + (size_t)d * nw;
+      int64_t badk = -1;
+      int st = A ? lwo_amplitude(len, x + o, y + o, z + o, bx + o, by + o, bz + o, ax + o,
+                                 ay + o, az + o, t0[p], dt[p], dirs + 3 * d, nw, omega, A,
+                                 &badk)
+                 : LWO_ENOMEM;
+      if (st != LWO_OK) {
+#pragma omp critical
+        {
+          if (st == LWO_ERANGE) {
+            if (first_bad < 0 || p < first_bad) first_bad = p;
+            if (status == LWO_OK) status = LWO_ERANGE;
+          } else {
+            status = st;
+          }
+        }
+        for (int32_t j = 0; j < nw; ++j) row[j] = 0.0;
+        continue;
+      }
+      double pref = weight[p] * charge[p] * charge[p] / four_pi2;
+      for (int32_t j = 0; j < nw; ++j) {
+        double a2 = 0.0;
+        for (int c = 0; c < 6; ++c) a2 += A[(size_t)j * 6 + c] * A[(size_t)j * 6 + c];
+        row[j] = pref * a2;
+      }
+    }
+    free(A);
+  }
+  /* Reduction over particles in index order (deterministic). */
+  memset(S_out, 0, sizeof(double) * per * (size_t)n_species);
+  for (int64_t p = 0; p < n_particles; ++p) {
+    int32_t s = species ? species[p] : 0;
+    double* dst = S_out + (size_t)s * per;
+    const double* src = own + (size_t)p * per;
+    for (size_t i = 0; i < per; ++i) dst[i] += src[i];
+  }
+  if (!per_particle) free(own);
+  if (bad_particle) *bad_particle = first_bad;
+  return status;
+}
+
+/*
+ * Single-bin spectrum values for a list of (direction, frequency) pairs,
+ * summed over all particles of the batch: out[i] = sum_p w_p q_p^2
+ * |A_p(dirs[i], omega[i])|^2 / (4 pi^2), restricted to species sel_species
+ * (or all particles when sel_species < 0).  Used to check large runs at a
+ * few sampled output bins.
+ */
+int lwo_sampled_bins(int64_t n_particles, const int64_t* offsets, const double* x,
+                     const double* y, const double* z, const double* bx, const double* by,
+                     const double* bz, const double* ax, const double* ay, const double* az,
+                     const double* t0, const double* dt, const double* charge,
+                     const double* weight, const int32_t* species, int32_t sel_species,
+                     int32_t n_bins, const double* dirs, const double* omega, double* out,
+                     int nthreads) {
+  if (n_particles < 0 || n_bins <= 0) return LWO_EINVAL;
+  double* own = (double*)calloc((size_t)n_particles * (size_t)n_bins + 1, sizeof(double));
+  if (!own) return LWO_ENOMEM;
+  int status = LWO_OK;
+  const double four_pi2 = 4.0 * M_PI * M_PI;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t task = 0; task < n_particles * (int64_t)n_bins; ++task) {
+    int64_t p = task / n_bins;
+    int32_t b = (int32_t)(task % n_bins);
+    if (sel_species >= 0 && species && species[p] != sel_species) continue;
+    int64_t o = offsets[p], len = offsets[p + 1] - offsets[p];
+    double A[6];
+    int64_t badk = -1;
+    int st = lwo_amplitude(len, x + o, y + o, z + o, bx + o, by + o, bz + o, ax + o, ay + o,
+                           az + o, t0[p], dt[p], dirs + 3 * b, 1, omega + b, A, &badk);
+    if (st != LWO_OK) {
+#pragma omp critical
+      status = st;
+      continue;
+    }
+    double a2 = 0.0;
+    for (int c = 0; c < 6; ++c) a2 += A[c] * A[c];
+    own[(size_t)p * n_bins + b] = weight[p] * charge[p] * charge[p] * a2 / four_pi2;
+  }
+  for (int32_t b = 0; b < n_bins; ++b) out[b] = 0.0;
+  for (int64_t p = 0; p < n_particles; ++p)
+    for (int32_t b = 0; b < n_bins; ++b) out[b] += own[(size_t)p * n_bins + b];
+  free(own);
+  return status;
+}
+
+int lwo_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
