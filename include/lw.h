@@ -1,0 +1,135 @@
+/*
+ * lw.h -- C ABI of the MI355X (gfx950) radiation spectral synthesis library.
+ *
+ * The library evaluates, on one GPU, the discretised Lienard-Wiechert
+ * spectral integral that the paper accumulates in situ for a sample of PIC
+ * particles (Section 2.2, "Radiation Spectral Synthesis": the discretised
+ * Rybicki-Lightman expression for d^2W/(dOmega domega), integrated over
+ * emission time with the retarded phase phi' = t' - n.r(t')/c, seen by far
+ * observers at arbitrary orientation, on log or linear frequency bins,
+ * summed over particles).  In the paper's units c = m_e = q_e = 1:
+ *
+ *   kappa_k  = 1 - n.beta_k
+ *   g_k      = n x ((n - beta_k) x betadot_k) / kappa_k^2
+ *   A_p(n,w) = sum_k g_k exp(i w (t_k - n.r_k)) dt_p
+ *   S(s,n,w) += sum_{p in species s} w_p q_p^2 |A_p(n,w)|^2 / (4 pi^2)
+ *
+ * S is the energy radiated per unit frequency and solid angle (incoherent
+ * synthesis, one of the two options of Section 2.2).
+ *
+ * Conventions
+ *   - Every call returns lw_status; nothing throws across the ABI.  After a
+ *     failure lw_last_error() describes it.
+ *   - Pointers named host_* are host memory; every pointer in lw_batch and
+ *     the workspace/per-particle pointers are device memory on the context's
+ *     device.  The caller owns them and keeps them valid until the stream has
+ *     passed the call.  The context owns its grids and the accumulator S.
+ *   - Calls that launch work are asynchronous and ordered on the context's
+ *     stream (a hipStream_t passed as void*; NULL = the default stream).
+ *   - Data errors detected on the device (|beta| >= 1, non-finite samples, a
+ *     species index outside [0, n_species)) record the lowest offending
+ *     particle index; the offending sample (or particle, for a bad species)
+ *     contributes nothing and the next lw_read_spectra returns LW_ERANGE.
+ *   - A context is not thread safe; use one context per host thread.
+ */
+#ifndef LW_H
+#define LW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LW_OK = 0,
+  LW_EINVAL = -1,       /* bad argument (message in lw_last_error) */
+  LW_ENOMEM = -2,       /* device allocation failed or workspace too small */
+  LW_EDEVICE = -3,      /* HIP runtime error */
+  LW_ESTATE = -4,       /* call out of order (e.g. accumulate before grids are set) */
+  LW_ERANGE = -5,       /* |beta| >= 1 or non-finite sample seen on the device */
+  LW_EUNSUPPORTED = -6  /* option not available */
+} lw_status;
+
+/* Arithmetic of the accumulation.
+ *   LW_PATH_FP32: retarded time, kappa, g and the phase w*tau reduced to a
+ *     turn fraction in FP64; phase factors and the sum over samples in FP32,
+ *     with FP64 partial sums every 16 samples.
+ *   LW_PATH_MFMA_F16 / LW_PATH_MFMA_BF16: the sum over samples as a dense
+ *     contraction on the matrix cores -- each particle's integrand is spread
+ *     onto a uniform retarded-time grid per frequency band, contracted with
+ *     a shared table of phase factors e^{i w q h} held in FP16 (BF16) hi/lo
+ *     pairs, FP32 accumulation, then deconvolved (see lw_mfma_error_bound). */
+typedef enum { LW_PATH_FP32 = 0, LW_PATH_MFMA_F16 = 1, LW_PATH_MFMA_BF16 = 2 } lw_path;
+
+/* Particle batch (structure of arrays, device pointers, borrowed).
+ * Particle p owns samples offsets[p] .. offsets[p+1]-1 (offsets non-decreasing,
+ * offsets[0] may be > 0); sample k of particle p is at time t0[p] + k*dt[p].
+ * beta = (bx,by,bz) = v/c, betadot = (ax,ay,az) = d(beta)/dt, r = (x,y,z).
+ * species may be NULL (all particles in species 0). */
+typedef struct {
+  int64_t n_particles;
+  const int64_t* offsets; /* [n_particles + 1] */
+  const double *x, *y, *z;
+  const double *bx, *by, *bz;
+  const float *ax, *ay, *az;
+  const double *t0, *dt;  /* [n_particles] */
+  const float *charge;    /* [n_particles] q_p in units of e */
+  const float *weight;    /* [n_particles] w_p (macro-particle weight) */
+  const int32_t* species; /* [n_particles] or NULL */
+} lw_batch;
+
+typedef struct lw_ctx lw_ctx;
+
+/* Create a context on HIP device `device`, ordered on `stream` (hipStream_t,
+ * borrowed; NULL = default stream).  *out receives the context. */
+lw_status lw_create(lw_ctx** out, int device, void* stream);
+/* Free the context and everything it owns (synchronises its stream). */
+void lw_destroy(lw_ctx* ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char* lw_last_error(const lw_ctx* ctx);
+/* Change the stream later calls are ordered on. */
+lw_status lw_set_stream(lw_ctx* ctx, void* stream);
+
+/* Observer directions (Section 2.2: several far-field observers at
+ * arbitrary orientation).  host_n_xyz is [nd][3], copied and normalised;
+ * a zero or non-finite vector is LW_EINVAL.  Resets S. */
+lw_status lw_set_directions(lw_ctx* ctx, const double* host_n_xyz, int32_t nd);
+/* Frequency points (Section 2.2: logarithmic or linear binning), host [nw],
+ * finite and > 0; copied.  Resets S. */
+lw_status lw_set_frequencies(lw_ctx* ctx, const double* host_omega, int32_t nw);
+/* w_j = wmin (wmax/wmin)^(j/(nw-1)), j = 0..nw-1, endpoints exact. Resets S. */
+lw_status lw_set_log_frequencies(lw_ctx* ctx, double wmin, double wmax, int32_t nw);
+/* Copy the current frequency points to host_omega [nw]. */
+lw_status lw_get_frequencies(const lw_ctx* ctx, double* host_omega);
+/* Number of species accumulated separately (>= 1, <= 8).  Resets S. */
+lw_status lw_set_species(lw_ctx* ctx, int32_t n_species);
+
+/* Device workspace (bytes) lw_accumulate needs for this batch and path. */
+lw_status lw_workspace_size(lw_ctx* ctx, const lw_batch* batch, lw_path path, size_t* bytes);
+
+/* Add the batch's spectrum into S (asynchronous).  workspace: device memory
+ * of at least lw_workspace_size bytes, 256-byte aligned.  per_particle: NULL
+ * or device float [n_particles][nd][nw] receiving each particle's own
+ * w_p q_p^2 |A_p|^2 / (4 pi^2).  Host-side checks (sizes, NULL pointers,
+ * workspace size and alignment) fail before any launch. */
+lw_status lw_accumulate(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
+                        size_t workspace_bytes, float* per_particle);
+
+/* Synchronise the stream and copy S to host_out [n_species][nd][nw] (FP64).
+ * Returns LW_ERANGE (with the particle index in lw_last_error) if a device
+ * data error was recorded since the last reset; S is copied regardless. */
+lw_status lw_read_spectra(lw_ctx* ctx, double* host_out);
+/* Zero S and the device error record (asynchronous). */
+lw_status lw_reset(lw_ctx* ctx);
+/* Replace S with host_in [n_species][nd][nw] (resume from a saved state). */
+lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
+
+/* Number of successful lw_accumulate calls since creation. */
+lw_status lw_stats(const lw_ctx* ctx, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LW_H */

@@ -1,0 +1,373 @@
+// lw_capi.hip -- host runtime behind the C ABI of include/lw.h.
+//
+// Owns the per-context device state (direction and frequency grids, the FP64
+// accumulator S, the device error record), validates arguments on the host,
+// picks launch shapes and enqueues the kernels on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "lw_internal.h"
+#include "lw_mfma.h"
+
+
+
+namespace {
+
+const unsigned long long kNoError = ~0ull;
+
+lw_status fail(lw_ctx* c, lw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+lw_status hip_fail(lw_ctx* c, hipError_t e, const char* what) {
+  return fail(c, LW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define LW_HIP(call, what)                        \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(c, e_, what); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+lw_status alloc_accumulator(lw_ctx* c) {
+  free_dev(c->d_S);
+  c->d_S = nullptr;
+  if (c->nd <= 0 || c->nw <= 0) return LW_OK;
+  size_t n = (size_t)c->ns * c->nd * c->nw;
+  LW_HIP(hipMalloc(&c->d_S, n * sizeof(double)), "hipMalloc(S)");
+  LW_HIP(lw::launch_fill_f64(c->d_S, (int64_t)n, 0.0, c->stream), "zero S");
+  return LW_OK;
+}
+
+// Orthonormal e1, e2 perpendicular to the unit vector n, (e1, e2, n) right-handed.
+void basis(const double n[3], double e1[3], double e2[3]) {
+  // pick the axis least aligned with n
+  double a[3] = {0, 0, 0};
+  int m = 0;
+  for (int i = 1; i < 3; ++i)
+    if (fabs(n[i]) < fabs(n[m])) m = i;
+  a[m] = 1.0;
+  // e1 = normalise(a - (a.n) n)
+  double an = a[0] * n[0] + a[1] * n[1] + a[2] * n[2];
+  for (int i = 0; i < 3; ++i) e1[i] = a[i] - an * n[i];
+  double l = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int i = 0; i < 3; ++i) e1[i] /= l;
+  // e2 = n x e1
+  e2[0] = n[1] * e1[2] - n[2] * e1[1];
+  e2[1] = n[2] * e1[0] - n[0] * e1[2];
+  e2[2] = n[0] * e1[1] - n[1] * e1[0];
+}
+
+lw_status check_batch(lw_ctx* c, const lw_batch* b) {
+  if (!b) return fail(c, LW_EINVAL, "batch is NULL");
+  if (b->n_particles < 0) return fail(c, LW_EINVAL, "n_particles < 0");
+  if (b->n_particles == 0) return LW_OK;
+  const void* need[] = {b->offsets, b->x, b->y, b->z, b->bx, b->by, b->bz, b->ax, b->ay, b->az,
+                        b->t0, b->dt, b->charge, b->weight};
+  const char* names[] = {"offsets", "x", "y", "z", "bx", "by", "bz", "ax", "ay", "az",
+                         "t0", "dt", "charge", "weight"};
+  for (int i = 0; i < 14; ++i)
+    if (!need[i]) return fail(c, LW_EINVAL, "batch.%s is NULL", names[i]);
+  return LW_OK;
+}
+
+lw_status check_grids(lw_ctx* c) {
+  if (c->nd <= 0) return fail(c, LW_ESTATE, "directions not set");
+  if (c->nw <= 0) return fail(c, LW_ESTATE, "frequencies not set");
+  return LW_OK;
+}
+
+// Frequencies per thread for the FP32 kernel.
+int pick_wpt(int32_t nw) {
+  if (nw <= lw::kThreads) return 1;
+  if (nw <= 2 * lw::kThreads) return 2;
+  if (nw <= 4 * lw::kThreads) return 4;
+  return 8;
+}
+
+struct DirectShape {
+  int wpt;
+  int32_t n_tiles;
+  int32_t pb;
+  int64_t n_blocks;
+};
+
+DirectShape direct_shape(const lw_ctx* c, int64_t P) {
+  DirectShape s;
+  s.wpt = pick_wpt(c->nw);
+  s.n_tiles = (c->nw + lw::kThreads * s.wpt - 1) / (lw::kThreads * s.wpt);
+  // aim at >= 8 work-groups per compute unit (256 CUs) before batching particles
+  const int64_t per_particle_items = (int64_t)c->nd * s.n_tiles;
+  int64_t pb = (P * per_particle_items) / (8 * 256);
+  if (pb < 1) pb = 1;
+  if (pb > 64) pb = 64;
+  s.pb = (int32_t)pb;
+  s.n_blocks = (P + pb - 1) / pb;
+  return s;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+lw_status lw_create(lw_ctx** out, int device, void* stream) {
+  if (!out) return LW_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return LW_EDEVICE;
+  if (device < 0 || device >= n) return LW_EINVAL;
+  lw_ctx* c = new lw_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  DeviceGuard g(device);
+  if (hipMalloc(&c->d_err, sizeof(unsigned long long)) != hipSuccess) {
+    delete c;
+    return LW_ENOMEM;
+  }
+  if (lw::launch_fill_u64(c->d_err, 1, kNoError, c->stream) != hipSuccess) {
+    (void)hipFree(c->d_err);
+    delete c;
+    return LW_EDEVICE;
+  }
+  c->mfma = lw::mfma_cache_create();
+  *out = c;
+  return LW_OK;
+}
+
+void lw_destroy(lw_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  lw::mfma_cache_destroy(c->mfma);
+  free_dev(c->d_dirs);
+  free_dev(c->d_wturn);
+  free_dev(c->d_omega);
+  free_dev(c->d_S);
+  free_dev(c->d_err);
+  delete c;
+}
+
+const char* lw_last_error(const lw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+lw_status lw_set_stream(lw_ctx* c, void* stream) {
+  if (!c) return LW_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return LW_OK;
+}
+
+lw_status lw_set_directions(lw_ctx* c, const double* n_xyz, int32_t nd) {
+  if (!c) return LW_EINVAL;
+  if (!n_xyz || nd <= 0) return fail(c, LW_EINVAL, "need nd > 0 directions");
+  std::vector<double> h((size_t)nd * lw::kDirStride);
+  for (int32_t d = 0; d < nd; ++d) {
+    const double* v = n_xyz + 3 * d;
+    double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!(l > 0.0) || !isfinite(l)) return fail(c, LW_EINVAL, "direction %d is zero or not finite", d);
+    double n[3] = {v[0] / l, v[1] / l, v[2] / l}, e1[3], e2[3];
+    basis(n, e1, e2);
+    for (int i = 0; i < 3; ++i) {
+      h[(size_t)d * 9 + i] = n[i];
+      h[(size_t)d * 9 + 3 + i] = e1[i];
+      h[(size_t)d * 9 + 6 + i] = e2[i];
+    }
+  }
+  DeviceGuard g(c->device);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  free_dev(c->d_dirs);
+  c->d_dirs = nullptr;
+  LW_HIP(hipMalloc(&c->d_dirs, h.size() * sizeof(double)), "hipMalloc(dirs)");
+  LW_HIP(hipMemcpy(c->d_dirs, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice),
+         "copy dirs");
+  c->h_dirs = h;
+  c->nd = nd;
+  lw::mfma_cache_invalidate(c->mfma);
+  return alloc_accumulator(c);
+}
+
+lw_status lw_set_frequencies(lw_ctx* c, const double* omega, int32_t nw) {
+  if (!c) return LW_EINVAL;
+  if (!omega || nw <= 0) return fail(c, LW_EINVAL, "need nw > 0 frequencies");
+  std::vector<double> w(omega, omega + nw), wt(nw);
+  for (int32_t j = 0; j < nw; ++j) {
+    if (!(w[j] > 0.0) || !isfinite(w[j])) return fail(c, LW_EINVAL, "frequency %d is not finite and > 0", j);
+    wt[j] = w[j] / (2.0 * M_PI);
+  }
+  DeviceGuard g(c->device);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  free_dev(c->d_wturn);
+  free_dev(c->d_omega);
+  c->d_wturn = c->d_omega = nullptr;
+  LW_HIP(hipMalloc(&c->d_wturn, nw * sizeof(double)), "hipMalloc(omega)");
+  LW_HIP(hipMalloc(&c->d_omega, nw * sizeof(double)), "hipMalloc(omega)");
+  LW_HIP(hipMemcpy(c->d_wturn, wt.data(), nw * sizeof(double), hipMemcpyHostToDevice), "copy omega");
+  LW_HIP(hipMemcpy(c->d_omega, w.data(), nw * sizeof(double), hipMemcpyHostToDevice), "copy omega");
+  c->h_omega = w;
+  c->nw = nw;
+  lw::mfma_cache_invalidate(c->mfma);
+  return alloc_accumulator(c);
+}
+
+lw_status lw_set_log_frequencies(lw_ctx* c, double wmin, double wmax, int32_t nw) {
+  if (!c) return LW_EINVAL;
+  if (!(wmin > 0.0) || !(wmax >= wmin) || !isfinite(wmax) || nw <= 0)
+    return fail(c, LW_EINVAL, "need 0 < wmin <= wmax and nw > 0");
+  std::vector<double> w(nw);
+  for (int32_t j = 0; j < nw; ++j)
+    w[j] = nw == 1 ? wmin : wmin * pow(wmax / wmin, (double)j / (double)(nw - 1));
+  w[0] = wmin;
+  if (nw > 1) w[nw - 1] = wmax;
+  return lw_set_frequencies(c, w.data(), nw);
+}
+
+lw_status lw_get_frequencies(const lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  memcpy(out, c->h_omega.data(), c->h_omega.size() * sizeof(double));
+  return LW_OK;
+}
+
+lw_status lw_set_species(lw_ctx* c, int32_t ns) {
+  if (!c) return LW_EINVAL;
+  if (ns < 1 || ns > lw::kMaxSpecies)
+    return fail(c, LW_EINVAL, "n_species must be in [1, %d]", lw::kMaxSpecies);
+  DeviceGuard g(c->device);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  c->ns = ns;
+  return alloc_accumulator(c);
+}
+
+lw_status lw_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes) {
+  if (!c || !bytes) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  if (!b || b->n_particles < 0) return fail(c, LW_EINVAL, "bad batch");
+  *bytes = 0;
+  if (path == LW_PATH_FP32) {
+    DirectShape s = direct_shape(c, b->n_particles);
+    *bytes = align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * sizeof(double));
+    return LW_OK;
+  }
+  if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    DeviceGuard g(c->device);
+    return lw::mfma_workspace_size(c, b, path, bytes);
+  }
+  return fail(c, LW_EINVAL, "unknown path %d", (int)path);
+}
+
+lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
+                        float* per_particle) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (b->n_particles == 0) return LW_OK;
+  size_t need = 0;
+  st = lw_workspace_size(c, b, path, &need);
+  if (st != LW_OK) return st;
+  if (need > 0 && (!ws || ws_bytes < need))
+    return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
+  if (((uintptr_t)ws & 255) != 0) return fail(c, LW_EINVAL, "workspace must be 256-byte aligned");
+  DeviceGuard g(c->device);
+  if (path == LW_PATH_FP32) {
+    DirectShape s = direct_shape(c, b->n_particles);
+    lw::DirectArgs a;
+    a.b = {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+           b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+    a.dirs = c->d_dirs;
+    a.wturn = c->d_wturn;
+    a.nd = c->nd;
+    a.nw = c->nw;
+    a.ns = c->ns;
+    a.pb = s.pb;
+    a.n_blocks = s.n_blocks;
+    a.n_tiles = s.n_tiles;
+    a.partial = (double*)ws;
+    a.per_particle = per_particle;
+    a.err = c->d_err;
+    LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32");
+    LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw,
+                                      c->d_S, c->stream),
+           "launch lw_reduce_partials");
+  } else if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    st = lw::mfma_accumulate(c, b, path, ws, ws_bytes, per_particle);
+    if (st != LW_OK) return st;
+  } else {
+    return fail(c, LW_EINVAL, "unknown path %d", (int)path);
+  }
+  c->calls += 1;
+  return LW_OK;
+}
+
+lw_status lw_read_spectra(lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  size_t n = (size_t)c->ns * c->nd * c->nw;
+  unsigned long long e = kNoError;
+  LW_HIP(hipMemcpyAsync(out, c->d_S, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy S");
+  LW_HIP(hipMemcpyAsync(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy err");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  if (e != kNoError)
+    return fail(c, LW_ERANGE, "particle %llu has |beta| >= 1 or a non-finite sample", e);
+  return LW_OK;
+}
+
+lw_status lw_reset(lw_ctx* c) {
+  if (!c) return LW_EINVAL;
+  DeviceGuard g(c->device);
+  if (c->d_S)
+    LW_HIP(lw::launch_fill_f64(c->d_S, (int64_t)c->ns * c->nd * c->nw, 0.0, c->stream), "zero S");
+  LW_HIP(lw::launch_fill_u64(c->d_err, 1, kNoError, c->stream), "reset error");
+  return LW_OK;
+}
+
+lw_status lw_load_accumulator(lw_ctx* c, const double* in) {
+  if (!c || !in) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  size_t n = (size_t)c->ns * c->nd * c->nw;
+  LW_HIP(hipMemcpyAsync(c->d_S, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "load S");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  return LW_OK;
+}
+
+lw_status lw_stats(const lw_ctx* c, int64_t* calls) {
+  if (!c || !calls) return LW_EINVAL;
+  *calls = c->calls;
+  return LW_OK;
+}
+
+}  // extern "C"

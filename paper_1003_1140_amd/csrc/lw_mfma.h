@@ -1,0 +1,14 @@
+// lw_mfma.h -- matrix-core path of the accumulation (spread + DFT contraction).
+#pragma once
+#include "lw_internal.h"
+
+namespace lw {
+
+MfmaPlanCache* mfma_cache_create();
+void mfma_cache_destroy(MfmaPlanCache* c);
+void mfma_cache_invalidate(MfmaPlanCache* c);
+lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);
+lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
+                          float* per_particle);
+
+}  // namespace lw

@@ -1,0 +1,220 @@
+"""ctypes binding of include/lw.h (argument marshalling only).
+
+Functions keep the C names (``lw_create``, ``lw_accumulate`` ...).  PyTorch
+supplies device memory and the HIP stream; no torch operation touches the
+accumulation itself.  The binding raises if liblw.so has not been built --
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblw.so")
+
+LW_OK, LW_EINVAL, LW_ENOMEM, LW_EDEVICE, LW_ESTATE, LW_ERANGE, LW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+LW_PATH_FP32, LW_PATH_MFMA_F16, LW_PATH_MFMA_BF16 = 0, 1, 2
+PATHS = {"fp32": LW_PATH_FP32, "mfma_f16": LW_PATH_MFMA_F16, "mfma_bf16": LW_PATH_MFMA_BF16}
+
+EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set_directions",
+            "lw_set_frequencies", "lw_set_log_frequencies", "lw_get_frequencies", "lw_set_species",
+            "lw_workspace_size", "lw_accumulate", "lw_read_spectra", "lw_reset",
+            "lw_load_accumulator", "lw_stats")
+
+
+class LWError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lw status {status}: {message}")
+        self.status = status
+
+
+class lw_batch(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int64),
+        ("offsets", ctypes.c_void_p),
+        ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+        ("bx", ctypes.c_void_p), ("by", ctypes.c_void_p), ("bz", ctypes.c_void_p),
+        ("ax", ctypes.c_void_p), ("ay", ctypes.c_void_p), ("az", ctypes.c_void_p),
+        ("t0", ctypes.c_void_p), ("dt", ctypes.c_void_p),
+        ("charge", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+        ("species", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblw.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1003_1140_amd/build.py`")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        sig = {
+            "lw_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, P]),
+            "lw_destroy": (None, [P]),
+            "lw_last_error": (ctypes.c_char_p, [P]),
+            "lw_set_stream": (ctypes.c_int, [P, P]),
+            "lw_set_directions": (ctypes.c_int, [P, P, I32]),
+            "lw_set_frequencies": (ctypes.c_int, [P, P, I32]),
+            "lw_set_log_frequencies": (ctypes.c_int, [P, D, D, I32]),
+            "lw_get_frequencies": (ctypes.c_int, [P, P]),
+            "lw_set_species": (ctypes.c_int, [P, I32]),
+            "lw_workspace_size": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int, ctypes.POINTER(SZ)]),
+            "lw_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int, P, SZ, P]),
+            "lw_read_spectra": (ctypes.c_int, [P, P]),
+            "lw_reset": (ctypes.c_int, [P]),
+            "lw_load_accumulator": (ctypes.c_int, [P, P]),
+            "lw_stats": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class DeviceBatch:
+    """A particle batch resident in device memory (torch tensors) plus its lw_batch view.
+
+    ``host`` is any object with the numpy arrays offsets, x, y, z, bx, by, bz,
+    ax, ay, az (float32), t0, dt, charge, weight and species.
+    """
+
+    F64 = ("x", "y", "z", "bx", "by", "bz", "t0", "dt")
+    F32 = ("ax", "ay", "az", "charge", "weight")
+
+    def __init__(self, tensors: dict, n_particles: int):
+        self.t = tensors
+        self.n_particles = int(n_particles)
+        self.struct = lw_batch()
+        self.struct.n_particles = self.n_particles
+        for name, _ in lw_batch._fields_[1:]:
+            ten = tensors.get(name)
+            setattr(self.struct, name, ten.data_ptr() if ten is not None else None)
+
+    @classmethod
+    def from_host(cls, host, device="cuda", with_species=True):
+        dev = torch.device(device)
+        t = {"offsets": torch.from_numpy(np.ascontiguousarray(host.offsets, dtype=np.int64)).to(dev)}
+        for k in cls.F64:
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(host, k), dtype=np.float64)).to(dev)
+        for k in cls.F32:
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(host, k), dtype=np.float32)).to(dev)
+        if with_species:
+            t["species"] = torch.from_numpy(np.ascontiguousarray(host.species, dtype=np.int32)).to(dev)
+        return cls(t, len(host.offsets) - 1)
+
+    @property
+    def n_samples(self) -> int:
+        o = self.t["offsets"]
+        return int((o[-1] - o[0]).item())
+
+
+class Context:
+    """One lw_ctx: grids, the FP64 accumulator and the device error record."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load_library()
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        st = self.lib.lw_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if st != LW_OK:
+            raise LWError(st, "lw_create failed")
+        self.h = h
+        self.nd = self.nw = 0
+        self.ns = 1
+
+    def _check(self, st):
+        if st != LW_OK:
+            raise LWError(st, self.lib.lw_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_directions(self, dirs):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        self._check(self.lib.lw_set_directions(self.h, _np_ptr(d), d.shape[0]))
+        self.nd = d.shape[0]
+
+    def set_frequencies(self, omega):
+        w = np.ascontiguousarray(omega, dtype=np.float64)
+        self._check(self.lib.lw_set_frequencies(self.h, _np_ptr(w), w.size))
+        self.nw = w.size
+
+    def set_log_frequencies(self, wmin, wmax, nw):
+        self._check(self.lib.lw_set_log_frequencies(self.h, wmin, wmax, nw))
+        self.nw = nw
+
+    def get_frequencies(self):
+        out = np.zeros(self.nw, dtype=np.float64)
+        self._check(self.lib.lw_get_frequencies(self.h, _np_ptr(out)))
+        return out
+
+    def set_species(self, ns):
+        self._check(self.lib.lw_set_species(self.h, ns))
+        self.ns = ns
+
+    def workspace_size(self, batch: DeviceBatch, path="fp32") -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.lw_workspace_size(self.h, ctypes.byref(batch.struct), PATHS.get(path, path),
+                                               ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, batch: DeviceBatch, path="fp32"):
+        n = self.workspace_size(batch, path)
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def accumulate(self, batch: DeviceBatch, path="fp32", workspace=None, per_particle=None):
+        if workspace is None:
+            workspace = self.workspace(batch, path)
+        pp = per_particle.data_ptr() if per_particle is not None else None
+        self._check(self.lib.lw_accumulate(self.h, ctypes.byref(batch.struct), PATHS.get(path, path),
+                                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                           ctypes.c_void_p(pp) if pp else None))
+        return workspace
+
+    def read_spectra(self):
+        out = np.zeros((self.ns, self.nd, self.nw), dtype=np.float64)
+        self._check(self.lib.lw_read_spectra(self.h, _np_ptr(out)))
+        return out
+
+    def read_spectra_status(self):
+        """(status, S, message) without raising on LW_ERANGE."""
+        out = np.zeros((self.ns, self.nd, self.nw), dtype=np.float64)
+        st = self.lib.lw_read_spectra(self.h, _np_ptr(out))
+        return st, out, self.lib.lw_last_error(self.h).decode()
+
+    def reset(self):
+        self._check(self.lib.lw_reset(self.h))
+
+    def load_accumulator(self, S):
+        s = np.ascontiguousarray(S, dtype=np.float64)
+        assert s.size == self.ns * self.nd * self.nw
+        self._check(self.lib.lw_load_accumulator(self.h, _np_ptr(s)))
+
+    def stats(self) -> int:
+        calls = ctypes.c_int64()
+        self._check(self.lib.lw_stats(self.h, ctypes.byref(calls)))
+        return calls.value

@@ -1,0 +1,192 @@
+"""GPU parity of the FP32 path against the FP64 oracle, through the C ABI.
+
+Tolerance: the FP32 path must match the oracle to 1e-5 relative, per
+(species, direction), on every frequency bin whose oracle value is at least
+1e-4 of that direction's peak (bins below that floor are dominated by the
+FP32 rounding of the phase factors and are reported, not bounded).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Batch, configs, orbits
+
+from _parity import all_bins_relative_error, band_relative_error, gpu_spectrum
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _report(name, S, ref):
+    print(f"[parity] {name}: band-limited rel err {band_relative_error(S, ref):.3e}, "
+          f"all-bin {all_bins_relative_error(S, ref):.3e}", flush=True)
+
+
+def test_synchrotron_workload():
+    cfg = configs.synchrotron_setup()
+    b = orbits.circular(cfg["gamma"], 1.0, cfg["n"], cfg["dt"], accel_dtype=np.float32)
+    ref = oracle.spectrum(b, cfg["dirs"], cfg["omega"], n_species=1)
+    S = gpu_spectrum(b, cfg["dirs"], cfg["omega"])
+    _report("synchrotron", S, ref)
+    assert band_relative_error(S, ref) <= TOL
+
+
+def test_jitter_subset():
+    r = configs.jitter_recipe()
+    b = workloads.generate(r, 0, 48)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 1024)
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    S = gpu_spectrum(b, dirs, om)
+    _report("jitter 48 particles", S, ref)
+    assert band_relative_error(S, ref) <= TOL
+
+
+def test_wide_subset_many_frequencies():
+    r = configs.wide_recipe()
+    b = workloads.generate(r, 1000, 6)
+    dirs = configs.dirs_wide()
+    om = configs.log_grid(0.1, 1e3, 2048)
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    S = gpu_spectrum(b, dirs, om)
+    _report("wide 6 particles x 16 dirs x 2048", S, ref)
+    assert band_relative_error(S, ref) <= TOL
+
+
+def test_uneven_species_subset():
+    r = configs.uneven_recipe()
+    b = workloads.generate(r, 0, 18)
+    dirs = configs.dirs_equal_area()[::4]
+    om = configs.log_grid(0.1, 1e3, 1024)
+    ref = oracle.spectrum(b, dirs, om, n_species=3)
+    S = gpu_spectrum(b, dirs, om, n_species=3)
+    _report("uneven 18 particles, 3 species", S, ref)
+    assert band_relative_error(S, ref) <= TOL
+
+
+@pytest.mark.parametrize("nw", [1, 300, 513])
+def test_ragged_lengths_and_frequency_tails(nw):
+    r = configs.uneven_recipe()
+    full = workloads.generate(r, 40, 9)
+    lens = [1, 63, 64, 65, 255, 256, 257, 1000, 0]
+    parts = []
+    for i, L in enumerate(lens):
+        one = full.select([i])
+        one.offsets = np.array([0, L], dtype=np.int64)
+        for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
+            setattr(one, k, getattr(one, k)[:L])
+        parts.append(one)
+    b = Batch.concat(parts)
+    dirs = np.array([[1, 0, 0], [0.2, -0.7, 0.4], [0, 0, -1]], dtype=float)
+    om = configs.log_grid(0.3, 700, nw) if nw > 1 else np.array([5.0])
+    ref, ref_pp = oracle.spectrum(b, dirs, om, n_species=3, per_particle=True)
+    S, pp = gpu_spectrum(b, dirs, om, n_species=3, per_particle=True)
+    _report(f"ragged nw={nw}", S, ref)
+    assert band_relative_error(S, ref) <= TOL
+    assert np.all(pp[8] == 0) and np.all(ref_pp[8] == 0)  # empty trajectory
+    for p in range(8):
+        assert band_relative_error(pp[p], ref_pp[p]) <= 2 * TOL
+
+
+def test_straight_motion_is_exactly_zero():
+    b = Batch.concat([orbits.straight([0.9, 0.1, 0], [1, 2, 3], 700, 0.01, accel_dtype=np.float32),
+                      orbits.straight([-0.3, 0.5, 0.6], [0, 0, 0], 300, 0.02, accel_dtype=np.float32)])
+    S = gpu_spectrum(b, configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 256))
+    assert np.all(S == 0.0)
+
+
+def test_data_errors_are_reported():
+    from paper_1003_1140_amd import LW_ERANGE, Context, DeviceBatch
+
+    r = configs.jitter_recipe(steps=300)
+    b = workloads.generate(r, 0, 6)
+    b.bx[b.offsets[3] + 17] = 1.0  # |beta| >= 1 in particle 3
+    b.z[b.offsets[5] + 2] = np.nan  # non-finite position in particle 5
+    c = Context(0)
+    c.set_directions(configs.dirs_jitter())
+    c.set_log_frequencies(0.1, 1e3, 64)
+    c.accumulate(DeviceBatch.from_host(b))
+    st, S, msg = c.read_spectra_status()
+    assert st == LW_ERANGE and "particle 3" in msg
+    assert np.all(np.isfinite(S))
+    c.reset()
+    good = b.select([0, 1, 2, 4])
+    c.accumulate(DeviceBatch.from_host(good))
+    st, S, msg = c.read_spectra_status()
+    assert st == 0
+    # out-of-range species
+    bad = b.select([0, 1])
+    bad.species = np.array([0, 5], dtype=np.int32)
+    c.reset()
+    c.accumulate(DeviceBatch.from_host(bad))
+    st, S, msg = c.read_spectra_status()
+    assert st == LW_ERANGE and "particle 1" in msg
+
+
+def test_deterministic_additive_and_resumable():
+    from paper_1003_1140_amd import Context, DeviceBatch
+
+    r = configs.jitter_recipe(steps=700)
+    b = workloads.generate(r, 0, 40)
+    c = Context(0)
+    c.set_directions(configs.dirs_jitter())
+    c.set_log_frequencies(0.1, 1e3, 512)
+    db = DeviceBatch.from_host(b)
+    c.accumulate(db)
+    S1 = c.read_spectra()
+    c.reset()
+    c.accumulate(db)
+    S2 = c.read_spectra()
+    assert np.array_equal(S1, S2)
+    c.accumulate(db)
+    assert np.array_equal(c.read_spectra(), 2 * S1)
+    # split the batch, save after the first part, resume in a fresh context
+    c.reset()
+    c.accumulate(DeviceBatch.from_host(b.select(range(0, 17))))
+    saved = c.read_spectra()
+    c2 = Context(0)
+    c2.set_directions(configs.dirs_jitter())
+    c2.set_log_frequencies(0.1, 1e3, 512)
+    c2.load_accumulator(saved)
+    c2.accumulate(DeviceBatch.from_host(b.select(range(17, 40))))
+    np.testing.assert_allclose(c2.read_spectra(), S1, rtol=1e-12)
+    np.testing.assert_allclose(c.get_frequencies(), configs.log_grid(0.1, 1e3, 512), rtol=1e-15)
+
+
+def test_full_size_workload_sampled_bins():
+    """The bench's launch: the whole 1e5-particle jitter ensemble x 4096 samples x 4 dirs x 1024 bins
+    in one lw_accumulate.  The oracle recomputes 12 sampled (direction, frequency) bins over all
+    1e5 particles, chunk by chunk as the ensemble is generated."""
+    import torch
+
+    from paper_1003_1140_amd import Context, DeviceBatch
+    from workloads.device import upload_chunks
+
+    r = configs.jitter_recipe()
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 1024)
+    rng = np.random.default_rng(5)
+    picks = [(d, int(j)) for d in range(4) for j in rng.choice(1024, 3, replace=False)]
+    pd = dirs[[d for d, _ in picks]]
+    pw = om[[j for _, j in picks]]
+    ref = np.zeros(len(picks))
+
+    def feed(h):
+        ref[:] += oracle.sampled_bins(h, pd, pw)
+
+    n = configs.WORKLOADS["jitter"]["n_particles"]
+    tensors, _ = upload_chunks(r, n, 8192, torch.device("cuda"), on_chunk=feed)
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(om)
+    c.accumulate(DeviceBatch(tensors, n), "fp32")
+    S = c.read_spectra()[0]
+    got = np.array([S[d, j] for d, j in picks])
+    rel = np.abs(got - ref) / ref
+    print(f"[parity] full jitter workload (1e5 particles), 12 sampled bins: max rel err {rel.max():.3e}",
+          flush=True)
+    peak = S.max(axis=1)
+    for i, (d, j) in enumerate(picks):
+        if ref[i] >= 1e-4 * peak[d]:
+            assert rel[i] <= TOL
