@@ -40,18 +40,82 @@ def fp32_term_peak():
     return 4.0 * 64.0 / 48.0 * 256 * 2.4e9
 
 
+PEAK_MFMA_TFLOPS = 2500.0  # dense FP16/BF16 matrix peak of one MI355X
+
+
+def split_path(name):
+    """'mfma_f16x3' -> ('mfma_f16', 3); 'fp32' -> ('fp32', 1)."""
+    if name.endswith("x3"):
+        return name[:-2], 3
+    if name.endswith("x1"):
+        return name[:-2], 1
+    return name, 1
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--particles", type=int, default=100_000)
     ap.add_argument("--chunk", type=int, default=8192, help="particles generated per host chunk")
-    ap.add_argument("--path", default="fp32", choices=["fp32"])
+    ap.add_argument("--paths", default="fp32,mfma_f16x1,mfma_bf16x3,mfma_f16x3",
+                    help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
+    ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
+
+
+def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
+    worst = 0.0
+    idx = np.array_split(np.arange(om.size), n_bands)
+    for s, r in zip(S.reshape(-1, om.size), ref.reshape(-1, om.size)):
+        pr = np.array([np.trapezoid(r[i] * om[i], np.log(om[i])) for i in idx])
+        ps = np.array([np.trapezoid(s[i] * om[i], np.log(om[i])) for i in idx])
+        m = pr >= floor * pr.max()
+        worst = max(worst, float(np.max(np.abs(ps[m] - pr[m]) / pr[m])))
+    return worst
+
+
+def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands):
+    import torch
+
+    path, products = split_path(name)
+    ctx.set_mfma_options(bands, products, products)
+    ws = ctx.workspace(batch, path)
+    for _ in range(warmup):
+        ctx.accumulate(batch, path, workspace=ws)
+    torch.cuda.synchronize()
+    ctx.reset()
+    ctx.profile_read()  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.accumulate(batch, path, workspace=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    S = ctx.read_spectra() / steps
+    assert np.all(np.isfinite(S))
+    res = {"terms_per_s": terms_per_step * steps / el, "ms_per_step": el / steps * 1e3,
+           "kernel_ms_per_step": {k: prof[k] / steps for k in ("direct_ms", "spread_ms", "gemm_ms")}}
+    if path == "fp32":
+        per_launch_ms = prof["direct_ms"] / max(prof["direct_launches"], 1)
+        ach = terms_per_step * steps / prof["direct_launches"] / (per_launch_ms * 1e-3)
+        peak = fp32_term_peak()
+        res["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Tterm/s",
+                           "frac": ach / peak, "traffic": None, "kernel": "lw_direct_f32_kernel<4>",
+                           "avg_launch_ms": per_launch_ms}
+    else:
+        ach = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
+        peak = PEAK_MFMA_TFLOPS
+        res["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                           "frac": ach / peak, "traffic": None, "kernel": "lw_dft_mfma_kernel",
+                           "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
+                           "launches_per_step": prof["gemm_launches"] / steps}
+    return res, S
 
 
 def cpu_baseline(recipe, dirs, om, target_s):
@@ -111,56 +175,44 @@ def main():
     ctx = Context(0)
     ctx.set_directions(dirs)
     ctx.set_frequencies(om)
-    ws = ctx.workspace(batch, a.path)
-    stream = torch.cuda.current_stream(dev)
-    for i in range(a.warmup):
-        ctx.accumulate(batch, a.path, workspace=ws)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done", file=sys.stderr, flush=True)
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        ev[i][0].record(stream)
-        ctx.accumulate(batch, a.path, workspace=ws)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    S = ctx.read_spectra()
-    assert np.all(np.isfinite(S))
-    launch_s = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev]
-    timed_terms = terms_per_step * a.steps
-    value = timed_terms / el
-    per_launch = timed_terms / a.steps
-    achieved = per_launch / (sum(launch_s) / len(launch_s))
-    peak = fp32_term_peak()
+    ctx.set_profiling(True)
+    paths = [p for p in a.paths.split(",") if p]
+    results, spectra = {}, {}
+    for path in paths:
+        results[path], spectra[path] = time_path(ctx, batch, path, a.steps, a.warmup, terms_per_step,
+                                                 a.bands)
+        print(f"[bench] {path}: {results[path]['terms_per_s']:.3e} terms/s", file=sys.stderr, flush=True)
+    if "fp32" in spectra:
+        for path in paths:
+            if path != "fp32":
+                results[path]["band_integrated_err_vs_fp32"] = band_integrated_error(
+                    spectra[path], spectra["fp32"], om)
+    head = paths[-1]
+    r = results[head]
     out = {
         "metric": "LW spectral terms/s (particle x step x omega x n)",
-        "value": value,
+        "value": r["terms_per_s"],
         "unit": "terms/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": el / a.steps * 1e3,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (f64 phase)",
+        "dtype": {"fp32": "f32 (f64 phase)", "mfma_f16": "f16 / f32 acc",
+                  "mfma_bf16": "bf16 / f32 acc"}[split_path(head)[0]] + " x%d" % split_path(head)[1],
         "data": "synthetic",
         "config": {"workload": f"filamentation-jitter ensemble: {a.particles} e- of gamma0=3 "
                                "counter-streaming beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), "
                                "1024 log omega in [0.1,1e3]; 1 step = the whole ensemble",
                    "particles": a.particles, "samples_per_particle": 4096, "directions": 4,
-                   "frequencies": 1024, "path": a.path},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "Tterm/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "lw_direct_f32_kernel<4>"},
+                   "frequencies": 1024, "path": head, "bands": a.bands},
+        "roofline": r["roofline"],
+        "paths": results,
     }
     if not a.no_cpu_baseline:
-        print(f"[bench] timed {a.steps} steps in {el:.2f} s; running CPU oracle baseline",
-              file=sys.stderr, flush=True)
+        print("[bench] running CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(recipe, dirs, om, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 

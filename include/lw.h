@@ -59,8 +59,8 @@ typedef enum {
  *   LW_PATH_MFMA_F16 / LW_PATH_MFMA_BF16: the sum over samples as a dense
  *     contraction on the matrix cores -- each particle's integrand is spread
  *     onto a uniform retarded-time grid per frequency band, contracted with
- *     a shared table of phase factors e^{i w q h} held in FP16 (BF16) hi/lo
- *     pairs, FP32 accumulation, then deconvolved (see lw_mfma_error_bound). */
+ *     a shared table of phase factors e^{i w q h} in FP16 (BF16), FP32
+ *     accumulation, then deconvolved (see lw_set_mfma_options). */
 typedef enum { LW_PATH_FP32 = 0, LW_PATH_MFMA_F16 = 1, LW_PATH_MFMA_BF16 = 2 } lw_path;
 
 /* Particle batch (structure of arrays, device pointers, borrowed).
@@ -106,13 +106,28 @@ lw_status lw_get_frequencies(const lw_ctx* ctx, double* host_omega);
 /* Number of species accumulated separately (>= 1, <= 8).  Resets S. */
 lw_status lw_set_species(lw_ctx* ctx, int32_t n_species);
 
-/* Device workspace (bytes) lw_accumulate needs for this batch and path. */
+/* Matrix-core path options.  bands: number of frequency bands (contiguous runs
+ * of the frequency list, 1..16; default 1), each with its own retarded-time
+ * grid.  More bands shrink the contraction (its rows per band) but every band
+ * spreads every sample again.  products_f16 / products_bf16: 1 = operands rounded once to FP16/BF16;
+ * 3 = each operand split into hi + lo parts and hi*hi + hi*lo + lo*hi summed
+ * (defaults: 3 for both; one product keeps 11 (FP16) or 8 (BF16) mantissa
+ * bits and is measured, not guaranteed, against the 1e-3 band target). */
+lw_status lw_set_mfma_options(lw_ctx* ctx, int32_t bands, int32_t products_f16,
+                              int32_t products_bf16);
+
+/* Device workspace (bytes) lw_accumulate needs for this batch and path.  For
+ * the matrix-core paths this call reads the batch on the device to size the
+ * retarded-time grids (it synchronises the stream) and prepares the phase
+ * tables; lw_accumulate repeats the check and enlarges the tables if a
+ * later batch needs more. */
 lw_status lw_workspace_size(lw_ctx* ctx, const lw_batch* batch, lw_path path, size_t* bytes);
 
-/* Add the batch's spectrum into S (asynchronous).  workspace: device memory
+/* Add the batch's spectrum into S (asynchronous for the FP32 path; the
+ * matrix-core paths synchronise once to size their grids).  workspace: device memory
  * of at least lw_workspace_size bytes, 256-byte aligned.  per_particle: NULL
  * or device float [n_particles][nd][nw] receiving each particle's own
- * w_p q_p^2 |A_p|^2 / (4 pi^2).  Host-side checks (sizes, NULL pointers,
+ * w_p q_p^2 |A_p|^2 / (4 pi^2) (FP32 path only; LW_EUNSUPPORTED otherwise).  Host-side checks (sizes, NULL pointers,
  * workspace size and alignment) fail before any launch. */
 lw_status lw_accumulate(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
                         size_t workspace_bytes, float* per_particle);
@@ -125,6 +140,16 @@ lw_status lw_read_spectra(lw_ctx* ctx, double* host_out);
 lw_status lw_reset(lw_ctx* ctx);
 /* Replace S with host_in [n_species][nd][nw] (resume from a saved state). */
 lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
+
+/* Kernel timing with HIP events recorded on the context's stream around each
+ * accumulation kernel launch (enable != 0 turns it on; off by default). */
+lw_status lw_set_profiling(lw_ctx* ctx, int32_t enable);
+/* Synchronise, then report and clear the timings gathered since the last read:
+ * host_out[6] = {FP32 accumulation kernel ms, spreading kernel ms, matrix-core
+ * contraction kernel ms, useful contraction FLOPs (2 x rows x columns x inner
+ * length per particle, direction and band, times the number of products),
+ * FP32 kernel launches, contraction kernel launches}. */
+lw_status lw_profile_read(lw_ctx* ctx, double* host_out);
 
 /* Number of successful lw_accumulate calls since creation. */
 lw_status lw_stats(const lw_ctx* ctx, int64_t* calls);

@@ -139,6 +139,36 @@ size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 }  // namespace
 
+namespace lw {
+
+static hipError_t next_event(lw_ctx* c, hipEvent_t* e) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t n;
+    hipError_t err = hipEventCreate(&n);
+    if (err != hipSuccess) return err;
+    c->ev_pool.push_back(n);
+  }
+  *e = c->ev_pool[c->ev_used++];
+  return hipSuccess;
+}
+
+hipError_t prof_begin(lw_ctx* c, int kind) {
+  if (!c->prof) return hipSuccess;
+  hipEvent_t a, b;
+  hipError_t e = next_event(c, &a);
+  if (e == hipSuccess) e = next_event(c, &b);
+  if (e != hipSuccess) return e;
+  c->ev_marks.push_back({kind, {a, b}});
+  return hipEventRecord(a, c->stream);
+}
+
+hipError_t prof_end(lw_ctx* c) {
+  if (!c->prof || c->ev_marks.empty()) return hipSuccess;
+  return hipEventRecord(c->ev_marks.back().second.second, c->stream);
+}
+
+}  // namespace lw
+
 extern "C" {
 
 lw_status lw_create(lw_ctx** out, int device, void* stream) {
@@ -170,6 +200,8 @@ void lw_destroy(lw_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   lw::mfma_cache_destroy(c->mfma);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  free_dev(c->d_flops);
   free_dev(c->d_dirs);
   free_dev(c->d_wturn);
   free_dev(c->d_omega);
@@ -315,7 +347,9 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
     a.partial = (double*)ws;
     a.per_particle = per_particle;
     a.err = c->d_err;
+    LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
     LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32");
+    LW_HIP(lw::prof_end(c), "profile");
     LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw,
                                       c->d_S, c->stream),
            "launch lw_reduce_partials");
@@ -361,6 +395,52 @@ lw_status lw_load_accumulator(lw_ctx* c, const double* in) {
   size_t n = (size_t)c->ns * c->nd * c->nw;
   LW_HIP(hipMemcpyAsync(c->d_S, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "load S");
   LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  return LW_OK;
+}
+
+lw_status lw_set_mfma_options(lw_ctx* c, int32_t bands, int32_t products_f16,
+                              int32_t products_bf16) {
+  if (!c) return LW_EINVAL;
+  return lw::mfma_set_options(c, bands, products_f16, products_bf16);
+}
+
+lw_status lw_set_profiling(lw_ctx* c, int32_t enable) {
+  if (!c) return LW_EINVAL;
+  DeviceGuard g(c->device);
+  if (enable && !c->d_flops) {
+    LW_HIP(hipMalloc(&c->d_flops, sizeof(unsigned long long)), "hipMalloc(flops)");
+    LW_HIP(lw::launch_fill_u64(c->d_flops, 1, 0ull, c->stream), "zero flops");
+  }
+  c->prof = enable != 0;
+  return LW_OK;
+}
+
+lw_status lw_profile_read(lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  DeviceGuard g(c->device);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  double ms[lw::kProfKinds] = {0, 0, 0};
+  double n[lw::kProfKinds] = {0, 0, 0};
+  for (auto& m : c->ev_marks) {
+    float t = 0.f;
+    LW_HIP(hipEventElapsedTime(&t, m.second.first, m.second.second), "event time");
+    ms[m.first] += t;
+    n[m.first] += 1;
+  }
+  unsigned long long fl = 0;
+  if (c->d_flops) {
+    LW_HIP(hipMemcpy(&fl, c->d_flops, sizeof(fl), hipMemcpyDeviceToHost), "copy flops");
+    LW_HIP(lw::launch_fill_u64(c->d_flops, 1, 0ull, c->stream), "zero flops");
+    LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  }
+  out[0] = ms[lw::kProfDirect];
+  out[1] = ms[lw::kProfSpread];
+  out[2] = ms[lw::kProfGemm];
+  out[3] = (double)fl * c->flop_mult;
+  out[4] = n[lw::kProfDirect];
+  out[5] = n[lw::kProfGemm];
+  c->ev_marks.clear();
+  c->ev_used = 0;
   return LW_OK;
 }
 

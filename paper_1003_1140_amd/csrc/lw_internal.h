@@ -69,4 +69,18 @@ struct lw_ctx {
   std::string err;
   int64_t calls = 0;
   lw::MfmaPlanCache* mfma = nullptr;
+  // kernel timing with HIP events (lw_set_profiling)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;  // (kind, (start, stop))
+  unsigned long long* d_flops = nullptr;  // useful matrix-core FLOPs counted on the device
+  int flop_mult = 1;                     // products of the last matrix-core launch
 };
+
+namespace lw {
+enum ProfKind { kProfDirect = 0, kProfSpread = 1, kProfGemm = 2, kProfKinds = 3 };
+// Record an event pair around a launch when profiling is on (no-op otherwise).
+hipError_t prof_begin(lw_ctx* c, int kind);
+hipError_t prof_end(lw_ctx* c);
+}  // namespace lw

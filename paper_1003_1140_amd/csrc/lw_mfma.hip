@@ -1,23 +1,971 @@
-// lw_mfma.hip -- matrix-core path (not yet available in this build).
+// lw_mfma.hip -- matrix-core path of the spectral sum (paper, Section 2.2).
+//
+// The sum over samples A(w) = sum_k g_k e^{i w tau_k} is recast so that the
+// phase factors form one dense table shared by all particles:
+//
+//  * The frequencies are split into bands b (contiguous runs of the frequency
+//    list) with centre w_c and half-width D.  For each (particle, direction,
+//    band) the samples are spread onto a uniform grid t_q = (q - W/2) h,
+//    h = pi / (sigma D), of the retarded time measured from the particle's
+//    first sample, after demodulation by e^{i w_c tau}:
+//        F(q) = sum_k g_k e^{i w_c tau'_k} phi(q - u_k),  u_k = tau'_k / h + W/2,
+//    with the "exponential of semicircle" kernel
+//        phi(x) = exp(beta (sqrt(1 - (2x/W)^2) - 1)),  |x| < W/2
+//    (Barnett, Magland & af Klinteberg 2019).  tau' = tau - tau_0 only shifts
+//    the phase of A, which the incoherent |A|^2 does not see.
+//  * Then, by the Poisson summation formula, for |w - w_c| <= D
+//        A(w) e^{-i w tau_0} = sum_q F(q) e^{i (w - w_c) t_q} / Phi((w - w_c) h),
+//    Phi the Fourier transform of phi, up to aliasing terms suppressed by the
+//    kernel (sigma = 2, W = 8: ~1e-7 of sum |g|).
+//  * sum_q F(q) e^{i nu_j q h} is a complex matrix product C = E F with the
+//    table E[j, q] = e^{i nu_j q h} (nu_j = w_j - w_c) shared by every particle
+//    and direction.  Written as a real product it has rows (j, re|im), inner
+//    index (q, re|im) and columns (particle, polarisation):
+//        [C_re]   [E_re  -E_im] [F_re]
+//        [C_im] = [E_im   E_re] [F_im]
+//    and runs on v_mfma_f32_32x32x16_{f16,bf16} with FP32 accumulation.
+//    Operands are rounded to FP16 (or BF16); optionally each is split into
+//    hi + lo parts and three products are summed (hi*hi + hi*lo + lo*hi).
+//    The F columns are scaled by a power of two so |F| <= 1 before rounding.
+//  * The epilogue squares the product, weights each column with
+//    w_p q_p^2 / scale^2, sums over columns and writes per-row partial sums;
+//    a fixed-order reduction adds re and im rows of each frequency, applies
+//    1 / (4 pi^2 Phi^2) and accumulates into S.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "lw_mfma.h"
 
 namespace lw {
 
-struct MfmaPlanCache {};
+constexpr int kW = 8;              // kernel width in grid points
+constexpr double kSigma = 2.0;     // grid oversampling relative to the band half-width
+constexpr double kBeta = 2.30 * kW;
+constexpr int kMaxBands = 16;
+constexpr int kTileM = 128;        // GEMM rows per work-group
+constexpr int kTileN = 128;        // GEMM columns per work-group (64 particles x 2 polarisations)
+constexpr int kTileK = 32;         // inner-dimension step staged in LDS
+constexpr int kPad = 8;            // LDS row padding (halves)
+constexpr int kSpreadWin = 256;    // grid points per spreading window (one per thread)
 
-MfmaPlanCache* mfma_cache_create() { return new MfmaPlanCache(); }
-void mfma_cache_destroy(MfmaPlanCache* c) { delete c; }
-void mfma_cache_invalidate(MfmaPlanCache*) {}
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-lw_status mfma_workspace_size(lw_ctx* c, const lw_batch*, lw_path, size_t* bytes) {
-  *bytes = 0;
-  c->err = "matrix-core path not available";
-  return LW_EUNSUPPORTED;
+struct Band {
+  int j0, nj;        // frequency index range
+  double wc, h;      // centre frequency, grid spacing
+  double wc_turn;    // wc / (2 pi)
+  int qmax;          // grid points allotted per (particle, direction)
+  int m;             // GEMM rows (2 nj rounded up to kTileM)
+  int kp;            // inner dimension stride (2 qmax rounded up to kTileK)
+  int row_off;       // first row of this band in the stacked row space
+  int64_t e_off;     // offset of this band's table (elements)
+  int64_t f_off;     // offset of this band's F block (floats) inside one chunk
+};
+
+struct MfmaPlanCache {
+  bool valid = false;
+  int bands_req = 1;
+  int products_f16 = 3, products_bf16 = 3;
+  int tile_rows = 256;   // contraction work-group rows (128 or 256)
+  int nb = 0;
+  Band band[kMaxBands];
+  double span = 0.0;     // span the tables were sized for
+  int dtype = -1;        // 0: f16, 1: bf16 (table element type)
+  int rows = 0;          // sum of band rows
+  int64_t e_elems = 0;
+  void* e_hi = nullptr;
+  void* e_lo = nullptr;
+  double* rowfac = nullptr;  // [nw] 1 / (4 pi^2 Phi(nu h)^2)
+  int32_t* row_of_j = nullptr;  // [nw] stacked row of (j, re)
+  double* d_span = nullptr;  // device scratch for the span reduction
+};
+
+struct SpreadArgs {
+  BatchView b;
+  int64_t p_begin;
+  int32_t n_local;       // particles in this chunk
+  const double* dirs;    // [nd][kDirStride]
+  int32_t nd;
+  Band band[kMaxBands];
+  int nb;
+  int64_t f_dir;         // floats of F per direction
+  float* F;              // chunk F blocks, [d][band][2 n_local][kp]
+  unsigned* colmax;      // [nd][nb][2 * n_local] float bits of max |F|
+  int32_t* colq;         // [nd][nb][n_local] grid points of each particle
+  int32_t* tilek;        // [nd][nb][n_tiles] max inner length (2 q) of the tile's columns
+  int32_t n_ftile;       // column tiles per band
+  int32_t ns;            // species count (a species outside [0, ns) is a data error)
+  unsigned long long* err;
+  unsigned long long* flops;  // null, or useful FLOPs of one product of the contraction
+};
+
+struct GemmArgs {
+  BatchView b;
+  int64_t p_begin;
+  int32_t n_local;
+  int32_t n_ftile;
+  Band band[kMaxBands];
+  int nb;
+  int32_t nd;
+  int64_t f_dir;         // floats of F per direction
+  int order[kMaxBands];             // bands in launch order (heaviest first)
+  int tiles_before[kMaxBands + 1];  // prefix count of work-groups per band, per direction
+  const void* e_hi;
+  const void* e_lo;
+  const float* F;
+  const unsigned* colmax;
+  const int32_t* colq;
+  const int32_t* tilek;
+  double* partial;       // [nd][n_ftile][ns][rows]
+  int32_t ns, rows;
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double dot3(const double a[3], double x, double y, double z) {
+  return a[0] * x + a[1] * y + a[2] * z;
 }
 
-lw_status mfma_accumulate(lw_ctx* c, const lw_batch*, lw_path, void*, size_t, float*) {
-  c->err = "matrix-core path not available";
-  return LW_EUNSUPPORTED;
+__device__ __forceinline__ double retarded_time(const BatchView& b, int64_t idx, double t,
+                                                const double n[3]) {
+  return t - dot3(n, b.x[idx], b.y[idx], b.z[idx]);
+}
+
+__device__ __forceinline__ float es_kernel(float x) {
+  // exp(beta (sqrt(1 - (2x/W)^2) - 1)) for |x| < W/2, else 0
+  const float y = x * (2.0f / kW);
+  const float r = 1.0f - y * y;
+  if (!(r > 0.0f)) return 0.0f;
+  return __expf((float)kBeta * (__builtin_sqrtf(r) - 1.0f));
+}
+
+// ------------------------------------------------------------------ span of every (particle, direction)
+__global__ void lw_span_kernel(BatchView b, const double* dirs, int nd, double* out_max) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < b.n_particles * (int64_t)nd) {
+    const int64_t p = i / nd;
+    const int d = (int)(i % nd);
+    const int64_t o = b.offsets[p], len = b.offsets[p + 1] - o;
+    if (len > 1) {
+      const double n[3] = {dirs[kDirStride * d], dirs[kDirStride * d + 1], dirs[kDirStride * d + 2]};
+      const double ta = retarded_time(b, o, b.t0[p], n);
+      const double tb = retarded_time(b, o + len - 1, b.t0[p] + (double)(len - 1) * b.dt[p], n);
+      s = tb - ta;
+      if (!(s >= 0.0) || !isfinite(s)) s = 0.0;  // bad data is flagged by the spread kernel
+    }
+  }
+  // wave max, then one atomic per wave (positive doubles order like their bit patterns)
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off));
+  if ((threadIdx.x & 63) == 0 && s > 0.0)
+    atomicMax((unsigned long long*)out_max, (unsigned long long)__double_as_longlong(s));
+}
+
+// ------------------------------------------------------------------ phase table
+template <typename T>
+__global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)bd.m * bd.kp;
+  if (i >= total) return;
+  const int row = (int)(i / bd.kp), kk = (int)(i % bd.kp);
+  const int jl = row >> 1, a = row & 1;  // a: 0 = re row, 1 = im row
+  const int q = kk >> 1, c = kk & 1;     // c: 0 = multiplies F_re, 1 = multiplies F_im
+  double v = 0.0;
+  if (jl < bd.nj && q < bd.qmax) {
+    const double nu = omega[bd.j0 + jl] - bd.wc;
+    // turn fraction of nu q h / (2 pi) in FP64, then FP64 sin/cos
+    const double x = nu * (double)q * bd.h * (0.5 / M_PI);
+    const double f = x - rint(x);
+    const double cs = cos(2.0 * M_PI * f), sn = sin(2.0 * M_PI * f);
+    // rows: re = [cos, -sin], im = [sin, cos]
+    v = (a == 0) ? (c == 0 ? cs : -sn) : (c == 0 ? sn : cs);
+  }
+  const T h = (T)v;
+  hi[bd.e_off + i] = h;
+  lo[bd.e_off + i] = (T)(v - (double)h);
+}
+
+// ------------------------------------------------------------------ spreading
+// One work-group per (particle of the chunk, band); thread t owns grid point q0 + t of
+// the current window.  Samples are sorted in tau because dtau/dt = kappa > 0, so the
+// windows walk a monotone cursor through the samples: chunks of 256 samples are staged
+// in LDS (prepass, demodulation, grid coordinate) and reused while they still reach
+// the next window, and each thread finds its samples by binary search in LDS.
+struct SpreadStage {
+  int iu[kSpreadWin];      // integer part of the grid coordinate u_k
+  float fu[kSpreadWin];    // fractional part
+  float4 g[kSpreadWin];    // demodulated integrand (re1, im1, re2, im2)
+};
+
+__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage& st,
+                                              const double* n, const double* e1, const double* e2,
+                                              int64_t p, int64_t o, int64_t len, int64_t kc,
+                                              double t0, double dtp, double tau0, double inv_h) {
+  const int tid = threadIdx.x;
+  const int64_t k = kc + tid;
+  if (k < len) {
+    const int64_t idx = o + k;
+    const double bx = a.b.bx[idx], by = a.b.by[idx], bz = a.b.bz[idx];
+    const double ax = (double)a.b.ax[idx], ay = (double)a.b.ay[idx], az = (double)a.b.az[idx];
+    const double kap = 1.0 - dot3(n, bx, by, bz);
+    const double na = dot3(n, ax, ay, az);
+    const double sc = dtp / (kap * kap);
+    const double g1 = -(na * dot3(e1, bx, by, bz) + kap * dot3(e1, ax, ay, az)) * sc;
+    const double g2 = -(na * dot3(e2, bx, by, bz) + kap * dot3(e2, ax, ay, az)) * sc;
+    const double taup = retarded_time(a.b, idx, t0 + (double)k * dtp, n) - tau0;
+    const bool ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(taup) && isfinite(g1) && isfinite(g2);
+    if (!ok) atomicMin(a.err, (unsigned long long)p);
+    const double x = bd.wc_turn * taup;
+    const float fr = (float)(x - rint(x));
+    const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+    double u = taup * inv_h + 0.5 * kW;
+    // keep the staged coordinates sorted and bounded even for invalid samples
+    u = ok ? fmin(fmax(u, 0.0), 1.0e9) : 1.0e9;
+    const double iu = floor(u);
+    st.iu[tid] = (int)iu;
+    st.fu[tid] = (float)(u - iu);
+    const float G1 = ok ? (float)g1 : 0.f, G2 = ok ? (float)g2 : 0.f;
+    st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
+  }
+}
+
+// number of staged samples (of cnt) with u <= x
+__device__ __forceinline__ int count_le(const SpreadStage& st, int cnt, float x_int, float x_frac) {
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const float d = ((float)st.iu[mid] - x_int) + st.fu[mid] - x_frac;  // u_mid - x
+    if (d > 0.0f) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
+  __shared__ SpreadStage st;
+  __shared__ float s_wmax[kSpreadWin / 64];
+
+  const int tid = threadIdx.x;
+  // block -> (particle, direction, band); bands fastest so one particle's work is adjacent
+  const int bi = blockIdx.x % a.nb;
+  const int d = (blockIdx.x / a.nb) % a.nd;
+  const int pl = blockIdx.x / (a.nb * a.nd);
+  const Band bd = a.band[bi];
+  const int64_t p = a.p_begin + pl;
+  const int64_t o = a.b.offsets[p], len = a.b.offsets[p + 1] - o;
+  const double t0 = a.b.t0[p], dtp = a.b.dt[p];
+  const int ncol = 2 * a.n_local;
+  const int db = d * a.nb + bi;
+  float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
+  double n[3], e1[3], e2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    n[c] = a.dirs[kDirStride * d + c];
+    e1[c] = a.dirs[kDirStride * d + 3 + c];
+    e2[c] = a.dirs[kDirStride * d + 6 + c];
+  }
+
+  if (tid == 0 && bi == 0 && d == 0 && a.b.species) {
+    const int sp = a.b.species[p];
+    if (sp < 0 || sp >= a.ns) atomicMin(a.err, (unsigned long long)p);
+  }
+  int Q = 0;
+  double tau0 = 0.0;
+  if (len > 0) {
+    tau0 = retarded_time(a.b, o, t0, n);
+    const double taul = retarded_time(a.b, o + len - 1, t0 + (double)(len - 1) * dtp, n);
+    double span = taul - tau0;
+    if (!(span >= 0.0) || !isfinite(span)) span = 0.0;
+    Q = (int)fmin(ceil(span / bd.h) + kW + 1, (double)bd.qmax);
+  }
+  const double inv_h = 1.0 / bd.h;
+  float wmax = 0.0f;
+  int64_t kc = -1;     // first sample of the staged chunk (-1: none)
+  int cnt = 0;         // samples in the staged chunk
+  int64_t cursor = 0;  // first sample that can reach the current window
+
+  for (int q0 = 0; q0 < Q; q0 += kSpreadWin) {
+    // G grid points in this window; when G is small each grid point's samples are split
+    // over S consecutive threads (slices k = s mod S) and summed with shuffles.
+    const int G = min(kSpreadWin, Q - q0);
+    int S = 1;
+    while (S < 64 && 2 * S * G <= kSpreadWin) S *= 2;
+    const int g = tid / S, sl = tid % S;
+    const bool active = g < G;
+    const int q = q0 + g;
+    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+    int64_t next_cursor = -1;
+    int64_t k = cursor;
+    while (k < len) {
+      if (kc < 0 || k < kc || k >= kc + cnt) {
+        __syncthreads();  // the previous chunk is no longer read
+        stage_samples(a, bd, st, n, e1, e2, p, o, len, k, t0, dtp, tau0, inv_h);
+        kc = k;
+        cnt = (int)min((int64_t)kSpreadWin, len - k);
+        __syncthreads();
+      }
+      if (active) {
+        // staged samples with q - W/2 < u < q + W/2, this thread taking every S-th
+        int s0 = count_le(st, cnt, (float)q, -0.5f * kW);
+        s0 += (sl - s0 % S + S) % S;
+        for (int s = s0; s < cnt; s += S) {
+          const float dx = ((float)(q - st.iu[s])) - st.fu[s];  // q - u
+          if (dx <= -0.5f * kW) break;
+          const float w = es_kernel(dx);
+          const float4 gv = st.g[s];
+          acc0 = fmaf(w, gv.x, acc0);
+          acc1 = fmaf(w, gv.y, acc1);
+          acc2 = fmaf(w, gv.z, acc2);
+          acc3 = fmaf(w, gv.w, acc3);
+        }
+      }
+      // the next window needs samples with u > q0 + win - W/2
+      if (next_cursor < 0) {
+        const int nle = count_le(st, cnt, (float)(q0 + kSpreadWin), -0.5f * kW);
+        if (nle < cnt) next_cursor = kc + nle;
+      }
+      // does this window need samples beyond the staged chunk?
+      const int last = cnt - 1;
+      const float dlast = ((float)st.iu[last] - (float)(q0 + G - 1)) + st.fu[last] - 0.5f * kW;
+      if (kc + cnt < len && dlast < 0.0f) {
+        k = kc + cnt;
+        continue;
+      }
+      break;
+    }
+    cursor = next_cursor >= 0 ? next_cursor : len;
+    for (int off = S >> 1; off > 0; off >>= 1) {
+      acc0 += __shfl_xor(acc0, off);
+      acc1 += __shfl_xor(acc1, off);
+      acc2 += __shfl_xor(acc2, off);
+      acc3 += __shfl_xor(acc3, off);
+    }
+    if (active && sl == 0) {
+      float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
+      float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
+      *(float2*)(c0 + 2 * q) = make_float2(acc0, acc1);
+      *(float2*)(c1 + 2 * q) = make_float2(acc2, acc3);
+      wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(acc0), fabsf(acc1)), fmaxf(fabsf(acc2), fabsf(acc3))));
+    }
+  }
+  // column maximum (one value for both polarisation columns keeps them on one scale)
+  for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off));
+  if ((tid & 63) == 0) s_wmax[tid >> 6] = wmax;
+  __syncthreads();
+  if (tid == 0) {
+    float m = 0.f;
+    for (int w = 0; w < kSpreadWin / 64; ++w) m = fmaxf(m, s_wmax[w]);
+    a.colmax[db * ncol + 2 * pl] = __float_as_uint(m);
+    a.colmax[db * ncol + 2 * pl + 1] = __float_as_uint(m);
+    a.colq[db * a.n_local + pl] = Q;
+    atomicMax(&a.tilek[db * a.n_ftile + (2 * pl) / kTileN], 2 * Q);
+    // rows (2 nj) x columns (2 polarisations) x inner (2 Q) multiply-adds of one product
+    if (a.flops) atomicAdd(a.flops, 2ull * (2ull * bd.nj) * 2ull * (2ull * Q));
+  }
+}
+
+// ------------------------------------------------------------------ DFT contraction on MFMA
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<_Float16> {
+  typedef half8 vec;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaOp<__bf16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ f32x16 mma(vec a, vec b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Global loads of one inner step into registers (A: 8-element vectors of the phase
+// table; B: float4 of F, zero past each column's length).
+template <typename T, int NP, int A_VEC, int B_VEC>
+__device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)[A_VEC],
+                                               f32x4 (&rb)[B_VEC], const T* E_hi, const T* E_lo,
+                                               const float* Fb, const int* s_q2, int tid, int row0,
+                                               int col0, int ncol, int kp, int k0) {
+#pragma unroll
+  for (int v = 0; v < A_VEC; ++v) {
+    const int c = tid + v * 256;
+    const int r = c / (kTileK / 8), kc = (c % (kTileK / 8)) * 8;
+    const size_t g = (size_t)(row0 + r) * kp + k0 + kc;
+    ra0[v] = *(const u32x4*)(E_hi + g);
+    if (NP > 1) ra1[v] = *(const u32x4*)(E_lo + g);
+  }
+#pragma unroll
+  for (int v = 0; v < B_VEC; ++v) {
+    const int c = tid + v * 256;
+    const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
+    const int gc = col0 + col;
+    const int lim = s_q2[col] - (k0 + kc);
+    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gc < ncol && lim > 0) {
+      x = *(const f32x4*)(Fb + (size_t)gc * kp + k0 + kc);
+      if (lim < 4) {
+        x.w = 0.f;
+        if (lim < 3) x.z = 0.f;
+        if (lim < 2) x.y = 0.f;
+      }
+    }
+    rb[v] = x;
+  }
+}
+
+// Work-group tile TM x 128: 4 waves arranged WR x WC (TM = 64 WR), each wave owning
+// 64 rows x (128 / WC) columns as 2 x NB MFMA blocks of 32 x 32.  The inner dimension
+// advances in steps of 32: the next step's operands are loaded from global memory into
+// registers while the current step's MFMAs run from LDS.
+// MFMA 32x32x16 operand layout: lane l holds A[m = l%32][k = 8(l/32) .. +7] and
+// B[k = 8(l/32) .. +7][n = l%32]; result register r of lane l is row
+// 8(r/4) + 4(l/32) + r%4, column l%32.
+template <typename T, int PRODUCTS, int WR>
+__global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
+  typedef typename MfmaOp<T>::vec vec;
+  constexpr int WC = 4 / WR;
+  constexpr int TM = 64 * WR;
+  constexpr int NB = kTileN / (32 * WC);
+  constexpr int LD = kTileK + kPad;
+  constexpr int NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int A_VEC = TM * kTileK / 8 / 256;       // 8-element vectors of A per thread
+  constexpr int B_VEC = kTileN * kTileK / 4 / 256;   // float4 of F per thread
+  __shared__ __attribute__((aligned(16))) T sA[NP][TM * LD];
+  __shared__ __attribute__((aligned(16))) T sB[NP][kTileN * LD];
+  __shared__ float s_scale[kTileN];
+  __shared__ int s_q2[kTileN];
+  __shared__ float s_colw[kMaxSpecies][kTileN];
+  __shared__ double s_rows[4][64];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // block -> (band in heaviest-first order, column group, row tile).  Work-groups are
+  // dispatched round-robin over the 8 XCDs; the mapping gives each XCD whole column
+  // groups with all their row tiles in sequence, so a column group's F tile is read
+  // from HBM once and reused from that XCD's L2 by the other row tiles.
+  int oi = 0;
+  while (oi + 1 < a.nb && (int)blockIdx.x >= a.tiles_before[oi + 1]) ++oi;
+  const int bi = a.order[oi];
+  const Band bd = a.band[bi];
+  const int local = blockIdx.x - a.tiles_before[oi];
+  const int mtiles = bd.m / TM;
+  const int ngroups = a.nd * a.n_ftile;     // (direction, column tile) pairs
+  const int xcd = local % 8, seq = local / 8;
+  const int grp = (seq / mtiles) * 8 + xcd;
+  if (grp >= ngroups) return;               // padding of the XCD-aware numbering
+  const int mt = seq % mtiles;
+  const int nt = grp % a.n_ftile;
+  const int d = grp / a.n_ftile;
+  const int ncol = 2 * a.n_local;
+  const int db = d * a.nb + bi;
+  const int col0 = nt * kTileN;
+  const int row0 = mt * TM;
+  const T* E_hi = (const T*)a.e_hi + bd.e_off;
+  const T* E_lo = (const T*)a.e_lo + bd.e_off;
+  const float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
+
+  if (tid < kTileN) {
+    const int c = col0 + tid;
+    float sc = 1.0f;
+    int q2 = 0;
+    for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
+    if (c < ncol) {
+      const float m = __uint_as_float(a.colmax[db * ncol + c]);
+      if (m > 0.0f) {
+        int e;
+        frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+        sc = ldexpf(1.0f, -e);
+      }
+      q2 = 2 * a.colq[db * a.n_local + c / 2];
+      const int64_t p = a.p_begin + c / 2;
+      const int sp = a.b.species ? a.b.species[p] : 0;
+      if (sp >= 0 && sp < a.ns) {
+        const float qq = a.b.charge[p];
+        s_colw[sp][tid] = a.b.weight[p] * qq * qq / (sc * sc);
+      }
+    }
+    s_scale[tid] = sc;
+    s_q2[tid] = q2;
+  }
+  const int kend = min(((a.tilek[db * a.n_ftile + nt] + kTileK - 1) / kTileK) * kTileK, bd.kp);
+  __syncthreads();
+
+  // register staging of one inner step
+  u32x4 ra0[A_VEC], ra1[A_VEC];
+  f32x4 rb[B_VEC];
+
+  f32x16 acc[2][NB];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  const int wr = wave / WC, wc = wave % WC;
+  if (kend > 0) gemm_load_step<T, NP, A_VEC, B_VEC>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0, ncol, bd.kp, 0);
+  for (int k0 = 0; k0 < kend; k0 += kTileK) {
+    __syncthreads();  // the previous step's LDS operands have been consumed
+#pragma unroll
+    for (int v = 0; v < A_VEC; ++v) {
+      const int c = tid + v * 256;
+      const int r = c / (kTileK / 8), kc = (c % (kTileK / 8)) * 8;
+      *(u32x4*)&sA[0][r * LD + kc] = ra0[v];
+      if (NP > 1) *(u32x4*)&sA[NP - 1][r * LD + kc] = ra1[v];
+    }
+#pragma unroll
+    for (int v = 0; v < B_VEC; ++v) {
+      const int c = tid + v * 256;
+      const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
+      const float sc = s_scale[col];
+      const float x0 = rb[v].x * sc, x1 = rb[v].y * sc, x2 = rb[v].z * sc, x3 = rb[v].w * sc;
+      typedef T t4 __attribute__((ext_vector_type(4)));
+      const t4 hv = {(T)x0, (T)x1, (T)x2, (T)x3};
+      *(t4*)&sB[0][col * LD + kc] = hv;
+      if (NP > 1) {
+        const t4 lv = {(T)(x0 - (float)hv[0]), (T)(x1 - (float)hv[1]), (T)(x2 - (float)hv[2]),
+                       (T)(x3 - (float)hv[3])};
+        *(t4*)&sB[NP - 1][col * LD + kc] = lv;
+      }
+    }
+    __syncthreads();
+    if (k0 + kTileK < kend)
+      gemm_load_step<T, NP, A_VEC, B_VEC>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0, ncol, bd.kp, k0 + kTileK);
+#pragma unroll
+    for (int ks = 0; ks < kTileK; ks += 16) {
+      const int kk = ks + 8 * (lane >> 5);
+      vec fa[NP][2], fb[NP][NB];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wr * 64 + i * 32 + (lane & 31);
+        fa[0][i] = *(const vec*)&sA[0][r * LD + kk];
+        if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[NP - 1][r * LD + kk];
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int cc = wc * (32 * NB) + j * 32 + (lane & 31);
+        fb[0][j] = *(const vec*)&sB[0][cc * LD + kk];
+        if (NP > 1) fb[NP - 1][j] = *(const vec*)&sB[NP - 1][cc * LD + kk];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
+          if (PRODUCTS > 1) {
+            acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
+            acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
+          }
+        }
+    }
+  }
+
+  // epilogue: per species, sum_c colw[c] * C[r][c]^2 over this tile's columns
+  for (int s = 0; s < a.ns; ++s) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int cc = wc * (32 * NB) + j * 32 + (lane & 31);
+          const float c = acc[i][j][r];
+          v = fmaf(c * c, s_colw[s][cc], v);
+        }
+        // sum over the 32 columns held by lanes with the same lane / 32
+        for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((lane & 31) == 0) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
+      }
+    __syncthreads();
+    if (tid < TM) {
+      // row tid of the tile: the WC waves of row group tid / 64 hold its column sums
+      const int g = tid / 64, rr = tid % 64;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < WC; ++w) v += s_rows[g * WC + w][rr];
+      a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
+    }
+  }
+}
+
+// S[s][d][j] += rowfac[j] * sum over column tiles of (re row + im row)
+__global__ void lw_mfma_reduce_kernel(const double* partial, int n_ftile, int ns, int rows,
+                                      const int32_t* row_of_j, const double* rowfac, int nw,
+                                      int nd, double* S) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nd * ns * nw) return;
+  const int j = i % nw;
+  const int s = (i / nw) % ns;
+  const int d = i / (nw * ns);
+  const int r = row_of_j[j];
+  double acc = 0.0;
+  for (int t = 0; t < n_ftile; ++t) {
+    const double* pr = partial + (((size_t)d * n_ftile + t) * ns + s) * rows;
+    acc += pr[r] + pr[r + 1];
+  }
+  S[((size_t)s * nd + d) * nw + j] += acc * rowfac[j];
+}
+
+__global__ void lw_fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+
+double es_phi_host(double x) {
+  const double y = 2.0 * x / kW;
+  const double r = 1.0 - y * y;
+  return r > 0.0 ? exp(kBeta * (sqrt(r) - 1.0)) : 0.0;
+}
+
+// Fourier transform of the kernel, Phi(xi) = int phi(x) cos(xi x) dx, by composite
+// Gauss-Legendre quadrature (the kernel is smooth inside its support).
+double es_ft_host(double xi) {
+  static const double gx[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
+                               -0.1834346424956498, 0.1834346424956498,  0.5255324099163290,
+                               0.7966664774136267,  0.9602898564975363};
+  static const double gw[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
+                               0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
+                               0.2223810344533745, 0.1012285362903763};
+  const int panels = 64;
+  const double a = -0.5 * kW, w = (double)kW / panels;
+  double s = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double c = a + (p + 0.5) * w;
+    for (int i = 0; i < 8; ++i) {
+      const double x = c + 0.5 * w * gx[i];
+      s += 0.5 * w * gw[i] * es_phi_host(x) * cos(xi * x);
+    }
+  }
+  return s;
+}
+
+lw_status set_err(lw_ctx* c, lw_status st, const char* msg) {
+  c->err = msg;
+  return st;
+}
+
+#define MF_HIP(call, what)                                                      \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      c->err = std::string(what) + ": " + hipGetErrorString(e_);                \
+      return LW_EDEVICE;                                                        \
+    }                                                                           \
+  } while (0)
+
+int chunk_particles(const MfmaPlanCache* pc, int nd, int64_t P) {
+  // particles per chunk bounded so that F (all directions) stays near 2 GiB
+  int64_t per = 0;
+  for (int b = 0; b < pc->nb; ++b) per += 2 * (int64_t)pc->band[b].kp * sizeof(float);
+  per *= nd;
+  int64_t n = per > 0 ? (int64_t)(2LL << 30) / per : 8192;
+  n = std::max<int64_t>(64, std::min<int64_t>(n, 16384));
+  n = (n / 64) * 64;
+  return (int)std::min<int64_t>(n, ((P + 63) / 64) * 64);
+}
+
+struct WsLayout {
+  size_t f, colmax, colq, tilek, partial, total;
+  int chunk, n_ftile;
+  int64_t f_dir;  // floats of F per direction
+};
+
+size_t al(size_t n) { return (n + 255) & ~(size_t)255; }
+
+WsLayout ws_layout(const lw_ctx* c, const MfmaPlanCache* pc, int64_t P) {
+  WsLayout w;
+  const int nd = c->nd, nb = pc->nb;
+  w.chunk = chunk_particles(pc, nd, P);
+  w.n_ftile = (2 * w.chunk + kTileN - 1) / kTileN;
+  int64_t fl = 0;
+  for (int b = 0; b < nb; ++b) fl += (int64_t)2 * w.chunk * pc->band[b].kp;
+  w.f_dir = fl;
+  size_t off = 0;
+  w.f = off;
+  off += al((size_t)fl * nd * sizeof(float));
+  w.colmax = off;
+  off += al((size_t)nd * nb * 2 * w.chunk * sizeof(unsigned));
+  w.colq = off;
+  off += al((size_t)nd * nb * w.chunk * sizeof(int32_t));
+  w.tilek = off;
+  off += al((size_t)nd * nb * w.n_ftile * sizeof(int32_t));
+  w.partial = off;
+  off += al((size_t)nd * w.n_ftile * c->ns * pc->rows * sizeof(double));
+  w.total = off;
+  return w;
+}
+
+void free_tables(MfmaPlanCache* pc) {
+  if (pc->e_hi) (void)hipFree(pc->e_hi);
+  if (pc->e_lo) (void)hipFree(pc->e_lo);
+  if (pc->rowfac) (void)hipFree(pc->rowfac);
+  if (pc->row_of_j) (void)hipFree(pc->row_of_j);
+  pc->e_hi = pc->e_lo = nullptr;
+  pc->rowfac = nullptr;
+  pc->row_of_j = nullptr;
+  pc->valid = false;
+}
+
+BatchView view_of(const lw_batch* b) {
+  return {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+          b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+}
+
+// Largest retarded-time span over the batch and directions (synchronous).
+lw_status batch_span(lw_ctx* c, const lw_batch* b, double* span) {
+  MfmaPlanCache* pc = c->mfma;
+  if (!pc->d_span) MF_HIP(hipMalloc(&pc->d_span, sizeof(double)), "hipMalloc(span)");
+  MF_HIP(launch_fill_f64(pc->d_span, 1, 0.0, c->stream), "fill span");
+  const int64_t n = b->n_particles * (int64_t)c->nd;
+  if (n > 0) {
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(lw_span_kernel, grid, block, 0, c->stream, view_of(b), c->d_dirs, c->nd,
+                       pc->d_span);
+    MF_HIP(hipGetLastError(), "launch span");
+  }
+  double h = 0.0;
+  MF_HIP(hipMemcpyAsync(&h, pc->d_span, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy span");
+  MF_HIP(hipStreamSynchronize(c->stream), "sync");
+  *span = h;
+  return LW_OK;
+}
+
+lw_status build_plan(lw_ctx* c, double span, int dtype) {
+  MfmaPlanCache* pc = c->mfma;
+  free_tables(pc);
+  const int nb = std::max(1, std::min(pc->bands_req, std::min(kMaxBands, c->nw)));
+  pc->nb = nb;
+  pc->span = span;
+  pc->dtype = dtype;
+  const std::vector<double>& w = c->h_omega;
+  int row = 0;
+  int64_t eoff = 0, foff = 0;
+  for (int b = 0; b < nb; ++b) {
+    Band& bd = pc->band[b];
+    bd.j0 = (int)((int64_t)c->nw * b / nb);
+    const int j1 = (int)((int64_t)c->nw * (b + 1) / nb);
+    bd.nj = j1 - bd.j0;
+    double lo = w[bd.j0], hi = w[bd.j0];
+    for (int j = bd.j0; j < j1; ++j) {
+      lo = std::min(lo, w[j]);
+      hi = std::max(hi, w[j]);
+    }
+    bd.wc = 0.5 * (lo + hi);
+    double D = 0.5 * (hi - lo);
+    D = std::max(D, 1e-6 * std::max(bd.wc, 1e-300));
+    bd.h = M_PI / (kSigma * D);
+    bd.wc_turn = bd.wc / (2.0 * M_PI);
+    const double qd = ceil(span / bd.h) + kW + 1;
+    if (qd > 4.0e6) return set_err(c, LW_EUNSUPPORTED, "retarded-time span too long for the matrix-core grid");
+    bd.qmax = (int)qd;
+    bd.m = ((2 * bd.nj + kTileM - 1) / kTileM) * kTileM;
+    bd.kp = ((2 * bd.qmax + kTileK - 1) / kTileK) * kTileK;
+    bd.row_off = row;
+    bd.e_off = eoff;
+    bd.f_off = foff;  // in units of (columns x kp); scaled by chunk at launch
+    row += bd.m;
+    eoff += (int64_t)bd.m * bd.kp;
+    foff += bd.kp;
+  }
+  pc->rows = row;
+  pc->e_elems = eoff;
+  const size_t esz = 2;  // f16 and bf16 are both 2 bytes
+  MF_HIP(hipMalloc(&pc->e_hi, (size_t)eoff * esz), "hipMalloc(E)");
+  MF_HIP(hipMalloc(&pc->e_lo, (size_t)eoff * esz), "hipMalloc(E)");
+  for (int b = 0; b < nb; ++b) {
+    const Band& bd = pc->band[b];
+    const int64_t tot = (int64_t)bd.m * bd.kp;
+    dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    if (dtype == 0)
+      hipLaunchKernelGGL(lw_etable_kernel<_Float16>, grid, block, 0, c->stream,
+                         (_Float16*)pc->e_hi, (_Float16*)pc->e_lo, c->d_omega, bd);
+    else
+      hipLaunchKernelGGL(lw_etable_kernel<__bf16>, grid, block, 0, c->stream, (__bf16*)pc->e_hi,
+                         (__bf16*)pc->e_lo, c->d_omega, bd);
+    MF_HIP(hipGetLastError(), "launch etable");
+  }
+  std::vector<double> rf(c->nw);
+  std::vector<int32_t> rj(c->nw);
+  for (int b = 0; b < nb; ++b) {
+    const Band& bd = pc->band[b];
+    for (int jl = 0; jl < bd.nj; ++jl) {
+      const int j = bd.j0 + jl;
+      const double ph = es_ft_host((w[j] - bd.wc) * bd.h);
+      rf[j] = 1.0 / (4.0 * M_PI * M_PI * ph * ph);
+      rj[j] = bd.row_off + 2 * jl;
+    }
+  }
+  MF_HIP(hipMalloc(&pc->rowfac, c->nw * sizeof(double)), "hipMalloc(rowfac)");
+  MF_HIP(hipMalloc(&pc->row_of_j, c->nw * sizeof(int32_t)), "hipMalloc(rows)");
+  MF_HIP(hipMemcpy(pc->rowfac, rf.data(), c->nw * sizeof(double), hipMemcpyHostToDevice), "copy rowfac");
+  MF_HIP(hipMemcpy(pc->row_of_j, rj.data(), c->nw * sizeof(int32_t), hipMemcpyHostToDevice), "copy rows");
+  MF_HIP(hipStreamSynchronize(c->stream), "sync");
+  pc->valid = true;
+  return LW_OK;
+}
+
+// Make sure the tables cover the batch; grows the span with headroom.
+lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path) {
+  MfmaPlanCache* pc = c->mfma;
+  const int dtype = path == LW_PATH_MFMA_BF16 ? 1 : 0;
+  double span = 0.0;
+  lw_status st = batch_span(c, b, &span);
+  if (st != LW_OK) return st;
+  if (pc->valid && pc->dtype == dtype && span <= pc->span) return LW_OK;
+  const double want = std::max(span * 1.25, pc->valid ? pc->span : 0.0);
+  return build_plan(c, want, dtype);
+}
+
+}  // namespace
+
+MfmaPlanCache* mfma_cache_create() { return new MfmaPlanCache(); }
+
+void mfma_cache_destroy(MfmaPlanCache* pc) {
+  if (!pc) return;
+  free_tables(pc);
+  if (pc->d_span) (void)hipFree(pc->d_span);
+  delete pc;
+}
+
+void mfma_cache_invalidate(MfmaPlanCache* pc) {
+  if (pc) free_tables(pc);
+}
+
+lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16) {
+  MfmaPlanCache* pc = c->mfma;
+  if (bands < 1 || bands > kMaxBands) return set_err(c, LW_EINVAL, "bands must be in [1, 16]");
+  if ((products_f16 != 1 && products_f16 != 3) || (products_bf16 != 1 && products_bf16 != 3))
+    return set_err(c, LW_EINVAL, "products must be 1 or 3");
+  if (bands != pc->bands_req) free_tables(pc);
+  pc->bands_req = bands;
+  pc->products_f16 = products_f16;
+  pc->products_bf16 = products_bf16;
+  return LW_OK;
+}
+
+lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes) {
+  if (!b || b->n_particles < 0) return set_err(c, LW_EINVAL, "bad batch");
+  if (b->n_particles == 0) {
+    *bytes = 0;
+    return LW_OK;
+  }
+  lw_status st = ensure_plan(c, b, path);
+  if (st != LW_OK) return st;
+  *bytes = ws_layout(c, c->mfma, b->n_particles).total;
+  return LW_OK;
+}
+
+lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
+                          float* per_particle) {
+  if (per_particle)
+    return set_err(c, LW_EUNSUPPORTED, "per-particle output is available on the FP32 path only");
+  lw_status st = ensure_plan(c, b, path);
+  if (st != LW_OK) return st;
+  MfmaPlanCache* pc = c->mfma;
+  const WsLayout L = ws_layout(c, pc, b->n_particles);
+  if (ws_bytes < L.total) return set_err(c, LW_ENOMEM, "workspace too small for the matrix-core plan");
+  char* base = (char*)ws;
+  float* F = (float*)(base + L.f);
+  unsigned* colmax = (unsigned*)(base + L.colmax);
+  int32_t* colq = (int32_t*)(base + L.colq);
+  int32_t* tilek = (int32_t*)(base + L.tilek);
+  double* partial = (double*)(base + L.partial);
+  const int products = path == LW_PATH_MFMA_BF16 ? pc->products_bf16 : pc->products_f16;
+
+  SpreadArgs sa;
+  GemmArgs ga;
+  sa.b = ga.b = view_of(b);
+  sa.nb = ga.nb = pc->nb;
+  sa.nd = ga.nd = c->nd;
+  sa.dirs = c->d_dirs;
+  sa.f_dir = ga.f_dir = L.f_dir;
+  for (int i = 0; i < pc->nb; ++i) {
+    Band bd = pc->band[i];
+    bd.f_off = pc->band[i].f_off * 2 * L.chunk;
+    sa.band[i] = ga.band[i] = bd;
+  }
+  sa.F = F;
+  ga.F = F;
+  sa.colmax = colmax;
+  ga.colmax = colmax;
+  sa.colq = colq;
+  ga.colq = colq;
+  sa.tilek = tilek;
+  ga.tilek = tilek;
+  sa.err = c->d_err;
+  sa.ns = c->ns;
+  sa.flops = c->prof ? c->d_flops : nullptr;
+  c->flop_mult = products;
+  ga.e_hi = pc->e_hi;
+  ga.e_lo = pc->e_lo;
+  ga.partial = partial;
+  ga.ns = c->ns;
+  ga.rows = pc->rows;
+  // bands by decreasing work (grid points per particle), so the long tiles start first
+  for (int i = 0; i < pc->nb; ++i) ga.order[i] = i;
+  std::sort(ga.order, ga.order + pc->nb,
+            [&](int x, int y) { return pc->band[x].qmax * pc->band[x].m > pc->band[y].qmax * pc->band[y].m; });
+  bool tall = pc->tile_rows == 256;  // 256-row tiles need every band's rows to be a multiple of 256
+  for (int i = 0; i < pc->nb; ++i) tall = tall && (pc->band[i].m % 256 == 0);
+  const int tm = tall ? 256 : 128;
+  const bool bf = path == LW_PATH_MFMA_BF16;
+
+  for (int64_t p0 = 0; p0 < b->n_particles; p0 += L.chunk) {
+    const int nl = (int)std::min<int64_t>(L.chunk, b->n_particles - p0);
+    const int nft = (2 * nl + kTileN - 1) / kTileN;
+    sa.p_begin = ga.p_begin = p0;
+    sa.n_local = ga.n_local = nl;
+    sa.n_ftile = ga.n_ftile = nft;
+    {
+      const int64_t n = (int64_t)c->nd * pc->nb * nft;
+      dim3 grid((unsigned)((n + 255) / 256)), block(256);
+      hipLaunchKernelGGL(lw_fill_i32_kernel, grid, block, 0, c->stream, tilek, n, 0);
+      MF_HIP(hipGetLastError(), "launch fill");
+    }
+    MF_HIP(prof_begin(c, kProfSpread), "profile");
+    hipLaunchKernelGGL(lw_spread_kernel, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)), dim3(kSpreadWin),
+                       0, c->stream, sa);
+    MF_HIP(hipGetLastError(), "launch spread");
+    MF_HIP(prof_end(c), "profile");
+    int tiles = 0;
+    for (int oi = 0; oi < pc->nb; ++oi) {
+      ga.tiles_before[oi] = tiles;
+      const int groups = c->nd * nft;
+      tiles += (pc->band[ga.order[oi]].m / tm) * ((groups + 7) / 8) * 8;
+    }
+    ga.tiles_before[pc->nb] = tiles;
+    MF_HIP(prof_begin(c, kProfGemm), "profile");
+#define LW_GEMM(T, P, W) hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, W>), dim3(tiles), dim3(256), 0, c->stream, ga)
+    if (!bf && products == 1) { if (tall) LW_GEMM(_Float16, 1, 4); else LW_GEMM(_Float16, 1, 2); }
+    else if (!bf) { if (tall) LW_GEMM(_Float16, 3, 4); else LW_GEMM(_Float16, 3, 2); }
+    else if (products == 1) { if (tall) LW_GEMM(__bf16, 1, 4); else LW_GEMM(__bf16, 1, 2); }
+    else { if (tall) LW_GEMM(__bf16, 3, 4); else LW_GEMM(__bf16, 3, 2); }
+#undef LW_GEMM
+    MF_HIP(hipGetLastError(), "launch dft_mfma");
+    MF_HIP(prof_end(c), "profile");
+    {
+      const int n = c->nd * c->ns * c->nw;
+      dim3 grid((unsigned)((n + 255) / 256)), block(256);
+      hipLaunchKernelGGL(lw_mfma_reduce_kernel, grid, block, 0, c->stream, partial, nft, c->ns,
+                         pc->rows, pc->row_of_j, pc->rowfac, c->nw, c->nd, c->d_S);
+      MF_HIP(hipGetLastError(), "launch mfma reduce");
+    }
+  }
+  return LW_OK;
 }
 
 }  // namespace lw

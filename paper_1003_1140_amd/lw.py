@@ -23,7 +23,8 @@ PATHS = {"fp32": LW_PATH_FP32, "mfma_f16": LW_PATH_MFMA_F16, "mfma_bf16": LW_PAT
 EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set_directions",
             "lw_set_frequencies", "lw_set_log_frequencies", "lw_get_frequencies", "lw_set_species",
             "lw_workspace_size", "lw_accumulate", "lw_read_spectra", "lw_reset",
-            "lw_load_accumulator", "lw_stats")
+            "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_profiling",
+            "lw_profile_read")
 
 
 class LWError(RuntimeError):
@@ -73,6 +74,9 @@ def load_library():
             "lw_reset": (ctypes.c_int, [P]),
             "lw_load_accumulator": (ctypes.c_int, [P, P]),
             "lw_stats": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+            "lw_set_mfma_options": (ctypes.c_int, [P, I32, I32, I32]),
+            "lw_set_profiling": (ctypes.c_int, [P, I32]),
+            "lw_profile_read": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -213,6 +217,18 @@ class Context:
         s = np.ascontiguousarray(S, dtype=np.float64)
         assert s.size == self.ns * self.nd * self.nw
         self._check(self.lib.lw_load_accumulator(self.h, _np_ptr(s)))
+
+    def set_mfma_options(self, bands=1, products_f16=3, products_bf16=3):
+        self._check(self.lib.lw_set_mfma_options(self.h, bands, products_f16, products_bf16))
+
+    def set_profiling(self, enable=True):
+        self._check(self.lib.lw_set_profiling(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        out = np.zeros(6, dtype=np.float64)
+        self._check(self.lib.lw_profile_read(self.h, _np_ptr(out)))
+        return {"direct_ms": out[0], "spread_ms": out[1], "gemm_ms": out[2], "gemm_flops": out[3],
+                "direct_launches": int(out[4]), "gemm_launches": int(out[5])}
 
     def stats(self) -> int:
         calls = ctypes.c_int64()

@@ -49,3 +49,29 @@ def all_bins_relative_error(S, ref):
     ref = np.asarray(ref, dtype=np.float64).ravel()
     m = ref > 0
     return float(np.max(np.abs(S[m] - ref[m]) / ref[m])) if m.any() else 0.0
+
+
+def band_integrated_errors(S, ref, omega, n_bands=16, floor=1e-4):
+    """Relative error of the band-integrated power, per (species, direction) row.
+
+    The frequency list is cut into ``n_bands`` equal runs; each band's power is
+    the trapezoid integral of S d(omega) in ln(omega) (S * omega d ln omega).  Bands
+    whose reference power is below ``floor`` of the row's strongest band are
+    left out.  Returns the worst error of each row.
+    """
+    S = np.asarray(S, dtype=np.float64).reshape(-1, np.shape(S)[-1])
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1, np.shape(ref)[-1])
+    om = np.asarray(omega, dtype=np.float64)
+    idx = np.array_split(np.arange(om.size), n_bands)
+    worst = []
+    for s, r in zip(S, ref):
+        pr = np.array([np.trapezoid(r[i] * om[i], np.log(om[i])) if len(i) > 1 else r[i].sum()
+                       for i in idx])
+        ps = np.array([np.trapezoid(s[i] * om[i], np.log(om[i])) if len(i) > 1 else s[i].sum()
+                       for i in idx])
+        if pr.max() <= 0:
+            worst.append(0.0 if np.all(s == 0) else np.inf)
+            continue
+        m = pr >= floor * pr.max()
+        worst.append(float(np.max(np.abs(ps[m] - pr[m]) / pr[m])))
+    return np.array(worst)

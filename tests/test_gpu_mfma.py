@@ -1,0 +1,148 @@
+"""GPU parity of the matrix-core paths against the FP64 oracle, through the C ABI.
+
+Accuracy statement of these paths: the power integrated over each of 16 equal
+log-frequency bands (per direction) is compared with the oracle for every band
+holding at least 1e-4 of the direction's strongest band.  Default operands
+(FP16 split into hi + lo parts, three products): within 1e-5.  BF16 hi + lo:
+within 1e-4.  One FP16 product with 8 frequency bands: within 1e-3 on
+ensembles; one product with a single band and one BF16 product are measured
+and printed only.  Per-bin errors are printed, not bounded.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Batch, configs, orbits
+
+from _parity import all_bins_relative_error, band_integrated_errors, band_relative_error, gpu_spectrum
+
+pytestmark = pytest.mark.gpu
+
+
+def run(b, dirs, om, path, bands=1, products_f16=3, products_bf16=3, n_species=1):
+    from paper_1003_1140_amd import Context
+
+    c = Context(0)
+    c.set_mfma_options(bands, products_f16, products_bf16)
+    return gpu_spectrum(b, dirs, om, path=path, n_species=n_species, ctx=c)
+
+
+def report(name, S, ref, om):
+    be = band_integrated_errors(S, ref, om)
+    print(f"[parity] {name}: band-integrated max {be.max():.3e}, per-bin (>=1e-4 peak) "
+          f"{band_relative_error(S, ref):.3e}, all-bin {all_bins_relative_error(S, ref):.3e}", flush=True)
+    return be
+
+
+@pytest.fixture(scope="module")
+def wide():
+    r = configs.wide_recipe()
+    b = workloads.generate(r, 1000, 6)
+    dirs = configs.dirs_wide()
+    om = configs.log_grid(0.1, 1e3, 2048)
+    return b, dirs, om, oracle.spectrum(b, dirs, om, n_species=1)
+
+
+def test_f16_single_product_wide_ensemble():
+    """48 particles of the wide workload: one FP16 product over 8 bands meets 1e-3."""
+    r = configs.wide_recipe()
+    b = workloads.generate(r, 2000, 48)
+    dirs = configs.dirs_wide()
+    om = configs.log_grid(0.1, 1e3, 2048)
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    S = run(b, dirs, om, "mfma_f16", bands=8, products_f16=1)
+    assert report("mfma f16 x1, 8 bands, wide 48 particles", S, ref, om).max() <= 1e-3
+    S = run(b, dirs, om, "mfma_f16", bands=1, products_f16=1)
+    be = report("mfma f16 x1, 1 band, wide 48 particles", S, ref, om)
+    assert be.max() <= 5e-3
+
+
+def test_f16_single_product_small_ensemble(wide):
+    """Six particles keep deep interference fringes; weak bands then see the FP16 rounding
+    (2^-11) more strongly.  Measured ~1.2e-3 with 8 bands; bounded at 2e-3 and printed."""
+    b, dirs, om, ref = wide
+    S = run(b, dirs, om, "mfma_f16", bands=8, products_f16=1)
+    assert report("mfma f16 x1, 8 bands, wide 6 particles", S, ref, om).max() <= 2e-3
+
+
+def test_f16_three_products_wide(wide):
+    b, dirs, om, ref = wide
+    S = run(b, dirs, om, "mfma_f16")
+    assert report("mfma f16 x3, wide 6 particles", S, ref, om).max() <= 1e-5
+
+
+def test_bf16_three_products_wide(wide):
+    b, dirs, om, ref = wide
+    S = run(b, dirs, om, "mfma_bf16", products_bf16=3)
+    assert report("mfma bf16 x3, wide 6 particles", S, ref, om).max() <= 1e-4
+
+
+def test_bf16_single_product_is_reported(wide):
+    """BF16 with one product keeps 8 mantissa bits; its error is measured and printed only."""
+    b, dirs, om, ref = wide
+    S = run(b, dirs, om, "mfma_bf16", products_bf16=1)
+    be = report("mfma bf16 x1, wide 6 particles", S, ref, om)
+    assert np.all(np.isfinite(be)) and be.max() < 0.1
+
+
+@pytest.mark.parametrize("bands", [2, 4, 16])
+def test_band_counts_jitter(bands):
+    r = configs.jitter_recipe()
+    b = workloads.generate(r, 0, 24)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 1024)
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    S = run(b, dirs, om, "mfma_f16", bands=bands, products_f16=3)
+    assert report(f"mfma f16 x3, jitter 24 particles, {bands} bands", S, ref, om).max() <= 1e-5
+
+
+def test_synchrotron_workload():
+    cfg = configs.synchrotron_setup()
+    b = orbits.circular(cfg["gamma"], 1.0, cfg["n"], cfg["dt"], accel_dtype=np.float32)
+    ref = oracle.spectrum(b, cfg["dirs"], cfg["omega"], n_species=1)
+    S = run(b, cfg["dirs"], cfg["omega"], "mfma_f16")
+    assert report("mfma f16 x3, synchrotron", S, ref, cfg["omega"]).max() <= 1e-5
+    S = run(b, cfg["dirs"], cfg["omega"], "mfma_f16", bands=8, products_f16=1)
+    assert report("mfma f16 x1, 8 bands, synchrotron", S, ref, cfg["omega"]).max() <= 1e-3
+
+
+def test_uneven_species_ragged():
+    r = configs.uneven_recipe()
+    b = workloads.generate(r, 0, 14)
+    lens = b.lengths().copy()
+    lens[3] = 0
+    lens[5] = 1
+    parts = []
+    for i, L in enumerate(lens):
+        one = b.select([i])
+        one.offsets = np.array([0, L], dtype=np.int64)
+        for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
+            setattr(one, k, getattr(one, k)[:L])
+        parts.append(one)
+    b = Batch.concat(parts)
+    dirs = configs.dirs_equal_area()[::8]
+    om = configs.log_grid(0.1, 1e3, 1000)
+    ref = oracle.spectrum(b, dirs, om, n_species=3)
+    S = run(b, dirs, om, "mfma_f16", products_f16=3, n_species=3)
+    assert report("mfma f16 x3, uneven 14 particles, 3 species", S, ref, om).max() <= 1e-5
+
+
+def test_straight_motion_is_exactly_zero():
+    b = Batch.concat([orbits.straight([0.9, 0.1, 0], [1, 2, 3], 700, 0.01, accel_dtype=np.float32),
+                      orbits.straight([-0.3, 0.5, 0.6], [0, 0, 0], 300, 0.02, accel_dtype=np.float32)])
+    S = run(b, configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 256), "mfma_f16")
+    assert np.all(S == 0.0)
+
+
+def test_agrees_with_fp32_path_on_a_large_batch():
+    """4096 jitter particles: the FP32 path (itself parity-checked) judges the matrix-core path."""
+    r = configs.jitter_recipe()
+    b = workloads.generate(r, 50_000, 4096)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 1024)
+    S32 = gpu_spectrum(b, dirs, om, path="fp32")
+    S16 = run(b, dirs, om, "mfma_f16")
+    assert report("mfma f16 x3 vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-5
+    S16 = run(b, dirs, om, "mfma_f16", products_f16=1)
+    assert report("mfma f16 x1 vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-3
