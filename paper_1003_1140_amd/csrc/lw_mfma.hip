@@ -391,14 +391,14 @@ struct MfmaOp<__bf16> {
 
 // Global loads of one inner step into registers (A: 8-element vectors of the phase
 // table; B: float4 of F, zero past each column's length).
-template <typename T, int NP, int A_VEC, int B_VEC>
+template <typename T, int NP, int A_VEC, int B_VEC, int NT>
 __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)[A_VEC],
                                                f32x4 (&rb)[B_VEC], const T* E_hi, const T* E_lo,
                                                const float* Fb, const int* s_q2, int tid, int row0,
                                                int col0, int ncol, int kp, int k0) {
 #pragma unroll
   for (int v = 0; v < A_VEC; ++v) {
-    const int c = tid + v * 256;
+    const int c = tid + v * NT;
     const int r = c / (kTileK / 8), kc = (c % (kTileK / 8)) * 8;
     const size_t g = (size_t)(row0 + r) * kp + k0 + kc;
     ra0[v] = *(const u32x4*)(E_hi + g);
@@ -406,7 +406,7 @@ __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)
   }
 #pragma unroll
   for (int v = 0; v < B_VEC; ++v) {
-    const int c = tid + v * 256;
+    const int c = tid + v * NT;
     const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
     const int gc = col0 + col;
     const int lim = s_q2[col] - (k0 + kc);
@@ -423,29 +423,62 @@ __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)
   }
 }
 
-// Work-group tile TM x 128: 4 waves arranged WR x WC (TM = 64 WR), each wave owning
-// 64 rows x (128 / WC) columns as 2 x NB MFMA blocks of 32 x 32.  The inner dimension
-// advances in steps of 32: the next step's operands are loaded from global memory into
-// registers while the current step's MFMAs run from LDS.
+// Registers -> LDS: A as loaded; B scaled to |F| <= 1 and rounded (hi, and lo = rest).
+template <typename T, int NP, int A_VEC, int B_VEC, int NT, int LD>
+__device__ __forceinline__ void gemm_store_step(const u32x4 (&ra0)[A_VEC], const u32x4 (&ra1)[A_VEC],
+                                                const f32x4 (&rb)[B_VEC], T* sA0, T* sA1, T* sB0,
+                                                T* sB1, const float* s_scale, int tid) {
+#pragma unroll
+  for (int v = 0; v < A_VEC; ++v) {
+    const int c = tid + v * NT;
+    const int r = c / (kTileK / 8), kc = (c % (kTileK / 8)) * 8;
+    *(u32x4*)&sA0[r * LD + kc] = ra0[v];
+    if (NP > 1) *(u32x4*)&sA1[r * LD + kc] = ra1[v];
+  }
+#pragma unroll
+  for (int v = 0; v < B_VEC; ++v) {
+    const int c = tid + v * NT;
+    const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
+    const float sc = s_scale[col];
+    const float x0 = rb[v].x * sc, x1 = rb[v].y * sc, x2 = rb[v].z * sc, x3 = rb[v].w * sc;
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    const t4 hv = {(T)x0, (T)x1, (T)x2, (T)x3};
+    *(t4*)&sB0[col * LD + kc] = hv;
+    if (NP > 1) {
+      const t4 lv = {(T)(x0 - (float)hv[0]), (T)(x1 - (float)hv[1]), (T)(x2 - (float)hv[2]),
+                     (T)(x3 - (float)hv[3])};
+      *(t4*)&sB1[col * LD + kc] = lv;
+    }
+  }
+}
+
+// Work-group tile TM x 128 with 8 waves arranged WM x WN (TM = 64 WM), each wave owning
+// 64 rows x (128 / WN) columns as 2 x NB MFMA blocks of 32 x 32.  The inner dimension
+// advances in steps of 32 through two LDS buffers: while the MFMAs of step k read one
+// buffer, the operands of step k+1 travel from global memory to registers and then to
+// the other buffer, with one barrier per step.
 // MFMA 32x32x16 operand layout: lane l holds A[m = l%32][k = 8(l/32) .. +7] and
 // B[k = 8(l/32) .. +7][n = l%32]; result register r of lane l is row
 // 8(r/4) + 4(l/32) + r%4, column l%32.
-template <typename T, int PRODUCTS, int WR>
-__global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
+template <typename T, int PRODUCTS, int WM>
+__global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
-  constexpr int WC = 4 / WR;
-  constexpr int TM = 64 * WR;
-  constexpr int NB = kTileN / (32 * WC);
+  constexpr int NT = 512;
+  constexpr int NW = NT / 64;
+  constexpr int WN = NW / WM;
+  constexpr int TM = 64 * WM;
+  constexpr int NB = kTileN / (32 * WN);
   constexpr int LD = kTileK + kPad;
   constexpr int NP = PRODUCTS > 1 ? 2 : 1;
-  constexpr int A_VEC = TM * kTileK / 8 / 256;       // 8-element vectors of A per thread
-  constexpr int B_VEC = kTileN * kTileK / 4 / 256;   // float4 of F per thread
-  __shared__ __attribute__((aligned(16))) T sA[NP][TM * LD];
-  __shared__ __attribute__((aligned(16))) T sB[NP][kTileN * LD];
+  constexpr int A_VEC = TM * kTileK / 8 / NT;       // 8-element vectors of A per thread
+  constexpr int B_VEC = kTileN * kTileK / 4 / NT;   // float4 of F per thread
+  static_assert(A_VEC >= 1 && B_VEC >= 1, "tile too small for the work-group");
+  __shared__ __attribute__((aligned(16))) T sA[2][NP][TM * LD];
+  __shared__ __attribute__((aligned(16))) T sB[2][NP][kTileN * LD];
   __shared__ float s_scale[kTileN];
   __shared__ int s_q2[kTileN];
   __shared__ float s_colw[kMaxSpecies][kTileN];
-  __shared__ double s_rows[4][64];
+  __shared__ double s_rows[NW][64];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // block -> (band in heaviest-first order, column group, row tile).  Work-groups are
@@ -499,10 +532,8 @@ __global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
   const int kend = min(((a.tilek[db * a.n_ftile + nt] + kTileK - 1) / kTileK) * kTileK, bd.kp);
   __syncthreads();
 
-  // register staging of one inner step
   u32x4 ra0[A_VEC], ra1[A_VEC];
   f32x4 rb[B_VEC];
-
   f32x16 acc[2][NB];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -511,35 +542,24 @@ __global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  const int wr = wave / WC, wc = wave % WC;
-  if (kend > 0) gemm_load_step<T, NP, A_VEC, B_VEC>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0, ncol, bd.kp, 0);
+  const int wr = wave / WN, wc = wave % WN;
+  if (kend > 0) {
+    gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0,
+                                            ncol, bd.kp, 0);
+    gemm_store_step<T, NP, A_VEC, B_VEC, NT, LD>(ra0, ra1, rb, sA[0][0], sA[0][NP - 1], sB[0][0],
+                                                 sB[0][NP - 1], s_scale, tid);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < kend; k0 += kTileK) {
-    __syncthreads();  // the previous step's LDS operands have been consumed
-#pragma unroll
-    for (int v = 0; v < A_VEC; ++v) {
-      const int c = tid + v * 256;
-      const int r = c / (kTileK / 8), kc = (c % (kTileK / 8)) * 8;
-      *(u32x4*)&sA[0][r * LD + kc] = ra0[v];
-      if (NP > 1) *(u32x4*)&sA[NP - 1][r * LD + kc] = ra1[v];
-    }
-#pragma unroll
-    for (int v = 0; v < B_VEC; ++v) {
-      const int c = tid + v * 256;
-      const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
-      const float sc = s_scale[col];
-      const float x0 = rb[v].x * sc, x1 = rb[v].y * sc, x2 = rb[v].z * sc, x3 = rb[v].w * sc;
-      typedef T t4 __attribute__((ext_vector_type(4)));
-      const t4 hv = {(T)x0, (T)x1, (T)x2, (T)x3};
-      *(t4*)&sB[0][col * LD + kc] = hv;
-      if (NP > 1) {
-        const t4 lv = {(T)(x0 - (float)hv[0]), (T)(x1 - (float)hv[1]), (T)(x2 - (float)hv[2]),
-                       (T)(x3 - (float)hv[3])};
-        *(t4*)&sB[NP - 1][col * LD + kc] = lv;
-      }
-    }
-    __syncthreads();
-    if (k0 + kTileK < kend)
-      gemm_load_step<T, NP, A_VEC, B_VEC>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0, ncol, bd.kp, k0 + kTileK);
+    const bool more = k0 + kTileK < kend;
+    if (more)
+      gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0,
+                                              ncol, bd.kp, k0 + kTileK);
+    const T* A0 = sA[buf][0];
+    const T* A1 = sA[buf][NP - 1];
+    const T* B0 = sB[buf][0];
+    const T* B1 = sB[buf][NP - 1];
 #pragma unroll
     for (int ks = 0; ks < kTileK; ks += 16) {
       const int kk = ks + 8 * (lane >> 5);
@@ -547,14 +567,14 @@ __global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int r = wr * 64 + i * 32 + (lane & 31);
-        fa[0][i] = *(const vec*)&sA[0][r * LD + kk];
-        if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[NP - 1][r * LD + kk];
+        fa[0][i] = *(const vec*)&A0[r * LD + kk];
+        if (NP > 1) fa[NP - 1][i] = *(const vec*)&A1[r * LD + kk];
       }
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const int cc = wc * (32 * NB) + j * 32 + (lane & 31);
-        fb[0][j] = *(const vec*)&sB[0][cc * LD + kk];
-        if (NP > 1) fb[NP - 1][j] = *(const vec*)&sB[NP - 1][cc * LD + kk];
+        fb[0][j] = *(const vec*)&B0[cc * LD + kk];
+        if (NP > 1) fb[NP - 1][j] = *(const vec*)&B1[cc * LD + kk];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -567,6 +587,11 @@ __global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
           }
         }
     }
+    if (more)
+      gemm_store_step<T, NP, A_VEC, B_VEC, NT, LD>(ra0, ra1, rb, sA[buf ^ 1][0], sA[buf ^ 1][NP - 1],
+                                                   sB[buf ^ 1][0], sB[buf ^ 1][NP - 1], s_scale, tid);
+    __syncthreads();
+    buf ^= 1;
   }
 
   // epilogue: per species, sum_c colw[c] * C[r][c]^2 over this tile's columns
@@ -589,11 +614,11 @@ __global__ __launch_bounds__(256) void lw_dft_mfma_kernel(GemmArgs a) {
       }
     __syncthreads();
     if (tid < TM) {
-      // row tid of the tile: the WC waves of row group tid / 64 hold its column sums
+      // row tid of the tile: the WN waves of row group tid / 64 hold its column sums
       const int g = tid / 64, rr = tid % 64;
       double v = 0.0;
 #pragma unroll
-      for (int w = 0; w < WC; ++w) v += s_rows[g * WC + w][rr];
+      for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][rr];
       a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
     }
   }
@@ -949,7 +974,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     }
     ga.tiles_before[pc->nb] = tiles;
     MF_HIP(prof_begin(c, kProfGemm), "profile");
-#define LW_GEMM(T, P, W) hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, W>), dim3(tiles), dim3(256), 0, c->stream, ga)
+#define LW_GEMM(T, P, W) hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, W>), dim3(tiles), dim3(512), 0, c->stream, ga)
     if (!bf && products == 1) { if (tall) LW_GEMM(_Float16, 1, 4); else LW_GEMM(_Float16, 1, 2); }
     else if (!bf) { if (tall) LW_GEMM(_Float16, 3, 4); else LW_GEMM(_Float16, 3, 2); }
     else if (products == 1) { if (tall) LW_GEMM(__bf16, 1, 4); else LW_GEMM(__bf16, 1, 2); }
