@@ -141,6 +141,45 @@ lw_status lw_reset(lw_ctx* ctx);
 /* Replace S with host_in [n_species][nd][nw] (resume from a saved state). */
 lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
 
+/* ---- batched launches (uneven lengths, several species) ----
+ * Plan a batch for the persistent launch (synchronous; reads the batch offsets).
+ * FP32 path: particles are ordered by decreasing trajectory length and grouped
+ * into work items (particle block x direction x frequency tile) that a fixed
+ * set of work-groups takes, heaviest first, from an atomic ticket queue.  Later
+ * lw_accumulate calls with the same batch (same offsets pointer and size) and
+ * the same grids use the plan; other batches use the plain grid launch.
+ * Matrix-core paths: sizes the retarded-time grids and phase tables, so that
+ * the following lw_accumulate / lw_graph_capture need no synchronisation. */
+lw_status lw_plan_batch(lw_ctx* ctx, const lw_batch* batch, lw_path path);
+
+/* Launch shape: wpt = frequencies per thread of the FP32 kernel (0 automatic,
+ * 1, 2, 4, 8); pb = particles per work item (0 automatic); persistent = use a
+ * matching lw_plan_batch plan (1) or always the plain grid (0); bands and
+ * tile_rows (128 or 256) for the matrix-core contraction (0 = unchanged). */
+lw_status lw_set_tuning(lw_ctx* ctx, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
+                        int32_t tile_rows);
+
+/* Autotuner: time the candidate launch shapes of `path` on `batch` (repeats
+ * timed runs each, HIP events on the context's stream), keep the fastest (as
+ * with lw_set_tuning, plus lw_plan_batch when it is persistent) and restore S.
+ * report (may be NULL): JSON text of every candidate's time and the choice,
+ * truncated to report_len.  cache_json (may be NULL): file receiving the
+ * same JSON.  Allocates and frees its own workspace. */
+lw_status lw_tune(lw_ctx* ctx, const lw_batch* batch, lw_path path, int32_t repeats,
+                  const char* cache_json, char* report, size_t report_len);
+
+/* HIP graph of one lw_accumulate(batch, path, workspace): captured on a
+ * private stream (so it also works when the context uses the null stream),
+ * replayed on the context's stream by lw_graph_launch; each replay adds the
+ * batch's spectrum into S like lw_accumulate.  The batch, workspace and the
+ * context's grids must stay unchanged while the graph is in use.  The
+ * graph clears its counters with kernels, not memset nodes. */
+typedef struct lw_graph lw_graph;
+lw_status lw_graph_capture(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
+                           size_t workspace_bytes, lw_graph** out);
+lw_status lw_graph_launch(lw_graph* graph);
+void lw_graph_destroy(lw_graph* graph);
+
 /* Kernel timing with HIP events recorded on the context's stream around each
  * accumulation kernel launch (enable != 0 turns it on; off by default). */
 lw_status lw_set_profiling(lw_ctx* ctx, int32_t enable);

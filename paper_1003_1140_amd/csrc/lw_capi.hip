@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -106,34 +107,8 @@ lw_status check_grids(lw_ctx* c) {
   return LW_OK;
 }
 
-// Frequencies per thread for the FP32 kernel.
-int pick_wpt(int32_t nw) {
-  if (nw <= lw::kThreads) return 1;
-  if (nw <= 2 * lw::kThreads) return 2;
-  if (nw <= 4 * lw::kThreads) return 4;
-  return 8;
-}
-
-struct DirectShape {
-  int wpt;
-  int32_t n_tiles;
-  int32_t pb;
-  int64_t n_blocks;
-};
-
-DirectShape direct_shape(const lw_ctx* c, int64_t P) {
-  DirectShape s;
-  s.wpt = pick_wpt(c->nw);
-  s.n_tiles = (c->nw + lw::kThreads * s.wpt - 1) / (lw::kThreads * s.wpt);
-  // aim at >= 8 work-groups per compute unit (256 CUs) before batching particles
-  const int64_t per_particle_items = (int64_t)c->nd * s.n_tiles;
-  int64_t pb = (P * per_particle_items) / (8 * 256);
-  if (pb < 1) pb = 1;
-  if (pb > 64) pb = 64;
-  s.pb = (int32_t)pb;
-  s.n_blocks = (P + pb - 1) / pb;
-  return s;
-}
+using lw::DirectShape;
+using lw::direct_shape;
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
@@ -200,6 +175,9 @@ void lw_destroy(lw_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   lw::mfma_cache_destroy(c->mfma);
+  free_dev(c->plan.d_perm);
+  free_dev(c->plan.d_order);
+  free_dev(c->d_ticket);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   free_dev(c->d_flops);
   free_dev(c->d_dirs);
@@ -347,8 +325,26 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
     a.partial = (double*)ws;
     a.per_particle = per_particle;
     a.err = c->d_err;
+    a.perm = nullptr;
+    a.order = nullptr;
+    a.ticket = nullptr;
+    a.n_items = 0;
+    const auto& pl = c->plan;
+    const bool persistent = c->tune_persistent && pl.valid && pl.offsets == (const void*)b->offsets &&
+                            pl.n == b->n_particles && pl.nd == c->nd && pl.nw == c->nw &&
+                            pl.ns == c->ns && pl.wpt == s.wpt && pl.pb == s.pb;
     LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
-    LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32");
+    if (persistent) {
+      a.perm = pl.d_perm;
+      a.order = pl.d_order;
+      a.ticket = c->d_ticket;
+      a.n_items = pl.n_items;
+      LW_HIP(lw::launch_fill_u32(c->d_ticket, 1, 0u, c->stream), "reset ticket");
+      LW_HIP(lw::launch_direct_f32_persistent(a, s.wpt, pl.workgroups, c->stream),
+             "launch lw_direct_f32 (persistent)");
+    } else {
+      LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32");
+    }
     LW_HIP(lw::prof_end(c), "profile");
     LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw,
                                       c->d_S, c->stream),
@@ -442,6 +438,171 @@ lw_status lw_profile_read(lw_ctx* c, double* out) {
   c->ev_marks.clear();
   c->ev_used = 0;
   return LW_OK;
+}
+
+lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    size_t bytes = 0;
+    return lw::mfma_workspace_size(c, b, path, &bytes);  // sizes the grids and phase tables
+  }
+  if (path != LW_PATH_FP32) return fail(c, LW_EINVAL, "unknown path %d", (int)path);
+  auto& pl = c->plan;
+  pl.valid = false;
+  const int64_t P = b->n_particles;
+  if (P == 0) return LW_OK;
+  std::vector<int64_t> off(P + 1);
+  LW_HIP(hipMemcpyAsync(off.data(), b->offsets, (P + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                        c->stream),
+         "copy offsets");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  std::vector<int64_t> perm(P);
+  for (int64_t p = 0; p < P; ++p) {
+    if (off[p + 1] < off[p]) return fail(c, LW_EINVAL, "offsets decrease at particle %lld", (long long)p);
+    perm[p] = p;
+  }
+  // longest trajectories first; equal lengths keep index order
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+    return off[x + 1] - off[x] > off[y + 1] - off[y];
+  });
+  const DirectShape s = direct_shape(c, P);
+  std::vector<int64_t> cost(s.n_blocks, 0);
+  for (int64_t i = 0; i < P; ++i) cost[i / s.pb] += off[perm[i] + 1] - off[perm[i]] + 1;
+  const int64_t n_items = s.n_blocks * (int64_t)c->nd * s.n_tiles;
+  std::vector<int64_t> order(n_items);
+  for (int64_t i = 0; i < n_items; ++i) order[i] = i;
+  // item id = (block * nd + d) * n_tiles + tile; heaviest blocks first
+  const int64_t per_block = (int64_t)c->nd * s.n_tiles;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t x, int64_t y) { return cost[x / per_block] > cost[y / per_block]; });
+  if (pl.perm_cap < (size_t)P) {
+    free_dev(pl.d_perm);
+    pl.d_perm = nullptr;
+    pl.perm_cap = 0;
+    LW_HIP(hipMalloc(&pl.d_perm, P * sizeof(int64_t)), "hipMalloc(perm)");
+    pl.perm_cap = P;
+  }
+  if (pl.order_cap < (size_t)n_items) {
+    free_dev(pl.d_order);
+    pl.d_order = nullptr;
+    pl.order_cap = 0;
+    LW_HIP(hipMalloc(&pl.d_order, n_items * sizeof(int64_t)), "hipMalloc(order)");
+    pl.order_cap = n_items;
+  }
+  if (!c->d_ticket) LW_HIP(hipMalloc(&c->d_ticket, sizeof(unsigned)), "hipMalloc(ticket)");
+  LW_HIP(hipMemcpy(pl.d_perm, perm.data(), P * sizeof(int64_t), hipMemcpyHostToDevice), "copy perm");
+  LW_HIP(hipMemcpy(pl.d_order, order.data(), n_items * sizeof(int64_t), hipMemcpyHostToDevice),
+         "copy order");
+  hipDeviceProp_t prop;
+  LW_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
+  const size_t shmem = sizeof(double) * (size_t)c->ns * lw::kThreads * s.wpt;
+  const int per_cu = lw::direct_persistent_occupancy(s.wpt, shmem);
+  pl.workgroups = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_items);
+  pl.offsets = (const void*)b->offsets;
+  pl.n = P;
+  pl.nd = c->nd;
+  pl.nw = c->nw;
+  pl.ns = c->ns;
+  pl.wpt = s.wpt;
+  pl.pb = s.pb;
+  pl.n_tiles = s.n_tiles;
+  pl.n_blocks = s.n_blocks;
+  pl.n_items = n_items;
+  pl.valid = true;
+  return LW_OK;
+}
+
+lw_status lw_set_tuning(lw_ctx* c, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
+                        int32_t tile_rows) {
+  if (!c) return LW_EINVAL;
+  if (wpt != 0 && wpt != 1 && wpt != 2 && wpt != 4 && wpt != 8)
+    return fail(c, LW_EINVAL, "frequencies per thread must be 0 (automatic), 1, 2, 4 or 8");
+  if (pb < 0 || pb > 4096) return fail(c, LW_EINVAL, "particles per item must be in [0, 4096]");
+  if (tile_rows != 0 && tile_rows != 128 && tile_rows != 256)
+    return fail(c, LW_EINVAL, "tile rows must be 0 (keep), 128 or 256");
+  c->tune_wpt = wpt;
+  c->tune_pb = pb;
+  c->tune_persistent = persistent ? 1 : 0;
+  lw_status st = LW_OK;
+  if (bands > 0) st = lw::mfma_set_bands(c, bands);
+  if (st == LW_OK && tile_rows > 0) st = lw::mfma_set_tile_rows(c, tile_rows);
+  return st;
+}
+
+lw_status lw_graph_capture(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
+                           lw_graph** out) {
+  if (!c || !out) return LW_EINVAL;
+  *out = nullptr;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    size_t bytes = 0;
+    st = lw::mfma_workspace_size(c, b, path, &bytes);  // plan the grids outside the capture
+    if (st != LW_OK) return st;
+  }
+  hipStream_t cs = nullptr;
+  LW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "create capture stream");
+  hipStream_t saved = c->stream;
+  const bool prof = c->prof;
+  c->stream = cs;
+  c->prof = false;
+  c->capturing = true;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = lw_accumulate(c, b, path, ws, ws_bytes, nullptr);
+    hipError_t e2 = hipStreamEndCapture(cs, &graph);
+    if (e2 != hipSuccess && st == LW_OK) st = hip_fail(c, e2, "end capture");
+  } else {
+    st = hip_fail(c, e, "begin capture");
+  }
+  c->capturing = false;
+  c->prof = prof;
+  c->stream = saved;
+  (void)hipStreamDestroy(cs);
+  if (st != LW_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  lw_graph* gr = new lw_graph();
+  gr->ctx = c;
+  gr->graph = graph;
+  e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    delete gr;
+    return hip_fail(c, e, "instantiate graph");
+  }
+  *out = gr;
+  return LW_OK;
+}
+
+lw_status lw_graph_launch(lw_graph* gr) {
+  if (!gr || !gr->ctx) return LW_EINVAL;
+  lw_ctx* c = gr->ctx;
+  DeviceGuard g(c->device);
+  LW_HIP(hipGraphLaunch(gr->exec, c->stream), "launch graph");
+  c->calls += 1;
+  return LW_OK;
+}
+
+void lw_graph_destroy(lw_graph* gr) {
+  if (!gr) return;
+  if (gr->ctx) {
+    DeviceGuard g(gr->ctx->device);
+    (void)hipStreamSynchronize(gr->ctx->stream);
+  }
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
 }
 
 lw_status lw_stats(const lw_ctx* c, int64_t* calls) {

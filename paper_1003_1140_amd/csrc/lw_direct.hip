@@ -65,13 +65,11 @@ __device__ __forceinline__ Staged prepass(const BatchView& b, int64_t idx, doubl
   return s;
 }
 
+// One work item: (block of pb particles, direction, frequency tile).
 template <int WPT>
-__global__ __launch_bounds__(kThreads) void lw_direct_f32_kernel(DirectArgs a) {
-  __shared__ Staged stage[kThreads];
-  extern __shared__ double sacc[];  // [ns][kThreads * WPT]
-
+__device__ __forceinline__ void direct_item(const DirectArgs& a, int64_t item, Staged* stage,
+                                            double* sacc) {
   const int tid = threadIdx.x;
-  int64_t item = blockIdx.x;
   const int tile = (int)(item % a.n_tiles);
   item /= a.n_tiles;
   const int d = (int)(item % a.nd);
@@ -97,7 +95,8 @@ __global__ __launch_bounds__(kThreads) void lw_direct_f32_kernel(DirectArgs a) {
 
   const int64_t p0 = blk * a.pb;
   const int64_t p1 = min(p0 + (int64_t)a.pb, a.b.n_particles);
-  for (int64_t p = p0; p < p1; ++p) {
+  for (int64_t pi = p0; pi < p1; ++pi) {
+    const int64_t p = a.perm ? a.perm[pi] : pi;
     const int64_t base = a.b.offsets[p];
     const int64_t len = a.b.offsets[p + 1] - base;
     const double t0 = a.b.t0[p], dtp = a.b.dt[p];
@@ -170,6 +169,29 @@ __global__ __launch_bounds__(kThreads) void lw_direct_f32_kernel(DirectArgs a) {
   }
 }
 
+template <int WPT>
+__global__ __launch_bounds__(kThreads) void lw_direct_f32_kernel(DirectArgs a) {
+  __shared__ Staged stage[kThreads];
+  extern __shared__ double sacc[];  // [ns][kThreads * WPT]
+  direct_item<WPT>(a, blockIdx.x, stage, sacc);
+}
+
+// Persistent form: a fixed set of work-groups pulls items, longest first, from a ticket.
+template <int WPT>
+__global__ __launch_bounds__(kThreads) void lw_direct_f32_persistent_kernel(DirectArgs a) {
+  __shared__ Staged stage[kThreads];
+  __shared__ int64_t s_item;
+  extern __shared__ double sacc[];  // [ns][kThreads * WPT]
+  for (;;) {
+    __syncthreads();  // the previous item's LDS use is over
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const int64_t i = s_item;
+    if (i >= a.n_items) break;
+    direct_item<WPT>(a, a.order ? a.order[i] : i, stage, sacc);
+  }
+}
+
 __global__ void lw_reduce_partials_kernel(const double* __restrict__ partial, int64_t n_blocks,
                                           int64_t rows, double* __restrict__ S) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,6 +234,57 @@ hipError_t launch_direct_f32(const DirectArgs& a, int wpt, hipStream_t stream) {
     case 4: hipLaunchKernelGGL(lw_direct_f32_kernel<4>, grid, block, shmem, stream, a); break;
     default: hipLaunchKernelGGL(lw_direct_f32_kernel<8>, grid, block, shmem, stream, a); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_f32_persistent(const DirectArgs& a, int wpt, int workgroups,
+                                        hipStream_t stream) {
+  if (a.n_items <= 0) return hipSuccess;
+  const size_t shmem = sizeof(double) * (size_t)a.ns * kThreads * wpt;
+  const void* fn = nullptr;
+  switch (wpt) {
+    case 1: fn = (const void*)lw_direct_f32_persistent_kernel<1>; break;
+    case 2: fn = (const void*)lw_direct_f32_persistent_kernel<2>; break;
+    case 4: fn = (const void*)lw_direct_f32_persistent_kernel<4>; break;
+    case 8: fn = (const void*)lw_direct_f32_persistent_kernel<8>; break;
+    default: return hipErrorInvalidValue;
+  }
+  if (shmem > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((unsigned)workgroups), block(kThreads);
+  switch (wpt) {
+    case 1: hipLaunchKernelGGL(lw_direct_f32_persistent_kernel<1>, grid, block, shmem, stream, a); break;
+    case 2: hipLaunchKernelGGL(lw_direct_f32_persistent_kernel<2>, grid, block, shmem, stream, a); break;
+    case 4: hipLaunchKernelGGL(lw_direct_f32_persistent_kernel<4>, grid, block, shmem, stream, a); break;
+    default: hipLaunchKernelGGL(lw_direct_f32_persistent_kernel<8>, grid, block, shmem, stream, a); break;
+  }
+  return hipGetLastError();
+}
+
+int direct_persistent_occupancy(int wpt, size_t shmem) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (wpt) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_direct_f32_persistent_kernel<1>, kThreads, shmem); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_direct_f32_persistent_kernel<2>, kThreads, shmem); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_direct_f32_persistent_kernel<4>, kThreads, shmem); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, lw_direct_f32_persistent_kernel<8>, kThreads, shmem); break;
+    default: break;
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t n, unsigned v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  hipLaunchKernelGGL(fill_u32_kernel, grid, block, 0, stream, p, n, v);
   return hipGetLastError();
 }
 

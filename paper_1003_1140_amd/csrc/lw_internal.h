@@ -40,10 +40,19 @@ struct DirectArgs {
   double* partial;       // [n_blocks][ns][nd][nw]
   float* per_particle;   // [P][nd][nw] or null
   unsigned long long* err;  // lowest offending particle index (atomic min)
+  // persistent launch (all null/0 for the plain grid)
+  const int64_t* perm;   // particle order (blocks take consecutive entries), or null
+  const int64_t* order;  // item order for the ticket queue, or null
+  unsigned* ticket;      // queue head, zeroed before the launch
+  int64_t n_items;
 };
 
 // Launchers (lw_direct.hip).
 hipError_t launch_direct_f32(const DirectArgs& a, int wpt, hipStream_t stream);
+// Persistent variant: `workgroups` work-groups take items from a.ticket until a.n_items.
+hipError_t launch_direct_f32_persistent(const DirectArgs& a, int wpt, int workgroups,
+                                        hipStream_t stream);
+hipError_t launch_fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t stream);
 hipError_t launch_reduce_partials(const double* partial, int64_t n_blocks, int64_t rows, double* S,
                                   hipStream_t stream);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
@@ -76,7 +85,61 @@ struct lw_ctx {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;  // (kind, (start, stop))
   unsigned long long* d_flops = nullptr;  // useful matrix-core FLOPs counted on the device
   int flop_mult = 1;                     // products of the last matrix-core launch
+  // FP32 launch shape overrides (0 = automatic); persistent launch when a plan matches
+  int tune_wpt = 0, tune_pb = 0, tune_persistent = 1;
+  struct Plan {
+    bool valid = false;
+    const void* offsets = nullptr;  // batch identity the plan was made for
+    int64_t n = -1;
+    int32_t nd = 0, nw = 0, ns = 0, wpt = 0, pb = 0, n_tiles = 0;
+    int64_t n_blocks = 0, n_items = 0;
+    int workgroups = 0;
+    int64_t* d_perm = nullptr;
+    size_t perm_cap = 0;
+    int64_t* d_order = nullptr;
+    size_t order_cap = 0;
+  } plan;
+  unsigned* d_ticket = nullptr;
+  bool capturing = false;  // inside lw_graph_capture: no synchronisation allowed
 };
+
+struct lw_graph {
+  lw_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace lw {
+// FP32 kernel launch shape.
+struct DirectShape {
+  int wpt;
+  int32_t n_tiles;
+  int32_t pb;
+  int64_t n_blocks;
+};
+inline int pick_wpt(int32_t nw) {
+  if (nw <= kThreads) return 1;
+  if (nw <= 2 * kThreads) return 2;
+  if (nw <= 4 * kThreads) return 4;
+  return 8;
+}
+inline DirectShape direct_shape(const lw_ctx* c, int64_t P) {
+  DirectShape s;
+  s.wpt = c->tune_wpt ? c->tune_wpt : pick_wpt(c->nw);
+  s.n_tiles = (c->nw + kThreads * s.wpt - 1) / (kThreads * s.wpt);
+  // aim at >= 8 work-groups per compute unit (256 CUs) before batching particles
+  const int64_t per_particle_items = (int64_t)c->nd * s.n_tiles;
+  int64_t pb = (P * per_particle_items) / (8 * 256);
+  if (pb < 1) pb = 1;
+  if (pb > 64) pb = 64;
+  if (c->tune_pb) pb = c->tune_pb;
+  s.pb = (int32_t)pb;
+  s.n_blocks = (P + pb - 1) / pb;
+  return s;
+}
+// Work-groups of the persistent FP32 kernel resident per compute unit.
+int direct_persistent_occupancy(int wpt, size_t shmem);
+}  // namespace lw
 
 namespace lw {
 enum ProfKind { kProfDirect = 0, kProfSpread = 1, kProfGemm = 2, kProfKinds = 3 };

@@ -843,10 +843,15 @@ lw_status build_plan(lw_ctx* c, double span, int dtype) {
   return LW_OK;
 }
 
-// Make sure the tables cover the batch; grows the span with headroom.
+// Make sure the tables cover the batch; grows the span with headroom.  Inside a graph
+// capture nothing may synchronise: the plan made before the capture is used as is.
 lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path) {
   MfmaPlanCache* pc = c->mfma;
   const int dtype = path == LW_PATH_MFMA_BF16 ? 1 : 0;
+  if (c->capturing) {
+    if (pc->valid && pc->dtype == dtype) return LW_OK;
+    return set_err(c, LW_ESTATE, "matrix-core tables must be planned before graph capture");
+  }
   double span = 0.0;
   lw_status st = batch_span(c, b, &span);
   if (st != LW_OK) return st;
@@ -879,6 +884,17 @@ lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_
   pc->bands_req = bands;
   pc->products_f16 = products_f16;
   pc->products_bf16 = products_bf16;
+  return LW_OK;
+}
+
+lw_status mfma_set_bands(lw_ctx* c, int bands) {
+  MfmaPlanCache* pc = c->mfma;
+  return mfma_set_options(c, bands, pc->products_f16, pc->products_bf16);
+}
+
+lw_status mfma_set_tile_rows(lw_ctx* c, int rows) {
+  if (rows != 128 && rows != 256) return set_err(c, LW_EINVAL, "tile rows must be 128 or 256");
+  c->mfma->tile_rows = rows;
   return LW_OK;
 }
 

@@ -24,7 +24,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_set_frequencies", "lw_set_log_frequencies", "lw_get_frequencies", "lw_set_species",
             "lw_workspace_size", "lw_accumulate", "lw_read_spectra", "lw_reset",
             "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_profiling",
-            "lw_profile_read")
+            "lw_profile_read", "lw_plan_batch", "lw_set_tuning", "lw_tune", "lw_graph_capture",
+            "lw_graph_launch", "lw_graph_destroy")
 
 
 class LWError(RuntimeError):
@@ -76,6 +77,14 @@ def load_library():
             "lw_stats": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
             "lw_set_mfma_options": (ctypes.c_int, [P, I32, I32, I32]),
             "lw_set_profiling": (ctypes.c_int, [P, I32]),
+            "lw_plan_batch": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int]),
+            "lw_set_tuning": (ctypes.c_int, [P, I32, I32, I32, I32, I32]),
+            "lw_tune": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int, I32, ctypes.c_char_p,
+                                       ctypes.c_char_p, SZ]),
+            "lw_graph_capture": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int, P, SZ,
+                                                ctypes.POINTER(P)]),
+            "lw_graph_launch": (ctypes.c_int, [P]),
+            "lw_graph_destroy": (None, [P]),
             "lw_profile_read": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
@@ -230,7 +239,61 @@ class Context:
         return {"direct_ms": out[0], "spread_ms": out[1], "gemm_ms": out[2], "gemm_flops": out[3],
                 "direct_launches": int(out[4]), "gemm_launches": int(out[5])}
 
+    def plan_batch(self, batch: DeviceBatch, path="fp32"):
+        self._check(self.lib.lw_plan_batch(self.h, ctypes.byref(batch.struct), PATHS.get(path, path)))
+
+    def set_tuning(self, wpt=0, pb=0, persistent=1, bands=0, tile_rows=0):
+        self._check(self.lib.lw_set_tuning(self.h, wpt, pb, persistent, bands, tile_rows))
+
+    def tune(self, batch: DeviceBatch, path="fp32", repeats=2, cache_json=None) -> dict:
+        import json
+
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self.lib.lw_tune(self.h, ctypes.byref(batch.struct), PATHS.get(path, path), repeats,
+                                     cache_json.encode() if cache_json else None, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def load_tuning(self, cache_json):
+        """Apply the choice recorded by tune(..., cache_json=...)."""
+        import json
+
+        with open(cache_json) as f:
+            best = json.load(f)["best"]
+        self.set_tuning(best["wpt"], best["pb"], best["persistent"], best["bands"], best["tile_rows"])
+
+    def graph_capture(self, batch: DeviceBatch, path="fp32", workspace=None) -> "Graph":
+        if workspace is None:
+            workspace = self.workspace(batch, path)
+        g = ctypes.c_void_p()
+        self._check(self.lib.lw_graph_capture(self.h, ctypes.byref(batch.struct), PATHS.get(path, path),
+                                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                              ctypes.byref(g)))
+        return Graph(self, g, workspace, batch)
+
     def stats(self) -> int:
         calls = ctypes.c_int64()
         self._check(self.lib.lw_stats(self.h, ctypes.byref(calls)))
         return calls.value
+
+
+class Graph:
+    """A captured lw_accumulate; keeps its workspace and batch alive."""
+
+    def __init__(self, ctx: Context, handle, workspace, batch):
+        self.ctx, self.h, self.workspace, self.batch = ctx, handle, workspace, batch
+
+    def launch(self):
+        st = self.ctx.lib.lw_graph_launch(self.h)
+        if st != LW_OK:
+            raise LWError(st, self.ctx.lib.lw_last_error(self.ctx.h).decode())
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.lw_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
