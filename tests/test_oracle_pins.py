@@ -341,3 +341,19 @@ def test_empty_particle_contributes_nothing():
     S, pp = oracle.spectrum(b, [[1, 0, 0]], [1.0, 5.0], per_particle=True)
     assert np.all(pp[1] == 0)
     assert np.all(S[0] == pp[0])
+
+
+def test_sampled_bins_equal_the_full_spectrum():
+    """The sampled-bin routine (used on the full workloads) agrees with lwo_spectrum bin by bin."""
+    b = _small_ensemble()
+    b.species = np.array([0, 1, 0], dtype=np.int32)
+    dirs = np.array([[1, 0, 0], [0.3, 0.4, -0.5], [0, 0, 1]], dtype=float)
+    om = log_grid(0.1, 50, 13)
+    S = oracle.spectrum(b, dirs, om, n_species=2)
+    picks = [(0, 0), (1, 5), (2, 12), (1, 7)]
+    d_, w_ = dirs[[d for d, _ in picks]], om[[j for _, j in picks]]
+    got_all = oracle.sampled_bins(b, d_, w_)
+    got_s1 = oracle.sampled_bins(b, d_, w_, species=1)
+    for i, (d, j) in enumerate(picks):
+        assert abs(got_all[i] - (S[0, d, j] + S[1, d, j])) <= 1e-13 * got_all[i]
+        assert abs(got_s1[i] - S[1, d, j]) <= 1e-13 * max(got_s1[i], 1e-300)
