@@ -180,6 +180,75 @@ lw_status lw_graph_capture(lw_ctx* ctx, const lw_batch* batch, lw_path path, voi
 lw_status lw_graph_launch(lw_graph* graph);
 void lw_graph_destroy(lw_graph* graph);
 
+/* Exact FP32 accumulation of the particles listed in `indices` (device int64
+ * [n_indices], each in [0, n_particles)) of `batch`: as lw_accumulate on the
+ * FP32 path restricted to those particles; per_particle (optional) keeps the
+ * [n_particles][nd][nw] layout of the whole batch and is written only for the
+ * listed particles.  Workspace: lw_workspace_size of a batch of n_indices
+ * particles.  Used to judge and to stand in for the surrogate. */
+lw_status lw_accumulate_subset(lw_ctx* ctx, const lw_batch* batch, const int64_t* indices,
+                               int64_t n_indices, void* workspace, size_t workspace_bytes,
+                               float* per_particle);
+
+/* ---- learned surrogate (not part of the paper's method) ----
+ * Features of every (particle, direction) pair: device float [n_particles][nd][16]
+ * (log Lorentz factor and spread; transverse-acceleration mean, rms, max and
+ * kurtosis; deflection in units of 1/gamma, rms and max; force reversals per
+ * unit time and the jitter frequency scale; log duration; log mean |betadot|;
+ * observer angle to the mean velocity times gamma; log mean and min kappa;
+ * fraction of samples with the observer inside the 1/gamma cone). */
+lw_status lw_features(lw_ctx* ctx, const lw_batch* batch, float* feats);
+
+/* Add the surrogate's predicted spectra to S: ylog = device [n_particles][nd][nw]
+ * log10 of each particle's own spectrum (without w q^2); err = device
+ * [n_particles][nd] predicted error or NULL.  Particles whose error exceeds
+ * `threshold` in any direction (or is NaN) get flags[p] = 1 (device int32
+ * [n_particles]) and are left out, for lw_accumulate_subset to add exactly; the
+ * others add w_p q_p^2 10^ylog to their species.  Fixed-order reduction.
+ * flagged, n_flagged (device int64 [n_particles] and [1], both or neither): the
+ * flagged particle indices in increasing order and their count.  Workspace:
+ * ceil(n_particles / 1024) x n_species x nd x nw doubles; at most 65535 x 1024
+ * particles per call (LW_ERANGE beyond). */
+lw_status lw_surrogate_accumulate(lw_ctx* ctx, const lw_batch* batch, const float* ylog,
+                                  const float* err, float threshold, int32_t* flags, int64_t* flagged,
+                                  int64_t* n_flagged, void* workspace, size_t workspace_bytes);
+
+/* Training targets from the exact kernel's per-particle output (lw_accumulate's
+ * per_particle array, device [n_particles][nd][nw]): out = log10(pp / (w q^2) +
+ * floor_value), device float of the same shape; floor_value > 0. */
+lw_status lw_surrogate_targets(lw_ctx* ctx, const lw_batch* batch, const float* per_particle,
+                               double floor_value, float* out);
+
+/* MLP n_in -> [Linear, GELU] x n_hidden -> Linear -> n_out, FP32 master weights,
+ * products in BF16 on the matrix cores with FP32 accumulation, AdamW updates,
+ * plus an error head (Linear on the last hidden layer -> 1).  Parameter layout:
+ * per layer W [out][in] row-major then b [out].  x, t, y, err are device
+ * [rows][width] FP32; the network allocates its activation workspace on first use
+ * of a row count (and keeps it).  Loss: mean squared error over rows and outputs. */
+typedef struct lw_mlp lw_mlp;
+lw_status lw_mlp_create(lw_ctx* ctx, int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out,
+                        uint64_t seed, lw_mlp** out);
+void lw_mlp_destroy(lw_mlp* net);
+lw_status lw_mlp_num_params(const lw_mlp* net, int64_t* count);
+/* host_head (may be NULL): the error head's hidden + 1 parameters. */
+lw_status lw_mlp_get_params(lw_mlp* net, float* host, int64_t count, float* host_head);
+lw_status lw_mlp_set_params(lw_mlp* net, const float* host, int64_t count, const float* host_head);
+/* Input normalisation applied in FP32 before the first product (so that
+ * features with a large offset keep their resolution in BF16): the network
+ * reads (x[k] - shift[k]) * scale[k].  shift, scale: host float [n_in], both
+ * NULL to remove it.  Used by every later forward, gradient and training call. */
+lw_status lw_mlp_set_input_norm(lw_mlp* net, const float* shift, const float* scale);
+/* y: device [rows][n_out]; err_head (may be NULL): device [rows], the error head's output. */
+lw_status lw_mlp_forward(lw_mlp* net, const float* x, int64_t rows, float* y, float* err_head);
+/* Loss and its gradient (copied to grad_host when not NULL), no update. */
+lw_status lw_mlp_loss_grad(lw_mlp* net, const float* x, const float* t, int64_t rows, float* grad_host,
+                           double* loss);
+lw_status lw_mlp_train_step(lw_mlp* net, const float* x, const float* t, int64_t rows, float lr,
+                            float weight_decay, double* loss);
+/* One AdamW step of the error head towards err_target [rows] (main net frozen). */
+lw_status lw_mlp_train_head_step(lw_mlp* net, const float* x, const float* err_target, int64_t rows,
+                                 float lr, double* loss);
+
 /* Kernel timing with HIP events recorded on the context's stream around each
  * accumulation kernel launch (enable != 0 turns it on; off by default). */
 lw_status lw_set_profiling(lw_ctx* ctx, int32_t enable);

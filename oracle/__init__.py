@@ -57,6 +57,8 @@ def _load():
         _lib = ctypes.CDLL(_SO)
         for name in ("lwo_amplitude", "lwo_spectrum", "lwo_sampled_bins", "lwo_max_threads"):
             getattr(_lib, name).restype = ctypes.c_int
+        _lib.mlpo_num_params.restype = ctypes.c_int64
+        _lib.mlpo_forward_backward.restype = ctypes.c_double
     return _lib
 
 
@@ -131,3 +133,31 @@ def sampled_bins(batch, dirs, omega, species=-1, nthreads=0):
     if st != LWO_OK:
         raise OracleError(st)
     return out
+
+
+# ---------------------------------------------------------------- surrogate network (FP64)
+def mlp_num_params(n_in, hidden, n_hidden, n_out):
+    return int(_load().mlpo_num_params(n_in, hidden, n_hidden, n_out))
+
+
+def mlp_gelu(z):
+    z = _f64(z)
+    out = np.empty_like(z)
+    _load().mlpo_gelu(_p(z), _p(out), ctypes.c_int64(z.size))
+    return out
+
+
+def mlp_forward_backward(shape, params, x, t=None, want_grad=False, want_hidden=False):
+    """shape = (n_in, hidden, n_hidden, n_out).  Returns dict(y, loss, grad, hidden)."""
+    n_in, hidden, n_hidden, n_out = shape
+    lib = _load()
+    params = _f64(params)
+    x = _f64(x)
+    rows = x.shape[0]
+    y = np.zeros((rows, n_out))
+    tt = _f64(t) if t is not None else None
+    grad = np.zeros(params.size) if want_grad else None
+    hid = np.zeros((rows, hidden)) if want_hidden else None
+    loss = lib.mlpo_forward_backward(n_in, hidden, n_hidden, n_out, _p(params), _p(x), _p(tt),
+                                     ctypes.c_int64(rows), _p(y), _p(grad), _p(hid))
+    return {"y": y, "loss": float(loss), "grad": grad, "hidden": hid}

@@ -517,6 +517,49 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   return LW_OK;
 }
 
+lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indices, int64_t n_idx,
+                               void* ws, size_t ws_bytes, float* per_particle) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (n_idx < 0 || (n_idx > 0 && !indices)) return fail(c, LW_EINVAL, "bad index list");
+  if (n_idx == 0) return LW_OK;
+  const DirectShape s = direct_shape(c, n_idx);
+  const size_t need = align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * sizeof(double));
+  if (!ws || ws_bytes < need)
+    return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
+  DeviceGuard g(c->device);
+  lw::DirectArgs a;
+  // the kernel walks n_idx positions and maps each through the index list
+  a.b = {n_idx,  b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+         b->ax,  b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  a.dirs = c->d_dirs;
+  a.wturn = c->d_wturn;
+  a.nd = c->nd;
+  a.nw = c->nw;
+  a.ns = c->ns;
+  a.pb = s.pb;
+  a.n_blocks = s.n_blocks;
+  a.n_tiles = s.n_tiles;
+  a.partial = (double*)ws;
+  a.per_particle = per_particle;
+  a.err = c->d_err;
+  a.perm = indices;
+  a.order = nullptr;
+  a.ticket = nullptr;
+  a.n_items = 0;
+  LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
+  LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32 (subset)");
+  LW_HIP(lw::prof_end(c), "profile");
+  LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw, c->d_S,
+                                    c->stream),
+         "launch lw_reduce_partials");
+  c->calls += 1;
+  return LW_OK;
+}
+
 lw_status lw_set_tuning(lw_ctx* c, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
                         int32_t tile_rows) {
   if (!c) return LW_EINVAL;

@@ -1,0 +1,813 @@
+// lw_surrogate.hip -- learned spectrum surrogate: trajectory features and a small MLP
+// trained and evaluated with BF16 matrix-core kernels (FP32 accumulation).
+//
+// The surrogate maps 16 features of one (particle, direction) pair to the
+// normalised log spectrum on a fixed frequency grid; the exact accumulation
+// kernels produce its training targets, judge a held-out fraction and take over
+// for the pairs its error head flags.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lw_internal.h"
+
+namespace lw {
+
+constexpr int kFeat = 16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------------ features
+// One work-group per (particle, group of up to kDirGroup directions): the
+// trajectory is read twice (moments, then deflections from the mean velocity)
+// and the direction-dependent sums of the group ride along with the first pass.
+// Sums in FP64, wave shuffles + LDS.
+constexpr int kDirGroup = 4;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const double* dirs, int nd,
+                                                          float* feats, unsigned long long* err) {
+  // direction-independent sums 0..10, then per direction g: kappa sum, kappa min, cone count
+  constexpr int NI = 11, NQ = NI + 3 * kDirGroup;
+  __shared__ double s_part[4][NQ];
+  __shared__ double s_tot[NQ];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n_groups = (nd + kDirGroup - 1) / kDirGroup;
+  const int64_t p = blockIdx.x / n_groups;
+  const int d0 = (int)(blockIdx.x % n_groups) * kDirGroup;
+  const int ng = min(kDirGroup, nd - d0);
+  double n[kDirGroup][3];
+  #pragma unroll
+  for (int g = 0; g < kDirGroup; ++g)
+    for (int c = 0; c < 3; ++c) n[g][c] = g < ng ? dirs[kDirStride * (d0 + g) + c] : 0.0;
+  const int64_t o = b.offsets[p], len = b.offsets[p + 1] - o;
+  double q[NQ];
+  #pragma unroll
+  for (int i = 0; i < NQ; ++i) q[i] = 0.0;
+  #pragma unroll
+  for (int g = 0; g < kDirGroup; ++g) q[NI + 3 * g + 1] = 1.0e300;
+  for (int64_t k = tid; k < len; k += 256) {
+    const int64_t i = o + k;
+    const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
+    const double ax = b.ax[i], ay = b.ay[i], az = b.az[i];
+    const double b2 = bx * bx + by * by + bz * bz;
+    if (!(b2 < 1.0)) {
+      atomicMin(err, (unsigned long long)p);
+      continue;
+    }
+    const double gam = 1.0 / sqrt(1.0 - b2);
+    const double bn = sqrt(b2);
+    const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
+    const double ux = bx * inv, uy = by * inv, uz = bz * inv;
+    const double apar = ax * ux + ay * uy + az * uz;
+    const double px = ax - apar * ux, py = ay - apar * uy, pz = az - apar * uz;
+    const double ap = sqrt(px * px + py * py + pz * pz);
+    q[0] += gam;
+    q[1] += gam * gam;
+    q[2] += ap;
+    q[3] += ap * ap;
+    q[4] += ap * ap * ap * ap;
+    if (k > 0) {
+      const double dot = ax * (double)b.ax[i - 1] + ay * (double)b.ay[i - 1] + az * (double)b.az[i - 1];
+      if (dot < 0.0) q[5] += 1.0;
+    }
+    q[6] = fmax(q[6], ap);
+    q[7] += ux;
+    q[8] += uy;
+    q[9] += uz;
+    q[10] += sqrt(ax * ax + ay * ay + az * az);
+    #pragma unroll
+    for (int g = 0; g < kDirGroup; ++g) {
+      const double* m = n[g];
+      const double kap = 1.0 - (m[0] * bx + m[1] * by + m[2] * bz);
+      const double cx = uy * m[2] - uz * m[1], cy = uz * m[0] - ux * m[2], cz = ux * m[1] - uy * m[0];
+      const double ang = atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * m[0] + uy * m[1] + uz * m[2]);
+      q[NI + 3 * g] += kap;
+      q[NI + 3 * g + 1] = fmin(q[NI + 3 * g + 1], kap);
+      if (ang < 1.0 / gam) q[NI + 3 * g + 2] += 1.0;
+    }
+  }
+  auto is_max = [](int i) { return i == 6; };
+  auto is_min = [](int i) { return i >= NI && (i - NI) % 3 == 1; };
+  #pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double v = is_max(i) ? wave_max(q[i]) : (is_min(i) ? wave_min(q[i]) : wave_sum(q[i]));
+    if (lane == 0) s_part[wave][i] = v;
+  }
+  __syncthreads();
+  if (tid < NQ) {
+    double v = s_part[0][tid];
+    for (int w = 1; w < 4; ++w)
+      v = is_max(tid) ? fmax(v, s_part[w][tid]) : (is_min(tid) ? fmin(v, s_part[w][tid]) : v + s_part[w][tid]);
+    s_tot[tid] = v;
+  }
+  __syncthreads();
+  const double N = (double)max(len, (int64_t)1);
+  double ex = s_tot[7], ey = s_tot[8], ez = s_tot[9];
+  const double el = sqrt(ex * ex + ey * ey + ez * ez);
+  const double ie = el > 0.0 ? 1.0 / el : 0.0;
+  ex *= ie;
+  ey *= ie;
+  ez *= ie;
+  // pass 2: deflection of the unit velocity from the mean direction
+  double th2 = 0.0, thmax = 0.0;
+  for (int64_t k = tid; k < len; k += 256) {
+    const int64_t i = o + k;
+    const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
+    const double bn = sqrt(bx * bx + by * by + bz * bz);
+    const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
+    const double ux = bx * inv, uy = by * inv, uz = bz * inv;
+    const double cx = uy * ez - uz * ey, cy = uz * ex - ux * ez, cz = ux * ey - uy * ex;
+    const double th = atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * ex + uy * ey + uz * ez);
+    th2 += th * th;
+    thmax = fmax(thmax, th);
+  }
+  th2 = wave_sum(th2);
+  thmax = wave_max(thmax);
+  __syncthreads();
+  if (lane == 0) {
+    s_part[wave][0] = th2;
+    s_part[wave][1] = thmax;
+  }
+  __syncthreads();
+  if (tid < ng) {
+    const int g = tid;
+    double t2 = 0.0, tm = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      t2 += s_part[w][0];
+      tm = fmax(tm, s_part[w][1]);
+    }
+    const double eps = 1e-12;
+    const double gm = s_tot[0] / N;
+    const double gvar = fmax(s_tot[1] / N - gm * gm, 0.0);
+    const double m2 = s_tot[3] / N;
+    const double T = N * b.dt[p];
+    const double rate = s_tot[5] / T;
+    const double* m = n[g];
+    const double cx = ey * m[2] - ez * m[1], cy = ez * m[0] - ex * m[2], cz = ex * m[1] - ey * m[0];
+    const double ang_ne = atan2(sqrt(cx * cx + cy * cy + cz * cz), ex * m[0] + ey * m[1] + ez * m[2]);
+    float* f = feats + ((size_t)p * nd + d0 + g) * kFeat;
+    f[0] = (float)log(gm);
+    f[1] = (float)(sqrt(gvar) / gm);
+    f[2] = (float)log(s_tot[2] / N + eps);
+    f[3] = (float)log(sqrt(m2) + eps);
+    f[4] = (float)log(s_tot[6] + eps);
+    f[5] = (float)(m2 > 0.0 ? (s_tot[4] / N) / (m2 * m2) : 0.0);
+    f[6] = (float)(gm * sqrt(t2 / N));
+    f[7] = (float)(gm * tm);
+    f[8] = (float)rate;
+    f[9] = (float)log(gm * gm * rate + 1e-6);
+    f[10] = (float)log(T);
+    f[11] = (float)log(s_tot[10] / N + eps);
+    f[12] = (float)(gm * ang_ne);
+    f[13] = (float)log(s_tot[NI + 3 * g] / N);
+    f[14] = (float)log(s_tot[NI + 3 * g + 1]);
+    f[15] = (float)(s_tot[NI + 3 * g + 2] / N);
+  }
+}
+
+// ------------------------------------------------------------------ BF16 MFMA GEMM
+// C[i][j] (ldc) = sum_k A(i,k) B(k,j) (+ bias[j]), A(i,k) = A[i*sai + k*sak],
+// B(k,j) = B[k*sbk + j*sbj]; FP32 operands are rounded to BF16 as they are staged in
+// LDS, products accumulate in FP32 on v_mfma_f32_32x32x16_bf16.  64 x 64 tile per
+// work-group of 4 waves (2 x 2 blocks of 32 x 32), inner steps of 16.
+struct GemmDesc {
+  const float* A;
+  int64_t sai, sak;
+  const float* B;
+  int64_t sbk, sbj;
+  float* C;
+  int64_t ldc;
+  const float* bias;
+  int64_t M, N, K;
+};
+
+__global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
+  constexpr int T = 64, KS = 16, LD = KS + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[T * LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[T * LD];  // stored [j][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * T, j0 = (int64_t)blockIdx.y * T;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  f32x16v acc;
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int64_t k0 = 0; k0 < g.K; k0 += KS) {
+    // 64 x 16 elements of A and of B: 4 each per thread
+    for (int e = tid; e < T * KS; e += 256) {
+      const int r = e / KS, kk = e % KS;
+      const int64_t ii = i0 + r, k = k0 + kk;
+      const float va = (ii < g.M && k < g.K) ? g.A[ii * g.sai + k * g.sak] : 0.0f;
+      sA[r * LD + kk] = (__bf16)va;
+      const int64_t jj = j0 + r;
+      const float vb = (jj < g.N && k < g.K) ? g.B[k * g.sbk + jj * g.sbj] : 0.0f;
+      sB[r * LD + kk] = (__bf16)vb;
+    }
+    __syncthreads();
+    const int kk = 8 * (lane >> 5);
+    const bf16x8 a = *(const bf16x8*)&sA[(wi + (lane & 31)) * LD + kk];
+    const bf16x8 bb = *(const bf16x8*)&sB[(wj + (lane & 31)) * LD + kk];
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+    __syncthreads();
+  }
+  for (int r = 0; r < 16; ++r) {
+    const int64_t ii = i0 + wi + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+    const int64_t jj = j0 + wj + (lane & 31);
+    if (ii < g.M && jj < g.N) g.C[ii * g.ldc + jj] = acc[r] + (g.bias ? g.bias[jj] : 0.0f);
+  }
+}
+
+hipError_t gemm_bf16(const GemmDesc& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64)), block(256);
+  hipLaunchKernelGGL(lw_gemm_bf16_kernel, grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ elementwise kernels
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
+  return cdf + z * pdf;
+}
+
+__global__ void lw_normalise_kernel(const float* x, int64_t n, int n_in, const float* norm, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int k = (int)(i % n_in);
+    out[i] = (x[i] - norm[k]) * norm[n_in + k];
+  }
+}
+
+__global__ void lw_gelu_kernel(const float* z, float* h, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) h[i] = gelu_f(z[i]);
+}
+
+__global__ void lw_gelu_back_kernel(const float* z, float* dh, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dh[i] *= gelu_grad_f(z[i]);
+}
+
+// dY = 2 (Y - T) / (rows * cols); per-block partial sums of (Y - T)^2
+__global__ void lw_mse_kernel(const float* y, const float* t, float* dy, int64_t n, double scale,
+                              double* partial) {
+  __shared__ double s[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e2 = 0.0;
+  if (i < n) {
+    const double e = (double)y[i] - (double)t[i];
+    e2 = e * e;
+    dy[i] = (float)(2.0 * e * scale);
+  }
+  e2 = wave_sum(e2);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+// column sums in row order (deterministic): out[j] = sum_r X[r][j]
+__global__ void lw_colsum_kernel(const float* x, int64_t rows, int64_t cols, float* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= cols) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) s += x[r * cols + j];
+  out[j] = (float)s;
+}
+
+__global__ void lw_adamw_kernel(float* p, float* m, float* v, const float* g, int64_t n, float lr,
+                                float wd, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
+}
+
+// error head: e[r] = w . h[r] + b (FP32 dot products, one thread per row)
+__global__ void lw_head_fwd_kernel(const float* h, int64_t rows, int hidden, const float* w, float* e) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float s = w[hidden];
+  for (int i = 0; i < hidden; ++i) s = fmaf(w[i], h[r * hidden + i], s);
+  e[r] = s;
+}
+
+// head gradient of mean (e - t)^2: one thread per parameter, rows in order
+__global__ void lw_head_grad_kernel(const float* h, const float* e, const float* t, int64_t rows,
+                                    int hidden, float* g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > hidden) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const double d = 2.0 * ((double)e[r] - (double)t[r]) / (double)rows;
+    s += d * (i < hidden ? (double)h[r * hidden + i] : 1.0);
+  }
+  g[i] = (float)s;
+}
+
+// flags[p] = 1 when any direction's predicted error exceeds the threshold
+__global__ void lw_flag_kernel(const float* err, int64_t P, int nd, float threshold, int32_t* flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  int f = 0;
+  if (err)
+    for (int d = 0; d < nd; ++d) f |= !(err[p * nd + d] <= threshold);
+  flags[p] = f;
+}
+
+// partial[slice][s][d][j] = sum over the slice's unflagged particles of 10^ylog[p][d][j]
+__global__ void lw_surrogate_sum_kernel(const float* ylog, const int32_t* flags, const int32_t* species,
+                                        const float* charge, const float* weight, int64_t P, int nd,
+                                        int nw, int ns, int64_t per_slice, double* partial) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // d * nw + j
+  const int64_t slice = blockIdx.y;
+  if (col >= (int64_t)nd * nw) return;
+  double acc[kMaxSpecies];
+  for (int s = 0; s < ns; ++s) acc[s] = 0.0;
+  const int64_t p0 = slice * per_slice, p1 = min(P, p0 + per_slice);
+  for (int64_t p = p0; p < p1; ++p) {
+    if (flags[p]) continue;
+    const int s = species ? species[p] : 0;
+    if (s < 0 || s >= ns) continue;
+    const double q = charge ? (double)charge[p] : 1.0;
+    const double w = weight ? (double)weight[p] : 1.0;
+    acc[s] += w * q * q * exp10((double)ylog[p * (int64_t)nd * nw + col]);
+  }
+  for (int s = 0; s < ns; ++s) partial[(slice * ns + s) * (int64_t)nd * nw + col] = acc[s];
+}
+
+// In-order list of the flagged particles (one work-group: per-thread counts over
+// contiguous ranges, an exclusive scan in LDS, then the writes); count[0] = total.
+__global__ __launch_bounds__(1024) void lw_compact_kernel(const int32_t* flags, int64_t P, int64_t* idx,
+                                                          int64_t* count) {
+  __shared__ int64_t s_scan[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (P + 1023) / 1024;
+  const int64_t a = min(P, (int64_t)t * chunk), e = min(P, a + chunk);
+  int64_t c = 0;
+  for (int64_t p = a; p < e; ++p) c += flags[p] != 0;
+  s_scan[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t v = t >= off ? s_scan[t - off] : 0;
+    __syncthreads();
+    s_scan[t] += v;
+    __syncthreads();
+  }
+  int64_t w = s_scan[t] - c;
+  for (int64_t p = a; p < e; ++p)
+    if (flags[p]) idx[w++] = p;
+  if (t == 1023) count[0] = s_scan[1023];
+}
+
+// out[p][d][j] = log10(pp[p][d][j] / (w_p q_p^2) + floor): training targets from the
+// exact kernel's per-particle spectra
+__global__ void lw_log_targets_kernel(const float* pp, const float* charge, const float* weight, int64_t P,
+                                      int64_t cols, double floor_value, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * cols) return;
+  const int64_t p = i / cols;
+  const double q = charge ? (double)charge[p] : 1.0;
+  const double w = weight ? (double)weight[p] : 1.0;
+  out[i] = (float)log10((double)pp[i] / (w * q * q) + floor_value);
+}
+
+}  // namespace lw
+
+// ------------------------------------------------------------------ network object
+struct lw_mlp {
+  lw_ctx* c = nullptr;
+  int n_in = 0, hidden = 0, n_hidden = 0, n_out = 0;
+  int64_t n_params = 0;
+  float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // main net (FP32 master)
+  float *hp = nullptr, *hm = nullptr, *hv = nullptr, *hg = nullptr;  // error head [hidden + 1]
+  int64_t step = 0, head_step = 0;
+  int64_t rows_cap = 0;
+  float* act = nullptr;  // z_l, h_l per hidden layer, y, dy, dh, dz, normalised x (rows_cap rows)
+  float* norm = nullptr;  // device [2][n_in]: input shift and scale, or null (identity)
+  double* loss_part = nullptr;
+  float* err_buf = nullptr;
+  std::vector<int64_t> w_off, b_off;
+};
+
+namespace {
+
+lw_status mlp_fail(lw_mlp* n, lw_status st, const std::string& msg) {
+  if (n && n->c) n->c->err = msg;
+  return st;
+}
+
+#define MLP_HIP(call, what)                                                    \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) return mlp_fail(n, LW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int width(const lw_mlp* n, int l) {  // input width of layer l, l = 0..n_hidden (+1 = output)
+  if (l == 0) return n->n_in;
+  if (l <= n->n_hidden) return n->hidden;
+  return n->n_out;
+}
+
+lw_status ensure_rows(lw_mlp* n, int64_t rows) {
+  if (rows <= n->rows_cap) return LW_OK;
+  if (n->act) (void)hipFree(n->act);
+  if (n->loss_part) (void)hipFree(n->loss_part);
+  if (n->err_buf) (void)hipFree(n->err_buf);
+  n->act = nullptr;
+  n->loss_part = nullptr;
+  n->err_buf = nullptr;
+  const int64_t per_row = (int64_t)2 * n->n_hidden * n->hidden + 2 * n->n_out + 2 * n->hidden + n->n_in;
+  MLP_HIP(hipMalloc(&n->act, (size_t)rows * per_row * sizeof(float)), "hipMalloc(activations)");
+  const int64_t blocks = (rows * std::max(n->n_out, 1) + 255) / 256;
+  MLP_HIP(hipMalloc(&n->loss_part, (size_t)blocks * sizeof(double)), "hipMalloc(loss)");
+  MLP_HIP(hipMalloc(&n->err_buf, (size_t)rows * sizeof(float)), "hipMalloc(err)");
+  n->rows_cap = rows;
+  return LW_OK;
+}
+
+float* z_of(lw_mlp* n, int l, int64_t rows) { return n->act + (size_t)(2 * l) * rows * n->hidden; }
+float* h_of(lw_mlp* n, int l, int64_t rows) { return n->act + (size_t)(2 * l + 1) * rows * n->hidden; }
+float* y_of(lw_mlp* n, int64_t rows) { return n->act + (size_t)(2 * n->n_hidden) * rows * n->hidden; }
+float* dy_of(lw_mlp* n, int64_t rows) { return y_of(n, rows) + (size_t)rows * n->n_out; }
+float* dh_of(lw_mlp* n, int64_t rows) { return dy_of(n, rows) + (size_t)rows * n->n_out; }
+float* dz_of(lw_mlp* n, int64_t rows) { return dh_of(n, rows) + (size_t)rows * n->hidden; }
+float* xn_of(lw_mlp* n, int64_t rows) { return dz_of(n, rows) + (size_t)rows * n->hidden; }
+
+// the network's input: x itself, or (x - shift) * scale in FP32 when a normalisation is set
+lw_status input_of(lw_mlp* n, const float* x, int64_t rows, const float** in) {
+  *in = x;
+  if (!n->norm) return LW_OK;
+  float* xn = xn_of(n, rows);
+  const int64_t cnt = rows * n->n_in;
+  hipLaunchKernelGGL(lw::lw_normalise_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                     n->c->stream, x, cnt, n->n_in, n->norm, xn);
+  MLP_HIP(hipGetLastError(), "normalise");
+  *in = xn;
+  return LW_OK;
+}
+
+// forward: fills z_l, h_l and y (into `y` if given, else the workspace)
+lw_status forward(lw_mlp* n, const float* x, int64_t rows, float* y) {
+  hipStream_t s = n->c->stream;
+  const float* in = x;
+  for (int l = 0; l <= n->n_hidden; ++l) {
+    const int din = width(n, l), dout = l < n->n_hidden ? n->hidden : n->n_out;
+    float* out = l < n->n_hidden ? z_of(n, l, rows) : y;
+    lw::GemmDesc g{in, din, 1, n->p + n->w_off[l], 1, din, out, dout, n->p + n->b_off[l], rows, dout, din};
+    MLP_HIP(lw::gemm_bf16(g, s), "gemm forward");
+    if (l < n->n_hidden) {
+      dim3 grid((unsigned)((rows * dout + 255) / 256));
+      hipLaunchKernelGGL(lw::lw_gelu_kernel, grid, dim3(256), 0, s, out, h_of(n, l, rows), rows * dout);
+      MLP_HIP(hipGetLastError(), "gelu");
+      in = h_of(n, l, rows);
+    }
+  }
+  return LW_OK;
+}
+
+// backward from dy (already in the workspace) into n->g
+lw_status backward(lw_mlp* n, const float* x, int64_t rows) {
+  hipStream_t s = n->c->stream;
+  const float* d = dy_of(n, rows);  // dLoss/d(pre-activation) of the current layer
+  for (int l = n->n_hidden; l >= 0; --l) {
+    const int din = width(n, l), dout = l < n->n_hidden ? n->hidden : n->n_out;
+    const float* in = l == 0 ? x : h_of(n, l - 1, rows);
+    // dW[o][i] = sum_r d[r][o] in[r][i]
+    lw::GemmDesc gw{d, 1, dout, in, din, 1, n->g + n->w_off[l], din, nullptr, dout, din, rows};
+    MLP_HIP(lw::gemm_bf16(gw, s), "gemm dW");
+    hipLaunchKernelGGL(lw::lw_colsum_kernel, dim3((unsigned)((dout + 255) / 256)), dim3(256), 0, s, d,
+                       rows, (int64_t)dout, n->g + n->b_off[l]);
+    MLP_HIP(hipGetLastError(), "colsum");
+    if (l > 0) {
+      // dh[r][i] = sum_o d[r][o] W[o][i], then times gelu'(z)
+      float* dh = (d == dz_of(n, rows)) ? dh_of(n, rows) : dz_of(n, rows);
+      lw::GemmDesc gx{d, dout, 1, n->p + n->w_off[l], din, 1, dh, din, nullptr, rows, din, dout};
+      MLP_HIP(lw::gemm_bf16(gx, s), "gemm dX");
+      dim3 grid((unsigned)((rows * din + 255) / 256));
+      hipLaunchKernelGGL(lw::lw_gelu_back_kernel, grid, dim3(256), 0, s, z_of(n, l - 1, rows), dh,
+                         rows * din);
+      MLP_HIP(hipGetLastError(), "gelu back");
+      d = dh;
+    }
+  }
+  return LW_OK;
+}
+
+lw_status mse(lw_mlp* n, const float* y, const float* t, float* dy, int64_t count, double* loss) {
+  hipStream_t s = n->c->stream;
+  const int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(lw::lw_mse_kernel, dim3((unsigned)blocks), dim3(256), 0, s, y, t, dy, count,
+                     1.0 / (double)count, n->loss_part);
+  MLP_HIP(hipGetLastError(), "mse");
+  if (loss) {
+    std::vector<double> part(blocks);
+    MLP_HIP(hipMemcpyAsync(part.data(), n->loss_part, blocks * sizeof(double), hipMemcpyDeviceToHost, s),
+            "copy loss");
+    MLP_HIP(hipStreamSynchronize(s), "sync");
+    double sum = 0.0;
+    for (double v : part) sum += v;
+    *loss = sum / (double)count;
+  }
+  return LW_OK;
+}
+
+lw_status adamw(lw_mlp* n, float* p, float* m, float* v, const float* g, int64_t count, int64_t step,
+                float lr, float wd) {
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(lw::lw_adamw_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     n->c->stream, p, m, v, g, count, lr, wd, b1, b2, 1e-8f, c1, c2);
+  MLP_HIP(hipGetLastError(), "adamw");
+  return LW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lw_status lw_features(lw_ctx* c, const lw_batch* b, float* feats) {
+  if (!c || !b || !feats) return LW_EINVAL;
+  if (c->nd <= 0) {
+    c->err = "directions not set";
+    return LW_ESTATE;
+  }
+  if (b->n_particles == 0) return LW_OK;
+  if (!b->offsets || !b->bx || !b->by || !b->bz || !b->ax || !b->ay || !b->az || !b->dt) {
+    c->err = "batch pointer is NULL";
+    return LW_EINVAL;
+  }
+  lw::BatchView v{b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+                  b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  const int64_t blocks = b->n_particles * (int64_t)((c->nd + lw::kDirGroup - 1) / lw::kDirGroup);
+  if (blocks > 0x7fffffffLL) {
+    c->err = "too many particles for one feature launch";
+    return LW_ERANGE;
+  }
+  hipLaunchKernelGGL(lw::lw_features_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream, v,
+                     c->d_dirs, c->nd, feats, c->d_err);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "launch lw_features";
+    return LW_EDEVICE;
+  }
+  return LW_OK;
+}
+
+lw_status lw_surrogate_accumulate(lw_ctx* c, const lw_batch* b, const float* ylog, const float* err,
+                                  float threshold, int32_t* flags, int64_t* flagged, int64_t* n_flagged,
+                                  void* ws, size_t ws_bytes) {
+  if (!c || !b || !ylog || !flags) return LW_EINVAL;
+  if (c->nd <= 0 || c->nw <= 0) {
+    c->err = "grids not set";
+    return LW_ESTATE;
+  }
+  const int64_t P = b->n_particles;
+  if (P == 0) return LW_OK;
+  const int64_t cols = (int64_t)c->nd * c->nw;
+  const int64_t per_slice = 1024;
+  const int64_t slices = (P + per_slice - 1) / per_slice;
+  if (slices > 65535) {
+    c->err = "at most 65535 x 1024 particles per surrogate call";
+    return LW_ERANGE;
+  }
+  if ((flagged == nullptr) != (n_flagged == nullptr)) {
+    c->err = "flagged and n_flagged go together";
+    return LW_EINVAL;
+  }
+  const size_t need = (size_t)slices * c->ns * cols * sizeof(double);
+  if (!ws || ws_bytes < need) {
+    c->err = "workspace too small for the surrogate reduction (" + std::to_string(need) + " bytes)";
+    return LW_ENOMEM;
+  }
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(lw::lw_flag_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, err, P, c->nd,
+                     threshold, flags);
+  hipLaunchKernelGGL(lw::lw_surrogate_sum_kernel, dim3((unsigned)((cols + 255) / 256), (unsigned)slices),
+                     dim3(256), 0, s, ylog, flags, b->species, b->charge, b->weight, P, c->nd, c->nw,
+                     c->ns, per_slice, (double*)ws);
+  if (lw::launch_reduce_partials((double*)ws, slices, (int64_t)c->ns * cols, c->d_S, s) != hipSuccess ||
+      hipGetLastError() != hipSuccess) {
+    c->err = "launch surrogate reduction";
+    return LW_EDEVICE;
+  }
+  if (flagged && n_flagged) {
+    hipLaunchKernelGGL(lw::lw_compact_kernel, dim3(1), dim3(1024), 0, s, flags, P, flagged, n_flagged);
+    if (hipGetLastError() != hipSuccess) {
+      c->err = "launch flag compaction";
+      return LW_EDEVICE;
+    }
+  }
+  return LW_OK;
+}
+
+lw_status lw_surrogate_targets(lw_ctx* c, const lw_batch* b, const float* per_particle, double floor_value,
+                               float* out) {
+  if (!c || !b || !per_particle || !out || !(floor_value > 0.0)) return LW_EINVAL;
+  const int64_t P = b->n_particles, cols = (int64_t)c->nd * c->nw;
+  if (P == 0 || cols == 0) return LW_OK;
+  const int64_t n = P * cols;
+  hipLaunchKernelGGL(lw::lw_log_targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     per_particle, b->charge, b->weight, P, cols, floor_value, out);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "launch lw_log_targets";
+    return LW_EDEVICE;
+  }
+  return LW_OK;
+}
+
+lw_status lw_mlp_create(lw_ctx* c, int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out,
+                        uint64_t seed, lw_mlp** out) {
+  if (!c || !out || n_in <= 0 || hidden <= 0 || n_hidden < 0 || n_out <= 0) return LW_EINVAL;
+  lw_mlp* n = new lw_mlp();
+  n->c = c;
+  n->n_in = n_in;
+  n->hidden = hidden;
+  n->n_hidden = n_hidden;
+  n->n_out = n_out;
+  int64_t off = 0;
+  for (int l = 0; l <= n_hidden; ++l) {
+    const int din = width(n, l), dout = l < n_hidden ? hidden : n_out;
+    n->w_off.push_back(off);
+    off += (int64_t)dout * din;
+    n->b_off.push_back(off);
+    off += dout;
+  }
+  n->n_params = off;
+  // initial weights: normal with variance 1/fan_in (Box-Muller on a 64-bit LCG), zero biases
+  std::vector<float> h(off, 0.0f);
+  uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
+  auto uni = [&]() {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    return ((st >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  };
+  for (int l = 0; l <= n_hidden; ++l) {
+    const int din = width(n, l), dout = l < n_hidden ? hidden : n_out;
+    const double sd = 1.0 / sqrt((double)din);
+    for (int64_t i = 0; i < (int64_t)dout * din; ++i) {
+      const double u1 = uni(), u2 = uni();
+      h[n->w_off[l] + i] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+    }
+  }
+  lw_status rc = LW_OK;
+  auto alloc = [&](float** p, int64_t cnt) {
+    if (rc == LW_OK && hipMalloc(p, (size_t)cnt * sizeof(float)) != hipSuccess) rc = LW_ENOMEM;
+  };
+  alloc(&n->p, off);
+  alloc(&n->m, off);
+  alloc(&n->v, off);
+  alloc(&n->g, off);
+  alloc(&n->hp, hidden + 1);
+  alloc(&n->hm, hidden + 1);
+  alloc(&n->hv, hidden + 1);
+  alloc(&n->hg, hidden + 1);
+  if (rc == LW_OK) {
+    std::vector<float> zeros(std::max<int64_t>(off, hidden + 1), 0.0f);
+    (void)hipMemcpy(n->p, h.data(), off * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemcpy(n->m, zeros.data(), off * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemcpy(n->v, zeros.data(), off * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemcpy(n->hp, zeros.data(), (hidden + 1) * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemcpy(n->hm, zeros.data(), (hidden + 1) * sizeof(float), hipMemcpyHostToDevice);
+    (void)hipMemcpy(n->hv, zeros.data(), (hidden + 1) * sizeof(float), hipMemcpyHostToDevice);
+  }
+  if (rc != LW_OK) {
+    lw_mlp_destroy(n);
+    c->err = "hipMalloc failed for the network";
+    return rc;
+  }
+  *out = n;
+  return LW_OK;
+}
+
+void lw_mlp_destroy(lw_mlp* n) {
+  if (!n) return;
+  if (n->c) (void)hipStreamSynchronize(n->c->stream);
+  for (void* p : {(void*)n->p, (void*)n->m, (void*)n->v, (void*)n->g, (void*)n->hp, (void*)n->hm,
+                  (void*)n->hv, (void*)n->hg, (void*)n->act, (void*)n->loss_part, (void*)n->err_buf,
+                  (void*)n->norm})
+    if (p) (void)hipFree(p);
+  delete n;
+}
+
+lw_status lw_mlp_num_params(const lw_mlp* n, int64_t* count) {
+  if (!n || !count) return LW_EINVAL;
+  *count = n->n_params;
+  return LW_OK;
+}
+
+lw_status lw_mlp_get_params(lw_mlp* n, float* host, int64_t count, float* host_head) {
+  if (!n || !host || count != n->n_params) return LW_EINVAL;
+  MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+  MLP_HIP(hipMemcpy(host, n->p, count * sizeof(float), hipMemcpyDeviceToHost), "copy params");
+  if (host_head) MLP_HIP(hipMemcpy(host_head, n->hp, (n->hidden + 1) * sizeof(float), hipMemcpyDeviceToHost), "copy head");
+  return LW_OK;
+}
+
+lw_status lw_mlp_set_params(lw_mlp* n, const float* host, int64_t count, const float* host_head) {
+  if (!n || !host || count != n->n_params) return LW_EINVAL;
+  MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+  MLP_HIP(hipMemcpy(n->p, host, count * sizeof(float), hipMemcpyHostToDevice), "copy params");
+  if (host_head) MLP_HIP(hipMemcpy(n->hp, host_head, (n->hidden + 1) * sizeof(float), hipMemcpyHostToDevice), "copy head");
+  return LW_OK;
+}
+
+lw_status lw_mlp_set_input_norm(lw_mlp* n, const float* shift, const float* scale) {
+  if (!n || (!shift) != (!scale)) return LW_EINVAL;
+  MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+  if (!shift) {
+    if (n->norm) (void)hipFree(n->norm);
+    n->norm = nullptr;
+    return LW_OK;
+  }
+  if (!n->norm) MLP_HIP(hipMalloc(&n->norm, 2 * (size_t)n->n_in * sizeof(float)), "hipMalloc(norm)");
+  MLP_HIP(hipMemcpy(n->norm, shift, n->n_in * sizeof(float), hipMemcpyHostToDevice), "copy shift");
+  MLP_HIP(hipMemcpy(n->norm + n->n_in, scale, n->n_in * sizeof(float), hipMemcpyHostToDevice), "copy scale");
+  return LW_OK;
+}
+
+lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, float* err_head) {
+  if (!n || !x || !y || rows < 0) return LW_EINVAL;
+  if (err_head && n->n_hidden < 1) return mlp_fail(n, LW_EINVAL, "the error head needs a hidden layer");
+  if (rows == 0) return LW_OK;
+  lw_status st = ensure_rows(n, rows);
+  const float* in = nullptr;
+  if (st == LW_OK) st = input_of(n, x, rows, &in);
+  if (st == LW_OK) st = forward(n, in, rows, y);
+  if (st != LW_OK) return st;
+  if (err_head) {
+    hipLaunchKernelGGL(lw::lw_head_fwd_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
+                       n->c->stream, h_of(n, n->n_hidden - 1, rows), rows, n->hidden, n->hp, err_head);
+    MLP_HIP(hipGetLastError(), "head forward");
+  }
+  return LW_OK;
+}
+
+lw_status lw_mlp_loss_grad(lw_mlp* n, const float* x, const float* t, int64_t rows, float* grad_host,
+                           double* loss) {
+  if (!n || !x || !t || rows <= 0) return LW_EINVAL;
+  lw_status st = ensure_rows(n, rows);
+  const float* in = nullptr;
+  if (st == LW_OK) st = input_of(n, x, rows, &in);
+  if (st == LW_OK) st = forward(n, in, rows, y_of(n, rows));
+  if (st == LW_OK) st = mse(n, y_of(n, rows), t, dy_of(n, rows), rows * n->n_out, loss);
+  if (st == LW_OK) st = backward(n, in, rows);
+  if (st == LW_OK && grad_host) {
+    MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+    MLP_HIP(hipMemcpy(grad_host, n->g, n->n_params * sizeof(float), hipMemcpyDeviceToHost), "copy grad");
+  }
+  return st;
+}
+
+lw_status lw_mlp_train_step(lw_mlp* n, const float* x, const float* t, int64_t rows, float lr, float wd,
+                            double* loss) {
+  lw_status st = lw_mlp_loss_grad(n, x, t, rows, nullptr, loss);
+  if (st != LW_OK) return st;
+  n->step += 1;
+  return adamw(n, n->p, n->m, n->v, n->g, n->n_params, n->step, lr, wd);
+}
+
+lw_status lw_mlp_train_head_step(lw_mlp* n, const float* x, const float* err_target, int64_t rows,
+                                 float lr, double* loss) {
+  if (!n || !x || !err_target || rows <= 0 || n->n_hidden < 1) return LW_EINVAL;
+  lw_status st = ensure_rows(n, rows);
+  const float* in = nullptr;
+  if (st == LW_OK) st = input_of(n, x, rows, &in);
+  if (st == LW_OK) st = forward(n, in, rows, y_of(n, rows));
+  if (st != LW_OK) return st;
+  hipStream_t s = n->c->stream;
+  const float* hlast = h_of(n, n->n_hidden - 1, rows);
+  hipLaunchKernelGGL(lw::lw_head_fwd_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s,
+                     hlast, rows, n->hidden, n->hp, n->err_buf);
+  MLP_HIP(hipGetLastError(), "head forward");
+  if (loss) {
+    st = mse(n, n->err_buf, err_target, dy_of(n, rows), rows, loss);
+    if (st != LW_OK) return st;
+  }
+  hipLaunchKernelGGL(lw::lw_head_grad_kernel, dim3((unsigned)((n->hidden + 1 + 255) / 256)), dim3(256), 0,
+                     s, hlast, n->err_buf, err_target, rows, n->hidden, n->hg);
+  MLP_HIP(hipGetLastError(), "head grad");
+  n->head_step += 1;
+  return adamw(n, n->hp, n->hm, n->hv, n->hg, n->hidden + 1, n->head_step, lr, 0.0f);
+}
+
+}  // extern "C"

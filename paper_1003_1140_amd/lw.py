@@ -25,7 +25,10 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_workspace_size", "lw_accumulate", "lw_read_spectra", "lw_reset",
             "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_profiling",
             "lw_profile_read", "lw_plan_batch", "lw_set_tuning", "lw_tune", "lw_graph_capture",
-            "lw_graph_launch", "lw_graph_destroy")
+            "lw_graph_launch", "lw_graph_destroy", "lw_accumulate_subset", "lw_features",
+            "lw_mlp_create", "lw_mlp_destroy", "lw_mlp_num_params", "lw_mlp_get_params",
+            "lw_mlp_set_params", "lw_mlp_set_input_norm", "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
+            "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets")
 
 
 class LWError(RuntimeError):
@@ -85,6 +88,22 @@ def load_library():
                                                 ctypes.POINTER(P)]),
             "lw_graph_launch": (ctypes.c_int, [P]),
             "lw_graph_destroy": (None, [P]),
+            "lw_accumulate_subset": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, I64, P, SZ, P]),
+            "lw_features": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
+            "lw_surrogate_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, ctypes.c_float, P, P,
+                                                       P, P, SZ]),
+            "lw_surrogate_targets": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, D, P]),
+            "lw_mlp_create": (ctypes.c_int, [P, I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]),
+            "lw_mlp_destroy": (None, [P]),
+            "lw_mlp_num_params": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
+            "lw_mlp_get_params": (ctypes.c_int, [P, P, I64, P]),
+            "lw_mlp_set_params": (ctypes.c_int, [P, P, I64, P]),
+            "lw_mlp_set_input_norm": (ctypes.c_int, [P, P, P]),
+            "lw_mlp_forward": (ctypes.c_int, [P, P, I64, P, P]),
+            "lw_mlp_loss_grad": (ctypes.c_int, [P, P, P, I64, P, ctypes.POINTER(D)]),
+            "lw_mlp_train_step": (ctypes.c_int, [P, P, P, I64, ctypes.c_float, ctypes.c_float,
+                                                 ctypes.POINTER(D)]),
+            "lw_mlp_train_head_step": (ctypes.c_int, [P, P, P, I64, ctypes.c_float, ctypes.POINTER(D)]),
             "lw_profile_read": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
@@ -150,6 +169,7 @@ class Context:
         self.h = h
         self.nd = self.nw = 0
         self.ns = 1
+        self.dirs = None
 
     def _check(self, st):
         if st != LW_OK:
@@ -170,6 +190,7 @@ class Context:
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
         self._check(self.lib.lw_set_directions(self.h, _np_ptr(d), d.shape[0]))
         self.nd = d.shape[0]
+        self.dirs = d.copy()
 
     def set_frequencies(self, omega):
         w = np.ascontiguousarray(omega, dtype=np.float64)
@@ -270,6 +291,59 @@ class Context:
                                               ctypes.byref(g)))
         return Graph(self, g, workspace, batch)
 
+    def accumulate_subset(self, batch: DeviceBatch, indices, workspace=None, per_particle=None):
+        """Exact FP32 accumulation of the particles in `indices` (device int64 tensor)."""
+        n = int(indices.numel())
+        if workspace is None:
+            sub = lw_batch()
+            ctypes.memmove(ctypes.byref(sub), ctypes.byref(batch.struct), ctypes.sizeof(lw_batch))
+            sub.n_particles = n
+            sz = ctypes.c_size_t()
+            self._check(self.lib.lw_workspace_size(self.h, ctypes.byref(sub), LW_PATH_FP32, ctypes.byref(sz)))
+            workspace = torch.empty(max(sz.value, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        pp = ctypes.c_void_p(per_particle.data_ptr()) if per_particle is not None else None
+        self._check(self.lib.lw_accumulate_subset(self.h, ctypes.byref(batch.struct),
+                                                  ctypes.c_void_p(indices.data_ptr()), n,
+                                                  ctypes.c_void_p(workspace.data_ptr()),
+                                                  workspace.numel(), pp))
+        return workspace
+
+    def surrogate_accumulate(self, batch: DeviceBatch, ylog, err, threshold, compact=False):
+        """Add 10^ylog of unflagged particles to S.
+
+        Returns the device flags [n_particles]; with compact=True also the device
+        int64 list of flagged particles (increasing) and its device count [1]."""
+        P = batch.n_particles
+        flags = torch.empty(P, dtype=torch.int32, device=ylog.device)
+        need = ((P + 1023) // 1024) * self.ns * self.nd * self.nw * 8
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=ylog.device)
+        ep = ctypes.c_void_p(err.data_ptr()) if err is not None else None
+        idx = cnt = None
+        if compact:
+            idx = torch.empty(max(P, 1), dtype=torch.int64, device=ylog.device)
+            cnt = torch.empty(1, dtype=torch.int64, device=ylog.device)
+        self._check(self.lib.lw_surrogate_accumulate(self.h, ctypes.byref(batch.struct),
+                                                     ctypes.c_void_p(ylog.data_ptr()), ep,
+                                                     float(threshold), ctypes.c_void_p(flags.data_ptr()),
+                                                     ctypes.c_void_p(idx.data_ptr()) if compact else None,
+                                                     ctypes.c_void_p(cnt.data_ptr()) if compact else None,
+                                                     ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return (flags, idx, cnt) if compact else flags
+
+    def surrogate_targets(self, batch: DeviceBatch, per_particle, floor=1e-30):
+        """log10(per-particle spectrum / (w q^2) + floor), device [n_particles][nd][nw]."""
+        out = torch.empty_like(per_particle)
+        self._check(self.lib.lw_surrogate_targets(self.h, ctypes.byref(batch.struct),
+                                                  ctypes.c_void_p(per_particle.data_ptr()), float(floor),
+                                                  ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def features(self, batch: DeviceBatch):
+        out = torch.empty((batch.n_particles, self.nd, 16), dtype=torch.float32,
+                          device=f"cuda:{self.device}")
+        self._check(self.lib.lw_features(self.h, ctypes.byref(batch.struct), ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def stats(self) -> int:
         calls = ctypes.c_int64()
         self._check(self.lib.lw_stats(self.h, ctypes.byref(calls)))
@@ -297,3 +371,79 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class MLP:
+    """lw_mlp: the surrogate network (BF16 matrix-core kernels, FP32 master weights)."""
+
+    def __init__(self, ctx: Context, n_in=16, hidden=256, n_hidden=3, n_out=256, seed=1):
+        self.ctx = ctx
+        self.shape = (n_in, hidden, n_hidden, n_out)
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.lw_mlp_create(ctx.h, n_in, hidden, n_hidden, n_out, seed, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        ctx._check(ctx.lib.lw_mlp_num_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.lw_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    def get_params(self):
+        p = np.zeros(self.n_params, dtype=np.float32)
+        head = np.zeros(self.shape[1] + 1, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.lw_mlp_get_params(self.h, _np_ptr(p), self.n_params, _np_ptr(head)))
+        return p, head
+
+    def set_params(self, params, head=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        hd = np.ascontiguousarray(head, dtype=np.float32) if head is not None else None
+        self.ctx._check(self.ctx.lib.lw_mlp_set_params(self.h, _np_ptr(p), self.n_params,
+                                                       _np_ptr(hd) if hd is not None else None))
+
+    def set_input_norm(self, shift=None, scale=None):
+        if shift is None:
+            self.ctx._check(self.ctx.lib.lw_mlp_set_input_norm(self.h, None, None))
+            return
+        sh = np.ascontiguousarray(shift, dtype=np.float32)
+        sc = np.ascontiguousarray(scale, dtype=np.float32)
+        assert sh.size == self.shape[0] and sc.size == self.shape[0]
+        self.ctx._check(self.ctx.lib.lw_mlp_set_input_norm(self.h, _np_ptr(sh), _np_ptr(sc)))
+
+    def forward(self, x, with_error=False):
+        rows = x.shape[0]
+        y = torch.empty((rows, self.shape[3]), dtype=torch.float32, device=x.device)
+        e = torch.empty(rows, dtype=torch.float32, device=x.device) if with_error else None
+        self.ctx._check(self.ctx.lib.lw_mlp_forward(self.h, self._ptr(x), rows, self._ptr(y), self._ptr(e)))
+        return (y, e) if with_error else y
+
+    def loss_grad(self, x, t):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx.lib.lw_mlp_loss_grad(self.h, self._ptr(x), self._ptr(t), x.shape[0],
+                                                      _np_ptr(g), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr=1e-3, weight_decay=0.0, want_loss=True):
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx.lib.lw_mlp_train_step(self.h, self._ptr(x), self._ptr(t), x.shape[0], lr,
+                                                       weight_decay, ctypes.byref(loss)))
+        return loss.value
+
+    def train_head_step(self, x, err_target, lr=1e-3):
+        loss = ctypes.c_double()
+        self.ctx._check(self.ctx.lib.lw_mlp_train_head_step(self.h, self._ptr(x), self._ptr(err_target),
+                                                            x.shape[0], lr, ctypes.byref(loss)))
+        return loss.value

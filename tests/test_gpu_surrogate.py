@@ -1,0 +1,324 @@
+"""GPU tests of the learned surrogate: features and network against the CPU
+oracles, training, the surrogate sum, the fallback list, and the gain over the
+exact path alone.
+
+Tolerances.  Features are FP64 sums rounded once to FP32 (rtol 2e-5); counts
+of reversals and of in-cone samples are FP64 decisions on the same inputs on
+both sides (they may differ by at most one sample on an exact tie).  The
+network multiplies BF16-rounded operands (unit roundoff u = 2^-8) with FP32
+accumulation: each layer's output carries a normwise error of order 2u, the
+backward pass of a network with L hidden layers compounds about 2L + 1 such
+roundings, so the bars are 2e-2 normwise for outputs and 5e-2 for each layer's
+gradient block.  A purely linear layer on operands that are already BF16
+values is exact up to FP32 accumulation (bar 1e-5).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import features as oracle_features
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_round(a):
+    """Round FP32 values to the nearest BF16 value (ties to even), kept as FP32."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def _ctx(dirs, omega, ns=1):
+    from paper_1003_1140_amd import Context
+
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(omega)
+    c.set_species(ns)
+    return c
+
+
+# ---------------------------------------------------------------- features
+@pytest.mark.parametrize("dirs_name", ["jitter", "six"])
+def test_features_match_oracle(dirs_name):
+    import torch
+
+    from paper_1003_1140_amd import DeviceBatch
+
+    recipe = configs.jitter_recipe(steps=700)
+    host = workloads.generate(recipe, 500, 5)
+    dirs = configs.dirs_jitter() if dirs_name == "jitter" else configs.dirs_wide()[:6]
+    c = _ctx(dirs, configs.log_grid(0.1, 1e3, 8))
+    f = c.features(DeviceBatch.from_host(host)).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    ref = oracle_features.features(host, dirs)
+    assert f.shape == ref.shape
+    T = host.dt[0] * 700
+    for j in range(16):
+        if j == 8:
+            np.testing.assert_allclose(f[..., j], ref[..., j], rtol=2e-5, atol=1.0 / T + 1e-6)
+        elif j == 15:
+            np.testing.assert_allclose(f[..., j], ref[..., j], rtol=0, atol=1.0 / 700 + 1e-6)
+        else:
+            np.testing.assert_allclose(f[..., j], ref[..., j], rtol=2e-5, atol=1e-6, err_msg=f"feature {j}")
+
+
+def test_features_of_uneven_lengths():
+    from paper_1003_1140_amd import DeviceBatch
+
+    recipe = configs.uneven_recipe()
+    host = workloads.generate(recipe, 0, 4)
+    dirs = configs.dirs_jitter()
+    c = _ctx(dirs, configs.log_grid(0.1, 1e3, 8))
+    f = c.features(DeviceBatch.from_host(host)).cpu().numpy().astype(np.float64)
+    ref = oracle_features.features(host, dirs)
+    keep = [j for j in range(16) if j not in (8, 15)]
+    np.testing.assert_allclose(f[..., keep], ref[..., keep], rtol=2e-5, atol=1e-6)
+
+
+# ---------------------------------------------------------------- network vs oracle
+def _net(c, shape, seed=3):
+    from paper_1003_1140_amd import MLP
+
+    return MLP(c, *shape, seed=seed)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_linear_layer_is_exact_on_bf16_operands():
+    import torch
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    shape = (16, 8, 0, 40)  # no hidden layer: y = x W^T + b
+    net = _net(c, shape)
+    rng = np.random.default_rng(5)
+    p = _bf16_round(rng.normal(size=net.n_params))
+    net.set_params(p)
+    for rows in (64, 100, 1):
+        x = _bf16_round(rng.normal(size=(rows, 16)))
+        y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
+        ref = oracle.mlp_forward_backward(shape, p.astype(np.float64), x.astype(np.float64))["y"]
+        np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("rows", [64, 150])
+def test_forward_and_gradients_match_oracle(rows):
+    import torch
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    shape = (16, 64, 3, 48)
+    net = _net(c, shape)
+    rng = np.random.default_rng(rows)
+    p0, _ = net.get_params()
+    p = p0 + rng.normal(scale=0.02, size=p0.size).astype(np.float32)  # non-zero biases
+    net.set_params(p)
+    x = rng.normal(size=(rows, 16)).astype(np.float32)
+    t = rng.normal(size=(rows, 48)).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = net.forward(xd).cpu().numpy()
+    loss, g = net.loss_grad(xd, td)
+    ref = oracle.mlp_forward_backward(shape, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
+                                      want_grad=True)
+    e_y = _rel(y, ref["y"])
+    print(f"[mlp] rows {rows}: output normwise {e_y:.2e}, loss {loss:.6f} vs {ref['loss']:.6f}", flush=True)
+    assert e_y < 2e-2
+    assert abs(loss - ref["loss"]) <= 2e-2 * ref["loss"]
+    # each layer's weight and bias blocks
+    widths = [16, 64, 64, 64, 48]
+    off = 0
+    for layer in range(4):
+        din, dout = widths[layer], widths[layer + 1]
+        for name, n in (("W", din * dout), ("b", dout)):
+            e = _rel(g[off:off + n], ref["grad"][off:off + n])
+            print(f"[mlp] layer {layer} d{name}: normwise {e:.2e}", flush=True)
+            assert e < 5e-2, (layer, name, e)
+            off += n
+    assert off == g.size
+
+
+def test_input_normalisation_matches_oracle_on_normalised_inputs():
+    import torch
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    shape = (16, 32, 2, 24)
+    net = _net(c, shape)
+    rng = np.random.default_rng(9)
+    shift = rng.normal(size=16).astype(np.float32) * 100 + 1000  # large offsets
+    scale = (1.0 / rng.uniform(0.5, 2.0, size=16)).astype(np.float32)
+    scale[3] = 0.0  # a dropped feature
+    net.set_input_norm(shift, scale)
+    x = (shift + rng.normal(size=(80, 16)) / scale.clip(1e-3)).astype(np.float32)
+    t = rng.normal(size=(80, 24)).astype(np.float32)
+    p, _ = net.get_params()
+    xn = (x.astype(np.float64) - shift) * scale
+    ref = oracle.mlp_forward_backward(shape, p.astype(np.float64), xn, t.astype(np.float64), want_grad=True)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    y = net.forward(xd).cpu().numpy()
+    _, g = net.loss_grad(xd, td)
+    assert _rel(y, ref["y"]) < 2e-2
+    assert _rel(g, ref["grad"]) < 5e-2
+
+
+def test_training_reduces_the_loss_and_error_head_learns():
+    import torch
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    shape = (16, 128, 3, 32)
+    net = _net(c, shape, seed=7)
+    rng = np.random.default_rng(11)
+    teacher = rng.normal(size=(16, 32)) / 4.0
+    x = rng.normal(size=(4096, 16)).astype(np.float32)
+    t = np.sin(x @ teacher).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    first = net.train_step(xd, td, lr=2e-3)
+    for _ in range(300):
+        last = net.train_step(xd, td, lr=2e-3)
+    print(f"[mlp] training loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.1 * first
+    # error head: learn |x_0| (a function of the input the trunk has features for)
+    e_t = torch.from_numpy(np.abs(x[:, 0]).astype(np.float32)).cuda()
+    h0 = net.train_head_step(xd, e_t, lr=3e-3)
+    for _ in range(300):
+        h1 = net.train_head_step(xd, e_t, lr=3e-3)
+    print(f"[mlp] head loss {h0:.4f} -> {h1:.4f}", flush=True)
+    assert h1 < 0.5 * h0
+    _, e = net.forward(xd, with_error=True)
+    assert np.isfinite(e.cpu().numpy()).all()
+
+
+# ---------------------------------------------------------------- surrogate sum, fallback, targets
+def _small_chunk(n=300, steps=512, seed_train=False):
+    from paper_1003_1140_amd import DeviceBatch
+    from workloads.gpu import generate_device
+
+    recipe = configs.surrogate_recipe(train=seed_train, steps=steps)
+    t, _ = generate_device(recipe, 0, n)
+    return DeviceBatch(t, n)
+
+
+def test_surrogate_sum_compaction_and_targets():
+    import torch
+
+    omega = configs.log_grid(0.1, 1e3, 64)
+    c = _ctx(configs.dirs_jitter(), omega)
+    b = _small_chunk(n=2500)
+    P, nd, nw = b.n_particles, c.nd, c.nw
+    rng = np.random.default_rng(2)
+    ylog = rng.normal(-2.0, 1.0, size=(P, nd, nw)).astype(np.float32)
+    err = rng.uniform(0, 1, size=(P, nd)).astype(np.float32)
+    yd, ed = torch.from_numpy(ylog).cuda(), torch.from_numpy(err).cuda()
+    flags, idx, cnt = c.surrogate_accumulate(b, yd, ed, 0.9, compact=True)
+    S = c.read_spectra()[0]
+    fl = flags.cpu().numpy()
+    want = (err > 0.9).any(1)
+    assert np.array_equal(fl != 0, want)
+    n = int(cnt.item())
+    assert np.array_equal(idx[:n].cpu().numpy(), np.flatnonzero(want))
+    w = b.t["weight"].cpu().numpy().astype(np.float64)
+    q = b.t["charge"].cpu().numpy().astype(np.float64)
+    keep = ~want
+    ref = np.einsum("p,pdj->dj", (w * q * q)[keep], 10.0 ** ylog[keep].astype(np.float64))
+    np.testing.assert_allclose(S, ref, rtol=1e-12)
+    # targets from per-particle exact spectra
+    c.reset()
+    pp = torch.zeros((P, nd, nw), dtype=torch.float32, device="cuda")
+    c.accumulate(b, "fp32", per_particle=pp)
+    c.read_spectra()
+    tg = c.surrogate_targets(b, pp).cpu().numpy()
+    ref_t = np.log10(pp.cpu().numpy().astype(np.float64) / (w * q * q)[:, None, None] + 1e-30)
+    np.testing.assert_allclose(tg, ref_t, rtol=0, atol=2e-6)
+
+
+def test_fallback_extremes_reduce_to_exact_and_to_surrogate():
+    import torch
+
+    from paper_1003_1140_amd import surrogate as sg
+
+    omega = configs.log_grid(0.1, 1e3, 32)
+    c = _ctx(configs.dirs_jitter(), omega)
+    b = _small_chunk(n=400)
+    c.accumulate(b, "fp32")
+    S_exact = c.read_spectra()
+    c.reset()
+    from paper_1003_1140_amd import MLP
+
+    net = MLP(c, 16, 64, 3, c.nw, seed=1)
+    sur = sg.Surrogate(net=net, threshold=0.0)
+    # threshold -inf: everything falls back to the exact path
+    r = sg.infer_chunk(c, sur, b, threshold=float("-inf"))
+    assert r["fallback"] == b.n_particles
+    np.testing.assert_allclose(c.read_spectra(), S_exact, rtol=1e-12)
+    # threshold +inf: nothing falls back; S is the plain surrogate sum
+    c.reset()
+    r = sg.infer_chunk(c, sur, b, threshold=float("inf"))
+    assert r["fallback"] == 0
+    x = c.features(b).view(-1, 16)
+    y = net.forward(x).cpu().numpy().astype(np.float64).reshape(b.n_particles, c.nd, c.nw)
+    w = (b.t["weight"] * b.t["charge"] ** 2).cpu().numpy().astype(np.float64)
+    ref = np.einsum("p,pdj->dj", w, 10.0 ** y)
+    np.testing.assert_allclose(c.read_spectra()[0], ref, rtol=1e-6)
+    torch.cuda.synchronize()
+
+
+def test_trained_surrogate_is_judged_and_gains_over_exact():
+    """End to end at reduced size: train on exact spectra, infer with the error-head
+    fallback and a held-out judge, and time the pipeline against the exact path
+    alone on the same particles."""
+    import torch
+
+    from paper_1003_1140_amd import surrogate as sg
+
+    omega = configs.log_grid(0.1, 1e3, 256)
+    c = _ctx(configs.dirs_jitter(), omega)
+    train_b = _small_chunk(n=6000, steps=4096, seed_train=True)
+    from paper_1003_1140_amd import DeviceBatch
+    from workloads.gpu import generate_device
+
+    rec_t = configs.surrogate_recipe(train=True, steps=4096)
+    tc, _ = generate_device(rec_t, 6000, 1500)
+    calib = DeviceBatch(tc, 1500)
+    sur = sg.train(c, train_b, calib, steps=800, batch_rows=4096, fallback_fraction=0.05, head_steps=300,
+                   log=lambda m: print(m, flush=True))
+    print(f"[surrogate] {sur.stats}", flush=True)
+    assert sur.train_loss[-1] < 0.25 * sur.train_loss[0]
+    del train_b, calib
+    rec_i = configs.surrogate_recipe(train=False, steps=4096)
+    ti, _ = generate_device(rec_i, 0, 20000)
+    b = DeviceBatch(ti, 20000)
+    held = torch.from_numpy(sg.held_out_indices(b.n_particles, 0, 0.05, 11406)).cuda()
+    # exact path alone
+    c.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.accumulate(b, "fp32")
+    S_exact = c.read_spectra()
+    t_exact = time.perf_counter() - t0
+    # pipeline (warm once for the network workspace)
+    c.reset()
+    sg.infer_chunk(c, sur, b)
+    c.reset()
+    judge = sg.Judge(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sg.infer_chunk(c, sur, b, judge=judge, held_idx=held)
+    S_pipe = c.read_spectra()
+    Se, Ss = judge.spectra()
+    t_pipe = time.perf_counter() - t0
+    held_err = sg.held_out_errors(Se, Ss)
+    m = S_exact >= 1e-4 * S_exact.max(axis=-1, keepdims=True)
+    ens = float(np.max(np.abs(S_pipe - S_exact)[m] / S_exact[m]))
+    print(f"[surrogate] fallback {r['fallback']} of {b.n_particles}; held-out ({judge.n}) per-bin max "
+          f"{held_err['per_bin_max']:.3e} median {held_err['per_bin_median']:.3e}; ensemble per-bin max "
+          f"{ens:.3e}; exact {t_exact * 1e3:.1f} ms, pipeline {t_pipe * 1e3:.1f} ms, gain "
+          f"{t_exact / t_pipe:.2f}x", flush=True)
+    assert r["fallback"] <= 0.15 * b.n_particles
+    assert held_err["per_bin_max"] < 0.15
+    assert ens < 0.15
+    assert t_exact / t_pipe > 1.5

@@ -1,0 +1,69 @@
+"""Pins of the FP64 surrogate-network reference and of the feature reference (CPU)."""
+import numpy as np
+import scipy.special as sp
+
+import oracle
+from oracle import features as feat
+from workloads import orbits
+
+SHAPE = (5, 7, 2, 4)
+
+
+def test_gelu_closed_form():
+    z = np.array([-3.0, -1.0, 0.0, 0.5, 1.0, 2.0])
+    np.testing.assert_allclose(oracle.mlp_gelu(z), z * 0.5 * (1 + sp.erf(z / np.sqrt(2))), rtol=1e-15)
+    assert abs(oracle.mlp_gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15
+
+
+def test_param_count_of_the_spectrum_network():
+    # 16 -> 256 -> 256 -> 256 -> 256
+    assert oracle.mlp_num_params(16, 256, 3, 256) == 16 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 256 + 256
+
+
+def test_linear_network_reduces_to_matrix_product():
+    # no hidden layer: y = W x + b
+    rng = np.random.default_rng(1)
+    W = rng.normal(size=(3, 4))
+    b = rng.normal(size=3)
+    x = rng.normal(size=(6, 4))
+    out = oracle.mlp_forward_backward((4, 1, 0, 3), np.concatenate([W.ravel(), b]), x)
+    np.testing.assert_allclose(out["y"], x @ W.T + b, rtol=1e-14)
+
+
+def test_gradient_against_central_differences():
+    rng = np.random.default_rng(2)
+    n = oracle.mlp_num_params(*SHAPE)
+    p = rng.normal(scale=0.5, size=n)
+    x = rng.normal(size=(9, SHAPE[0]))
+    t = rng.normal(size=(9, SHAPE[3]))
+    g = oracle.mlp_forward_backward(SHAPE, p, x, t, want_grad=True)["grad"]
+    h = 1e-6
+    for i in rng.choice(n, 25, replace=False):
+        e = np.zeros(n)
+        e[i] = h
+        fd = (oracle.mlp_forward_backward(SHAPE, p + e, x, t)["loss"] -
+              oracle.mlp_forward_backward(SHAPE, p - e, x, t)["loss"]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_features_of_uniform_circular_motion():
+    """gamma constant, |a_perp| = beta omega0 exactly, no force along beta."""
+    g, w0, n, dt = 5.0, 2.0, 4000, 2 * np.pi / 2.0 / 4000
+    b = orbits.circular(g, w0, n, dt)
+    beta = np.sqrt(1 - 1 / g**2)
+    f = feat.features(b, [[0.0, 0.0, 1.0]])[0, 0]
+    assert abs(f[0] - np.log(g)) < 1e-12
+    assert f[1] < 1e-12
+    assert abs(f[2] - np.log(beta * w0)) < 1e-9
+    assert abs(f[4] - np.log(beta * w0)) < 1e-9
+    assert abs(f[5] - 1.0) < 1e-9
+    assert abs(f[10] - np.log(n * dt)) < 1e-12
+    # observer along the orbit axis: kappa = 1 everywhere, never inside the 1/gamma cone
+    assert abs(f[13]) < 1e-12 and abs(f[14]) < 1e-12 and f[15] == 0.0
+
+
+def test_features_of_straight_motion():
+    b = orbits.straight([0.6, 0.0, 0.0], [0, 0, 0], 100, 0.01)
+    f = feat.features(b, [[1.0, 0.0, 0.0]])[0, 0]
+    assert f[2] == np.log(feat.EPS) and f[8] == 0.0 and f[6] == 0.0
+    assert abs(f[13] - np.log(0.4)) < 1e-12 and f[15] == 1.0  # looking down the velocity

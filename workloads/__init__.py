@@ -48,6 +48,7 @@ def _load():
         _lib.wl_generate.restype = ctypes.c_int
         _lib.wl_field_info.restype = ctypes.c_int
         _lib.wl_field_eval.restype = ctypes.c_int
+        _lib.wl_field_coeffs.restype = ctypes.c_int
     return _lib
 
 

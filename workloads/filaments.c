@@ -232,6 +232,24 @@ int wl_field_info(const wl_recipe* r, int32_t* n_modes, double* brms, double* kb
   return 0;
 }
 
+/* Field coefficients C_ij = a e^{i phi} on the [(imax+1)][(2 imax+1)] lattice table
+ * (for the device generator).  Returns imax, or a negative value if cap is too small. */
+int wl_field_coeffs(const wl_recipe* r, double* cre, double* cim, int64_t cap, double* k0) {
+  wl_field f;
+  if (field_build(r, &f) != 0) return -2;
+  int64_t cells = (int64_t)(f.imax + 1) * (2 * f.imax + 1);
+  int imax = f.imax;
+  if (cells > cap) {
+    field_free(&f);
+    return -1;
+  }
+  memcpy(cre, f.cre, sizeof(double) * (size_t)cells);
+  memcpy(cim, f.cim, sizeof(double) * (size_t)cells);
+  *k0 = f.k0;
+  field_free(&f);
+  return imax;
+}
+
 /* B_y sampled at given points (for tests of the field statistics). */
 int wl_field_eval(const wl_recipe* r, int64_t n, const double* x, const double* z, double* by) {
   wl_field f;
