@@ -11,7 +11,13 @@ trajectories (25 GB) already resident in HBM.
 metric: terms/s, a term being one (particle, sample, direction, frequency)
 product of the spectral sum.
 
-Prints one JSON line.  Options: --steps K --warmup W --particles P --path fp32.
+A second leg measures the learned surrogate on its own workload (one ensemble
+of the same generator, 256 log frequencies): training on 1.25e5 particles'
+exact spectra, then inference on 1e6 particles with the error-head fallback and
+a 1 % held-out judge, against the exact FP32 path on the same particles.
+
+Prints one JSON line.  Options: --steps K --warmup W --particles P --paths ...
+--no-surrogate.
 """
 from __future__ import annotations
 
@@ -65,6 +71,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
+    ap.add_argument("--surrogate-chunk", type=int, default=100_000)
+    ap.add_argument("--surrogate-steps", type=int, default=1500)
+    ap.add_argument("--host-generator", action="store_true",
+                    help="generate the throughput ensemble on the host (default: on the device)")
     return ap.parse_args()
 
 
@@ -139,15 +151,107 @@ def cpu_baseline(recipe, dirs, om, target_s):
                       f"{len(om)} freqs, FP64 libm sin/cos, {el:.1f} s"}
 
 
-def upload_ensemble(recipe, n, chunk, dev):
-    """The whole ensemble in device memory, generated on the host chunk by chunk."""
+def upload_ensemble(recipe, n, chunk, dev, host=False):
+    """The whole ensemble in device memory, generated on the device (or on the host)."""
     from paper_1003_1140_amd import DeviceBatch
-    from workloads.device import upload_chunks
 
-    tensors, ns = upload_chunks(recipe, n, chunk, dev)
+    if host:
+        from workloads.device import upload_chunks
+
+        tensors, ns = upload_chunks(recipe, n, chunk, dev)
+    else:
+        from workloads.gpu import generate_device
+
+        tensors, ns = generate_device(recipe, 0, n, dev)
     b = DeviceBatch(tensors, n)
     b.n_samples_host = ns
     return b
+
+
+def surrogate_leg(a, log):
+    """Train the surrogate, then time it against the exact path on 1e6 particles."""
+    import torch
+
+    from paper_1003_1140_amd import Context, DeviceBatch
+    from paper_1003_1140_amd import surrogate as sg
+    from workloads import configs
+    from workloads.gpu import generate_device
+
+    cfg = configs.WORKLOADS["surrogate"]
+    rec = configs.surrogate_recipe(cfg["steps"])
+    dirs, om = configs.dirs_jitter(), configs.log_grid(*cfg["omega"])
+    ctxs = []
+    for _ in range(1 + 3):  # surrogate pipeline, then exact subsamples at 1/16, 1/8, 1/4
+        c = Context(0)
+        c.set_directions(dirs)
+        c.set_frequencies(om)
+        ctxs.append(c)
+    ctx, subs = ctxs[0], ctxs[1:]
+    fracs = (1 / 16, 1 / 8, 1 / 4)
+    exact = Context(0)
+    exact.set_directions(dirs)
+    exact.set_frequencies(om)
+    t = time.perf_counter()
+    tt, _ = generate_device(rec, 0, cfg["n_train"])
+    tc, _ = generate_device(rec, cfg["n_train"], cfg["n_calib"])
+    log(f"[bench] surrogate: generated {cfg['n_train']} + {cfg['n_calib']} particles in "
+        f"{time.perf_counter() - t:.1f} s")
+    sur = sg.train(ctx, DeviceBatch(tt, cfg["n_train"]), DeviceBatch(tc, cfg["n_calib"]),
+                   steps=a.surrogate_steps, fallback_fraction=cfg["fallback"], log=log)
+    del tt, tc
+    torch.cuda.empty_cache()
+    ctx.reset()
+    judge = sg.Judge(ctx)
+    n, chunk, first = a.surrogate_infer, min(a.surrogate_chunk, a.surrogate_infer), cfg["infer_first_id"]
+    t_exact = t_pipe = 0.0
+    fallback = 0
+    terms = 0.0
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        tb, ns = generate_device(rec, first + c0, m)
+        b = DeviceBatch(tb, m)
+        terms += float(ns) * len(dirs) * len(om)
+        held = torch.from_numpy(sg.held_out_indices(m, first + c0, cfg["held_out"], 11406)).cuda()
+        if c0 == 0:  # allocate the network's activation workspace before timing
+            sur.net.forward(ctx.features(b).view(-1, 16))
+            ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        exact.accumulate(b, "fp32")
+        exact.read_spectra()
+        t1 = time.perf_counter()
+        r = sg.infer_chunk(ctx, sur, b, judge=judge, held_idx=held)
+        ctx.read_spectra()
+        t2 = time.perf_counter()
+        t_exact += t1 - t0
+        t_pipe += t2 - t1
+        fallback += r["fallback"]
+        for f, sc in zip(fracs, subs):
+            sc.accumulate(b.head(max(1, int(round(f * m)))), "fp32")
+        del tb, b
+    S_pipe, S_exact = ctx.read_spectra(), exact.read_spectra()
+    Se, Sp, Ss = judge.spectra()
+    held_err = sg.held_out_errors(Se, Sp)
+    sur_only = sg.held_out_errors(Se, Ss)
+    ens = sg.held_out_errors(S_exact, S_pipe)
+    sub = {f"{f:.4f}": sg.held_out_errors(S_exact, sc.read_spectra() / f)["per_bin_median"]
+           for f, sc in zip(fracs, subs)}
+    return {
+        "workload": f"{n} particles (ids from {first}) of the surrogate ensemble, 4096 steps, 4 dirs, "
+                    f"256 log omega in [0.1,1e3]; trained on {cfg['n_train']} particles' exact spectra "
+                    f"({sur.stats['train_pairs']} pairs), calibrated on {cfg['n_calib']}",
+        "equivalent_terms_per_s": terms / t_pipe, "exact_terms_per_s": terms / t_exact,
+        "gain_vs_exact": t_exact / t_pipe, "seconds_pipeline": t_pipe, "seconds_exact": t_exact,
+        "fallback_fraction": fallback / n, "held_out_particles": judge.n,
+        "held_out_per_bin_max": held_err["per_bin_max"], "held_out_per_bin_median": held_err["per_bin_median"],
+        "held_out_band_integrated_max": band_integrated_error(Sp, Se, om),
+        "held_out_surrogate_only_per_bin_max": sur_only["per_bin_max"],
+        "held_out_surrogate_only_per_bin_median": sur_only["per_bin_median"],
+        "ensemble_per_bin_max": ens["per_bin_max"], "ensemble_per_bin_median": ens["per_bin_median"],
+        "ensemble_band_integrated_max": band_integrated_error(S_pipe, S_exact, om),
+        "exact_subsample_per_bin_median": sub,
+        "train": {k: v for k, v in sur.stats.items()},
+    }
 
 
 def main():
@@ -167,7 +271,7 @@ def main():
     dirs = configs.dirs_jitter()
     om = configs.log_grid(0.1, 1e3, 1024)
     t = time.perf_counter()
-    batch = upload_ensemble(recipe, a.particles, a.chunk, dev)
+    batch = upload_ensemble(recipe, a.particles, a.chunk, dev, host=a.host_generator)
     terms_per_step = float(batch.n_samples_host) * len(dirs) * len(om)
     print(f"[bench] generated and uploaded {a.particles} particles ({batch.n_samples_host} samples) "
           f"in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
@@ -211,6 +315,12 @@ def main():
         "roofline": r["roofline"],
         "paths": results,
     }
+    if not a.no_surrogate:
+        del batch
+        torch.cuda.empty_cache()
+        out["surrogate"] = surrogate_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[bench] surrogate: {out['surrogate']['equivalent_terms_per_s']:.3e} equivalent terms/s, "
+              f"gain {out['surrogate']['gain_vs_exact']:.2f}x", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         print("[bench] running CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(recipe, dirs, om, a.cpu_seconds)

@@ -85,7 +85,8 @@ typedef struct lw_ctx lw_ctx;
 /* Create a context on HIP device `device`, ordered on `stream` (hipStream_t,
  * borrowed; NULL = default stream).  *out receives the context. */
 lw_status lw_create(lw_ctx** out, int device, void* stream);
-/* Free the context and everything it owns (synchronises its stream). */
+/* Free the context and everything it owns (synchronises its stream).  Networks
+ * (lw_mlp) and graphs (lw_graph) made on it refer to it: destroy them first. */
 void lw_destroy(lw_ctx* ctx);
 /* Text of the last error on this context; valid until the next call on it. */
 const char* lw_last_error(const lw_ctx* ctx);
@@ -194,24 +195,29 @@ lw_status lw_accumulate_subset(lw_ctx* ctx, const lw_batch* batch, const int64_t
  * Features of every (particle, direction) pair: device float [n_particles][nd][16]
  * (log Lorentz factor and spread; transverse-acceleration mean, rms, max and
  * kurtosis; deflection in units of 1/gamma, rms and max; force reversals per
- * unit time and the jitter frequency scale; log duration; log mean |betadot|;
+ * unit time and the jitter frequency scale; log duration; log of the energy
+ * per unit solid angle radiated towards n, the Riemann sum of
+ * |n x ((n - beta) x betadot)|^2 / kappa^5 dt / (4 pi) (Jackson eq. 14.38, equal
+ * by Parseval to the frequency integral of the spectrum), plus 1e-30;
  * observer angle to the mean velocity times gamma; log mean and min kappa;
  * fraction of samples with the observer inside the 1/gamma cone). */
 lw_status lw_features(lw_ctx* ctx, const lw_batch* batch, float* feats);
 
 /* Add the surrogate's predicted spectra to S: ylog = device [n_particles][nd][nw]
- * log10 of each particle's own spectrum (without w q^2); err = device
+ * log10 of each particle's own spectrum (without w q^2); calib (may be NULL) =
+ * device [nd][nw] log10 correction added to every particle's ylog; err = device
  * [n_particles][nd] predicted error or NULL.  Particles whose error exceeds
  * `threshold` in any direction (or is NaN) get flags[p] = 1 (device int32
  * [n_particles]) and are left out, for lw_accumulate_subset to add exactly; the
- * others add w_p q_p^2 10^ylog to their species.  Fixed-order reduction.
+ * others add w_p q_p^2 10^(ylog + calib) to their species.  Fixed-order reduction.
  * flagged, n_flagged (device int64 [n_particles] and [1], both or neither): the
  * flagged particle indices in increasing order and their count.  Workspace:
  * ceil(n_particles / 1024) x n_species x nd x nw doubles; at most 65535 x 1024
  * particles per call (LW_ERANGE beyond). */
 lw_status lw_surrogate_accumulate(lw_ctx* ctx, const lw_batch* batch, const float* ylog,
-                                  const float* err, float threshold, int32_t* flags, int64_t* flagged,
-                                  int64_t* n_flagged, void* workspace, size_t workspace_bytes);
+                                  const float* calib, const float* err, float threshold, int32_t* flags,
+                                  int64_t* flagged, int64_t* n_flagged, void* workspace,
+                                  size_t workspace_bytes);
 
 /* Training targets from the exact kernel's per-particle output (lw_accumulate's
  * per_particle array, device [n_particles][nd][nw]): out = log10(pp / (w q^2) +
@@ -238,6 +244,11 @@ lw_status lw_mlp_set_params(lw_mlp* net, const float* host, int64_t count, const
  * reads (x[k] - shift[k]) * scale[k].  shift, scale: host float [n_in], both
  * NULL to remove it.  Used by every later forward, gradient and training call. */
 lw_status lw_mlp_set_input_norm(lw_mlp* net, const float* shift, const float* scale);
+/* Output skip: every output gets coeff * x[input_index] (the raw input, before
+ * the normalisation) added, in forward, gradient and training calls alike, so
+ * the network learns the outputs relative to that input; input_index = -1
+ * removes it. */
+lw_status lw_mlp_set_output_skip(lw_mlp* net, int32_t input_index, float coeff);
 /* y: device [rows][n_out]; err_head (may be NULL): device [rows], the error head's output. */
 lw_status lw_mlp_forward(lw_mlp* net, const float* x, int64_t rows, float* y, float* err_head);
 /* Loss and its gradient (copied to grad_host when not NULL), no update. */

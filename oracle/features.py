@@ -10,7 +10,7 @@ the beam (kappa statistics).  EPS keeps logarithms finite.
  0 ln <gamma>                 8  force reversals per unit time (rate)
  1 std(gamma) / <gamma>       9  ln(<gamma>^2 rate + 1e-6)
  2 ln(<|a_perp|> + EPS)      10  ln T, T = N dt
- 3 ln(rms |a_perp| + EPS)    11  ln(<|betadot|> + EPS)
+ 3 ln(rms |a_perp| + EPS)    11  ln(E + 1e-30), E the radiated energy per unit solid angle
  4 ln(max |a_perp| + EPS)    12  <gamma> angle(n, mean beam direction)
  5 <a_perp^4> / <a_perp^2>^2 13  ln <kappa>
  6 <gamma> theta_rms          14  ln min kappa
@@ -18,7 +18,10 @@ the beam (kappa statistics).  EPS keeps logarithms finite.
 
 a_perp is the part of d(beta)/dt perpendicular to beta; theta the angle of
 beta to the mean unit velocity; a force reversal is a sample whose d(beta)/dt
-has a negative dot product with the previous sample's.
+has a negative dot product with the previous sample's.  E is the Riemann sum
+over the samples of |n x ((n - beta) x betadot)|^2 / kappa^5 dt / (4 pi), the
+energy per unit solid angle radiated towards n (Jackson, eq. 14.38), which by
+Parseval's theorem is the frequency integral of the spectrum in direction n.
 """
 import numpy as np
 
@@ -51,6 +54,8 @@ def features_one(beta, bdot, dt, n):
     kap = 1.0 - beta @ n
     ang_n = np.arctan2(np.linalg.norm(np.cross(bhat, n[None, :]), axis=1), bhat @ n)
     ang_ne = np.arctan2(np.linalg.norm(np.cross(e, n)), e @ n)
+    v = np.cross(n[None, :], np.cross(n[None, :] - beta, bdot))
+    energy = np.sum(np.einsum("ij,ij->i", v, v) / kap**5) * dt / (4.0 * np.pi)
     return np.array([
         np.log(g),
         gam.std() / g,
@@ -63,7 +68,7 @@ def features_one(beta, bdot, dt, n):
         rate,
         np.log(g * g * rate + 1e-6),
         np.log(T),
-        np.log(np.mean(np.sqrt(np.einsum("ij,ij->i", bdot, bdot))) + EPS),
+        np.log(energy + 1e-30),
         g * ang_ne,
         np.log(kap.mean()),
         np.log(kap.min()),

@@ -44,8 +44,9 @@ __device__ __forceinline__ double wave_min(double v) {
 
 __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const double* dirs, int nd,
                                                           float* feats, unsigned long long* err) {
-  // direction-independent sums 0..10, then per direction g: kappa sum, kappa min, cone count
-  constexpr int NI = 11, NQ = NI + 3 * kDirGroup;
+  // direction-independent sums 0..9, then per direction g: kappa sum, kappa min, cone count,
+  // radiated energy sum |n x ((n - beta) x betadot)|^2 / kappa^5
+  constexpr int NI = 10, NQ = NI + 4 * kDirGroup;
   __shared__ double s_part[4][NQ];
   __shared__ double s_tot[NQ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
   #pragma unroll
-  for (int g = 0; g < kDirGroup; ++g) q[NI + 3 * g + 1] = 1.0e300;
+  for (int g = 0; g < kDirGroup; ++g) q[NI + 4 * g + 1] = 1.0e300;
   for (int64_t k = tid; k < len; k += 256) {
     const int64_t i = o + k;
     const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
@@ -92,20 +93,25 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
     q[7] += ux;
     q[8] += uy;
     q[9] += uz;
-    q[10] += sqrt(ax * ax + ay * ay + az * az);
     #pragma unroll
     for (int g = 0; g < kDirGroup; ++g) {
       const double* m = n[g];
       const double kap = 1.0 - (m[0] * bx + m[1] * by + m[2] * bz);
       const double cx = uy * m[2] - uz * m[1], cy = uz * m[0] - ux * m[2], cz = ux * m[1] - uy * m[0];
       const double ang = atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * m[0] + uy * m[1] + uz * m[2]);
-      q[NI + 3 * g] += kap;
-      q[NI + 3 * g + 1] = fmin(q[NI + 3 * g + 1], kap);
-      if (ang < 1.0 / gam) q[NI + 3 * g + 2] += 1.0;
+      q[NI + 4 * g] += kap;
+      q[NI + 4 * g + 1] = fmin(q[NI + 4 * g + 1], kap);
+      if (ang < 1.0 / gam) q[NI + 4 * g + 2] += 1.0;
+      // w = (n - beta) x betadot, v = n x w
+      const double dx = m[0] - bx, dy = m[1] - by, dz = m[2] - bz;
+      const double wx = dy * az - dz * ay, wy = dz * ax - dx * az, wz = dx * ay - dy * ax;
+      const double vx = m[1] * wz - m[2] * wy, vy = m[2] * wx - m[0] * wz, vz = m[0] * wy - m[1] * wx;
+      const double k2 = kap * kap;
+      q[NI + 4 * g + 3] += (vx * vx + vy * vy + vz * vz) / (k2 * k2 * kap);
     }
   }
   auto is_max = [](int i) { return i == 6; };
-  auto is_min = [](int i) { return i >= NI && (i - NI) % 3 == 1; };
+  auto is_min = [](int i) { return i >= NI && (i - NI) % 4 == 1; };
   #pragma unroll
   for (int i = 0; i < NQ; ++i) {
     const double v = is_max(i) ? wave_max(q[i]) : (is_min(i) ? wave_min(q[i]) : wave_sum(q[i]));
@@ -175,16 +181,17 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
     f[8] = (float)rate;
     f[9] = (float)log(gm * gm * rate + 1e-6);
     f[10] = (float)log(T);
-    f[11] = (float)log(s_tot[10] / N + eps);
+    f[11] = (float)log(s_tot[NI + 4 * g + 3] * b.dt[p] / (4.0 * M_PI) + 1e-30);
     f[12] = (float)(gm * ang_ne);
-    f[13] = (float)log(s_tot[NI + 3 * g] / N);
-    f[14] = (float)log(s_tot[NI + 3 * g + 1]);
-    f[15] = (float)(s_tot[NI + 3 * g + 2] / N);
+    f[13] = (float)log(s_tot[NI + 4 * g] / N);
+    f[14] = (float)log(s_tot[NI + 4 * g + 1]);
+    f[15] = (float)(s_tot[NI + 4 * g + 2] / N);
   }
 }
 
 // ------------------------------------------------------------------ BF16 MFMA GEMM
-// C[i][j] (ldc) = sum_k A(i,k) B(k,j) (+ bias[j]), A(i,k) = A[i*sai + k*sak],
+// C[i][j] (ldc) = sum_k A(i,k) B(k,j) (+ bias[j]) (+ row_coeff * row_add[i*row_stride]),
+// A(i,k) = A[i*sai + k*sak],
 // B(k,j) = B[k*sbk + j*sbj]; FP32 operands are rounded to BF16 as they are staged in
 // LDS, products accumulate in FP32 on v_mfma_f32_32x32x16_bf16.  64 x 64 tile per
 // work-group of 4 waves (2 x 2 blocks of 32 x 32), inner steps of 16.
@@ -197,6 +204,9 @@ struct GemmDesc {
   int64_t ldc;
   const float* bias;
   int64_t M, N, K;
+  const float* row_add = nullptr;  // per-row term added to every column, or null
+  int64_t row_stride = 0;
+  float row_coeff = 0.0f;
 };
 
 __global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
@@ -229,7 +239,9 @@ __global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
   for (int r = 0; r < 16; ++r) {
     const int64_t ii = i0 + wi + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
     const int64_t jj = j0 + wj + (lane & 31);
-    if (ii < g.M && jj < g.N) g.C[ii * g.ldc + jj] = acc[r] + (g.bias ? g.bias[jj] : 0.0f);
+    if (ii < g.M && jj < g.N)
+      g.C[ii * g.ldc + jj] = acc[r] + (g.bias ? g.bias[jj] : 0.0f) +
+                             (g.row_add ? g.row_coeff * g.row_add[ii * g.row_stride] : 0.0f);
   }
 }
 
@@ -336,8 +348,10 @@ __global__ void lw_flag_kernel(const float* err, int64_t P, int nd, float thresh
   flags[p] = f;
 }
 
-// partial[slice][s][d][j] = sum over the slice's unflagged particles of 10^ylog[p][d][j]
-__global__ void lw_surrogate_sum_kernel(const float* ylog, const int32_t* flags, const int32_t* species,
+// partial[slice][s][d][j] = sum over the slice's unflagged particles of
+// w q^2 10^(ylog[p][d][j] + calib[d][j])
+__global__ void lw_surrogate_sum_kernel(const float* ylog, const float* calib, const int32_t* flags,
+                                        const int32_t* species,
                                         const float* charge, const float* weight, int64_t P, int nd,
                                         int nw, int ns, int64_t per_slice, double* partial) {
   const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // d * nw + j
@@ -346,13 +360,14 @@ __global__ void lw_surrogate_sum_kernel(const float* ylog, const int32_t* flags,
   double acc[kMaxSpecies];
   for (int s = 0; s < ns; ++s) acc[s] = 0.0;
   const int64_t p0 = slice * per_slice, p1 = min(P, p0 + per_slice);
+  const double off = calib ? (double)calib[col] : 0.0;
   for (int64_t p = p0; p < p1; ++p) {
     if (flags[p]) continue;
     const int s = species ? species[p] : 0;
     if (s < 0 || s >= ns) continue;
     const double q = charge ? (double)charge[p] : 1.0;
     const double w = weight ? (double)weight[p] : 1.0;
-    acc[s] += w * q * q * exp10((double)ylog[p * (int64_t)nd * nw + col]);
+    acc[s] += w * q * q * exp10((double)ylog[p * (int64_t)nd * nw + col] + off);
   }
   for (int s = 0; s < ns; ++s) partial[(slice * ns + s) * (int64_t)nd * nw + col] = acc[s];
 }
@@ -406,6 +421,8 @@ struct lw_mlp {
   int64_t rows_cap = 0;
   float* act = nullptr;  // z_l, h_l per hidden layer, y, dy, dh, dz, normalised x (rows_cap rows)
   float* norm = nullptr;  // device [2][n_in]: input shift and scale, or null (identity)
+  int skip_index = -1;    // raw input added (times skip_coeff) to every output, or -1
+  float skip_coeff = 0.0f;
   double* loss_part = nullptr;
   float* err_buf = nullptr;
   std::vector<int64_t> w_off, b_off;
@@ -469,13 +486,18 @@ lw_status input_of(lw_mlp* n, const float* x, int64_t rows, const float** in) {
 }
 
 // forward: fills z_l, h_l and y (into `y` if given, else the workspace)
-lw_status forward(lw_mlp* n, const float* x, int64_t rows, float* y) {
+lw_status forward(lw_mlp* n, const float* raw, const float* x, int64_t rows, float* y) {
   hipStream_t s = n->c->stream;
   const float* in = x;
   for (int l = 0; l <= n->n_hidden; ++l) {
     const int din = width(n, l), dout = l < n->n_hidden ? n->hidden : n->n_out;
     float* out = l < n->n_hidden ? z_of(n, l, rows) : y;
     lw::GemmDesc g{in, din, 1, n->p + n->w_off[l], 1, din, out, dout, n->p + n->b_off[l], rows, dout, din};
+    if (l == n->n_hidden && n->skip_index >= 0) {
+      g.row_add = raw + n->skip_index;
+      g.row_stride = n->n_in;
+      g.row_coeff = n->skip_coeff;
+    }
     MLP_HIP(lw::gemm_bf16(g, s), "gemm forward");
     if (l < n->n_hidden) {
       dim3 grid((unsigned)((rows * dout + 255) / 256));
@@ -574,9 +596,9 @@ lw_status lw_features(lw_ctx* c, const lw_batch* b, float* feats) {
   return LW_OK;
 }
 
-lw_status lw_surrogate_accumulate(lw_ctx* c, const lw_batch* b, const float* ylog, const float* err,
-                                  float threshold, int32_t* flags, int64_t* flagged, int64_t* n_flagged,
-                                  void* ws, size_t ws_bytes) {
+lw_status lw_surrogate_accumulate(lw_ctx* c, const lw_batch* b, const float* ylog, const float* calib,
+                                  const float* err, float threshold, int32_t* flags, int64_t* flagged,
+                                  int64_t* n_flagged, void* ws, size_t ws_bytes) {
   if (!c || !b || !ylog || !flags) return LW_EINVAL;
   if (c->nd <= 0 || c->nw <= 0) {
     c->err = "grids not set";
@@ -604,7 +626,7 @@ lw_status lw_surrogate_accumulate(lw_ctx* c, const lw_batch* b, const float* ylo
   hipLaunchKernelGGL(lw::lw_flag_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, err, P, c->nd,
                      threshold, flags);
   hipLaunchKernelGGL(lw::lw_surrogate_sum_kernel, dim3((unsigned)((cols + 255) / 256), (unsigned)slices),
-                     dim3(256), 0, s, ylog, flags, b->species, b->charge, b->weight, P, c->nd, c->nw,
+                     dim3(256), 0, s, ylog, calib, flags, b->species, b->charge, b->weight, P, c->nd, c->nw,
                      c->ns, per_slice, (double*)ws);
   if (lw::launch_reduce_partials((double*)ws, slices, (int64_t)c->ns * cols, c->d_S, s) != hipSuccess ||
       hipGetLastError() != hipSuccess) {
@@ -745,6 +767,13 @@ lw_status lw_mlp_set_input_norm(lw_mlp* n, const float* shift, const float* scal
   return LW_OK;
 }
 
+lw_status lw_mlp_set_output_skip(lw_mlp* n, int32_t input_index, float coeff) {
+  if (!n || input_index < -1 || input_index >= n->n_in) return LW_EINVAL;
+  n->skip_index = input_index;
+  n->skip_coeff = input_index >= 0 ? coeff : 0.0f;
+  return LW_OK;
+}
+
 lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, float* err_head) {
   if (!n || !x || !y || rows < 0) return LW_EINVAL;
   if (err_head && n->n_hidden < 1) return mlp_fail(n, LW_EINVAL, "the error head needs a hidden layer");
@@ -752,7 +781,7 @@ lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, floa
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);
-  if (st == LW_OK) st = forward(n, in, rows, y);
+  if (st == LW_OK) st = forward(n, x, in, rows, y);
   if (st != LW_OK) return st;
   if (err_head) {
     hipLaunchKernelGGL(lw::lw_head_fwd_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
@@ -768,7 +797,7 @@ lw_status lw_mlp_loss_grad(lw_mlp* n, const float* x, const float* t, int64_t ro
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);
-  if (st == LW_OK) st = forward(n, in, rows, y_of(n, rows));
+  if (st == LW_OK) st = forward(n, x, in, rows, y_of(n, rows));
   if (st == LW_OK) st = mse(n, y_of(n, rows), t, dy_of(n, rows), rows * n->n_out, loss);
   if (st == LW_OK) st = backward(n, in, rows);
   if (st == LW_OK && grad_host) {
@@ -792,7 +821,7 @@ lw_status lw_mlp_train_head_step(lw_mlp* n, const float* x, const float* err_tar
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);
-  if (st == LW_OK) st = forward(n, in, rows, y_of(n, rows));
+  if (st == LW_OK) st = forward(n, x, in, rows, y_of(n, rows));
   if (st != LW_OK) return st;
   hipStream_t s = n->c->stream;
   const float* hlast = h_of(n, n->n_hidden - 1, rows);

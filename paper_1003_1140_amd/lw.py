@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 import torch
@@ -27,7 +28,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_profile_read", "lw_plan_batch", "lw_set_tuning", "lw_tune", "lw_graph_capture",
             "lw_graph_launch", "lw_graph_destroy", "lw_accumulate_subset", "lw_features",
             "lw_mlp_create", "lw_mlp_destroy", "lw_mlp_num_params", "lw_mlp_get_params",
-            "lw_mlp_set_params", "lw_mlp_set_input_norm", "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
+            "lw_mlp_set_params", "lw_mlp_set_input_norm", "lw_mlp_set_output_skip",
+            "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
             "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets")
 
 
@@ -90,8 +92,8 @@ def load_library():
             "lw_graph_destroy": (None, [P]),
             "lw_accumulate_subset": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, I64, P, SZ, P]),
             "lw_features": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
-            "lw_surrogate_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, ctypes.c_float, P, P,
-                                                       P, P, SZ]),
+            "lw_surrogate_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, P, ctypes.c_float,
+                                                       P, P, P, P, SZ]),
             "lw_surrogate_targets": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, D, P]),
             "lw_mlp_create": (ctypes.c_int, [P, I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]),
             "lw_mlp_destroy": (None, [P]),
@@ -99,6 +101,7 @@ def load_library():
             "lw_mlp_get_params": (ctypes.c_int, [P, P, I64, P]),
             "lw_mlp_set_params": (ctypes.c_int, [P, P, I64, P]),
             "lw_mlp_set_input_norm": (ctypes.c_int, [P, P, P]),
+            "lw_mlp_set_output_skip": (ctypes.c_int, [P, I32, ctypes.c_float]),
             "lw_mlp_forward": (ctypes.c_int, [P, P, I64, P, P]),
             "lw_mlp_loss_grad": (ctypes.c_int, [P, P, P, I64, P, ctypes.POINTER(D)]),
             "lw_mlp_train_step": (ctypes.c_int, [P, P, P, I64, ctypes.c_float, ctypes.c_float,
@@ -149,6 +152,11 @@ class DeviceBatch:
             t["species"] = torch.from_numpy(np.ascontiguousarray(host.species, dtype=np.int32)).to(dev)
         return cls(t, len(host.offsets) - 1)
 
+    def head(self, n: int) -> "DeviceBatch":
+        """The first n particles (a view sharing the arrays)."""
+        assert 0 <= n <= self.n_particles
+        return DeviceBatch(self.t, n)
+
     @property
     def n_samples(self) -> int:
         o = self.t["offsets"]
@@ -170,6 +178,7 @@ class Context:
         self.nd = self.nw = 0
         self.ns = 1
         self.dirs = None
+        self._children = weakref.WeakSet()  # networks and graphs, destroyed before the context
 
     def _check(self, st):
         if st != LW_OK:
@@ -177,6 +186,8 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
+            for child in list(getattr(self, "_children", ())):
+                child.close()
             self.lib.lw_destroy(self.h)
             self.h = None
 
@@ -308,8 +319,8 @@ class Context:
                                                   workspace.numel(), pp))
         return workspace
 
-    def surrogate_accumulate(self, batch: DeviceBatch, ylog, err, threshold, compact=False):
-        """Add 10^ylog of unflagged particles to S.
+    def surrogate_accumulate(self, batch: DeviceBatch, ylog, err, threshold, compact=False, calib=None):
+        """Add 10^(ylog + calib) of unflagged particles to S (calib: device [nd][nw] or None).
 
         Returns the device flags [n_particles]; with compact=True also the device
         int64 list of flagged particles (increasing) and its device count [1]."""
@@ -322,8 +333,9 @@ class Context:
         if compact:
             idx = torch.empty(max(P, 1), dtype=torch.int64, device=ylog.device)
             cnt = torch.empty(1, dtype=torch.int64, device=ylog.device)
+        cp = ctypes.c_void_p(calib.data_ptr()) if calib is not None else None
         self._check(self.lib.lw_surrogate_accumulate(self.h, ctypes.byref(batch.struct),
-                                                     ctypes.c_void_p(ylog.data_ptr()), ep,
+                                                     ctypes.c_void_p(ylog.data_ptr()), cp, ep,
                                                      float(threshold), ctypes.c_void_p(flags.data_ptr()),
                                                      ctypes.c_void_p(idx.data_ptr()) if compact else None,
                                                      ctypes.c_void_p(cnt.data_ptr()) if compact else None,
@@ -355,6 +367,7 @@ class Graph:
 
     def __init__(self, ctx: Context, handle, workspace, batch):
         self.ctx, self.h, self.workspace, self.batch = ctx, handle, workspace, batch
+        ctx._children.add(self)
 
     def launch(self):
         st = self.ctx.lib.lw_graph_launch(self.h)
@@ -362,9 +375,9 @@ class Graph:
             raise LWError(st, self.ctx.lib.lw_last_error(self.ctx.h).decode())
 
     def close(self):
-        if self.h:
+        if self.h and self.ctx.h:
             self.ctx.lib.lw_graph_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -382,14 +395,15 @@ class MLP:
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.lw_mlp_create(ctx.h, n_in, hidden, n_hidden, n_out, seed, ctypes.byref(h)))
         self.h = h
+        ctx._children.add(self)
         n = ctypes.c_int64()
         ctx._check(ctx.lib.lw_mlp_num_params(h, ctypes.byref(n)))
         self.n_params = n.value
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and self.ctx.h:
             self.ctx.lib.lw_mlp_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -421,6 +435,9 @@ class MLP:
         sc = np.ascontiguousarray(scale, dtype=np.float32)
         assert sh.size == self.shape[0] and sc.size == self.shape[0]
         self.ctx._check(self.ctx.lib.lw_mlp_set_input_norm(self.h, _np_ptr(sh), _np_ptr(sc)))
+
+    def set_output_skip(self, input_index=-1, coeff=0.0):
+        self.ctx._check(self.ctx.lib.lw_mlp_set_output_skip(self.h, int(input_index), float(coeff)))
 
     def forward(self, x, with_error=False):
         rows = x.shape[0]

@@ -12,15 +12,25 @@ the host in FP64 from copies.
 * inputs: the 16 trajectory features, normalised in FP32 inside the network
   (shift and scale from the training set; constant features get scale 0);
 * network: 16 -> 3 x 256 (GELU) -> n_omega on BF16 matrix cores with FP32
-  accumulation, AdamW with a cosine learning-rate schedule; the last layer starts
-  from the per-bin mean and spread of the targets;
+  accumulation, AdamW with a cosine learning-rate schedule.  Feature 11 is the
+  log of the energy radiated towards n, which by Parseval's theorem is the
+  frequency integral of the pair's spectrum; it is added to every output, so
+  the network learns the spectral shape, log10(S / E), while the heavy-tailed
+  amplitude comes from the trajectory exactly.  The last layer starts from the
+  per-bin mean and spread of that shape;
 * calibration split (particles the network never saw): the error head learns
-  each pair's RMS log10 error, the fallback threshold is the quantile that sends
-  a chosen fraction of particles to the exact path, and a per-bin factor removes
-  the bias of 10^<log S> against <S> in the summed spectra;
+  the log10 of each pair's share in the error of the summed spectrum, the mean
+  over bins of |S_pred - S| / <S>_d (with <S>_d the mean per-pair spectrum of
+  the direction on the training set), so that the fallback goes to the pairs
+  that would damage the ensemble most, not to those whose own log error is
+  large; the fallback threshold is the quantile that sends a chosen fraction of
+  particles to the exact path, and a factor per direction and bin, fitted on
+  the particles the threshold keeps on the surrogate, removes the bias of
+  10^<log S> against <S> in their summed spectra (applied by the surrogate sum);
 * inference: unflagged particles add their predicted spectra, flagged ones are
   accumulated exactly; a seeded held-out fraction is also accumulated exactly
-  and by the surrogate alone, on judge contexts, and compared.
+  and by the pipeline (surrogate, or exact where flagged), on judge contexts,
+  and compared.
 """
 from __future__ import annotations
 
@@ -33,6 +43,8 @@ import torch
 from .lw import MLP, Context, DeviceBatch
 
 FLOOR = 1e-30
+ENERGY_FEATURE = 11  # ln(E + 1e-30)
+LOG10E = 1.0 / np.log(10.0)
 
 
 def exact_log_spectra(ctx: Context, batch: DeviceBatch) -> torch.Tensor:
@@ -53,13 +65,14 @@ def _host(t) -> np.ndarray:
 class Surrogate:
     net: MLP             # network with its error head and input normalisation
     threshold: float     # error-head threshold of the exact fallback
+    calib: object = None  # device [nd][nw] log10 correction of the summed predictions
     train_loss: list = field(default_factory=list)
     head_loss: list = field(default_factory=list)
     stats: dict = field(default_factory=dict)
 
 
 def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batch_rows=4096, lr=1e-3,
-          weight_decay=1e-5, fallback_fraction=0.05, head_steps=600, head_lr=3e-3, seed=1,
+          weight_decay=1e-5, fallback_fraction=0.05, head_steps=1000, head_lr=3e-3, seed=1,
           log=None) -> Surrogate:
     """Train the network on `batch` and its error head and calibration on `calib`."""
     dev = torch.device(f"cuda:{ctx.device}")
@@ -69,11 +82,14 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
     torch.cuda.synchronize(dev)
     t_targets = time.perf_counter() - t_start
     xh, yh = _host(x), _host(y)
+    s_mean = (10.0 ** yh).reshape(-1, ctx.nd, ctx.nw).mean(0)  # <S>_d per bin
     mu_x, sd_x = xh.mean(0), xh.std(0)
     scale_x = np.where(sd_x > 1e-6 * (np.abs(mu_x) + 1.0), 1.0 / np.maximum(sd_x, 1e-300), 0.0)
-    mu_y, sd_y = yh.mean(0), np.maximum(yh.std(0), 1e-3)
+    shape_h = yh - LOG10E * xh[:, ENERGY_FEATURE:ENERGY_FEATURE + 1]
+    mu_y, sd_y = shape_h.mean(0), np.maximum(shape_h.std(0), 1e-3)
     net = MLP(ctx, 16, 256, 3, ctx.nw, seed=seed)
     net.set_input_norm(mu_x, scale_x)
+    net.set_output_skip(ENERGY_FEATURE, LOG10E)
     p, head = net.get_params()
     n_out = ctx.nw
     off_last = p.size - (n_out * 256 + n_out)
@@ -100,52 +116,76 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
     pred = net.forward(xc)
     ph, ych = _host(pred), _host(yc)
     rms = np.sqrt(np.mean((ph - ych) ** 2, axis=1))
-    rms_d = torch.from_numpy(rms.astype(np.float32)).to(dev)
+    sm = np.tile(s_mean, (ph.shape[0] // ctx.nd, 1))
+    share = np.log10(np.mean(np.abs(10.0 ** ph - 10.0 ** ych) / sm, axis=1) + FLOOR)
+    share_d = torch.from_numpy(share.astype(np.float32)).to(dev)
+    p, head = net.get_params()
+    head[:] = 0.0
+    head[-1] = share.mean()
+    net.set_params(p, head)
     head_losses = []
     for step in range(head_steps):
         idx = torch.randint(0, xc.shape[0], (min(batch_rows, xc.shape[0]),), device=dev, generator=g)
-        head_losses.append(net.train_head_step(xc[idx].contiguous(), rms_d[idx].contiguous(), lr=head_lr))
-    ratio = (10.0 ** ych).sum(0) / (10.0 ** ph).sum(0)
-    p, head = net.get_params()
-    p = p.astype(np.float64)
-    p[-n_out:] += np.log10(ratio)
-    net.set_params(p.astype(np.float32), head)
+        lr_t = head_lr * 0.5 * (1.0 + np.cos(np.pi * step / head_steps))
+        head_losses.append(net.train_head_step(xc[idx].contiguous(), share_d[idx].contiguous(), lr=float(lr_t)))
     _, err = net.forward(xc, with_error=True)
     per_particle = _host(err).reshape(-1, ctx.nd).max(1)
     thr = float(np.quantile(per_particle, 1.0 - fallback_fraction)) if fallback_fraction > 0 else float("inf")
+    kept = per_particle <= thr
+    sh = (10.0 ** ych).reshape(-1, ctx.nd, ctx.nw)[kept].sum(0)
+    sp = (10.0 ** ph).reshape(-1, ctx.nd, ctx.nw)[kept].sum(0)
+    ratio = np.where(sp > 0, sh / np.where(sp > 0, sp, 1.0), 1.0)
+    ratio = np.where(ratio > 0, ratio, 1.0)
+    calib_d = torch.from_numpy(np.log10(ratio).astype(np.float32).ravel()).to(dev)
     stats = {"train_pairs": int(rows), "calib_pairs": int(xc.shape[0]), "steps": steps,
              "final_train_loss": float(np.mean(losses[-50:])) if losses else None,
              "calib_rms_log10_median": float(np.median(rms)), "calib_rms_log10_p90": float(np.quantile(rms, 0.9)),
              "calib_bias_log10_max": float(np.max(np.abs(np.log10(ratio)))), "threshold": thr,
+             "head_loss_first": head_losses[0] if head_losses else None,
+             "head_loss_last": float(np.mean(head_losses[-50:])) if head_losses else None,
              "seconds_targets": t_targets, "seconds_train": t_train}
-    return Surrogate(net=net, threshold=thr, train_loss=losses, head_loss=head_losses, stats=stats)
+    sur = Surrogate(net=net, threshold=thr, calib=calib_d, train_loss=losses, head_loss=head_losses,
+                    stats=stats)
+    sur.input_shift, sur.input_scale, sur.calib_ratio = mu_x, scale_x, ratio
+    return sur
 
 
 class Judge:
-    """Exact and surrogate-only accumulators of the held-out particles."""
+    """Accumulators of the held-out particles: exact, as the pipeline estimates them
+    (surrogate, exact where flagged), and surrogate alone."""
 
     def __init__(self, ctx: Context):
         om = ctx.get_frequencies()
-        self.exact = Context(ctx.device)
-        self.sur = Context(ctx.device)
-        for c in (self.exact, self.sur):
+        self.exact, self.pipe, self.sur = Context(ctx.device), Context(ctx.device), Context(ctx.device)
+        for c in (self.exact, self.pipe, self.sur):
             c.set_directions(ctx.dirs)
             c.set_frequencies(om)
             c.set_species(ctx.ns)
         self.n = 0
 
-    def add(self, batch: DeviceBatch, ylog, held_idx):
-        """held_idx: device int64 indices (increasing) of the chunk's held-out particles."""
+    def add(self, batch: DeviceBatch, ylog, held_idx, flags, calib=None):
+        """held_idx: device int64 indices (increasing) of the chunk's held-out particles;
+        flags: the pipeline's fallback flags of the chunk."""
         if held_idx.numel() == 0:
             return
+        dev = ylog.device
         self.exact.accumulate_subset(batch, held_idx)
-        mask = torch.ones(batch.n_particles, self.sur.nd, dtype=torch.float32, device=ylog.device)
-        mask[held_idx] = 0.0
-        self.sur.surrogate_accumulate(batch, ylog, mask, 0.5)
+        held = torch.zeros(batch.n_particles, dtype=torch.bool, device=dev)
+        held[held_idx] = True
+        flagged = flags != 0
+        only_held = torch.where(held, 0.0, 1.0).to(torch.float32)[:, None].expand(-1, self.sur.nd).contiguous()
+        self.sur.surrogate_accumulate(batch, ylog, only_held, 0.5, calib=calib)
+        kept_held = torch.where(held & ~flagged, 0.0, 1.0).to(torch.float32)[:, None]
+        self.pipe.surrogate_accumulate(batch, ylog, kept_held.expand(-1, self.pipe.nd).contiguous(), 0.5,
+                                       calib=calib)
+        exact_held = torch.nonzero(held & flagged, as_tuple=False).view(-1)
+        if exact_held.numel():
+            self.pipe.accumulate_subset(batch, exact_held)
         self.n += int(held_idx.numel())
 
     def spectra(self):
-        return self.exact.read_spectra(), self.sur.read_spectra()
+        """(exact, pipeline, surrogate-only) spectra of the held-out particles."""
+        return self.exact.read_spectra(), self.pipe.read_spectra(), self.sur.read_spectra()
 
 
 def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge | None = None, held_idx=None,
@@ -154,12 +194,12 @@ def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge |
     thr = sur.threshold if threshold is None else threshold
     x = ctx.features(batch).view(-1, 16)
     ylog, err = sur.net.forward(x, with_error=True)
-    _, idx, cnt = ctx.surrogate_accumulate(batch, ylog, err, thr, compact=True)
+    flags, idx, cnt = ctx.surrogate_accumulate(batch, ylog, err, thr, compact=True, calib=sur.calib)
     n_flag = int(cnt.item())
     if n_flag:
         ctx.accumulate_subset(batch, idx[:n_flag])
     if judge is not None and held_idx is not None:
-        judge.add(batch, ylog, held_idx)
+        judge.add(batch, ylog, held_idx, flags, calib=sur.calib)
     return {"fallback": n_flag}
 
 

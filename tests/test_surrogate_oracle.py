@@ -67,3 +67,21 @@ def test_features_of_straight_motion():
     f = feat.features(b, [[1.0, 0.0, 0.0]])[0, 0]
     assert f[2] == np.log(feat.EPS) and f[8] == 0.0 and f[6] == 0.0
     assert abs(f[13] - np.log(0.4)) < 1e-12 and f[15] == 1.0  # looking down the velocity
+
+
+def test_energy_feature_is_the_frequency_integral_of_the_spectrum():
+    """exp(feature 11) = int_0^inf S dw (Parseval) for a band-limited orbit, checked
+    against the spectral oracle integrated over a fine linear frequency grid."""
+    b = orbits.gaussian_oscillator(0.05, 1.0, 6.0, 0.5, 1500, 0.06)
+    for th in (0.0, 0.7, 1.9):
+        nvec = np.array([np.sin(th) * np.cos(0.3), np.sin(th) * np.sin(0.3), np.cos(th)])
+        f = feat.features(b, [nvec])[0, 0]
+        om = np.linspace(0.0, 12.0, 2401)
+        S = oracle.spectrum(b, [nvec], om, n_species=1)[0, 0]
+        assert abs(np.exp(f[11]) / np.trapezoid(S, om) - 1) < 1e-6
+
+
+def test_energy_feature_of_straight_motion_is_zero():
+    b = orbits.straight([0.3, 0.4, 0.0], [0, 0, 0], 50, 0.1)
+    f = feat.features(b, [[0.0, 0.0, 1.0], [0.6, 0.8, 0.0]])[0]
+    assert np.all(f[:, 11] == np.log(1e-30))

@@ -15,8 +15,11 @@ Five workloads, all in PIC units (c = m_e = q_e = 1, omega in omega_p):
 * ``uneven``: 4e5 particles, 47.5 % electrons, 47.5 % positrons, 5 % ions
   (mass 16), gamma0 in {2, 5, 15}, lengths uniform in [256, 8192], 64
   equal-area directions, 1024 log frequencies.
-* ``surrogate``: the jitter generator with its own seeds, 256 log frequencies
-  over [0.1, 1e3], training and inference populations.
+* ``surrogate``: the jitter generator with its own seed, 256 log frequencies
+  over [0.1, 1e3].  Training, calibration and inference particles are disjoint
+  id ranges of one ensemble, so they move through the same filament field (one
+  simulation, as for an in-situ diagnostic); ``surrogate_recipe_other_field``
+  draws a second field realisation for the cross-field check.
 """
 from __future__ import annotations
 
@@ -24,8 +27,8 @@ import numpy as np
 
 from . import make_recipe
 
-SEEDS = {"jitter": 11401, "jitter_wide": 11402, "uneven": 11403, "surrogate_train": 11405,
-         "surrogate_infer": 11406}
+SEEDS = {"jitter": 11401, "jitter_wide": 11402, "uneven": 11403, "surrogate": 11405,
+         "surrogate_other_field": 11406}
 DT = 0.005  # sample spacing: a tenth of a Courant-limited PIC step on a 0.1 c/omega_p grid
 
 
@@ -92,9 +95,12 @@ def uneven_recipe(seed=SEEDS["uneven"]):
                        ion_mass=16.0, len_range=(256, 8192))
 
 
-def surrogate_recipe(train=True, steps=4096):
-    return make_recipe(SEEDS["surrogate_train" if train else "surrogate_infer"], steps=steps,
-                       gammas=(3.0,), dt=DT)
+def surrogate_recipe(steps=4096):
+    return make_recipe(SEEDS["surrogate"], steps=steps, gammas=(3.0,), dt=DT)
+
+
+def surrogate_recipe_other_field(steps=4096):
+    return make_recipe(SEEDS["surrogate_other_field"], steps=steps, gammas=(3.0,), dt=DT)
 
 
 WORKLOADS = {
@@ -103,6 +109,7 @@ WORKLOADS = {
     "jitter_wide": dict(n_particles=1_000_000, steps=2048, dirs=dirs_wide, omega=(0.1, 1e3, 2048)),
     "uneven": dict(n_particles=400_000, steps=None, dirs=dirs_equal_area, omega=(0.1, 1e3, 1024),
                    n_species=3),
-    "surrogate": dict(n_train=125_000, n_infer=1_000_000, steps=4096, dirs=dirs_jitter,
-                      omega=(0.1, 1e3, 256)),
+    "surrogate": dict(n_train=125_000, n_calib=25_000, n_infer=1_000_000, infer_first_id=1 << 20,
+                      steps=4096, dirs=dirs_jitter, omega=(0.1, 1e3, 256), held_out=0.01,
+                      fallback=0.05),
 }
