@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
     ap.add_argument("--surrogate-chunk", type=int, default=100_000)
     ap.add_argument("--surrogate-steps", type=int, default=1500)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (scales HBM byte counters)")
     ap.add_argument("--host-generator", action="store_true",
                     help="generate the throughput ensemble on the host (default: on the device)")
     return ap.parse_args()
@@ -267,6 +269,14 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if a.copy_probe_mib > 0:
+        n = a.copy_probe_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {n} bytes read and {n} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     recipe = configs.jitter_recipe()
     dirs = configs.dirs_jitter()
     om = configs.log_grid(0.1, 1e3, 1024)

@@ -101,7 +101,6 @@ struct SpreadArgs {
   float* F;              // chunk F blocks, [d][band][2 n_local][kp]
   unsigned* colmax;      // [nd][nb][2 * n_local] float bits of max |F|
   int32_t* colq;         // [nd][nb][n_local] grid points of each particle
-  int32_t* tilek;        // [nd][nb][n_tiles] max inner length (2 q) of the tile's columns
   int32_t n_ftile;       // column tiles per band
   int32_t ns;            // species count (a species outside [0, ns) is a data error)
   unsigned long long* err;
@@ -124,7 +123,7 @@ struct GemmArgs {
   const float* F;
   const unsigned* colmax;
   const int32_t* colq;
-  const int32_t* tilek;
+  const int32_t* perm;   // [nd][nb][n_local] particles of each (direction, band) by decreasing q
   double* partial;       // [nd][n_ftile][ns][rows]
   int32_t ns, rows;
 };
@@ -365,10 +364,46 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     a.colmax[db * ncol + 2 * pl] = __float_as_uint(m);
     a.colmax[db * ncol + 2 * pl + 1] = __float_as_uint(m);
     a.colq[db * a.n_local + pl] = Q;
-    atomicMax(&a.tilek[db * a.n_ftile + (2 * pl) / kTileN], 2 * Q);
     // rows (2 nj) x columns (2 polarisations) x inner (2 Q) multiply-adds of one product
     if (a.flops) atomicAdd(a.flops, 2ull * (2ull * bd.nj) * 2ull * (2ull * Q));
   }
+}
+
+// ------------------------------------------------------------------ column order
+// One work-group per (direction, band): the chunk's particles ordered by decreasing
+// grid length q (ties by index), so that each contraction tile holds columns of
+// similar inner length and stops where its longest column ends.  Bitonic sort of
+// 64-bit keys in LDS: deterministic.
+constexpr int kMaxChunk = 16384;
+
+__global__ __launch_bounds__(1024) void lw_sort_columns_kernel(const int32_t* colq, int n_local,
+                                                               int32_t* perm) {
+  __shared__ unsigned long long key[kMaxChunk];
+  const int seg = blockIdx.x;
+  const int32_t* q = colq + (size_t)seg * n_local;
+  int n2 = 1;
+  while (n2 < n_local) n2 <<= 1;
+  for (int i = threadIdx.x; i < n2; i += blockDim.x)
+    key[i] = i < n_local ? ((unsigned long long)(0x7fffffffu - (unsigned)q[i]) << 32) | (unsigned)i
+                         : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const unsigned long long x = key[i], y = key[l];
+          if ((x > y) == up) {
+            key[i] = y;
+            key[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < n_local; i += blockDim.x)
+    perm[(size_t)seg * n_local + i] = (int32_t)(key[i] & 0xffffffffull);
 }
 
 // ------------------------------------------------------------------ DFT contraction on MFMA
@@ -394,8 +429,8 @@ struct MfmaOp<__bf16> {
 template <typename T, int NP, int A_VEC, int B_VEC, int NT>
 __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)[A_VEC],
                                                f32x4 (&rb)[B_VEC], const T* E_hi, const T* E_lo,
-                                               const float* Fb, const int* s_q2, int tid, int row0,
-                                               int col0, int ncol, int kp, int k0) {
+                                               const float* Fb, const int* s_q2, const int* s_fcol,
+                                               int tid, int row0, int kp, int k0) {
 #pragma unroll
   for (int v = 0; v < A_VEC; ++v) {
     const int c = tid + v * NT;
@@ -408,11 +443,11 @@ __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)
   for (int v = 0; v < B_VEC; ++v) {
     const int c = tid + v * NT;
     const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
-    const int gc = col0 + col;
+    const int fc = s_fcol[col];
     const int lim = s_q2[col] - (k0 + kc);
     f32x4 x = {0.f, 0.f, 0.f, 0.f};
-    if (gc < ncol && lim > 0) {
-      x = *(const f32x4*)(Fb + (size_t)gc * kp + k0 + kc);
+    if (fc >= 0 && lim > 0) {
+      x = *(const f32x4*)(Fb + (size_t)fc * kp + k0 + kc);
       if (lim < 4) {
         x.w = 0.f;
         if (lim < 3) x.z = 0.f;
@@ -477,6 +512,8 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   __shared__ __attribute__((aligned(16))) T sB[2][NP][kTileN * LD];
   __shared__ float s_scale[kTileN];
   __shared__ int s_q2[kTileN];
+  __shared__ int s_fcol[kTileN];  // F column of each tile column (-1 past the chunk)
+  __shared__ int s_kmax;
   __shared__ float s_colw[kMaxSpecies][kTileN];
   __shared__ double s_rows[NW][64];
 
@@ -506,20 +543,25 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   const T* E_lo = (const T*)a.e_lo + bd.e_off;
   const float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
 
+  if (tid == 0) s_kmax = 0;
+  __syncthreads();
   if (tid < kTileN) {
     const int c = col0 + tid;
     float sc = 1.0f;
-    int q2 = 0;
+    int q2 = 0, fc = -1;
     for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
     if (c < ncol) {
-      const float m = __uint_as_float(a.colmax[db * ncol + c]);
+      const int pl = a.perm[db * a.n_local + c / 2];  // columns in decreasing-length order
+      fc = 2 * pl + (c & 1);
+      const float m = __uint_as_float(a.colmax[db * ncol + fc]);
       if (m > 0.0f) {
         int e;
         frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
         sc = ldexpf(1.0f, -e);
       }
-      q2 = 2 * a.colq[db * a.n_local + c / 2];
-      const int64_t p = a.p_begin + c / 2;
+      q2 = 2 * a.colq[db * a.n_local + pl];
+      atomicMax(&s_kmax, q2);
+      const int64_t p = a.p_begin + pl;
       const int sp = a.b.species ? a.b.species[p] : 0;
       if (sp >= 0 && sp < a.ns) {
         const float qq = a.b.charge[p];
@@ -528,9 +570,10 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
     }
     s_scale[tid] = sc;
     s_q2[tid] = q2;
+    s_fcol[tid] = fc;
   }
-  const int kend = min(((a.tilek[db * a.n_ftile + nt] + kTileK - 1) / kTileK) * kTileK, bd.kp);
   __syncthreads();
+  const int kend = min(((s_kmax + kTileK - 1) / kTileK) * kTileK, bd.kp);
 
   u32x4 ra0[A_VEC], ra1[A_VEC];
   f32x4 rb[B_VEC];
@@ -544,8 +587,8 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 
   const int wr = wave / WN, wc = wave % WN;
   if (kend > 0) {
-    gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0,
-                                            ncol, bd.kp, 0);
+    gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, s_fcol, tid, row0,
+                                            bd.kp, 0);
     gemm_store_step<T, NP, A_VEC, B_VEC, NT, LD>(ra0, ra1, rb, sA[0][0], sA[0][NP - 1], sB[0][0],
                                                  sB[0][NP - 1], s_scale, tid);
   }
@@ -554,8 +597,8 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   for (int k0 = 0; k0 < kend; k0 += kTileK) {
     const bool more = k0 + kTileK < kend;
     if (more)
-      gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, tid, row0, col0,
-                                              ncol, bd.kp, k0 + kTileK);
+      gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, s_fcol, tid, row0,
+                                              bd.kp, k0 + kTileK);
     const T* A0 = sA[buf][0];
     const T* A1 = sA[buf][NP - 1];
     const T* B0 = sB[buf][0];
@@ -642,11 +685,6 @@ __global__ void lw_mfma_reduce_kernel(const double* partial, int n_ftile, int ns
   S[((size_t)s * nd + d) * nw + j] += acc * rowfac[j];
 }
 
-__global__ void lw_fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -693,18 +731,18 @@ lw_status set_err(lw_ctx* c, lw_status st, const char* msg) {
   } while (0)
 
 int chunk_particles(const MfmaPlanCache* pc, int nd, int64_t P) {
-  // particles per chunk bounded so that F (all directions) stays near 2 GiB
+  // particles per chunk bounded so that F (all directions) stays near 6 GiB
   int64_t per = 0;
   for (int b = 0; b < pc->nb; ++b) per += 2 * (int64_t)pc->band[b].kp * sizeof(float);
   per *= nd;
-  int64_t n = per > 0 ? (int64_t)(2LL << 30) / per : 8192;
-  n = std::max<int64_t>(64, std::min<int64_t>(n, 16384));
+  int64_t n = per > 0 ? (int64_t)(6LL << 30) / per : 8192;
+  n = std::max<int64_t>(64, std::min<int64_t>(n, kMaxChunk));
   n = (n / 64) * 64;
   return (int)std::min<int64_t>(n, ((P + 63) / 64) * 64);
 }
 
 struct WsLayout {
-  size_t f, colmax, colq, tilek, partial, total;
+  size_t f, colmax, colq, perm, partial, total;
   int chunk, n_ftile;
   int64_t f_dir;  // floats of F per direction
 };
@@ -726,8 +764,8 @@ WsLayout ws_layout(const lw_ctx* c, const MfmaPlanCache* pc, int64_t P) {
   off += al((size_t)nd * nb * 2 * w.chunk * sizeof(unsigned));
   w.colq = off;
   off += al((size_t)nd * nb * w.chunk * sizeof(int32_t));
-  w.tilek = off;
-  off += al((size_t)nd * nb * w.n_ftile * sizeof(int32_t));
+  w.perm = off;
+  off += al((size_t)nd * nb * w.chunk * sizeof(int32_t));
   w.partial = off;
   off += al((size_t)nd * w.n_ftile * c->ns * pc->rows * sizeof(double));
   w.total = off;
@@ -923,7 +961,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   float* F = (float*)(base + L.f);
   unsigned* colmax = (unsigned*)(base + L.colmax);
   int32_t* colq = (int32_t*)(base + L.colq);
-  int32_t* tilek = (int32_t*)(base + L.tilek);
+  int32_t* perm = (int32_t*)(base + L.perm);
   double* partial = (double*)(base + L.partial);
   const int products = path == LW_PATH_MFMA_BF16 ? pc->products_bf16 : pc->products_f16;
 
@@ -945,8 +983,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   ga.colmax = colmax;
   sa.colq = colq;
   ga.colq = colq;
-  sa.tilek = tilek;
-  ga.tilek = tilek;
+  ga.perm = perm;
   sa.err = c->d_err;
   sa.ns = c->ns;
   sa.flops = c->prof ? c->d_flops : nullptr;
@@ -971,17 +1008,14 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     sa.p_begin = ga.p_begin = p0;
     sa.n_local = ga.n_local = nl;
     sa.n_ftile = ga.n_ftile = nft;
-    {
-      const int64_t n = (int64_t)c->nd * pc->nb * nft;
-      dim3 grid((unsigned)((n + 255) / 256)), block(256);
-      hipLaunchKernelGGL(lw_fill_i32_kernel, grid, block, 0, c->stream, tilek, n, 0);
-      MF_HIP(hipGetLastError(), "launch fill");
-    }
     MF_HIP(prof_begin(c, kProfSpread), "profile");
     hipLaunchKernelGGL(lw_spread_kernel, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)), dim3(kSpreadWin),
                        0, c->stream, sa);
     MF_HIP(hipGetLastError(), "launch spread");
     MF_HIP(prof_end(c), "profile");
+    hipLaunchKernelGGL(lw_sort_columns_kernel, dim3((unsigned)(c->nd * pc->nb)), dim3(1024), 0, c->stream,
+                       colq, nl, perm);
+    MF_HIP(hipGetLastError(), "launch column sort");
     int tiles = 0;
     for (int oi = 0; oi < pc->nb; ++oi) {
       ga.tiles_before[oi] = tiles;
