@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--paths", default="fp32,mfma_f16x1,mfma_bf16x3,mfma_f16x3",
                     help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
     ap.add_argument("--bands", type=int, default=1)
+    ap.add_argument("--tile-rows", type=int, default=0, help="contraction tile rows (128 or 256; 0: default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -290,6 +291,8 @@ def main():
     ctx.set_directions(dirs)
     ctx.set_frequencies(om)
     ctx.set_profiling(True)
+    if a.tile_rows:
+        ctx.set_tuning(tile_rows=a.tile_rows)
     paths = [p for p in a.paths.split(",") if p]
     results, spectra = {}, {}
     for path in paths:

@@ -75,7 +75,7 @@ struct MfmaPlanCache {
   bool valid = false;
   int bands_req = 1;
   int products_f16 = 3, products_bf16 = 3;
-  int tile_rows = 256;   // contraction work-group rows (128 or 256)
+  int tile_rows = 128;   // contraction work-group rows (128 or 256)
   int nb = 0;
   Band band[kMaxBands];
   double span = 0.0;     // span the tables were sized for
@@ -425,7 +425,9 @@ struct MfmaOp<__bf16> {
 };
 
 // Global loads of one inner step into registers (A: 8-element vectors of the phase
-// table; B: float4 of F, zero past each column's length).
+// table; B: float4 of F).  The loads are unconditional (columns past the chunk read
+// column 0) so that nothing waits on them before they are stored; the store step
+// zeroes what lies past each column's length.
 template <typename T, int NP, int A_VEC, int B_VEC, int NT>
 __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)[A_VEC],
                                                f32x4 (&rb)[B_VEC], const T* E_hi, const T* E_lo,
@@ -443,26 +445,18 @@ __device__ __forceinline__ void gemm_load_step(u32x4 (&ra0)[A_VEC], u32x4 (&ra1)
   for (int v = 0; v < B_VEC; ++v) {
     const int c = tid + v * NT;
     const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
-    const int fc = s_fcol[col];
-    const int lim = s_q2[col] - (k0 + kc);
-    f32x4 x = {0.f, 0.f, 0.f, 0.f};
-    if (fc >= 0 && lim > 0) {
-      x = *(const f32x4*)(Fb + (size_t)fc * kp + k0 + kc);
-      if (lim < 4) {
-        x.w = 0.f;
-        if (lim < 3) x.z = 0.f;
-        if (lim < 2) x.y = 0.f;
-      }
-    }
-    rb[v] = x;
+    const int fc = max(s_fcol[col], 0);
+    rb[v] = *(const f32x4*)(Fb + (size_t)fc * kp + k0 + kc);
   }
 }
 
-// Registers -> LDS: A as loaded; B scaled to |F| <= 1 and rounded (hi, and lo = rest).
+// Registers -> LDS: A as loaded; B scaled to |F| <= 1 and rounded (hi, and lo = rest),
+// zero past each column's length.
 template <typename T, int NP, int A_VEC, int B_VEC, int NT, int LD>
 __device__ __forceinline__ void gemm_store_step(const u32x4 (&ra0)[A_VEC], const u32x4 (&ra1)[A_VEC],
                                                 const f32x4 (&rb)[B_VEC], T* sA0, T* sA1, T* sB0,
-                                                T* sB1, const float* s_scale, int tid) {
+                                                T* sB1, const float* s_scale, const int* s_q2,
+                                                const int* s_fcol, int tid, int k0) {
 #pragma unroll
   for (int v = 0; v < A_VEC; ++v) {
     const int c = tid + v * NT;
@@ -474,8 +468,10 @@ __device__ __forceinline__ void gemm_store_step(const u32x4 (&ra0)[A_VEC], const
   for (int v = 0; v < B_VEC; ++v) {
     const int c = tid + v * NT;
     const int col = c / (kTileK / 4), kc = (c % (kTileK / 4)) * 4;
+    const int lim = s_fcol[col] >= 0 ? s_q2[col] - (k0 + kc) : 0;  // valid elements of the float4
     const float sc = s_scale[col];
-    const float x0 = rb[v].x * sc, x1 = rb[v].y * sc, x2 = rb[v].z * sc, x3 = rb[v].w * sc;
+    const float x0 = lim > 0 ? rb[v].x * sc : 0.f, x1 = lim > 1 ? rb[v].y * sc : 0.f;
+    const float x2 = lim > 2 ? rb[v].z * sc : 0.f, x3 = lim > 3 ? rb[v].w * sc : 0.f;
     typedef T t4 __attribute__((ext_vector_type(4)));
     const t4 hv = {(T)x0, (T)x1, (T)x2, (T)x3};
     *(t4*)&sB0[col * LD + kc] = hv;
@@ -590,7 +586,7 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
     gemm_load_step<T, NP, A_VEC, B_VEC, NT>(ra0, ra1, rb, E_hi, E_lo, Fb, s_q2, s_fcol, tid, row0,
                                             bd.kp, 0);
     gemm_store_step<T, NP, A_VEC, B_VEC, NT, LD>(ra0, ra1, rb, sA[0][0], sA[0][NP - 1], sB[0][0],
-                                                 sB[0][NP - 1], s_scale, tid);
+                                                 sB[0][NP - 1], s_scale, s_q2, s_fcol, tid, 0);
   }
   __syncthreads();
   int buf = 0;
@@ -619,20 +615,26 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
         fb[0][j] = *(const vec*)&B0[cc * LD + kk];
         if (NP > 1) fb[NP - 1][j] = *(const vec*)&B1[cc * LD + kk];
       }
+      // products outermost: consecutive MFMAs write different accumulators
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
-          if (PRODUCTS > 1) {
-            acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
-            acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
-          }
-        }
+        for (int j = 0; j < NB; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
+      if (PRODUCTS > 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
+      }
     }
     if (more)
       gemm_store_step<T, NP, A_VEC, B_VEC, NT, LD>(ra0, ra1, rb, sA[buf ^ 1][0], sA[buf ^ 1][NP - 1],
-                                                   sB[buf ^ 1][0], sB[buf ^ 1][NP - 1], s_scale, tid);
+                                                   sB[buf ^ 1][0], sB[buf ^ 1][NP - 1], s_scale, s_q2,
+                                                   s_fcol, tid, k0 + kTileK);
     __syncthreads();
     buf ^= 1;
   }
@@ -662,6 +664,228 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][rr];
+      a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ 128 x 128 variant
+// Four waves (2 x 2, each 64 x 64 as 2 x 2 MFMA blocks) per work-group, so that two
+// work-groups share a CU and one computes while the other waits on memory.  LDS rows
+// hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored at
+// slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over
+// 64 four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen
+// distinct 16-byte slots modulo 256 bytes: the fragment reads (sixteen consecutive rows,
+// one chunk) and the staging writes (four rows, four chunks) both do.
+__device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
+
+template <typename T, int PRODUCTS>
+__global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
+  typedef typename MfmaOp<T>::vec vec;
+  constexpr int NT = 256, TM = 128, TN = 128, NP = PRODUCTS > 1 ? 2 : 1;
+  static_assert(kTileK == 32, "four 16-byte chunks per LDS row");
+  __shared__ __attribute__((aligned(16))) T sA[2][NP][TM * 32];
+  __shared__ __attribute__((aligned(16))) T sB[2][NP][TN * 32];
+  __shared__ float s_scale[TN];
+  __shared__ int s_q2[TN];
+  __shared__ int s_fcol[TN];
+  __shared__ float s_colw[kMaxSpecies][TN];
+  __shared__ double s_rows[4][64];
+  __shared__ int s_kmax;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int oi = 0;
+  while (oi + 1 < a.nb && (int)blockIdx.x >= a.tiles_before[oi + 1]) ++oi;
+  const int bi = a.order[oi];
+  const Band bd = a.band[bi];
+  const int local = blockIdx.x - a.tiles_before[oi];
+  const int mtiles = bd.m / TM;
+  const int ngroups = a.nd * a.n_ftile;
+  const int xcd = local % 8, seq = local / 8;
+  const int grp = (seq / mtiles) * 8 + xcd;
+  if (grp >= ngroups) return;
+  const int mt = seq % mtiles;
+  const int nt = grp % a.n_ftile;
+  const int d = grp / a.n_ftile;
+  const int ncol = 2 * a.n_local;
+  const int db = d * a.nb + bi;
+  const int col0 = nt * TN;
+  const int row0 = mt * TM;
+  const T* E_hi = (const T*)a.e_hi + bd.e_off;
+  const T* E_lo = (const T*)a.e_lo + bd.e_off;
+  const float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
+
+  if (tid == 0) s_kmax = 0;
+  __syncthreads();
+  if (tid < TN) {
+    const int c = col0 + tid;
+    float sc = 1.0f;
+    int q2 = 0, fc = -1;
+    for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
+    if (c < ncol) {
+      const int pl = a.perm[db * a.n_local + c / 2];
+      fc = 2 * pl + (c & 1);
+      const float m = __uint_as_float(a.colmax[db * ncol + fc]);
+      if (m > 0.0f) {
+        int e;
+        frexpf(m, &e);
+        sc = ldexpf(1.0f, -e);
+      }
+      q2 = 2 * a.colq[db * a.n_local + pl];
+      atomicMax(&s_kmax, q2);
+      const int64_t p = a.p_begin + pl;
+      const int sp = a.b.species ? a.b.species[p] : 0;
+      if (sp >= 0 && sp < a.ns) {
+        const float qq = a.b.charge[p];
+        s_colw[sp][tid] = a.b.weight[p] * qq * qq / (sc * sc);
+      }
+    }
+    s_scale[tid] = sc;
+    s_q2[tid] = q2;
+    s_fcol[tid] = fc;
+  }
+  __syncthreads();
+  const int kend = min(((s_kmax + kTileK - 1) / kTileK) * kTileK, bd.kp);
+
+  // staging: thread t moves chunk t % 4 of rows (columns) t / 4 and t / 4 + 64.  Two
+  // register sets keep two stages in flight, so a stage's global loads have two
+  // compute phases to arrive before they are written to LDS.
+  const int sr = tid >> 2, sc4 = tid & 3;
+  typedef u32x4 RegA[2][NP];
+  typedef f32x4 RegB[2][2];
+  // the thread's two columns: F offset (column 0 stands in past the chunk, masked at
+  // store time), length and scale stay fixed over the inner loop
+  size_t fofs[2];
+  int q2v[2];
+  float sclv[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int col = sr + 64 * v;
+    fofs[v] = (size_t)max(s_fcol[col], 0) * bd.kp + sc4 * 8;
+    q2v[v] = s_fcol[col] >= 0 ? s_q2[col] : 0;
+    sclv[v] = s_scale[col];
+  }
+  auto load = [&](RegA& ra, RegB& rb, int k0) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const size_t g = (size_t)(row0 + sr + 64 * v) * bd.kp + k0 + sc4 * 8;
+      ra[v][0] = *(const u32x4*)(E_hi + g);
+      if (NP > 1) ra[v][NP - 1] = *(const u32x4*)(E_lo + g);
+      const float* src = Fb + fofs[v] + k0;
+      rb[v][0] = *(const f32x4*)src;
+      rb[v][1] = *(const f32x4*)(src + 4);
+    }
+  };
+  auto store = [&](const RegA& ra, const RegB& rb, int buf, int k0) {
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int r = sr + 64 * v;
+      *(u32x4*)&sA[buf][0][swz(r, sc4)] = ra[v][0];
+      if (NP > 1) *(u32x4*)&sA[buf][NP - 1][swz(r, sc4)] = ra[v][NP - 1];
+      const float scl = sclv[v];
+      const int lim = q2v[v] - (k0 + sc4 * 8);  // valid elements of these eight
+      typedef T t8 __attribute__((ext_vector_type(8)));
+      t8 hv, lv;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float x = e < lim ? (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl : 0.0f;
+        hv[e] = (T)x;
+        if (NP > 1) lv[e] = (T)(x - (float)hv[e]);
+      }
+      *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
+      if (NP > 1) *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = lv;
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  const int wr = wave >> 1, wc = wave & 1;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int ch = 2 * ks + (lane >> 5);
+      vec fa[NP][2], fb[NP][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wr * 64 + i * 32 + (lane & 31);
+        fa[0][i] = *(const vec*)&sA[buf][0][swz(r, ch)];
+        if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[buf][NP - 1][swz(r, ch)];
+        const int cc = wc * 64 + i * 32 + (lane & 31);
+        fb[0][i] = *(const vec*)&sB[buf][0][swz(cc, ch)];
+        if (NP > 1) fb[NP - 1][i] = *(const vec*)&sB[buf][NP - 1][swz(cc, ch)];
+      }
+      // products outermost: consecutive MFMAs write different accumulators
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
+      if (PRODUCTS > 1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
+      }
+    }
+  };
+
+  // stage s of the inner dimension covers [32 s, 32 s + 32); LDS buffer s % 2
+  const int nst = kend / kTileK;
+  const int last = max(nst - 1, 0) * kTileK;
+  RegA ra0, ra1;
+  RegB rb0, rb1;
+  if (nst > 0) {
+    load(ra0, rb0, 0);
+    load(ra1, rb1, min(kTileK, last));
+    store(ra0, rb0, 0, 0);
+  }
+  __syncthreads();
+  // Loads and stores run unconditionally (stages past the end re-read the last one and
+  // fill a buffer nobody reads), so the loop body has no branches around memory
+  // operations and the wait counters stay exact: a stage's loads are waited for only
+  // when that stage is stored, two compute phases later.
+  for (int st = 0; st < nst; st += 2) {
+    // buffer 0 holds stage st, register set 1 stage st + 1
+    load(ra0, rb0, min((st + 2) * kTileK, last));
+    compute(0);
+    store(ra1, rb1, 1, (st + 1) * kTileK);
+    __syncthreads();
+    if (st + 1 >= nst) break;
+    load(ra1, rb1, min((st + 3) * kTileK, last));
+    compute(1);
+    store(ra0, rb0, 0, (st + 2) * kTileK);
+    __syncthreads();
+  }
+
+  for (int s = 0; s < a.ns; ++s) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int cc = wc * 64 + j * 32 + (lane & 31);
+          const float c = acc[i][j][r];
+          v = fmaf(c * c, s_colw[s][cc], v);
+        }
+        for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((lane & 31) == 0) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
+      }
+    __syncthreads();
+    if (tid < TM) {
+      const int g = tid / 64, rr = tid % 64;
+      const double v = s_rows[g * 2][rr] + s_rows[g * 2 + 1][rr];
       a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
     }
   }
@@ -1025,11 +1249,14 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     ga.tiles_before[pc->nb] = tiles;
     MF_HIP(prof_begin(c, kProfGemm), "profile");
 #define LW_GEMM(T, P, W) hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, W>), dim3(tiles), dim3(512), 0, c->stream, ga)
-    if (!bf && products == 1) { if (tall) LW_GEMM(_Float16, 1, 4); else LW_GEMM(_Float16, 1, 2); }
-    else if (!bf) { if (tall) LW_GEMM(_Float16, 3, 4); else LW_GEMM(_Float16, 3, 2); }
-    else if (products == 1) { if (tall) LW_GEMM(__bf16, 1, 4); else LW_GEMM(__bf16, 1, 2); }
-    else { if (tall) LW_GEMM(__bf16, 3, 4); else LW_GEMM(__bf16, 3, 2); }
+#define LW_GEMM128(T, P) \
+  hipLaunchKernelGGL((lw_dft_mfma_t128_kernel<T, P>), dim3(tiles), dim3(256), 0, c->stream, ga)
+    if (!bf && products == 1) { if (tall) LW_GEMM(_Float16, 1, 4); else LW_GEMM128(_Float16, 1); }
+    else if (!bf) { if (tall) LW_GEMM(_Float16, 3, 4); else LW_GEMM128(_Float16, 3); }
+    else if (products == 1) { if (tall) LW_GEMM(__bf16, 1, 4); else LW_GEMM128(__bf16, 1); }
+    else { if (tall) LW_GEMM(__bf16, 3, 4); else LW_GEMM128(__bf16, 3); }
 #undef LW_GEMM
+#undef LW_GEMM128
     MF_HIP(hipGetLastError(), "launch dft_mfma");
     MF_HIP(prof_end(c), "profile");
     {
