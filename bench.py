@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--paths", default="fp32,mfma_f16x1,mfma_bf16x3,mfma_f16x3",
                     help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
     ap.add_argument("--bands", type=int, default=1)
-    ap.add_argument("--tile-rows", type=int, default=0, help="contraction tile rows (128 or 256; 0: default)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256 (0: library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,7 +95,13 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
     return worst
 
 
-def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands):
+TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4> (128 x 256 tiles)",
+                1: "lw_dft_mfma_r128_kernel<WN=2> (128 x 128 tiles)",
+                2: "lw_dft_mfma_kernel (256 x 128 tiles)",
+                3: "lw_dft_mfma_r128_kernel<WN=4> (128 x 256 tiles)"}
+
+
+def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
     import torch
 
     path, products = split_path(name)
@@ -127,7 +134,7 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands):
         ach = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
         peak = PEAK_MFMA_TFLOPS
         res["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                           "frac": ach / peak, "traffic": None, "kernel": "lw_dft_mfma_kernel",
+                           "frac": ach / peak, "traffic": None, "kernel": TILE_KERNELS[tile],
                            "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
                            "launches_per_step": prof["gemm_launches"] / steps}
     return res, S
@@ -291,13 +298,13 @@ def main():
     ctx.set_directions(dirs)
     ctx.set_frequencies(om)
     ctx.set_profiling(True)
-    if a.tile_rows:
-        ctx.set_tuning(tile_rows=a.tile_rows)
+    if a.tile:
+        ctx.set_tuning(tile=a.tile)
     paths = [p for p in a.paths.split(",") if p]
     results, spectra = {}, {}
     for path in paths:
         results[path], spectra[path] = time_path(ctx, batch, path, a.steps, a.warmup, terms_per_step,
-                                                 a.bands)
+                                                 a.bands, a.tile)
         print(f"[bench] {path}: {results[path]['terms_per_s']:.3e} terms/s", file=sys.stderr, flush=True)
     if "fp32" in spectra:
         for path in paths:

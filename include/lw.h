@@ -155,10 +155,12 @@ lw_status lw_plan_batch(lw_ctx* ctx, const lw_batch* batch, lw_path path);
 
 /* Launch shape: wpt = frequencies per thread of the FP32 kernel (0 automatic,
  * 1, 2, 4, 8); pb = particles per work item (0 automatic); persistent = use a
- * matching lw_plan_batch plan (1) or always the plain grid (0); bands and
- * tile_rows (128 or 256) for the matrix-core contraction (0 = unchanged). */
+ * matching lw_plan_batch plan (1) or always the plain grid (0); bands and the
+ * contraction tile (rows x columns per work-group: LW_TILE_128x128,
+ * LW_TILE_256x128, LW_TILE_128x256) for the matrix-core path; 0 = unchanged. */
+enum { LW_TILE_128x128 = 1, LW_TILE_256x128 = 2, LW_TILE_128x256 = 3 };
 lw_status lw_set_tuning(lw_ctx* ctx, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
-                        int32_t tile_rows);
+                        int32_t tile);
 
 /* Autotuner: time the candidate launch shapes of `path` on `batch` (repeats
  * timed runs each, HIP events on the context's stream), keep the fastest (as

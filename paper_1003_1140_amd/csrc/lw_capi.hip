@@ -561,19 +561,19 @@ lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indi
 }
 
 lw_status lw_set_tuning(lw_ctx* c, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
-                        int32_t tile_rows) {
+                        int32_t tile) {
   if (!c) return LW_EINVAL;
   if (wpt != 0 && wpt != 1 && wpt != 2 && wpt != 4 && wpt != 8)
     return fail(c, LW_EINVAL, "frequencies per thread must be 0 (automatic), 1, 2, 4 or 8");
   if (pb < 0 || pb > 4096) return fail(c, LW_EINVAL, "particles per item must be in [0, 4096]");
-  if (tile_rows != 0 && tile_rows != 128 && tile_rows != 256)
-    return fail(c, LW_EINVAL, "tile rows must be 0 (keep), 128 or 256");
+  if (tile < 0 || tile > 3)
+    return fail(c, LW_EINVAL, "contraction tile must be 0 (keep), 1 (128x128), 2 (256x128) or 3 (128x256)");
   c->tune_wpt = wpt;
   c->tune_pb = pb;
   c->tune_persistent = persistent ? 1 : 0;
   lw_status st = LW_OK;
   if (bands > 0) st = lw::mfma_set_bands(c, bands);
-  if (st == LW_OK && tile_rows > 0) st = lw::mfma_set_tile_rows(c, tile_rows);
+  if (st == LW_OK && tile > 0) st = lw::mfma_set_tile(c, tile);
   return st;
 }
 

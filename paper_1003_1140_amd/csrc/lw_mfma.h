@@ -9,7 +9,7 @@ void mfma_cache_destroy(MfmaPlanCache* c);
 void mfma_cache_invalidate(MfmaPlanCache* c);
 lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16);
 lw_status mfma_set_bands(lw_ctx* c, int bands);
-lw_status mfma_set_tile_rows(lw_ctx* c, int rows);
+lw_status mfma_set_tile(lw_ctx* c, int tile);
 lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);
 lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
                           float* per_particle);

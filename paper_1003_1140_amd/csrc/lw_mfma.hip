@@ -75,7 +75,7 @@ struct MfmaPlanCache {
   bool valid = false;
   int bands_req = 1;
   int products_f16 = 3, products_bf16 = 3;
-  int tile_rows = 128;   // contraction work-group rows (128 or 256)
+  int tile = 3;          // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256
   int nb = 0;
   Band band[kMaxBands];
   double span = 0.0;     // span the tables were sized for
@@ -669,9 +669,11 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   }
 }
 
-// ------------------------------------------------------------------ 128 x 128 variant
-// Four waves (2 x 2, each 64 x 64 as 2 x 2 MFMA blocks) per work-group, so that two
-// work-groups share a CU and one computes while the other waits on memory.  LDS rows
+// ------------------------------------------------------------------ 128-row variants
+// 128 x (64 WN) tiles: 2 x WN waves, each 64 x 64 as 2 x 2 MFMA blocks.  WN = 2 gives
+// 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4 gives 128 x 256
+// tiles of eight waves, which halve the phase-table bytes per product: the table
+// tiles are re-read by every column group, so they set the memory traffic.  LDS rows
 // hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored at
 // slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over
 // 64 four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen
@@ -679,18 +681,21 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 // one chunk) and the staging writes (four rows, four chunks) both do.
 __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
 
-template <typename T, int PRODUCTS>
-__global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
+template <typename T, int PRODUCTS, int WN>
+__global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
-  constexpr int NT = 256, TM = 128, TN = 128, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int NT = 128 * WN, NW = 2 * WN, TM = 128, TN = 64 * WN, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int AV = TM * 4 / NT;  // 16-byte table chunks per thread and stage
+  constexpr int BV = TN * 4 / NT;  // 8-float F chunks per thread and stage
   static_assert(kTileK == 32, "four 16-byte chunks per LDS row");
+  static_assert(AV >= 1 && BV >= 1, "staging layout");
   __shared__ __attribute__((aligned(16))) T sA[2][NP][TM * 32];
   __shared__ __attribute__((aligned(16))) T sB[2][NP][TN * 32];
   __shared__ float s_scale[TN];
   __shared__ int s_q2[TN];
   __shared__ int s_fcol[TN];
   __shared__ float s_colw[kMaxSpecies][TN];
-  __shared__ double s_rows[4][64];
+  __shared__ double s_rows[NW][64];
   __shared__ int s_kmax;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -747,30 +752,33 @@ __global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
   __syncthreads();
   const int kend = min(((s_kmax + kTileK - 1) / kTileK) * kTileK, bd.kp);
 
-  // staging: thread t moves chunk t % 4 of rows (columns) t / 4 and t / 4 + 64.  Two
+  // staging: thread t moves chunk t % 4 of rows (columns) t / 4 + (NT / 4) v.  Two
   // register sets keep two stages in flight, so a stage's global loads have two
   // compute phases to arrive before they are written to LDS.
   const int sr = tid >> 2, sc4 = tid & 3;
-  typedef u32x4 RegA[2][NP];
-  typedef f32x4 RegB[2][2];
+  typedef u32x4 RegA[AV][NP];
+  typedef f32x4 RegB[BV][2];
   // the thread's two columns: F offset (column 0 stands in past the chunk, masked at
   // store time), length and scale stay fixed over the inner loop
-  size_t fofs[2];
-  int q2v[2];
-  float sclv[2];
+  size_t fofs[BV];
+  int q2v[BV];
+  float sclv[BV];
 #pragma unroll
-  for (int v = 0; v < 2; ++v) {
-    const int col = sr + 64 * v;
+  for (int v = 0; v < BV; ++v) {
+    const int col = sr + (NT / 4) * v;
     fofs[v] = (size_t)max(s_fcol[col], 0) * bd.kp + sc4 * 8;
     q2v[v] = s_fcol[col] >= 0 ? s_q2[col] : 0;
     sclv[v] = s_scale[col];
   }
   auto load = [&](RegA& ra, RegB& rb, int k0) {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const size_t g = (size_t)(row0 + sr + 64 * v) * bd.kp + k0 + sc4 * 8;
+    for (int v = 0; v < AV; ++v) {
+      const size_t g = (size_t)(row0 + sr + (NT / 4) * v) * bd.kp + k0 + sc4 * 8;
       ra[v][0] = *(const u32x4*)(E_hi + g);
       if (NP > 1) ra[v][NP - 1] = *(const u32x4*)(E_lo + g);
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
       const float* src = Fb + fofs[v] + k0;
       rb[v][0] = *(const f32x4*)src;
       rb[v][1] = *(const f32x4*)(src + 4);
@@ -778,10 +786,14 @@ __global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
   };
   auto store = [&](const RegA& ra, const RegB& rb, int buf, int k0) {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int r = sr + 64 * v;
+    for (int v = 0; v < AV; ++v) {
+      const int r = sr + (NT / 4) * v;
       *(u32x4*)&sA[buf][0][swz(r, sc4)] = ra[v][0];
       if (NP > 1) *(u32x4*)&sA[buf][NP - 1][swz(r, sc4)] = ra[v][NP - 1];
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int r = sr + (NT / 4) * v;
       const float scl = sclv[v];
       const int lim = q2v[v] - (k0 + sc4 * 8);  // valid elements of these eight
       typedef T t8 __attribute__((ext_vector_type(8)));
@@ -805,7 +817,7 @@ __global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WN, wc = wave % WN;
   auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
@@ -885,7 +897,9 @@ __global__ __launch_bounds__(256, 2) void lw_dft_mfma_t128_kernel(GemmArgs a) {
     __syncthreads();
     if (tid < TM) {
       const int g = tid / 64, rr = tid % 64;
-      const double v = s_rows[g * 2][rr] + s_rows[g * 2 + 1][rr];
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][rr];
       a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
     }
   }
@@ -1154,9 +1168,9 @@ lw_status mfma_set_bands(lw_ctx* c, int bands) {
   return mfma_set_options(c, bands, pc->products_f16, pc->products_bf16);
 }
 
-lw_status mfma_set_tile_rows(lw_ctx* c, int rows) {
-  if (rows != 128 && rows != 256) return set_err(c, LW_EINVAL, "tile rows must be 128 or 256");
-  c->mfma->tile_rows = rows;
+lw_status mfma_set_tile(lw_ctx* c, int tile) {
+  if (tile < 1 || tile > 3) return set_err(c, LW_EINVAL, "tile shape must be 1, 2 or 3");
+  c->mfma->tile = tile;
   return LW_OK;
 }
 
@@ -1221,14 +1235,16 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   for (int i = 0; i < pc->nb; ++i) ga.order[i] = i;
   std::sort(ga.order, ga.order + pc->nb,
             [&](int x, int y) { return pc->band[x].qmax * pc->band[x].m > pc->band[y].qmax * pc->band[y].m; });
-  bool tall = pc->tile_rows == 256;  // 256-row tiles need every band's rows to be a multiple of 256
-  for (int i = 0; i < pc->nb; ++i) tall = tall && (pc->band[i].m % 256 == 0);
-  const int tm = tall ? 256 : 128;
+  int tile = pc->tile;  // 256-row tiles need every band's rows to be a multiple of 256
+  for (int i = 0; i < pc->nb; ++i)
+    if (tile == 2 && pc->band[i].m % 256 != 0) tile = 1;
+  const int tm = tile == 2 ? 256 : 128;
+  const int tn = tile == 3 ? 256 : 128;
   const bool bf = path == LW_PATH_MFMA_BF16;
 
   for (int64_t p0 = 0; p0 < b->n_particles; p0 += L.chunk) {
     const int nl = (int)std::min<int64_t>(L.chunk, b->n_particles - p0);
-    const int nft = (2 * nl + kTileN - 1) / kTileN;
+    const int nft = (2 * nl + tn - 1) / tn;
     sa.p_begin = ga.p_begin = p0;
     sa.n_local = ga.n_local = nl;
     sa.n_ftile = ga.n_ftile = nft;
@@ -1248,15 +1264,20 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     }
     ga.tiles_before[pc->nb] = tiles;
     MF_HIP(prof_begin(c, kProfGemm), "profile");
-#define LW_GEMM(T, P, W) hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, W>), dim3(tiles), dim3(512), 0, c->stream, ga)
-#define LW_GEMM128(T, P) \
-  hipLaunchKernelGGL((lw_dft_mfma_t128_kernel<T, P>), dim3(tiles), dim3(256), 0, c->stream, ga)
-    if (!bf && products == 1) { if (tall) LW_GEMM(_Float16, 1, 4); else LW_GEMM128(_Float16, 1); }
-    else if (!bf) { if (tall) LW_GEMM(_Float16, 3, 4); else LW_GEMM128(_Float16, 3); }
-    else if (products == 1) { if (tall) LW_GEMM(__bf16, 1, 4); else LW_GEMM128(__bf16, 1); }
-    else { if (tall) LW_GEMM(__bf16, 3, 4); else LW_GEMM128(__bf16, 3); }
+#define LW_GEMM(T, P)                                                                            \
+  do {                                                                                           \
+    if (tile == 2)                                                                               \
+      hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+    else if (tile == 3)                                                                          \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+    else                                                                                         \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
+  } while (0)
+    if (!bf && products == 1) LW_GEMM(_Float16, 1);
+    else if (!bf) LW_GEMM(_Float16, 3);
+    else if (products == 1) LW_GEMM(__bf16, 1);
+    else LW_GEMM(__bf16, 3);
 #undef LW_GEMM
-#undef LW_GEMM128
     MF_HIP(hipGetLastError(), "launch dft_mfma");
     MF_HIP(prof_end(c), "profile");
     {

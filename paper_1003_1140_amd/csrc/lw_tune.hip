@@ -24,16 +24,16 @@
 namespace {
 
 struct Candidate {
-  int wpt, pb, persistent, bands, tile_rows;
+  int wpt, pb, persistent, bands, tile;
   double ms;
 };
 
 std::string to_json(const Candidate& c) {
   char buf[256];
   snprintf(buf, sizeof(buf),
-           "{\"wpt\": %d, \"pb\": %d, \"persistent\": %d, \"bands\": %d, \"tile_rows\": %d, "
+           "{\"wpt\": %d, \"pb\": %d, \"persistent\": %d, \"bands\": %d, \"tile\": %d, "
            "\"ms\": %.4f}",
-           c.wpt, c.pb, c.persistent, c.bands, c.tile_rows, c.ms);
+           c.wpt, c.pb, c.persistent, c.bands, c.tile, c.ms);
   return buf;
 }
 
@@ -88,7 +88,7 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
                 cands.end());
   } else {
     for (int bands : {1, 2})
-      for (int rows : {128, 256}) cands.push_back({0, 0, 1, bands, rows, 0.0});
+      for (int tile : {1, 2, 3}) cands.push_back({0, 0, 1, bands, tile, 0.0});
   }
 
   hipEvent_t e0, e1;
@@ -102,7 +102,7 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
     if (fp32)
       st = lw_set_tuning(c, cd.wpt, cd.pb, cd.persistent, 0, 0);
     else
-      st = lw_set_tuning(c, c->tune_wpt, c->tune_pb, c->tune_persistent, cd.bands, cd.tile_rows);
+      st = lw_set_tuning(c, c->tune_wpt, c->tune_pb, c->tune_persistent, cd.bands, cd.tile);
     if (st != LW_OK) break;
     if (fp32 && cd.persistent) {
       st = lw_plan_batch(c, b, path);
@@ -150,7 +150,7 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
       st = lw_set_tuning(c, best->wpt, best->pb, best->persistent, 0, 0);
       if (st == LW_OK && best->persistent) st = lw_plan_batch(c, b, path);
     } else {
-      st = lw_set_tuning(c, c->tune_wpt, c->tune_pb, c->tune_persistent, best->bands, best->tile_rows);
+      st = lw_set_tuning(c, c->tune_wpt, c->tune_pb, c->tune_persistent, best->bands, best->tile);
     }
   }
   std::string js = std::string("{\"path\": ") + std::to_string((int)path) + ", \"best\": " +

@@ -274,8 +274,9 @@ class Context:
     def plan_batch(self, batch: DeviceBatch, path="fp32"):
         self._check(self.lib.lw_plan_batch(self.h, ctypes.byref(batch.struct), PATHS.get(path, path)))
 
-    def set_tuning(self, wpt=0, pb=0, persistent=1, bands=0, tile_rows=0):
-        self._check(self.lib.lw_set_tuning(self.h, wpt, pb, persistent, bands, tile_rows))
+    def set_tuning(self, wpt=0, pb=0, persistent=1, bands=0, tile=0):
+        """tile: 0 keep, 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256 contraction tiles."""
+        self._check(self.lib.lw_set_tuning(self.h, wpt, pb, persistent, bands, tile))
 
     def tune(self, batch: DeviceBatch, path="fp32", repeats=2, cache_json=None) -> dict:
         import json
@@ -291,7 +292,7 @@ class Context:
 
         with open(cache_json) as f:
             best = json.load(f)["best"]
-        self.set_tuning(best["wpt"], best["pb"], best["persistent"], best["bands"], best["tile_rows"])
+        self.set_tuning(best["wpt"], best["pb"], best["persistent"], best["bands"], best["tile"])
 
     def graph_capture(self, batch: DeviceBatch, path="fp32", workspace=None) -> "Graph":
         if workspace is None:

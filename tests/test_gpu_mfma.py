@@ -20,13 +20,13 @@ from _parity import all_bins_relative_error, band_integrated_errors, band_relati
 pytestmark = pytest.mark.gpu
 
 
-def run(b, dirs, om, path, bands=1, products_f16=3, products_bf16=3, n_species=1, tile_rows=0):
+def run(b, dirs, om, path, bands=1, products_f16=3, products_bf16=3, n_species=1, tile=0):
     from paper_1003_1140_amd import Context
 
     c = Context(0)
     c.set_mfma_options(bands, products_f16, products_bf16)
-    if tile_rows:
-        c.set_tuning(tile_rows=tile_rows)
+    if tile:
+        c.set_tuning(tile=tile)
     return gpu_spectrum(b, dirs, om, path=path, n_species=n_species, ctx=c)
 
 
@@ -80,17 +80,17 @@ def test_bf16_three_products_wide(wide):
     assert report("mfma bf16 x3, wide 6 particles", S, ref, om).max() <= 1e-4
 
 
-@pytest.mark.parametrize("tile_rows", [128, 256])
-def test_contraction_tile_shapes(wide, tile_rows):
-    """Both contraction kernels (128 x 128 tiles of four waves, 256 x 128 of eight) meet
-    the bounds of the default operands, and one FP16 product with 8 bands."""
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_contraction_tile_shapes(wide, tile):
+    """Every contraction tile (1: 128 x 128 of four waves, 2: 256 x 128 of eight, 3: 128 x 256
+    of eight) meets the bounds of the default operands, and one FP16 product with 8 bands."""
     b, dirs, om, ref = wide
-    S = run(b, dirs, om, "mfma_f16", tile_rows=tile_rows)
-    assert report(f"mfma f16 x3, {tile_rows}-row tiles", S, ref, om).max() <= 1e-5
-    S = run(b, dirs, om, "mfma_bf16", tile_rows=tile_rows)
-    assert report(f"mfma bf16 x3, {tile_rows}-row tiles", S, ref, om).max() <= 1e-4
-    S = run(b, dirs, om, "mfma_f16", bands=8, products_f16=1, tile_rows=tile_rows)
-    assert report(f"mfma f16 x1, 8 bands, {tile_rows}-row tiles", S, ref, om).max() <= 2e-3
+    S = run(b, dirs, om, "mfma_f16", tile=tile)
+    assert report(f"mfma f16 x3, tile {tile}", S, ref, om).max() <= 1e-5
+    S = run(b, dirs, om, "mfma_bf16", tile=tile)
+    assert report(f"mfma bf16 x3, tile {tile}", S, ref, om).max() <= 1e-4
+    S = run(b, dirs, om, "mfma_f16", bands=8, products_f16=1, tile=tile)
+    assert report(f"mfma f16 x1, 8 bands, tile {tile}", S, ref, om).max() <= 2e-3
 
 
 def test_bf16_single_product_is_reported(wide):
@@ -161,5 +161,6 @@ def test_agrees_with_fp32_path_on_a_large_batch():
     assert report("mfma f16 x3 vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-5
     S16 = run(b, dirs, om, "mfma_f16", products_f16=1)
     assert report("mfma f16 x1 vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-3
-    S16 = run(b, dirs, om, "mfma_f16", tile_rows=128)
-    assert report("mfma f16 x3 (128-row tiles) vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-5
+    for tile in (1, 2):
+        S16 = run(b, dirs, om, "mfma_f16", tile=tile)
+        assert report(f"mfma f16 x3 (tile {tile}) vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-5
