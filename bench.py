@@ -70,10 +70,13 @@ def parse():
     ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--tile", type=int, default=0,
                     help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256 (0: library default)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-particles", type=int, default=8000,
+                    help="particles of the uneven three-species workload in the batched leg")
     ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
     ap.add_argument("--surrogate-chunk", type=int, default=100_000)
     ap.add_argument("--surrogate-steps", type=int, default=1500)
@@ -145,12 +148,13 @@ def cpu_baseline(recipe, dirs, om, target_s):
     import workloads
 
     nthreads = oracle.max_threads()
-    cal = workloads.generate(recipe, 10_000_000, 2)
+    ncal = 2 * nthreads  # enough particles to occupy every thread
+    cal = workloads.generate(recipe, 10_000_000, ncal)
     t = time.perf_counter()
     oracle.spectrum(cal, dirs, om, n_species=1, nthreads=nthreads)
     dt_cal = time.perf_counter() - t
-    per_particle = dt_cal / 2
-    n = int(max(2, min(512, target_s / max(per_particle, 1e-6))))
+    per_particle = dt_cal / ncal
+    n = int(max(2, min(2048, target_s / max(per_particle, 1e-6))))
     sample = workloads.generate(recipe, 10_000_000, n)
     t = time.perf_counter()
     oracle.spectrum(sample, dirs, om, n_species=1, nthreads=nthreads)
@@ -176,6 +180,76 @@ def upload_ensemble(recipe, n, chunk, dev, host=False):
     b = DeviceBatch(tensors, n)
     b.n_samples_host = ns
     return b
+
+
+def batched_leg(a, log):
+    """Uneven multi-species workload: plain grid vs persistent launch vs autotuned shape,
+    and a captured graph of the tuned launch (FP32 path), plus the tuned matrix-core path."""
+    import torch
+
+    from paper_1003_1140_amd import Context, DeviceBatch
+    from workloads import configs
+    from workloads.gpu import generate_device
+
+    n = a.batched_particles
+    rec = configs.uneven_recipe()
+    t, ns = generate_device(rec, 0, n)
+    b = DeviceBatch(t, n)
+    dirs, om = configs.dirs_equal_area(), configs.log_grid(0.1, 1e3, 1024)
+    terms = float(ns) * len(dirs) * len(om)
+    ctx = Context(0)
+    ctx.set_directions(dirs)
+    ctx.set_frequencies(om)
+    ctx.set_species(3)
+    ctx.set_profiling(True)
+
+    def timed(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    out = {"workload": f"{n} particles of the uneven workload (47.5 % e-, 47.5 % e+, 5 % ions of mass 16; "
+                       f"gamma0 2/5/15; lengths U[256, 8192]; {ns} samples), 64 equal-area directions, "
+                       f"1024 log omega in [0.1, 1e3], 3 species", "terms": terms}
+    ws = ctx.workspace(b, "fp32")
+    ctx.set_tuning(persistent=0)
+    s_plain = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
+    S_plain = ctx.read_spectra() / 3.0
+    ctx.reset()
+    ctx.set_tuning(persistent=1)
+    ctx.plan_batch(b, "fp32")
+    s_pers = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
+    t0 = time.perf_counter()
+    rep_fp32 = ctx.tune(b, "fp32", repeats=1)
+    t_tune = time.perf_counter() - t0
+    ws = ctx.workspace(b, "fp32")  # the tuned shape may need a different workspace
+    ctx.reset()
+    ctx.profile_read()
+    s_tuned = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
+    prof = ctx.profile_read()
+    S_tuned = ctx.read_spectra() / 3.0
+    m = S_plain > 1e-4 * S_plain.max(axis=-1, keepdims=True)
+    tuned_vs_plain = float(np.max(np.abs(S_tuned - S_plain)[m] / S_plain[m]))
+    g = ctx.graph_capture(b, "fp32", workspace=ws)
+    s_graph = timed(g.launch)
+    g.close()
+    rep_mfma = ctx.tune(b, "mfma_f16", repeats=1)
+    wsm = ctx.workspace(b, "mfma_f16")
+    s_mfma = timed(lambda: ctx.accumulate(b, "mfma_f16", workspace=wsm))
+    ctx.read_spectra()
+    out.update({"fp32_plain_grid_terms_per_s": terms / s_plain, "fp32_persistent_terms_per_s": terms / s_pers,
+                "fp32_tuned_terms_per_s": terms / s_tuned, "fp32_tuned_graph_terms_per_s": terms / s_graph,
+                "mfma_f16x3_tuned_terms_per_s": terms / s_mfma, "tuner_seconds_fp32": t_tune,
+                "tuned_fp32": rep_fp32["best"], "tuned_mfma": rep_mfma["best"],
+                "fp32_tuned_kernel_ms": prof["direct_ms"] / max(prof["direct_launches"], 1),
+                "fp32_tuned_vs_plain_max_rel": tuned_vs_plain})
+    log(f"[bench] batched: plain {terms / s_plain:.3e}, persistent {terms / s_pers:.3e}, tuned "
+        f"{terms / s_tuned:.3e}, graph {terms / s_graph:.3e}, mfma {terms / s_mfma:.3e} terms/s")
+    return out
 
 
 def surrogate_leg(a, log):
@@ -221,17 +295,17 @@ def surrogate_leg(a, log):
         tb, ns = generate_device(rec, first + c0, m)
         b = DeviceBatch(tb, m)
         terms += float(ns) * len(dirs) * len(om)
-        held = torch.from_numpy(sg.held_out_indices(m, first + c0, cfg["held_out"], 11406)).cuda()
+        held = sg.held_out_indices(m, first + c0, cfg["held_out"], 11406)
         if c0 == 0:  # allocate the network's activation workspace before timing
             sur.net.forward(ctx.features(b).view(-1, 16))
             ctx.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         exact.accumulate(b, "fp32")
-        exact.read_spectra()
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = sg.infer_chunk(ctx, sur, b, judge=judge, held_idx=held)
-        ctx.read_spectra()
+        r = sg.infer_chunk(ctx, sur, b, judge=judge, held=held)
+        torch.cuda.synchronize()
         t2 = time.perf_counter()
         t_exact += t1 - t0
         t_pipe += t2 - t1
@@ -335,8 +409,12 @@ def main():
         "roofline": r["roofline"],
         "paths": results,
     }
+    del batch
+    torch.cuda.empty_cache()
+    if not a.no_batched:
+        out["batched"] = batched_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
     if not a.no_surrogate:
-        del batch
         torch.cuda.empty_cache()
         out["surrogate"] = surrogate_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
         print(f"[bench] surrogate: {out['surrogate']['equivalent_terms_per_s']:.3e} equivalent terms/s, "

@@ -93,21 +93,23 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
     q[7] += ux;
     q[8] += uy;
     q[9] += uz;
+    // inside the 1/gamma cone around the velocity: the angle to n is below 1/gamma
+    // (<= 1 rad), i.e. the cosine u.n exceeds cos(1/gamma); a particle at rest has
+    // angle 0 by convention
+    const double cos_cone = cos(1.0 / gam);
     #pragma unroll
     for (int g = 0; g < kDirGroup; ++g) {
       const double* m = n[g];
       const double kap = 1.0 - (m[0] * bx + m[1] * by + m[2] * bz);
-      const double cx = uy * m[2] - uz * m[1], cy = uz * m[0] - ux * m[2], cz = ux * m[1] - uy * m[0];
-      const double ang = atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * m[0] + uy * m[1] + uz * m[2]);
       q[NI + 4 * g] += kap;
       q[NI + 4 * g + 1] = fmin(q[NI + 4 * g + 1], kap);
-      if (ang < 1.0 / gam) q[NI + 4 * g + 2] += 1.0;
+      if (bn == 0.0 || ux * m[0] + uy * m[1] + uz * m[2] > cos_cone) q[NI + 4 * g + 2] += 1.0;
       // w = (n - beta) x betadot, v = n x w
       const double dx = m[0] - bx, dy = m[1] - by, dz = m[2] - bz;
       const double wx = dy * az - dz * ay, wy = dz * ax - dx * az, wz = dx * ay - dy * ax;
       const double vx = m[1] * wz - m[2] * wy, vy = m[2] * wx - m[0] * wz, vz = m[0] * wy - m[1] * wx;
-      const double k2 = kap * kap;
-      q[NI + 4 * g + 3] += (vx * vx + vy * vy + vz * vz) / (k2 * k2 * kap);
+      const double ik = 1.0 / kap, ik2 = ik * ik;
+      q[NI + 4 * g + 3] += (vx * vx + vy * vy + vz * vz) * (ik2 * ik2 * ik);
     }
   }
   auto is_max = [](int i) { return i == 6; };
@@ -295,12 +297,36 @@ __global__ void lw_mse_kernel(const float* y, const float* t, float* dy, int64_t
   if (threadIdx.x == 0) partial[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
 }
 
-// column sums in row order (deterministic): out[j] = sum_r X[r][j]
-__global__ void lw_colsum_kernel(const float* x, int64_t rows, int64_t cols, float* out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cols) return;
+// Weighted column sums in two fixed-order stages (deterministic):
+// out[j] = sum_r w_r X[r][j], with X[r][cols] = 1 for j == cols (a bias column) and
+// w_r = 1, or w_r = scale (e_r - t_r) when e is given.  Stage 1: work-group (j-block of
+// 64, row block) sums its rows in four interleaved lanes; stage 2 adds the row blocks.
+constexpr int kColsumRows = 128;  // rows per stage-1 work-group
+
+__global__ __launch_bounds__(256) void lw_colsum_stage1_kernel(const float* x, int64_t rows, int cols,
+                                                               int n_out, const float* e, const float* t,
+                                                               double scale, double* partial) {
+  __shared__ double sp[4][64];
+  const int jl = threadIdx.x & 63, lane4 = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  const int64_t r0 = (int64_t)blockIdx.y * kColsumRows, r1 = min(rows, r0 + kColsumRows);
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) s += x[r * cols + j];
+  if (j < n_out)
+    for (int64_t r = r0 + lane4; r < r1; r += 4) {
+      const double w = e ? scale * ((double)e[r] - (double)t[r]) : 1.0;
+      s += w * (j < cols ? (double)x[r * cols + j] : 1.0);
+    }
+  sp[lane4][jl] = s;
+  __syncthreads();
+  if (lane4 == 0 && j < n_out)
+    partial[(size_t)blockIdx.y * n_out + j] = ((sp[0][jl] + sp[1][jl]) + sp[2][jl]) + sp[3][jl];
+}
+
+__global__ void lw_colsum_stage2_kernel(const double* partial, int blocks, int n_out, float* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_out) return;
+  double s = 0.0;
+  for (int b = 0; b < blocks; ++b) s += partial[(size_t)b * n_out + j];
   out[j] = (float)s;
 }
 
@@ -325,18 +351,6 @@ __global__ void lw_head_fwd_kernel(const float* h, int64_t rows, int hidden, con
   e[r] = s;
 }
 
-// head gradient of mean (e - t)^2: one thread per parameter, rows in order
-__global__ void lw_head_grad_kernel(const float* h, const float* e, const float* t, int64_t rows,
-                                    int hidden, float* g) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > hidden) return;
-  double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const double d = 2.0 * ((double)e[r] - (double)t[r]) / (double)rows;
-    s += d * (i < hidden ? (double)h[r * hidden + i] : 1.0);
-  }
-  g[i] = (float)s;
-}
 
 // flags[p] = 1 when any direction's predicted error exceeds the threshold
 __global__ void lw_flag_kernel(const float* err, int64_t P, int nd, float threshold, int32_t* flags) {
@@ -424,6 +438,7 @@ struct lw_mlp {
   int skip_index = -1;    // raw input added (times skip_coeff) to every output, or -1
   float skip_coeff = 0.0f;
   double* loss_part = nullptr;
+  double* col_part = nullptr;  // stage-1 partial column sums [row blocks][max(n_out, hidden + 1)]
   float* err_buf = nullptr;
   std::vector<int64_t> w_off, b_off;
 };
@@ -452,15 +467,34 @@ lw_status ensure_rows(lw_mlp* n, int64_t rows) {
   if (n->act) (void)hipFree(n->act);
   if (n->loss_part) (void)hipFree(n->loss_part);
   if (n->err_buf) (void)hipFree(n->err_buf);
+  if (n->col_part) (void)hipFree(n->col_part);
   n->act = nullptr;
   n->loss_part = nullptr;
   n->err_buf = nullptr;
+  n->col_part = nullptr;
   const int64_t per_row = (int64_t)2 * n->n_hidden * n->hidden + 2 * n->n_out + 2 * n->hidden + n->n_in;
   MLP_HIP(hipMalloc(&n->act, (size_t)rows * per_row * sizeof(float)), "hipMalloc(activations)");
   const int64_t blocks = (rows * std::max(n->n_out, 1) + 255) / 256;
   MLP_HIP(hipMalloc(&n->loss_part, (size_t)blocks * sizeof(double)), "hipMalloc(loss)");
   MLP_HIP(hipMalloc(&n->err_buf, (size_t)rows * sizeof(float)), "hipMalloc(err)");
+  const int64_t rblocks = (rows + lw::kColsumRows - 1) / lw::kColsumRows;
+  const int64_t widest = std::max<int64_t>(std::max(n->n_out, n->hidden + 1), n->hidden);
+  MLP_HIP(hipMalloc(&n->col_part, (size_t)rblocks * widest * sizeof(double)), "hipMalloc(column sums)");
   n->rows_cap = rows;
+  return LW_OK;
+}
+
+// out[j] = sum_r w_r X[r][j] over j < n_out (see lw_colsum_stage1_kernel)
+lw_status colsum(lw_mlp* n, const float* x, int64_t rows, int cols, int n_out, const float* e,
+                 const float* t, double scale, float* out) {
+  hipStream_t s = n->c->stream;
+  const int rblocks = (int)((rows + lw::kColsumRows - 1) / lw::kColsumRows);
+  hipLaunchKernelGGL(lw::lw_colsum_stage1_kernel, dim3((unsigned)((n_out + 63) / 64), (unsigned)rblocks),
+                     dim3(256), 0, s, x, rows, cols, n_out, e, t, scale, n->col_part);
+  MLP_HIP(hipGetLastError(), "column sums");
+  hipLaunchKernelGGL(lw::lw_colsum_stage2_kernel, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, s,
+                     n->col_part, rblocks, n_out, out);
+  MLP_HIP(hipGetLastError(), "column sums");
   return LW_OK;
 }
 
@@ -519,9 +553,8 @@ lw_status backward(lw_mlp* n, const float* x, int64_t rows) {
     // dW[o][i] = sum_r d[r][o] in[r][i]
     lw::GemmDesc gw{d, 1, dout, in, din, 1, n->g + n->w_off[l], din, nullptr, dout, din, rows};
     MLP_HIP(lw::gemm_bf16(gw, s), "gemm dW");
-    hipLaunchKernelGGL(lw::lw_colsum_kernel, dim3((unsigned)((dout + 255) / 256)), dim3(256), 0, s, d,
-                       rows, (int64_t)dout, n->g + n->b_off[l]);
-    MLP_HIP(hipGetLastError(), "colsum");
+    lw_status cst = colsum(n, d, rows, dout, dout, nullptr, nullptr, 1.0, n->g + n->b_off[l]);
+    if (cst != LW_OK) return cst;
     if (l > 0) {
       // dh[r][i] = sum_o d[r][o] W[o][i], then times gelu'(z)
       float* dh = (d == dz_of(n, rows)) ? dh_of(n, rows) : dz_of(n, rows);
@@ -726,6 +759,7 @@ void lw_mlp_destroy(lw_mlp* n) {
   if (n->c) (void)hipStreamSynchronize(n->c->stream);
   for (void* p : {(void*)n->p, (void*)n->m, (void*)n->v, (void*)n->g, (void*)n->hp, (void*)n->hm,
                   (void*)n->hv, (void*)n->hg, (void*)n->act, (void*)n->loss_part, (void*)n->err_buf,
+                  (void*)n->col_part,
                   (void*)n->norm})
     if (p) (void)hipFree(p);
   delete n;
@@ -832,9 +866,9 @@ lw_status lw_mlp_train_head_step(lw_mlp* n, const float* x, const float* err_tar
     st = mse(n, n->err_buf, err_target, dy_of(n, rows), rows, loss);
     if (st != LW_OK) return st;
   }
-  hipLaunchKernelGGL(lw::lw_head_grad_kernel, dim3((unsigned)((n->hidden + 1 + 255) / 256)), dim3(256), 0,
-                     s, hlast, n->err_buf, err_target, rows, n->hidden, n->hg);
-  MLP_HIP(hipGetLastError(), "head grad");
+  // gradient of mean (e - t)^2: weights and bias as weighted column sums of [h | 1]
+  st = colsum(n, hlast, rows, n->hidden, n->hidden + 1, n->err_buf, err_target, 2.0 / (double)rows, n->hg);
+  if (st != LW_OK) return st;
   n->head_step += 1;
   return adamw(n, n->hp, n->hm, n->hv, n->hg, n->hidden + 1, n->head_step, lr, 0.0f);
 }

@@ -163,43 +163,48 @@ class Judge:
             c.set_species(ctx.ns)
         self.n = 0
 
-    def add(self, batch: DeviceBatch, ylog, held_idx, flags, calib=None):
-        """held_idx: device int64 indices (increasing) of the chunk's held-out particles;
-        flags: the pipeline's fallback flags of the chunk."""
-        if held_idx.numel() == 0:
+    def add(self, batch: DeviceBatch, ylog, held, flagged, calib=None):
+        """held: host int64 indices (increasing) of the chunk's held-out particles;
+        flagged: host int64 indices of the particles the pipeline computed exactly."""
+        if held.size == 0:
             return
         dev = ylog.device
-        self.exact.accumulate_subset(batch, held_idx)
-        held = torch.zeros(batch.n_particles, dtype=torch.bool, device=dev)
-        held[held_idx] = True
-        flagged = flags != 0
-        only_held = torch.where(held, 0.0, 1.0).to(torch.float32)[:, None].expand(-1, self.sur.nd).contiguous()
-        self.sur.surrogate_accumulate(batch, ylog, only_held, 0.5, calib=calib)
-        kept_held = torch.where(held & ~flagged, 0.0, 1.0).to(torch.float32)[:, None]
-        self.pipe.surrogate_accumulate(batch, ylog, kept_held.expand(-1, self.pipe.nd).contiguous(), 0.5,
-                                       calib=calib)
-        exact_held = torch.nonzero(held & flagged, as_tuple=False).view(-1)
-        if exact_held.numel():
-            self.pipe.accumulate_subset(batch, exact_held)
-        self.n += int(held_idx.numel())
+        P, nd = batch.n_particles, self.sur.nd
+        held_d = torch.from_numpy(held).to(dev, non_blocking=True)
+        self.exact.accumulate_subset(batch, held_d)
+        # an "error" of 0 keeps a particle on the surrogate sum, 1 leaves it out (threshold 0.5)
+        keep = torch.ones((P, nd), dtype=torch.float32, device=dev)
+        keep[held_d] = 0.0
+        self.sur.surrogate_accumulate(batch, ylog, keep, 0.5, calib=calib)
+        held_flagged = np.intersect1d(held, flagged, assume_unique=True)
+        if held_flagged.size:
+            hf = torch.from_numpy(held_flagged).to(dev, non_blocking=True)
+            keep[hf] = 1.0
+            self.pipe.accumulate_subset(batch, hf)
+        self.pipe.surrogate_accumulate(batch, ylog, keep, 0.5, calib=calib)
+        self.n += int(held.size)
 
     def spectra(self):
         """(exact, pipeline, surrogate-only) spectra of the held-out particles."""
         return self.exact.read_spectra(), self.pipe.read_spectra(), self.sur.read_spectra()
 
 
-def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge | None = None, held_idx=None,
+def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge | None = None, held=None,
                 threshold=None) -> dict:
-    """Add the surrogate estimate of one chunk to ctx's S (exact for flagged particles)."""
+    """Add the surrogate estimate of one chunk to ctx's S (exact for flagged particles).
+
+    held: host int64 indices (increasing) of the chunk's held-out particles, judged when
+    a Judge is given."""
     thr = sur.threshold if threshold is None else threshold
     x = ctx.features(batch).view(-1, 16)
     ylog, err = sur.net.forward(x, with_error=True)
-    flags, idx, cnt = ctx.surrogate_accumulate(batch, ylog, err, thr, compact=True, calib=sur.calib)
+    _, idx, cnt = ctx.surrogate_accumulate(batch, ylog, err, thr, compact=True, calib=sur.calib)
     n_flag = int(cnt.item())
     if n_flag:
         ctx.accumulate_subset(batch, idx[:n_flag])
-    if judge is not None and held_idx is not None:
-        judge.add(batch, ylog, held_idx, flags, calib=sur.calib)
+    if judge is not None and held is not None:
+        flagged = idx[:n_flag].cpu().numpy() if n_flag else np.zeros(0, dtype=np.int64)
+        judge.add(batch, ylog, np.asarray(held, dtype=np.int64), flagged, calib=sur.calib)
     return {"fallback": n_flag}
 
 

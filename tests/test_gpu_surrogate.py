@@ -288,7 +288,7 @@ def test_trained_surrogate_is_judged_and_gains_over_exact():
     del train_b, calib
     first = 1 << 20  # inference ids, disjoint from the training and calibration ids
     b = _small_chunk(n=40000, steps=4096, first_id=first)
-    held = torch.from_numpy(sg.held_out_indices(b.n_particles, first, 0.05, 7)).cuda()
+    held = sg.held_out_indices(b.n_particles, first, 0.05, 7)
     # exact path alone
     c.reset()
     torch.cuda.synchronize()
@@ -298,12 +298,12 @@ def test_trained_surrogate_is_judged_and_gains_over_exact():
     t_exact = time.perf_counter() - t0
     # pipeline (warm once for the network workspace and the judge's index plumbing)
     c.reset()
-    sg.infer_chunk(c, sur, b, judge=sg.Judge(c), held_idx=held)
+    sg.infer_chunk(c, sur, b, judge=sg.Judge(c), held=held)
     c.reset()
     judge = sg.Judge(c)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = sg.infer_chunk(c, sur, b, judge=judge, held_idx=held)
+    r = sg.infer_chunk(c, sur, b, judge=judge, held=held)
     S_pipe = c.read_spectra()
     Se, Sp, Ss = judge.spectra()
     t_pipe = time.perf_counter() - t0
