@@ -98,6 +98,28 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
     return worst
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md")
+
+
+def profiled_traffic(path, tile, particles):
+    """HBM bytes per contraction launch from the committed counter profile of this exact
+    configuration, or None when the kernel source changed since it was taken."""
+    import hashlib
+
+    if path != "mfma_f16x3" or tile not in (0, 3) or particles != 100_000:
+        return None
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip"), "rb").read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4> (128 x 256 tiles)",
                 1: "lw_dft_mfma_r128_kernel<WN=2> (128 x 128 tiles)",
                 2: "lw_dft_mfma_kernel (256 x 128 tiles)",
@@ -387,6 +409,7 @@ def main():
                     spectra[path], spectra["fp32"], om)
     head = paths[-1]
     r = results[head]
+    r["roofline"]["traffic"] = profiled_traffic(head, a.tile, a.particles)
     out = {
         "metric": "LW spectral terms/s (particle x step x omega x n)",
         "value": r["terms_per_s"],
