@@ -55,7 +55,8 @@ def _load():
         if not os.path.exists(_SO):
             build(force=True)
         _lib = ctypes.CDLL(_SO)
-        for name in ("lwo_amplitude", "lwo_spectrum", "lwo_sampled_bins", "lwo_max_threads"):
+        for name in ("lwo_amplitude", "lwo_spectrum", "lwo_sampled_bins", "lwo_max_threads",
+                     "lwo_coherent_spectrum"):
             getattr(_lib, name).restype = ctypes.c_int
         _lib.mlpo_num_params.restype = ctypes.c_int64
         _lib.mlpo_forward_backward.restype = ctypes.c_double
@@ -113,6 +114,30 @@ def spectrum(batch, dirs, omega, n_species=None, per_particle=False, nthreads=0)
     if st != LWO_OK:
         raise OracleError(st, bad.value)
     return (S, pp) if per_particle else S
+
+
+def coherent_spectrum(batch, dirs, omega, n_species=None, with_amplitude=False, nthreads=0):
+    """Coherent S[s, d, j] = |sum_p w_p q_p A_p|^2 / (4 pi^2) (and the summed amplitude
+    [s, d, j, 3] complex when asked)."""
+    lib = _load()
+    dirs = _f64(np.atleast_2d(dirs))
+    om = _f64(omega)
+    spec = np.ascontiguousarray(batch.species, dtype=np.int32)
+    if n_species is None:
+        n_species = int(spec.max()) + 1 if spec.size else 1
+    S = np.zeros((n_species, dirs.shape[0], om.size), dtype=np.float64)
+    A = np.zeros((n_species, dirs.shape[0], om.size, 3, 2), dtype=np.float64) if with_amplitude else None
+    arrs = [_f64(getattr(batch, k)) for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az")]
+    offs = np.ascontiguousarray(batch.offsets - batch.offsets[0], dtype=np.int64)
+    bad = ctypes.c_int64(-1)
+    st = lib.lwo_coherent_spectrum(ctypes.c_int64(batch.n_particles), _p(offs), *[_p(a) for a in arrs],
+                                   _p(_f64(batch.t0)), _p(_f64(batch.dt)), _p(_f64(batch.charge)),
+                                   _p(_f64(batch.weight)), _p(spec), ctypes.c_int32(n_species), _p(dirs),
+                                   ctypes.c_int32(dirs.shape[0]), _p(om), ctypes.c_int32(om.size), _p(S),
+                                   _p(A), ctypes.c_int(nthreads), ctypes.byref(bad))
+    if st != LWO_OK:
+        raise OracleError(st, bad.value)
+    return (S, A[..., 0] + 1j * A[..., 1]) if with_amplitude else S
 
 
 def sampled_bins(batch, dirs, omega, species=-1, nthreads=0):

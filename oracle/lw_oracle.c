@@ -283,3 +283,84 @@ int lwo_max_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * Coherent synthesis (Section 2.2: the sum over particles taken inside the squared
+ * modulus): the amplitudes of all particles of a species add before squaring,
+ *
+ *   A_s(n, w) = sum_{p in s} w_p q_p A_p(n, w),   S_coh(s, n, w) = |A_s|^2 / (4 pi^2).
+ *
+ * A macro-particle of weight w stands for w real particles on the same trajectory, so
+ * its amplitude counts w times.  S_out[s][d][j] is overwritten; A_out (may be NULL)
+ * receives A_s as [s][d][j][3 components][re, im].  OpenMP over directions; particles
+ * are added in index order (deterministic).
+ */
+int lwo_coherent_spectrum(int64_t n_particles, const int64_t* offsets, const double* x,
+                          const double* y, const double* z, const double* bx, const double* by,
+                          const double* bz, const double* ax, const double* ay, const double* az,
+                          const double* t0, const double* dt, const double* charge,
+                          const double* weight, const int32_t* species, int32_t n_species,
+                          const double* dirs, int32_t nd, const double* omega, int32_t nw,
+                          double* S_out, double* A_out, int nthreads, int64_t* bad_particle) {
+  if (n_particles < 0 || nd <= 0 || nw <= 0 || n_species <= 0) return LWO_EINVAL;
+  for (int32_t d = 0; d < nd; ++d) {
+    double tmp[3];
+    if (!unit3(dirs + 3 * d, tmp)) return LWO_EINVAL;
+  }
+  for (int64_t p = 0; p < n_particles; ++p) {
+    if (offsets[p + 1] < offsets[p]) return LWO_EINVAL;
+    if (species && (species[p] < 0 || species[p] >= n_species)) return LWO_EINVAL;
+  }
+  const size_t per_s = (size_t)nd * (size_t)nw * 6;
+  double* Atot = (double*)calloc(per_s * (size_t)n_species, sizeof(double));
+  if (!Atot) return LWO_ENOMEM;
+  int64_t first_bad = -1;
+  int status = LWO_OK;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel
+  {
+    double* A = (double*)malloc(sizeof(double) * 6 * (size_t)nw);
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t d = 0; d < nd; ++d) {
+      for (int64_t p = 0; p < n_particles; ++p) {
+        const int64_t o = offsets[p], len = offsets[p + 1] - offsets[p];
+        int64_t badk = -1;
+        const int st = A ? lwo_amplitude(len, x + o, y + o, z + o, bx + o, by + o, bz + o, ax + o,
+                                         ay + o, az + o, t0[p], dt[p], dirs + 3 * d, nw, omega, A,
+                                         &badk)
+                         : LWO_ENOMEM;
+        if (st != LWO_OK) {
+#pragma omp critical
+          {
+            if (st == LWO_ERANGE) {
+              if (first_bad < 0 || p < first_bad) first_bad = p;
+              if (status == LWO_OK) status = LWO_ERANGE;
+            } else {
+              status = st;
+            }
+          }
+          continue;
+        }
+        const int32_t s = species ? species[p] : 0;
+        const double amp = weight[p] * charge[p];
+        double* dst = Atot + (size_t)s * per_s + (size_t)d * nw * 6;
+        for (size_t i = 0; i < (size_t)nw * 6; ++i) dst[i] += amp * A[i];
+      }
+    }
+    free(A);
+  }
+  const double four_pi2 = 4.0 * M_PI * M_PI;
+  for (int32_t s = 0; s < n_species; ++s)
+    for (size_t dj = 0; dj < (size_t)nd * nw; ++dj) {
+      const double* a = Atot + (size_t)s * per_s + dj * 6;
+      double a2 = 0.0;
+      for (int c = 0; c < 6; ++c) a2 += a[c] * a[c];
+      S_out[(size_t)s * nd * nw + dj] = a2 / four_pi2;
+    }
+  if (A_out) memcpy(A_out, Atot, sizeof(double) * per_s * (size_t)n_species);
+  free(Atot);
+  if (bad_particle) *bad_particle = first_bad;
+  return status;
+}

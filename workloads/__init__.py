@@ -105,6 +105,21 @@ class Batch:
         per = {k: getattr(self, k)[idx] for k in ("t0", "dt", "charge", "weight", "species")}
         return Batch(offsets=offs, meta=dict(self.meta), **sub, **per)
 
+    def time_window(self, k0, k1) -> "Batch":
+        """Samples k0 .. k1-1 of every particle (clipped to its length), each particle's
+        t0 moved to the window's first sample: the chunk an in-situ recorder sees between
+        two snapshots."""
+        lens = self.lengths()
+        a = np.minimum(lens, k0)
+        b = np.minimum(lens, np.maximum(k1, k0))
+        offs = np.zeros(len(lens) + 1, dtype=np.int64)
+        np.cumsum(b - a, out=offs[1:])
+        take = np.concatenate([np.arange(self.offsets[i] + a[i], self.offsets[i] + b[i])
+                               for i in range(len(lens))]) if len(lens) else np.zeros(0, dtype=np.int64)
+        sub = {k: getattr(self, k)[take] for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az")}
+        per = {k: getattr(self, k).copy() for k in ("dt", "charge", "weight", "species")}
+        return Batch(offsets=offs, meta=dict(self.meta), t0=self.t0 + a * self.dt, **sub, **per)
+
     @staticmethod
     def concat(batches) -> "Batch":
         lens = np.concatenate([b.lengths() for b in batches])
