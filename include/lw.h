@@ -142,6 +142,54 @@ lw_status lw_reset(lw_ctx* ctx);
 /* Replace S with host_in [n_species][nd][nw] (resume from a saved state). */
 lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
 
+/* ---- coherent synthesis and in-situ recording (Section 2.2, recording scheme) ----
+ * The observed power is the squared modulus of the time integral of the summed
+ * retarded fields: amplitudes add before squaring.  Summed over the particles of
+ * a species (coherent synthesis) that is
+ *   A_s(n, w) = sum_{p in s} w_p q_p A_p(n, w),  S = |A_s|^2 / (4 pi^2),
+ * and squared per particle (incoherent synthesis, the default) it is
+ * S = sum_p w_p q_p^2 |A_p|^2 / (4 pi^2).  Because the integral runs from the
+ * start of recording to the current step, a spectrum taken over a later stretch
+ * of time is the difference of two recorded spectra, P(t1) - P(t0).  Species
+ * slots double as collection regions: the caller assigns each particle to one.
+ *
+ * Amplitudes are stored as four FP64 numbers per (direction, frequency): the real
+ * and imaginary part of the component on e1, then those on e2, where (e1, e2, n)
+ * is the orthonormal right-handed basis of lw_get_basis (A is perpendicular to n).
+ *
+ * lw_set_coherent: 1 = coherent, 0 = incoherent synthesis.  Resets S (and A).
+ * In coherent mode lw_accumulate (FP32 path; LW_EUNSUPPORTED for the
+ * matrix-core paths, which drop each particle's absolute phase) and
+ * lw_accumulate_subset add w_p q_p A_p into A_s; time windows of a run passed as
+ * successive batches (each particle's t0 is the window's first sample time)
+ * therefore build the integral over the whole run; lw_read_spectra returns
+ * |A_s|^2 / (4 pi^2), and lw_reset zeroes A.  The surrogate is incoherent only. */
+lw_status lw_set_coherent(lw_ctx* ctx, int32_t coherent);
+/* host_out [nd][9]: per direction n, e1, e2 (unit vectors, FP64). */
+lw_status lw_get_basis(const lw_ctx* ctx, double* host_out);
+/* Coherent mode only (LW_ESTATE otherwise).  Synchronise and copy A_s to
+ * host_out [n_species][nd][nw][4]; LW_ERANGE as for lw_read_spectra. */
+lw_status lw_read_amplitudes(lw_ctx* ctx, double* host_out);
+/* Coherent mode only: replace A_s with host_in [n_species][nd][nw][4] (resume). */
+lw_status lw_load_amplitudes(lw_ctx* ctx, const double* host_in);
+/* Per-particle amplitude state for incoherent in-situ recording.  amp: device
+ * FP64 [n_particles][nd][nw][4], 16-byte aligned, owned by the caller, zeroed
+ * by the caller before the first window; each call adds the batch's raw
+ * amplitude A_p (without w_p q_p) of every particle into its own row, so
+ * windows of one run must list the particles in the same order.  Leaves S and
+ * A_s alone; samples with |beta| >= 1 or non-finite values are recorded for the
+ * next read as in lw_accumulate.  FP32 path, asynchronous, no workspace. */
+lw_status lw_accumulate_amplitudes(lw_ctx* ctx, const lw_batch* batch, double* amp);
+/* Device workspace (bytes) of lw_spectrum_from_amplitudes for n_particles. */
+lw_status lw_amplitude_workspace_size(lw_ctx* ctx, int64_t n_particles, size_t* bytes);
+/* Add the spectrum of a per-particle amplitude state into the accumulator:
+ * S += sum_p w_p q_p^2 |amp_p|^2 / (4 pi^2) (incoherent) or A_s += sum_p w_p q_p
+ * amp_p (coherent).  Only batch.n_particles, charge, weight and species are
+ * read.  Call lw_reset first for the spectrum P(t) of the state alone.
+ * Asynchronous; deterministic (fixed summation order). */
+lw_status lw_spectrum_from_amplitudes(lw_ctx* ctx, const lw_batch* batch, const double* amp,
+                                      void* workspace, size_t workspace_bytes);
+
 /* ---- batched launches (uneven lengths, several species) ----
  * Plan a batch for the persistent launch (synchronous; reads the batch offsets).
  * FP32 path: particles are ordered by decreasing trajectory length and grouped

@@ -59,15 +59,25 @@ void free_dev(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// S [ns][nd][nw], and in coherent synthesis the summed amplitudes A [ns][nd][nw][4]; both zeroed.
 lw_status alloc_accumulator(lw_ctx* c) {
   free_dev(c->d_S);
+  free_dev(c->d_A);
   c->d_S = nullptr;
+  c->d_A = nullptr;
   if (c->nd <= 0 || c->nw <= 0) return LW_OK;
   size_t n = (size_t)c->ns * c->nd * c->nw;
   LW_HIP(hipMalloc(&c->d_S, n * sizeof(double)), "hipMalloc(S)");
   LW_HIP(lw::launch_fill_f64(c->d_S, (int64_t)n, 0.0, c->stream), "zero S");
+  if (c->coherent) {
+    LW_HIP(hipMalloc(&c->d_A, 4 * n * sizeof(double)), "hipMalloc(A)");
+    LW_HIP(lw::launch_fill_f64(c->d_A, (int64_t)(4 * n), 0.0, c->stream), "zero A");
+  }
   return LW_OK;
 }
+
+// Accumulator the FP32 kernel's partial rows are reduced into.
+double* direct_target(lw_ctx* c) { return c->coherent ? c->d_A : c->d_S; }
 
 // Orthonormal e1, e2 perpendicular to the unit vector n, (e1, e2, n) right-handed.
 void basis(const double n[3], double e1[3], double e2[3]) {
@@ -184,6 +194,7 @@ void lw_destroy(lw_ctx* c) {
   free_dev(c->d_wturn);
   free_dev(c->d_omega);
   free_dev(c->d_S);
+  free_dev(c->d_A);
   free_dev(c->d_err);
   delete c;
 }
@@ -284,7 +295,8 @@ lw_status lw_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* 
   *bytes = 0;
   if (path == LW_PATH_FP32) {
     DirectShape s = direct_shape(c, b->n_particles);
-    *bytes = align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * sizeof(double));
+    *bytes = align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * lw::direct_ncomp(c) *
+                      sizeof(double));
     return LW_OK;
   }
   if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
@@ -302,6 +314,10 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
   st = check_batch(c, b);
   if (st != LW_OK) return st;
   if (b->n_particles == 0) return LW_OK;
+  if (c->coherent && path != LW_PATH_FP32)
+    return fail(c, LW_EUNSUPPORTED,
+                "coherent synthesis runs on the FP32 path (the matrix-core path drops each "
+                "particle's absolute phase)");
   size_t need = 0;
   st = lw_workspace_size(c, b, path, &need);
   if (st != LW_OK) return st;
@@ -319,11 +335,13 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
     a.nd = c->nd;
     a.nw = c->nw;
     a.ns = c->ns;
+    a.ncomp = lw::direct_ncomp(c);
     a.pb = s.pb;
     a.n_blocks = s.n_blocks;
     a.n_tiles = s.n_tiles;
     a.partial = (double*)ws;
     a.per_particle = per_particle;
+    a.amp = nullptr;
     a.err = c->d_err;
     a.perm = nullptr;
     a.order = nullptr;
@@ -332,7 +350,8 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
     const auto& pl = c->plan;
     const bool persistent = c->tune_persistent && pl.valid && pl.offsets == (const void*)b->offsets &&
                             pl.n == b->n_particles && pl.nd == c->nd && pl.nw == c->nw &&
-                            pl.ns == c->ns && pl.wpt == s.wpt && pl.pb == s.pb;
+                            pl.ns == c->ns && pl.ncomp == a.ncomp && pl.wpt == s.wpt &&
+                            pl.pb == s.pb;
     LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
     if (persistent) {
       a.perm = pl.d_perm;
@@ -346,8 +365,9 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
       LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32");
     }
     LW_HIP(lw::prof_end(c), "profile");
-    LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw,
-                                      c->d_S, c->stream),
+    LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks,
+                                      (int64_t)c->ns * c->nd * c->nw * a.ncomp, direct_target(c),
+                                      c->stream),
            "launch lw_reduce_partials");
   } else if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
     st = lw::mfma_accumulate(c, b, path, ws, ws_bytes, per_particle);
@@ -366,6 +386,8 @@ lw_status lw_read_spectra(lw_ctx* c, double* out) {
   DeviceGuard g(c->device);
   size_t n = (size_t)c->ns * c->nd * c->nw;
   unsigned long long e = kNoError;
+  if (c->coherent)
+    LW_HIP(lw::launch_coherent_power(c->d_A, (int64_t)n, c->d_S, c->stream), "launch coherent power");
   LW_HIP(hipMemcpyAsync(out, c->d_S, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy S");
   LW_HIP(hipMemcpyAsync(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy err");
   LW_HIP(hipStreamSynchronize(c->stream), "sync");
@@ -379,6 +401,8 @@ lw_status lw_reset(lw_ctx* c) {
   DeviceGuard g(c->device);
   if (c->d_S)
     LW_HIP(lw::launch_fill_f64(c->d_S, (int64_t)c->ns * c->nd * c->nw, 0.0, c->stream), "zero S");
+  if (c->d_A)
+    LW_HIP(lw::launch_fill_f64(c->d_A, (int64_t)4 * c->ns * c->nd * c->nw, 0.0, c->stream), "zero A");
   LW_HIP(lw::launch_fill_u64(c->d_err, 1, kNoError, c->stream), "reset error");
   return LW_OK;
 }
@@ -387,6 +411,8 @@ lw_status lw_load_accumulator(lw_ctx* c, const double* in) {
   if (!c || !in) return LW_EINVAL;
   lw_status st = check_grids(c);
   if (st != LW_OK) return st;
+  if (c->coherent)
+    return fail(c, LW_ESTATE, "coherent synthesis keeps amplitudes: use lw_load_amplitudes");
   DeviceGuard g(c->device);
   size_t n = (size_t)c->ns * c->nd * c->nw;
   LW_HIP(hipMemcpyAsync(c->d_S, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "load S");
@@ -500,7 +526,7 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
          "copy order");
   hipDeviceProp_t prop;
   LW_HIP(hipGetDeviceProperties(&prop, c->device), "device properties");
-  const size_t shmem = sizeof(double) * (size_t)c->ns * lw::kThreads * s.wpt;
+  const size_t shmem = lw::direct_lds(c->ns, lw::direct_ncomp(c), s.wpt);
   const int per_cu = lw::direct_persistent_occupancy(s.wpt, shmem);
   pl.workgroups = (int)std::min<int64_t>((int64_t)prop.multiProcessorCount * per_cu, n_items);
   pl.offsets = (const void*)b->offsets;
@@ -508,6 +534,7 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   pl.nd = c->nd;
   pl.nw = c->nw;
   pl.ns = c->ns;
+  pl.ncomp = lw::direct_ncomp(c);
   pl.wpt = s.wpt;
   pl.pb = s.pb;
   pl.n_tiles = s.n_tiles;
@@ -527,7 +554,9 @@ lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indi
   if (n_idx < 0 || (n_idx > 0 && !indices)) return fail(c, LW_EINVAL, "bad index list");
   if (n_idx == 0) return LW_OK;
   const DirectShape s = direct_shape(c, n_idx);
-  const size_t need = align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * sizeof(double));
+  const int ncomp = lw::direct_ncomp(c);
+  const size_t need =
+      align256((size_t)s.n_blocks * c->ns * c->nd * c->nw * ncomp * sizeof(double));
   if (!ws || ws_bytes < need)
     return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
   DeviceGuard g(c->device);
@@ -540,11 +569,13 @@ lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indi
   a.nd = c->nd;
   a.nw = c->nw;
   a.ns = c->ns;
+  a.ncomp = ncomp;
   a.pb = s.pb;
   a.n_blocks = s.n_blocks;
   a.n_tiles = s.n_tiles;
   a.partial = (double*)ws;
   a.per_particle = per_particle;
+  a.amp = nullptr;
   a.err = c->d_err;
   a.perm = indices;
   a.order = nullptr;
@@ -553,8 +584,8 @@ lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indi
   LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
   LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32 (subset)");
   LW_HIP(lw::prof_end(c), "profile");
-  LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw, c->d_S,
-                                    c->stream),
+  LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw * ncomp,
+                                    direct_target(c), c->stream),
          "launch lw_reduce_partials");
   c->calls += 1;
   return LW_OK;
@@ -646,6 +677,126 @@ void lw_graph_destroy(lw_graph* gr) {
   if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
   if (gr->graph) (void)hipGraphDestroy(gr->graph);
   delete gr;
+}
+
+lw_status lw_set_coherent(lw_ctx* c, int32_t coherent) {
+  if (!c) return LW_EINVAL;
+  DeviceGuard g(c->device);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  c->coherent = coherent != 0;
+  return alloc_accumulator(c);
+}
+
+lw_status lw_get_basis(const lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  if (c->nd <= 0) return LW_ESTATE;
+  memcpy(out, c->h_dirs.data(), c->h_dirs.size() * sizeof(double));
+  return LW_OK;
+}
+
+lw_status lw_read_amplitudes(lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  if (!c->coherent) return fail(c, LW_ESTATE, "amplitudes are kept in coherent synthesis only");
+  DeviceGuard g(c->device);
+  size_t n = (size_t)4 * c->ns * c->nd * c->nw;
+  unsigned long long e = kNoError;
+  LW_HIP(hipMemcpyAsync(out, c->d_A, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy A");
+  LW_HIP(hipMemcpyAsync(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy err");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  if (e != kNoError)
+    return fail(c, LW_ERANGE, "particle %llu has |beta| >= 1 or a non-finite sample", e);
+  return LW_OK;
+}
+
+lw_status lw_load_amplitudes(lw_ctx* c, const double* in) {
+  if (!c || !in) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  if (!c->coherent) return fail(c, LW_ESTATE, "amplitudes are kept in coherent synthesis only");
+  DeviceGuard g(c->device);
+  size_t n = (size_t)4 * c->ns * c->nd * c->nw;
+  LW_HIP(hipMemcpyAsync(c->d_A, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "load A");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  return LW_OK;
+}
+
+lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, double* amp) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (b->n_particles == 0) return LW_OK;
+  if (!amp) return fail(c, LW_EINVAL, "amplitude state is NULL");
+  if (((uintptr_t)amp & 15) != 0) return fail(c, LW_EINVAL, "amplitude state must be 16-byte aligned");
+  DeviceGuard g(c->device);
+  const DirectShape s = direct_shape(c, b->n_particles);
+  lw::DirectArgs a;
+  a.b = {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+         b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  a.dirs = c->d_dirs;
+  a.wturn = c->d_wturn;
+  a.nd = c->nd;
+  a.nw = c->nw;
+  a.ns = c->ns;
+  a.ncomp = 4;
+  a.pb = s.pb;
+  a.n_blocks = s.n_blocks;
+  a.n_tiles = s.n_tiles;
+  a.partial = nullptr;
+  a.per_particle = nullptr;
+  a.amp = amp;
+  a.err = c->d_err;
+  a.perm = nullptr;
+  a.order = nullptr;
+  a.ticket = nullptr;
+  a.n_items = 0;
+  LW_HIP(lw::prof_begin(c, lw::kProfDirect), "profile");
+  LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32 (amplitude state)");
+  LW_HIP(lw::prof_end(c), "profile");
+  c->calls += 1;
+  return LW_OK;
+}
+
+lw_status lw_amplitude_workspace_size(lw_ctx* c, int64_t n_particles, size_t* bytes) {
+  if (!c || !bytes) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  if (n_particles < 0) return fail(c, LW_EINVAL, "n_particles < 0");
+  const int64_t n_blocks = (n_particles + lw::kAmpRows - 1) / lw::kAmpRows;
+  *bytes = align256((size_t)n_blocks * c->ns * c->nd * c->nw * lw::direct_ncomp(c) * sizeof(double));
+  return LW_OK;
+}
+
+lw_status lw_spectrum_from_amplitudes(lw_ctx* c, const lw_batch* b, const double* amp, void* ws,
+                                      size_t ws_bytes) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  if (!b || b->n_particles < 0) return fail(c, LW_EINVAL, "bad batch");
+  if (b->n_particles == 0) return LW_OK;
+  if (!b->charge || !b->weight) return fail(c, LW_EINVAL, "batch.charge and batch.weight are needed");
+  if (!amp) return fail(c, LW_EINVAL, "amplitude state is NULL");
+  if (((uintptr_t)amp & 15) != 0) return fail(c, LW_EINVAL, "amplitude state must be 16-byte aligned");
+  size_t need = 0;
+  st = lw_amplitude_workspace_size(c, b->n_particles, &need);
+  if (st != LW_OK) return st;
+  if (!ws || ws_bytes < need)
+    return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
+  if (((uintptr_t)ws & 255) != 0) return fail(c, LW_EINVAL, "workspace must be 256-byte aligned");
+  DeviceGuard g(c->device);
+  const int ncomp = lw::direct_ncomp(c);
+  const int64_t cols = (int64_t)c->nd * c->nw;
+  const int64_t n_blocks = (b->n_particles + lw::kAmpRows - 1) / lw::kAmpRows;
+  LW_HIP(lw::launch_amp_reduce(amp, b->n_particles, cols, b->charge, b->weight, b->species, c->ns,
+                               ncomp, (double*)ws, c->d_err, c->stream),
+         "launch lw_amp_reduce");
+  LW_HIP(lw::launch_reduce_partials((const double*)ws, n_blocks, (int64_t)c->ns * cols * ncomp,
+                                    direct_target(c), c->stream),
+         "launch lw_reduce_partials");
+  return LW_OK;
 }
 
 lw_status lw_stats(const lw_ctx* c, int64_t* calls) {

@@ -17,10 +17,14 @@
 //      four FP32 FMAs add g1, g2 times (cos, sin) into the running sums.  The
 //      FP32 sums are folded into FP64 every 16 samples.
 // At the end of a particle, w q^2 |A|^2 / (4 pi^2) is added (FP64) to an LDS
-// accumulator of the particle's species; at the end of the item the
-// accumulators are written to the item's own rows of the partial buffer, and
-// lw_reduce_partials sums the rows in a fixed order, so results are bitwise
-// reproducible.
+// accumulator of the particle's species (incoherent synthesis); in coherent
+// synthesis the four amplitude components times w q are added instead, so the
+// particles of a species interfere before the square is taken.  At the end of
+// the item the accumulators are written to the item's own rows of the partial
+// buffer, and lw_reduce_partials sums the rows in a fixed order, so results are
+// bitwise reproducible.  With a per-particle amplitude state (in-situ
+// recording over time windows) the raw amplitude A_p of the window is added to
+// the particle's own state row; that pass needs no LDS accumulator.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -89,9 +93,10 @@ __device__ __forceinline__ void direct_item(const DirectArgs& a, int64_t item, S
     e1[c] = a.dirs[kDirStride * d + 3 + c];
     e2[c] = a.dirs[kDirStride * d + 6 + c];
   }
-  for (int s = 0; s < a.ns; ++s)
+  const int nrow = a.partial ? a.ns * a.ncomp : 0;  // LDS accumulator rows of WPT x kThreads
+  for (int r = 0; r < nrow; ++r)
 #pragma unroll
-    for (int i = 0; i < WPT; ++i) sacc[(s * WPT + i) * kThreads + tid] = 0.0;
+    for (int i = 0; i < WPT; ++i) sacc[(r * WPT + i) * kThreads + tid] = 0.0;
 
   const int64_t p0 = blk * a.pb;
   const int64_t p1 = min(p0 + (int64_t)a.pb, a.b.n_particles);
@@ -143,28 +148,48 @@ __device__ __forceinline__ void direct_item(const DirectArgs& a, int64_t item, S
           for (int c = 0; c < 4; ++c) acc[i][c] += (double)f32[i][c];
       }
     }
+    if (a.amp) {  // this thread alone owns rows (p, d, jw[i]) of the state
+#pragma unroll
+      for (int i = 0; i < WPT; ++i) {
+        if (jw[i] < a.nw) {
+          double* o = a.amp + (((size_t)p * a.nd + d) * a.nw + jw[i]) * 4;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) o[c] += acc[i][c];
+        }
+      }
+    }
+    if (!a.partial) continue;
     int sp = a.b.species ? a.b.species[p] : 0;
     if (sp < 0 || sp >= a.ns) {  // out-of-range species: reported, contributes nothing
       if (tid == 0) record_error(a.err, p);
       continue;
     }
     const double q = (double)a.b.charge[p];
-    const double fac = (double)a.b.weight[p] * q * q * (1.0 / (4.0 * M_PI * M_PI));
+    const double wq = (double)a.b.weight[p] * q;
+    const double fac = wq * q * (1.0 / (4.0 * M_PI * M_PI));
+    if (a.ncomp == 4) {
+#pragma unroll
+      for (int i = 0; i < WPT; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sacc[((sp * 4 + c) * WPT + i) * kThreads + tid] += wq * acc[i][c];
+    }
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
       const double s2 = fac * (acc[i][0] * acc[i][0] + acc[i][1] * acc[i][1] +
                                acc[i][2] * acc[i][2] + acc[i][3] * acc[i][3]);
-      sacc[(sp * WPT + i) * kThreads + tid] += s2;
+      if (a.ncomp == 1) sacc[(sp * WPT + i) * kThreads + tid] += s2;
       if (a.per_particle && jw[i] < a.nw)
         a.per_particle[((size_t)p * a.nd + d) * a.nw + jw[i]] = (float)s2;
     }
   }
+  if (!a.partial) return;
   for (int s = 0; s < a.ns; ++s) {
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
-      if (jw[i] < a.nw)
-        a.partial[(((size_t)blk * a.ns + s) * a.nd + d) * a.nw + jw[i]] =
-            sacc[(s * WPT + i) * kThreads + tid];
+      if (jw[i] >= a.nw) continue;
+      const size_t row = (((size_t)blk * a.ns + s) * a.nd + d) * a.nw + jw[i];
+      for (int c = 0; c < a.ncomp; ++c)
+        a.partial[row * a.ncomp + c] = sacc[((s * a.ncomp + c) * WPT + i) * kThreads + tid];
     }
   }
 }
@@ -172,7 +197,7 @@ __device__ __forceinline__ void direct_item(const DirectArgs& a, int64_t item, S
 template <int WPT>
 __global__ __launch_bounds__(kThreads) void lw_direct_f32_kernel(DirectArgs a) {
   __shared__ Staged stage[kThreads];
-  extern __shared__ double sacc[];  // [ns][kThreads * WPT]
+  extern __shared__ double sacc[];  // [ns][ncomp][WPT][kThreads]
   direct_item<WPT>(a, blockIdx.x, stage, sacc);
 }
 
@@ -181,7 +206,7 @@ template <int WPT>
 __global__ __launch_bounds__(kThreads) void lw_direct_f32_persistent_kernel(DirectArgs a) {
   __shared__ Staged stage[kThreads];
   __shared__ int64_t s_item;
-  extern __shared__ double sacc[];  // [ns][kThreads * WPT]
+  extern __shared__ double sacc[];  // [ns][ncomp][WPT][kThreads]
   for (;;) {
     __syncthreads();  // the previous item's LDS use is over
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.ticket, 1u);
@@ -214,7 +239,8 @@ __global__ void fill_u64_kernel(unsigned long long* p, int64_t n, unsigned long 
 hipError_t launch_direct_f32(const DirectArgs& a, int wpt, hipStream_t stream) {
   const int64_t items = a.n_blocks * (int64_t)a.nd * a.n_tiles;
   if (items <= 0) return hipSuccess;
-  const size_t shmem = sizeof(double) * (size_t)a.ns * kThreads * wpt;
+  const size_t shmem = a.partial ? direct_lds(a.ns, a.ncomp, wpt) : 0;
+  if (shmem > kMaxDirectLds) return hipErrorInvalidValue;
   dim3 grid((unsigned)items), block(kThreads);
   const void* fn = nullptr;
   switch (wpt) {
@@ -240,7 +266,8 @@ hipError_t launch_direct_f32(const DirectArgs& a, int wpt, hipStream_t stream) {
 hipError_t launch_direct_f32_persistent(const DirectArgs& a, int wpt, int workgroups,
                                         hipStream_t stream) {
   if (a.n_items <= 0) return hipSuccess;
-  const size_t shmem = sizeof(double) * (size_t)a.ns * kThreads * wpt;
+  const size_t shmem = a.partial ? direct_lds(a.ns, a.ncomp, wpt) : 0;
+  if (shmem > kMaxDirectLds) return hipErrorInvalidValue;
   const void* fn = nullptr;
   switch (wpt) {
     case 1: fn = (const void*)lw_direct_f32_persistent_kernel<1>; break;

@@ -34,11 +34,13 @@ struct DirectArgs {
   const double* dirs;    // [nd][kDirStride]
   const double* wturn;   // [nw] omega / (2 pi): frequency in turns per unit time
   int32_t nd, nw, ns;
+  int32_t ncomp;         // rows per (species, direction, frequency): 1 = power, 4 = amplitude
   int32_t pb;            // particles per work item
   int64_t n_blocks;      // ceil(P / pb)
   int32_t n_tiles;       // frequency tiles of kThreads * WPT
-  double* partial;       // [n_blocks][ns][nd][nw]
+  double* partial;       // [n_blocks][ns][nd][nw][ncomp], or null (amplitude state only)
   float* per_particle;   // [P][nd][nw] or null
+  double* amp;           // per-particle amplitude state [P][nd][nw][4] (added into), or null
   unsigned long long* err;  // lowest offending particle index (atomic min)
   // persistent launch (all null/0 for the plain grid)
   const int64_t* perm;   // particle order (blocks take consecutive entries), or null
@@ -59,6 +61,16 @@ hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v,
                            hipStream_t stream);
 
+// Amplitude state (lw_amplitude.hip).  Particles per row block of the state reduction.
+constexpr int kAmpRows = 256;
+// partial[blk][ns][cols][ncomp] from amp[P][cols][4]: w q^2 |a|^2 / (4 pi^2) (ncomp 1) or
+// w q a (ncomp 4), summed over the block's particles by species.
+hipError_t launch_amp_reduce(const double* amp, int64_t P, int64_t cols, const float* charge,
+                             const float* weight, const int32_t* species, int ns, int ncomp,
+                             double* partial, unsigned long long* err, hipStream_t stream);
+// S[i] = |A_i|^2 / (4 pi^2) for the n four-component amplitudes A.
+hipError_t launch_coherent_power(const double* A, int64_t n, double* S, hipStream_t stream);
+
 struct MfmaPlanCache;
 
 }  // namespace lw
@@ -74,6 +86,9 @@ struct lw_ctx {
   double* d_wturn = nullptr;     // omega / (2 pi)
   double* d_omega = nullptr;
   double* d_S = nullptr;         // [ns][nd][nw]
+  // coherent synthesis: summed amplitudes [ns][nd][nw][4] = (Re, Im) on e1, then on e2
+  bool coherent = false;
+  double* d_A = nullptr;
   unsigned long long* d_err = nullptr;
   std::string err;
   int64_t calls = 0;
@@ -91,7 +106,7 @@ struct lw_ctx {
     bool valid = false;
     const void* offsets = nullptr;  // batch identity the plan was made for
     int64_t n = -1;
-    int32_t nd = 0, nw = 0, ns = 0, wpt = 0, pb = 0, n_tiles = 0;
+    int32_t nd = 0, nw = 0, ns = 0, ncomp = 0, wpt = 0, pb = 0, n_tiles = 0;
     int64_t n_blocks = 0, n_items = 0;
     int workgroups = 0;
     int64_t* d_perm = nullptr;
@@ -123,9 +138,17 @@ inline int pick_wpt(int32_t nw) {
   if (nw <= 4 * kThreads) return 4;
   return 8;
 }
+// Rows per (species, direction, frequency) of the FP32 accumulator in this context's mode.
+inline int direct_ncomp(const lw_ctx* c) { return c->coherent ? 4 : 1; }
+// LDS of the per-species accumulator: ns * ncomp * WPT * kThreads doubles, kept within 160 KiB.
+constexpr size_t kMaxDirectLds = 160 * 1024;
+inline size_t direct_lds(int ns, int ncomp, int wpt) {
+  return sizeof(double) * (size_t)ns * ncomp * kThreads * wpt;
+}
 inline DirectShape direct_shape(const lw_ctx* c, int64_t P) {
   DirectShape s;
   s.wpt = c->tune_wpt ? c->tune_wpt : pick_wpt(c->nw);
+  while (s.wpt > 1 && direct_lds(c->ns, direct_ncomp(c), s.wpt) > kMaxDirectLds) s.wpt /= 2;
   s.n_tiles = (c->nw + kThreads * s.wpt - 1) / (kThreads * s.wpt);
   // aim at >= 8 work-groups per compute unit (256 CUs) before batching particles
   const int64_t per_particle_items = (int64_t)c->nd * s.n_tiles;

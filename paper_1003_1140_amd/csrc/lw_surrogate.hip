@@ -637,6 +637,10 @@ lw_status lw_surrogate_accumulate(lw_ctx* c, const lw_batch* b, const float* ylo
     c->err = "grids not set";
     return LW_ESTATE;
   }
+  if (c->coherent) {
+    c->err = "the surrogate estimates incoherent spectra only";
+    return LW_EUNSUPPORTED;
+  }
   const int64_t P = b->n_particles;
   if (P == 0) return LW_OK;
   const int64_t cols = (int64_t)c->nd * c->nw;

@@ -55,13 +55,19 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
   (void)hipGetDevice(&prev);
   if (prev != c->device) (void)hipSetDevice(c->device);
 
-  const size_t nS = (size_t)c->ns * c->nd * c->nw;
+  if (c->coherent && path != LW_PATH_FP32) {
+    c->err = "coherent synthesis runs on the FP32 path only";
+    return LW_EUNSUPPORTED;
+  }
+  // the accumulator the timed runs add into: S, or the summed amplitudes in coherent synthesis
+  double* acc = c->coherent ? c->d_A : c->d_S;
+  const size_t nS = (size_t)c->ns * c->nd * c->nw * (c->coherent ? 4 : 1);
   double* saved = nullptr;
   if (hipMalloc(&saved, nS * sizeof(double)) != hipSuccess) {
     c->err = "hipMalloc failed while tuning";
     return LW_ENOMEM;
   }
-  (void)hipMemcpyAsync(saved, c->d_S, nS * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(saved, acc, nS * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
 
   std::vector<Candidate> cands;
   const bool fp32 = path == LW_PATH_FP32;
@@ -135,7 +141,7 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   // restore the accumulator
-  (void)hipMemcpyAsync(c->d_S, saved, nS * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(acc, saved, nS * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(saved);
   if (st != LW_OK) {

@@ -30,7 +30,9 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_mlp_create", "lw_mlp_destroy", "lw_mlp_num_params", "lw_mlp_get_params",
             "lw_mlp_set_params", "lw_mlp_set_input_norm", "lw_mlp_set_output_skip",
             "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
-            "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets")
+            "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets",
+            "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
+            "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes")
 
 
 class LWError(RuntimeError):
@@ -108,6 +110,13 @@ def load_library():
                                                  ctypes.POINTER(D)]),
             "lw_mlp_train_head_step": (ctypes.c_int, [P, P, P, I64, ctypes.c_float, ctypes.POINTER(D)]),
             "lw_profile_read": (ctypes.c_int, [P, P]),
+            "lw_set_coherent": (ctypes.c_int, [P, I32]),
+            "lw_get_basis": (ctypes.c_int, [P, P]),
+            "lw_read_amplitudes": (ctypes.c_int, [P, P]),
+            "lw_load_amplitudes": (ctypes.c_int, [P, P]),
+            "lw_accumulate_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
+            "lw_amplitude_workspace_size": (ctypes.c_int, [P, I64, ctypes.POINTER(SZ)]),
+            "lw_spectrum_from_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, SZ]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -177,6 +186,7 @@ class Context:
         self.h = h
         self.nd = self.nw = 0
         self.ns = 1
+        self.coherent = False
         self.dirs = None
         self._children = weakref.WeakSet()  # networks and graphs, destroyed before the context
 
@@ -258,6 +268,52 @@ class Context:
         s = np.ascontiguousarray(S, dtype=np.float64)
         assert s.size == self.ns * self.nd * self.nw
         self._check(self.lib.lw_load_accumulator(self.h, _np_ptr(s)))
+
+    # ---- coherent synthesis and in-situ recording ----
+    def set_coherent(self, coherent=True):
+        self._check(self.lib.lw_set_coherent(self.h, 1 if coherent else 0))
+        self.coherent = bool(coherent)
+
+    def get_basis(self):
+        """[nd][3][3]: n, e1, e2 per direction."""
+        out = np.zeros((self.nd, 9), dtype=np.float64)
+        self._check(self.lib.lw_get_basis(self.h, _np_ptr(out)))
+        return out.reshape(self.nd, 3, 3)
+
+    def read_amplitudes(self):
+        """Summed amplitudes [ns][nd][nw][4]: (Re, Im) on e1, then on e2 (coherent mode)."""
+        out = np.zeros((self.ns, self.nd, self.nw, 4), dtype=np.float64)
+        self._check(self.lib.lw_read_amplitudes(self.h, _np_ptr(out)))
+        return out
+
+    def load_amplitudes(self, A):
+        a = np.ascontiguousarray(A, dtype=np.float64)
+        assert a.size == 4 * self.ns * self.nd * self.nw
+        self._check(self.lib.lw_load_amplitudes(self.h, _np_ptr(a)))
+
+    def amplitude_state(self, n_particles):
+        """A zeroed per-particle amplitude state, device FP64 [n_particles][nd][nw][4]."""
+        return torch.zeros((n_particles, self.nd, self.nw, 4), dtype=torch.float64,
+                           device=f"cuda:{self.device}")
+
+    def accumulate_amplitudes(self, batch: DeviceBatch, state):
+        assert state.dtype == torch.float64 and state.is_contiguous()
+        assert state.numel() == batch.n_particles * self.nd * self.nw * 4
+        self._check(self.lib.lw_accumulate_amplitudes(self.h, ctypes.byref(batch.struct),
+                                                      ctypes.c_void_p(state.data_ptr())))
+
+    def spectrum_from_amplitudes(self, batch: DeviceBatch, state, workspace=None):
+        assert state.dtype == torch.float64 and state.is_contiguous()
+        assert state.numel() == batch.n_particles * self.nd * self.nw * 4
+        if workspace is None:
+            n = ctypes.c_size_t()
+            self._check(self.lib.lw_amplitude_workspace_size(self.h, batch.n_particles, ctypes.byref(n)))
+            workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(self.lib.lw_spectrum_from_amplitudes(self.h, ctypes.byref(batch.struct),
+                                                         ctypes.c_void_p(state.data_ptr()),
+                                                         ctypes.c_void_p(workspace.data_ptr()),
+                                                         workspace.numel()))
+        return workspace
 
     def set_mfma_options(self, bands=1, products_f16=3, products_bf16=3):
         self._check(self.lib.lw_set_mfma_options(self.h, bands, products_f16, products_bf16))

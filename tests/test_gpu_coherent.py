@@ -1,0 +1,273 @@
+"""GPU parity of coherent synthesis and in-situ (time-windowed) recording, through the C ABI.
+
+Coherent synthesis adds w_p q_p A_p over a species before squaring; in-situ
+recording integrates the amplitude from the start of the run, so a spectrum over
+a later stretch of time is the difference of two recorded ones (Section 2.2,
+recording scheme).  References come from the FP64 oracle.
+
+Tolerance.  The FP32 path holds each particle's |A_p|^2 to 1e-5 relative on bins
+at least 1e-4 of a direction's peak, i.e. its amplitude to about 5e-6.  The
+errors of different particles are independent, so the error of a summed
+amplitude is bounded by TOL times the root sum of squares of the terms,
+R = sqrt(sum_p |w_p q_p A_p|^2).  Summed amplitudes are compared against that
+scale on bins whose R^2 is at least 1e-4 of the direction's largest; where the
+particles add in phase (identical copies) the coherent power itself is held to
+the incoherent bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import Batch, configs, orbits
+
+from _parity import band_relative_error
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _ctx(dirs, omega, ns=1, coherent=True):
+    from paper_1003_1140_amd import Context
+
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(omega)
+    c.set_species(ns)
+    c.set_coherent(coherent)
+    return c
+
+
+def _xyz(A4, basis):
+    """[..., nd, nw, 4] on (e1, e2) -> complex [..., nd, nw, 3]."""
+    e1 = basis[:, 1, :][:, None, :]
+    e2 = basis[:, 2, :][:, None, :]
+    a1 = (A4[..., 0] + 1j * A4[..., 1])[..., None]
+    a2 = (A4[..., 2] + 1j * A4[..., 3])[..., None]
+    return a1 * e1 + a2 * e2
+
+
+def _rss2(batch, dirs, omega, ns):
+    """sum_p |w_p q_p A_p|^2 per (s, d, j) from the oracle (weights squared)."""
+    b2 = batch.select(np.arange(batch.n_particles))
+    b2.weight = batch.weight.astype(np.float64) ** 2
+    return oracle.spectrum(b2, dirs, omega, n_species=ns) * (4 * np.pi**2)
+
+
+def _amp_error(A_gpu, A_ref, rss2, floor=1e-4):
+    """max over live bins of |A_gpu - A_ref| / R, R^2 >= floor * max over the direction."""
+    err = np.sqrt(np.sum(np.abs(A_gpu - A_ref) ** 2, axis=-1))
+    r = np.sqrt(rss2)
+    worst = 0.0
+    for idx in np.ndindex(rss2.shape[:-1]):
+        if rss2[idx].max() == 0.0:  # no particle of this species: nothing may appear
+            assert np.all(err[idx] == 0.0)
+            continue
+        m = rss2[idx] >= floor * rss2[idx].max()
+        if m.any():
+            worst = max(worst, float(np.max(err[idx][m] / r[idx][m])))
+    return worst
+
+
+def _run_coherent(batch, dirs, omega, ns):
+    from paper_1003_1140_amd import DeviceBatch
+
+    c = _ctx(dirs, omega, ns)
+    c.accumulate(DeviceBatch.from_host(batch))
+    S = c.read_spectra()
+    A = _xyz(c.read_amplitudes(), c.get_basis())
+    c.close()
+    return S, A
+
+
+@pytest.mark.parametrize("case", ["jitter", "uneven_species"])
+def test_coherent_matches_oracle(case):
+    if case == "jitter":
+        b = workloads.generate(configs.jitter_recipe(), 0, 40)
+        dirs, om, ns = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024), 1
+    else:
+        b = workloads.generate(configs.uneven_recipe(), 0, 18)
+        dirs, om, ns = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 700), 3
+    S_ref, A_ref = oracle.coherent_spectrum(b, dirs, om, n_species=ns, with_amplitude=True)
+    S, A = _run_coherent(b, dirs, om, ns)
+    rss2 = _rss2(b, dirs, om, ns)
+    e = _amp_error(A, A_ref, rss2)
+    print(f"[coherent] {case}: amplitude error / R = {e:.3e}", flush=True)
+    assert e <= TOL
+    # the power follows from the amplitude: |S - S_ref| <= (2 |A| dA + dA^2) / (4 pi^2)
+    dA = TOL * np.sqrt(rss2)
+    live = rss2 >= 1e-4 * rss2.max(axis=-1, keepdims=True)
+    bound = (2 * np.sqrt(S_ref * 4 * np.pi**2) * dA + dA**2) / (4 * np.pi**2)
+    assert np.all(np.abs(S - S_ref)[live] <= bound[live] * 1.0001 + 1e-300)
+
+
+def test_in_phase_copies_hold_the_incoherent_bar():
+    cfg = configs.synchrotron_setup()
+    one = orbits.circular(cfg["gamma"], 1.0, cfg["n"], cfg["dt"], accel_dtype=np.float32)
+    b = Batch.concat([one] * 7)
+    S, _ = _run_coherent(b, cfg["dirs"], cfg["omega"], 1)
+    ref = oracle.coherent_spectrum(b, cfg["dirs"], cfg["omega"], n_species=1)
+    np.testing.assert_allclose(ref, 49.0 * oracle.spectrum(one, cfg["dirs"], cfg["omega"], n_species=1),
+                               rtol=1e-12)
+    assert band_relative_error(S, ref) <= TOL
+
+
+def test_opposite_charges_cancel_exactly():
+    b1 = workloads.generate(configs.jitter_recipe(), 3, 1)
+    b2 = b1.select([0])
+    b2.charge = -b1.charge
+    b = Batch.concat([b1, b2])
+    S, A = _run_coherent(b, configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 300), 1)
+    assert np.all(S == 0.0) and np.all(A == 0.0)
+
+
+def _windows(b, cuts):
+    edges = [0, *cuts, int(b.lengths().max()) + 1]
+    return [b.time_window(k0, k1) for k0, k1 in zip(edges[:-1], edges[1:])]
+
+
+def test_coherent_time_windows_and_snapshot_differences():
+    from paper_1003_1140_amd import DeviceBatch
+
+    b = workloads.generate(configs.uneven_recipe(), 100, 12)
+    dirs, om = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 512)
+    wins = _windows(b, [700, 1500])
+    c = _ctx(dirs, om, 3)
+    basis = c.get_basis()
+    A_snap, S_snap = [], []
+    for w in wins:
+        c.accumulate(DeviceBatch.from_host(w))
+        S_snap.append(c.read_spectra())
+        A_snap.append(_xyz(c.read_amplitudes(), basis))
+    c.close()
+    # error scale: every (particle, window) term is rounded on its own
+    rss2 = _rss2(Batch.concat(wins), dirs, om, 3)
+    recorded = None
+    for i, w in enumerate(wins):
+        recorded = w if recorded is None else Batch.concat([recorded, w])
+        S_ref, A_ref = oracle.coherent_spectrum(recorded, dirs, om, n_species=3, with_amplitude=True)
+        e = _amp_error(A_snap[i], A_ref, rss2)
+        print(f"[coherent] snapshot {i}: amplitude error / R = {e:.3e}", flush=True)
+        assert e <= TOL
+    # the spectrum of the last stretch is the difference of the last two snapshots
+    full = oracle.coherent_spectrum(b, dirs, om, n_species=3)
+    upto = oracle.coherent_spectrum(Batch.concat(wins[:2]), dirs, om, n_species=3)
+    d_gpu, d_ref = S_snap[2] - S_snap[1], full - upto
+    scale = np.max(rss2, axis=-1) / (4 * np.pi**2)
+    empty = scale == 0  # a species with no particles in this sample
+    assert np.all(d_gpu[empty] == 0.0)
+    assert np.max(np.abs(d_gpu - d_ref)[~empty] / scale[~empty][:, None]) <= 4 * TOL
+
+
+def test_incoherent_amplitude_state_over_windows():
+    from paper_1003_1140_amd import DeviceBatch
+
+    b = workloads.generate(configs.uneven_recipe(), 200, 16)
+    dirs, om = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 600)
+    wins = _windows(b, [300, 1100, 1101])
+    c = _ctx(dirs, om, 3, coherent=False)
+    state = c.amplitude_state(b.n_particles)
+    naive = np.zeros((3, len(dirs), len(om)))
+    for w in wins:
+        dw = DeviceBatch.from_host(w)
+        c.accumulate_amplitudes(dw, state)
+        c.reset()
+        c.accumulate(dw)
+        naive += c.read_spectra()
+    c.reset()
+    c.spectrum_from_amplitudes(DeviceBatch.from_host(b), state)
+    S = c.read_spectra()
+    ref = oracle.spectrum(b, dirs, om, n_species=3)
+    print(f"[in-situ] incoherent state: band error {band_relative_error(S, ref):.3e}, "
+          f"per-window sum off by {band_relative_error(naive, ref):.3e}", flush=True)
+    assert band_relative_error(S, ref) <= TOL
+    # squaring each window alone drops the cross terms between windows
+    assert band_relative_error(naive, ref) > 100 * TOL
+    # each particle's state row is its own amplitude
+    st = _xyz(state.cpu().numpy(), c.get_basis())
+    for p in (0, 5, 15):
+        one = b.select([p])
+        one.charge = np.ones(1)
+        one.weight = np.ones(1)
+        one.species = np.zeros(1, dtype=np.int32)
+        _, a_ref = oracle.coherent_spectrum(one, dirs, om, n_species=1, with_amplitude=True)
+        e = _amp_error(st[p][None], a_ref, np.sum(np.abs(a_ref) ** 2, axis=-1))
+        assert e <= TOL, (p, e)
+    c.close()
+
+
+def test_amplitude_state_reduces_like_the_accumulator():
+    """One window: the state's spectrum equals lw_accumulate's up to summation order."""
+    from paper_1003_1140_amd import DeviceBatch
+
+    b = workloads.generate(configs.uneven_recipe(), 0, 700)  # several row blocks of the reduction
+    dirs, om = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 300)
+    db = DeviceBatch.from_host(b)
+    for coherent in (False, True):
+        c = _ctx(dirs, om, 3, coherent=coherent)
+        c.accumulate(db)
+        direct = c.read_spectra()
+        state = c.amplitude_state(b.n_particles)
+        c.accumulate_amplitudes(db, state)
+        c.reset()
+        c.spectrum_from_amplitudes(db, state)
+        via_state = c.read_spectra()
+        if coherent:
+            np.testing.assert_allclose(via_state, direct, rtol=1e-9, atol=1e-12 * direct.max())
+        else:
+            np.testing.assert_allclose(via_state, direct, rtol=1e-12, atol=0)
+        c.close()
+
+
+def test_graph_replays_in_coherent_mode():
+    from paper_1003_1140_amd import DeviceBatch
+
+    b = workloads.generate(configs.jitter_recipe(), 7, 20)
+    dirs, om = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 256)
+    db = DeviceBatch.from_host(b)
+    c = _ctx(dirs, om)
+    c.accumulate(db)
+    A1 = c.read_amplitudes()
+    c.reset()
+    g = c.graph_capture(db)
+    for k in range(1, 4):
+        g.launch()
+        A = c.read_amplitudes()  # eager work and a synchronisation between replays
+        np.testing.assert_allclose(A, k * A1, rtol=1e-12, atol=1e-12 * np.abs(A1).max())
+    g.close()
+    c.close()
+
+
+def test_coherent_mode_errors_and_resume():
+    from paper_1003_1140_amd import DeviceBatch, LWError
+
+    b = workloads.generate(configs.jitter_recipe(), 0, 4)
+    dirs, om = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 128)
+    db = DeviceBatch.from_host(b)
+    c = _ctx(dirs, om)
+    with pytest.raises(LWError) as ei:
+        c.accumulate(db, "mfma_f16")
+    assert ei.value.status == -6
+    with pytest.raises(LWError) as ei:
+        c.load_accumulator(np.zeros((1, len(dirs), len(om))))
+    assert ei.value.status == -4
+    c.accumulate(db)
+    A = c.read_amplitudes()
+    S = c.read_spectra()
+    # resume: reload the amplitudes into a fresh coherent context, add the same batch again
+    c2 = _ctx(dirs, om)
+    c2.load_amplitudes(A)
+    np.testing.assert_array_equal(c2.read_spectra(), S)
+    c2.accumulate(db)
+    c.accumulate(db)
+    np.testing.assert_array_equal(c2.read_amplitudes(), c.read_amplitudes())
+    # the tuner restores the summed amplitudes
+    before = c.read_amplitudes()
+    c.tune(db, "fp32", repeats=1)
+    np.testing.assert_array_equal(c.read_amplitudes(), before)
+    c.set_coherent(False)
+    with pytest.raises(LWError) as ei:
+        c.read_amplitudes()
+    assert ei.value.status == -4
+    c2.close()
+    c.close()
