@@ -47,6 +47,7 @@ def fp32_term_peak():
 
 
 PEAK_MFMA_TFLOPS = 2500.0  # dense FP16/BF16 matrix peak of one MI355X
+PEAK_HBM_GBS = 8000.0  # HBM3E bandwidth of one MI355X
 
 
 def split_path(name):
@@ -75,6 +76,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-insitu", action="store_true")
+    ap.add_argument("--windows", type=int, default=4, help="time windows of the in-situ leg")
     ap.add_argument("--batched-particles", type=int, default=8000,
                     help="particles of the uneven three-species workload in the batched leg")
     ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
@@ -202,6 +205,135 @@ def upload_ensemble(recipe, n, chunk, dev, host=False):
     b = DeviceBatch(tensors, n)
     b.n_samples_host = ns
     return b
+
+
+def window_batches(batch, n_windows, dev):
+    """Split a batch of equal-length trajectories into n_windows consecutive time windows
+    (each particle's t0 moved to the window's first sample), as an in-situ recorder sees
+    the run between snapshots."""
+    import torch
+
+    from paper_1003_1140_amd import DeviceBatch
+
+    P = batch.n_particles
+    offs = batch.t["offsets"].cpu().numpy()
+    L = int(offs[1] - offs[0]) if P else 0
+    assert np.all(np.diff(offs) == L), "window_batches needs equal trajectory lengths"
+    edges = [round(i * L / n_windows) for i in range(n_windows + 1)]
+    out = []
+    for k0, k1 in zip(edges[:-1], edges[1:]):
+        t = {}
+        for k, v in batch.t.items():
+            if k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
+                t[k] = v.view(P, L)[:, k0:k1].contiguous().view(-1)
+            elif k == "offsets":
+                t[k] = torch.arange(P + 1, dtype=torch.int64, device=dev) * (k1 - k0)
+            elif k == "t0":
+                t[k] = v + k0 * batch.t["dt"]
+            else:
+                t[k] = v
+        out.append(DeviceBatch(t, P))
+    return out
+
+
+def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
+    """Coherent synthesis and in-situ recording on the headline ensemble (FP32 path).
+
+    coherent: one pass adding w q A_p into the summed species amplitude.
+    in-situ: the run cut into time windows; each window's amplitudes are added to a
+    per-particle FP64 state and a spectrum snapshot is taken from the state after
+    every window (what the recording scheme does between simulation steps); the last
+    snapshot must equal the one-pass spectrum."""
+    import torch
+
+    from paper_1003_1140_amd import Context
+
+    dev = torch.device("cuda:0")
+    res = {}
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(om)
+    c.set_coherent(True)
+    ws = c.workspace(batch, "fp32")
+    c.accumulate(batch, "fp32", workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    c.reset()
+    steps = max(1, min(a.steps, 2))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.accumulate(batch, "fp32", workspace=ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    S_coh = c.read_spectra()
+    res["coherent_terms_per_s"] = terms_per_step * steps / el
+    res["coherent_over_incoherent_peak"] = float(S_coh.max() / (steps * steps) / S_fp32.max())
+    log(f"[bench] coherent: {res['coherent_terms_per_s']:.3e} terms/s")
+    del ws
+    c.close()
+
+    wins = window_batches(batch, a.windows, dev)
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(om)
+    state = c.amplitude_state(batch.n_particles)
+    ws = torch.empty(max(256, c.amplitude_workspace_size(batch.n_particles)), dtype=torch.uint8, device=dev)
+    c.accumulate_amplitudes(wins[0], state)  # warm-up
+    c.spectrum_from_amplitudes(batch, state, ws)
+    torch.cuda.synchronize()
+    state.zero_()
+    snap_ms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    snaps = []
+    for w in wins:
+        c.accumulate_amplitudes(w, state)
+        c.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.spectrum_from_amplitudes(batch, state, ws)
+        e1.record()
+        snaps.append(c.read_spectra())
+        snap_ms.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    avg, diag = c.spectral_diagnostics(weights=None)
+    diag_ms = (time.perf_counter() - t1) * 1e3
+    state_bytes = state.numel() * 8
+    ms = float(np.mean(snap_ms))
+    gbs = state_bytes / (ms * 1e-3) / 1e9
+    res.update({
+        "windows": a.windows,
+        "insitu_terms_per_s": terms_per_step / el,
+        "insitu_ms_per_step": el * 1e3,
+        "state_bytes": state_bytes,
+        "snapshot_ms": ms,
+        "snapshot_roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                              "kernel": "lw_amp_reduce_kernel + lw_reduce_partials"},
+        "last_snapshot_vs_one_pass_band_err": band_relative(snaps[-1], S_fp32),
+        "diagnostics_ms": diag_ms,
+        "observer_average": {"omega_peak": float(diag[0, -1, 2]), "alpha": float(diag[0, -1, 4]),
+                             "beta": float(diag[0, -1, 6])},
+        "per_observer_omega_peak": [float(x) for x in diag[0, :-1, 2]],
+    })
+    log(f"[bench] in-situ ({a.windows} windows, snapshot after each): {res['insitu_terms_per_s']:.3e} "
+        f"terms/s, snapshot {ms:.2f} ms ({gbs:.0f} GB/s), last vs one pass "
+        f"{res['last_snapshot_vs_one_pass_band_err']:.2e}")
+    del state, ws, wins
+    c.close()
+    return res
+
+
+def band_relative(S, ref, floor=1e-4):
+    S = np.asarray(S).reshape(-1, np.shape(S)[-1])
+    ref = np.asarray(ref).reshape(-1, np.shape(ref)[-1])
+    worst = 0.0
+    for s_, r_ in zip(S, ref):
+        m = r_ >= floor * r_.max()
+        if m.any():
+            worst = max(worst, float(np.max(np.abs(s_[m] - r_[m]) / r_[m])))
+    return worst
 
 
 def batched_leg(a, log):
@@ -432,6 +564,9 @@ def main():
         "roofline": r["roofline"],
         "paths": results,
     }
+    if not a.no_insitu and "fp32" in spectra:
+        out["insitu"] = insitu_leg(a, batch, terms_per_step, dirs, om, spectra["fp32"],
+                                   lambda m: print(m, file=sys.stderr, flush=True))
     del batch
     torch.cuda.empty_cache()
     if not a.no_batched:

@@ -190,6 +190,25 @@ lw_status lw_amplitude_workspace_size(lw_ctx* ctx, int64_t n_particles, size_t* 
 lw_status lw_spectrum_from_amplitudes(lw_ctx* ctx, const lw_batch* batch, const double* amp,
                                       void* workspace, size_t workspace_bytes);
 
+/* ---- spectral diagnostics (Section 3.3; observers as in Section 2.2) ----
+ * Observer-averaged spectrum and, per (species, observer) and for the average,
+ * the peak and the low/high-frequency power-law indices:
+ *   avg[s][j] = sum_d a_d S[s][d][j] / sum_d a_d  (a: host_weights [nd], a_d >= 0,
+ *               NULL = equal weights);
+ *   k = first index of the largest S over the frequency list; omega_peak = the
+ *   vertex of the parabola through (ln w, ln S) at k-1, k, k+1 when it opens
+ *   downwards (kept within [w_{k-1}, w_{k+1}]), else w_k;
+ *   alpha, beta = least-squares slopes of ln S on ln w over the bins with S > 0
+ *   and lo w_k <= w <= hi w_k; ranges = host {alpha_lo, alpha_hi, beta_lo,
+ *   beta_hi} (NULL = {0.01, 0.3, 3, 30}); NaN with fewer than two bins.
+ * S: device FP64 [n_species][nd][nw] (e.g. a snapshot difference), or NULL for the
+ * context's current spectrum (|A_s|^2 / (4 pi^2) in coherent mode).
+ * avg_out: host [n_species][nw] or NULL.  diag_out: host [n_species][nd + 1][8],
+ * each row {k, w_k, omega_peak, S_k, alpha, n_alpha, beta, n_beta}, row nd being
+ * the average's.  Synchronous; device errors of earlier calls are not reported here. */
+lw_status lw_spectral_diagnostics(lw_ctx* ctx, const double* S, const double* host_weights,
+                                  const double* ranges, double* avg_out, double* diag_out);
+
 /* ---- batched launches (uneven lengths, several species) ----
  * Plan a batch for the persistent launch (synchronous; reads the batch offsets).
  * FP32 path: particles are ordered by decreasing trajectory length and grouped

@@ -25,55 +25,74 @@
 
 namespace lw {
 
+constexpr int kUnroll = 4;
+
+template <int NCOMP>
 __global__ __launch_bounds__(256) void lw_amp_reduce_kernel(
     const double* __restrict__ amp, int64_t P, int64_t cols, const float* __restrict__ charge,
-    const float* __restrict__ weight, const int32_t* __restrict__ species, int ns, int ncomp,
+    const float* __restrict__ weight, const int32_t* __restrict__ species, int ns,
     int64_t n_blocks, double* __restrict__ partial, unsigned long long* err) {
   const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool live = col < cols;
   for (int64_t blk = blockIdx.y; blk < n_blocks; blk += gridDim.y) {
-    double acc[kMaxSpecies][4];
+    double acc[kMaxSpecies][NCOMP];
 #pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) acc[s][0] = acc[s][1] = acc[s][2] = acc[s][3] = 0.0;
+    for (int s = 0; s < kMaxSpecies; ++s)
+#pragma unroll
+      for (int c = 0; c < NCOMP; ++c) acc[s][c] = 0.0;
     const int64_t p0 = blk * kAmpRows;
     const int64_t p1 = min(p0 + (int64_t)kAmpRows, P);
-    for (int64_t p = p0; p < p1; ++p) {
-      const int sp = species ? species[p] : 0;
-      if (sp < 0 || sp >= ns) {  // reported once, contributes nothing
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(err, (unsigned long long)p);
-        continue;
+    // kUnroll rows are loaded before any is summed (more bytes in flight per wave); the
+    // sums still take the rows in particle order
+    for (int64_t pb = p0; pb < p1; pb += kUnroll) {
+      double v[kUnroll][4];
+      int sp[kUnroll];
+      double wq[kUnroll], q[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t p = pb + u;
+        const bool in = p < p1;
+        sp[u] = in ? (species ? species[p] : 0) : -1;
+        q[u] = in ? (double)charge[p] : 0.0;
+        wq[u] = in ? (double)weight[p] * q[u] : 0.0;
+        v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
+        if (in && live) {
+          const double2* src = reinterpret_cast<const double2*>(amp + ((size_t)p * cols + col) * 4);
+          const double2 lo = src[0], hi = src[1];
+          v[u][0] = lo.x;
+          v[u][1] = lo.y;
+          v[u][2] = hi.x;
+          v[u][3] = hi.y;
+        }
       }
-      double v[4] = {0.0, 0.0, 0.0, 0.0};
-      if (live) {
-        const double2* src = reinterpret_cast<const double2*>(amp + ((size_t)p * cols + col) * 4);
-        const double2 lo = src[0], hi = src[1];
-        v[0] = lo.x;
-        v[1] = lo.y;
-        v[2] = hi.x;
-        v[3] = hi.y;
-      }
-      const double q = (double)charge[p];
-      const double wq = (double)weight[p] * q;
-      if (ncomp == 4) {
 #pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s)
-          if (s == sp)
+      for (int u = 0; u < kUnroll; ++u) {
+        // rows past the block end carry sp = -1 and are skipped silently
+        if (pb + u < p1 && (sp[u] < 0 || sp[u] >= ns)) {  // reported once, contributes nothing
+          if (blockIdx.x == 0 && threadIdx.x == 0) atomicMin(err, (unsigned long long)(pb + u));
+        }
+        if (NCOMP == 4) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[s][c] += wq * v[c];
-      } else {
-        const double fac = wq * q * (1.0 / (4.0 * M_PI * M_PI));
-        const double s2 = fac * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+          for (int s = 0; s < kMaxSpecies; ++s)
 #pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s)
-          if (s == sp) acc[s][0] += s2;
+            for (int c = 0; c < NCOMP; ++c) acc[s][c] += (s == sp[u]) ? wq[u] * v[u][c] : 0.0;
+        } else {
+          const double fac = wq[u] * q[u] * (1.0 / (4.0 * M_PI * M_PI));
+          const double s2 =
+              fac * (v[u][0] * v[u][0] + v[u][1] * v[u][1] + v[u][2] * v[u][2] + v[u][3] * v[u][3]);
+#pragma unroll
+          for (int s = 0; s < kMaxSpecies; ++s) acc[s][0] += (s == sp[u]) ? s2 : 0.0;
+        }
       }
     }
     if (!live) continue;
 #pragma unroll
     for (int s = 0; s < kMaxSpecies; ++s) {
-      if (s >= ns) break;
-      double* dst = partial + (((size_t)blk * ns + s) * cols + col) * ncomp;
-      for (int c = 0; c < ncomp; ++c) dst[c] = acc[s][c];
+      if (s < ns) {
+        double* dst = partial + (((size_t)blk * ns + s) * cols + col) * NCOMP;
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) dst[c] = acc[s][c];
+      }
     }
   }
 }
@@ -96,8 +115,12 @@ hipError_t launch_amp_reduce(const double* amp, int64_t P, int64_t cols, const f
   const int64_t col_tiles = (cols + 255) / 256;
   if (col_tiles > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)col_tiles, (unsigned)std::min<int64_t>(n_blocks, 65535)), block(256);
-  hipLaunchKernelGGL(lw_amp_reduce_kernel, grid, block, 0, stream, amp, P, cols, charge, weight,
-                     species, ns, ncomp, n_blocks, partial, err);
+  if (ncomp == 4)
+    hipLaunchKernelGGL(lw_amp_reduce_kernel<4>, grid, block, 0, stream, amp, P, cols, charge, weight,
+                       species, ns, n_blocks, partial, err);
+  else
+    hipLaunchKernelGGL(lw_amp_reduce_kernel<1>, grid, block, 0, stream, amp, P, cols, charge, weight,
+                       species, ns, n_blocks, partial, err);
   return hipGetLastError();
 }
 

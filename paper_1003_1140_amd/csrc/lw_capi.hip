@@ -195,6 +195,7 @@ void lw_destroy(lw_ctx* c) {
   free_dev(c->d_omega);
   free_dev(c->d_S);
   free_dev(c->d_A);
+  free_dev(c->d_diag);
   free_dev(c->d_err);
   delete c;
 }
@@ -796,6 +797,55 @@ lw_status lw_spectrum_from_amplitudes(lw_ctx* c, const lw_batch* b, const double
   LW_HIP(lw::launch_reduce_partials((const double*)ws, n_blocks, (int64_t)c->ns * cols * ncomp,
                                     direct_target(c), c->stream),
          "launch lw_reduce_partials");
+  return LW_OK;
+}
+
+lw_status lw_spectral_diagnostics(lw_ctx* c, const double* S, const double* weights,
+                                  const double* ranges, double* avg_out, double* diag_out) {
+  if (!c || !diag_out) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  const int nd = c->nd, nw = c->nw, ns = c->ns;
+  std::vector<double> a(nd, 1.0);
+  if (weights) a.assign(weights, weights + nd);
+  double a_sum = 0.0;
+  for (int d = 0; d < nd; ++d) {
+    if (!(a[d] >= 0.0) || !isfinite(a[d])) return fail(c, LW_EINVAL, "weight %d is negative or not finite", d);
+    a_sum += a[d];
+  }
+  if (!(a_sum > 0.0)) return fail(c, LW_EINVAL, "observer weights sum to zero");
+  double r[4] = {1e-2, 0.3, 3.0, 30.0};
+  if (ranges) memcpy(r, ranges, sizeof(r));
+  for (int i = 0; i < 4; i += 2)
+    if (!(r[i] > 0.0) || !(r[i + 1] >= r[i]) || !isfinite(r[i + 1]))
+      return fail(c, LW_EINVAL, "slope window %d must satisfy 0 < lo <= hi", i / 2);
+  DeviceGuard g(c->device);
+  const size_t n_avg = (size_t)ns * nw, n_out = (size_t)ns * (nd + 1) * lw::kDiagFields;
+  const size_t need = (size_t)nd + n_avg + n_out;
+  if (c->diag_cap < need) {
+    LW_HIP(hipStreamSynchronize(c->stream), "sync");
+    free_dev(c->d_diag);
+    c->d_diag = nullptr;
+    c->diag_cap = 0;
+    LW_HIP(hipMalloc(&c->d_diag, need * sizeof(double)), "hipMalloc(diagnostics)");
+    c->diag_cap = need;
+  }
+  double* d_a = c->d_diag;
+  double* d_avg = d_a + nd;
+  double* d_out = d_avg + n_avg;
+  if (!S) {
+    if (c->coherent)
+      LW_HIP(lw::launch_coherent_power(c->d_A, (int64_t)ns * nd * nw, c->d_S, c->stream),
+             "launch coherent power");
+    S = c->d_S;
+  }
+  LW_HIP(hipMemcpyAsync(d_a, a.data(), nd * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy weights");
+  LW_HIP(lw::launch_spectral_diagnostics(S, d_a, a_sum, ns, nd, nw, c->d_omega, r, d_avg, d_out, c->stream),
+         "launch diagnostics");
+  if (avg_out)
+    LW_HIP(hipMemcpyAsync(avg_out, d_avg, n_avg * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy avg");
+  LW_HIP(hipMemcpyAsync(diag_out, d_out, n_out * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy diag");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
   return LW_OK;
 }
 

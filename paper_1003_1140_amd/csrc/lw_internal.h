@@ -71,6 +71,14 @@ hipError_t launch_amp_reduce(const double* amp, int64_t P, int64_t cols, const f
 // S[i] = |A_i|^2 / (4 pi^2) for the n four-component amplitudes A.
 hipError_t launch_coherent_power(const double* A, int64_t n, double* S, hipStream_t stream);
 
+// Spectral diagnostics (lw_diagnostics.hip): observer average avg [ns][nw] with weights a [nd]
+// (sum a_sum), then per (species, row) [k, w_k, w_peak, S_k, alpha, n_alpha, beta, n_beta]
+// into out [ns][nd + 1][8]; ranges = alpha_lo, alpha_hi, beta_lo, beta_hi.
+constexpr int kDiagFields = 8;
+hipError_t launch_spectral_diagnostics(const double* S, const double* a, double a_sum, int ns, int nd,
+                                       int nw, const double* omega, const double ranges[4],
+                                       double* avg, double* out, hipStream_t stream);
+
 struct MfmaPlanCache;
 
 }  // namespace lw
@@ -89,6 +97,9 @@ struct lw_ctx {
   // coherent synthesis: summed amplitudes [ns][nd][nw][4] = (Re, Im) on e1, then on e2
   bool coherent = false;
   double* d_A = nullptr;
+  // diagnostics scratch: weights [nd], average [ns][nw], rows [ns][nd + 1][8]
+  double* d_diag = nullptr;
+  size_t diag_cap = 0;
   unsigned long long* d_err = nullptr;
   std::string err;
   int64_t calls = 0;

@@ -32,7 +32,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
             "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets",
             "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
-            "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes")
+            "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes",
+            "lw_spectral_diagnostics")
 
 
 class LWError(RuntimeError):
@@ -117,6 +118,7 @@ def load_library():
             "lw_accumulate_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
             "lw_amplitude_workspace_size": (ctypes.c_int, [P, I64, ctypes.POINTER(SZ)]),
             "lw_spectrum_from_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, SZ]),
+            "lw_spectral_diagnostics": (ctypes.c_int, [P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -302,18 +304,43 @@ class Context:
         self._check(self.lib.lw_accumulate_amplitudes(self.h, ctypes.byref(batch.struct),
                                                       ctypes.c_void_p(state.data_ptr())))
 
+    def amplitude_workspace_size(self, n_particles) -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.lw_amplitude_workspace_size(self.h, n_particles, ctypes.byref(n)))
+        return n.value
+
     def spectrum_from_amplitudes(self, batch: DeviceBatch, state, workspace=None):
         assert state.dtype == torch.float64 and state.is_contiguous()
         assert state.numel() == batch.n_particles * self.nd * self.nw * 4
         if workspace is None:
-            n = ctypes.c_size_t()
-            self._check(self.lib.lw_amplitude_workspace_size(self.h, batch.n_particles, ctypes.byref(n)))
-            workspace = torch.empty(max(n.value, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            workspace = torch.empty(max(self.amplitude_workspace_size(batch.n_particles), 256),
+                                    dtype=torch.uint8, device=f"cuda:{self.device}")
         self._check(self.lib.lw_spectrum_from_amplitudes(self.h, ctypes.byref(batch.struct),
                                                          ctypes.c_void_p(state.data_ptr()),
                                                          ctypes.c_void_p(workspace.data_ptr()),
                                                          workspace.numel()))
         return workspace
+
+    def spectral_diagnostics(self, S=None, weights=None, alpha_range=None, beta_range=None):
+        """(average [ns][nw], rows [ns][nd + 1][8]) of S (device FP64 [ns][nd][nw] tensor) or of
+        the context's spectrum; each row {k, w_k, omega_peak, S_k, alpha, n_alpha, beta, n_beta}."""
+        avg = np.zeros((self.ns, self.nw), dtype=np.float64)
+        diag = np.zeros((self.ns, self.nd + 1, 8), dtype=np.float64)
+        sp = None
+        if S is not None:
+            assert S.dtype == torch.float64 and S.is_contiguous() and S.numel() == self.ns * self.nd * self.nw
+            sp = ctypes.c_void_p(S.data_ptr())
+        wp = None
+        if weights is not None:
+            wa = np.ascontiguousarray(weights, dtype=np.float64)
+            assert wa.size == self.nd
+            wp = _np_ptr(wa)
+        rp = None
+        if alpha_range is not None or beta_range is not None:
+            ra = np.array([*(alpha_range or (1e-2, 0.3)), *(beta_range or (3.0, 30.0))], dtype=np.float64)
+            rp = _np_ptr(ra)
+        self._check(self.lib.lw_spectral_diagnostics(self.h, sp, wp, rp, _np_ptr(avg), _np_ptr(diag)))
+        return avg, diag
 
     def set_mfma_options(self, bands=1, products_f16=3, products_bf16=3):
         self._check(self.lib.lw_set_mfma_options(self.h, bands, products_f16, products_bf16))
