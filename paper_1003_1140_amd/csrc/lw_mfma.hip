@@ -193,58 +193,84 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 }
 
 // ------------------------------------------------------------------ spreading
-// One work-group per (particle of the chunk, band); thread t owns grid point q0 + t of
-// the current window.  Samples are sorted in tau because dtau/dt = kappa > 0, so the
-// windows walk a monotone cursor through the samples: chunks of 256 samples are staged
-// in LDS (prepass, demodulation, grid coordinate) and reused while they still reach
-// the next window, and each thread finds its samples by binary search in LDS.
+// One work-group per (particle of the chunk, direction, band).  Samples are sorted in
+// tau because dtau/dt = kappa > 0, so each sample's W = 8 taps cover grid points
+// lo_s .. lo_s + 7 with lo_s = floor(u_s) - 3 nondecreasing in s.  The trajectory is
+// walked in chunks of 256 samples, each staged once:
+//   1. one thread per sample: prepass, demodulation, grid coordinate and its 8 tap
+//      weights phi(lo_s + i - u_s), kept in LDS;
+//   2. first[x] = the first sample of the chunk whose taps reach grid point base + x
+//      (built by the samples themselves, no search); the samples reaching q are then
+//      exactly first[x] .. first[x + W] - 1, since each covers W consecutive points;
+//   3. one thread (or S threads taking every S-th sample, summed with shuffles) per grid
+//      point adds w g over its samples into a ring of running grid sums in LDS;
+//   4. grid points below the next chunk's first tap are final: they are written to F
+//      (FP32) and their ring slots cleared.
+// The next chunk starts with the sample that did not fit the ring, so every grid point
+// of a chunk lies within kRing of the oldest pending one.
+constexpr int kRing = 1024;  // grid points held in LDS (power of two)
+
 struct SpreadStage {
-  int iu[kSpreadWin];      // integer part of the grid coordinate u_k
-  float fu[kSpreadWin];    // fractional part
-  float4 g[kSpreadWin];    // demodulated integrand (re1, im1, re2, im2)
+  int lo[kSpreadWin];             // first grid point of each sample's taps
+  float w[kW][kSpreadWin];        // tap weights
+  float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2)
+  int first[kRing + kW];          // first sample reaching grid point base + x
+  float4 acc[kRing];              // running grid sums, slot q mod kRing
 };
 
-__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage& st,
-                                              const double* n, const double* e1, const double* e2,
-                                              int64_t p, int64_t o, int64_t len, int64_t kc,
-                                              double t0, double dtp, double tau0, double inv_h) {
-  const int tid = threadIdx.x;
-  const int64_t k = kc + tid;
-  if (k < len) {
-    const int64_t idx = o + k;
-    const double bx = a.b.bx[idx], by = a.b.by[idx], bz = a.b.bz[idx];
-    const double ax = (double)a.b.ax[idx], ay = (double)a.b.ay[idx], az = (double)a.b.az[idx];
-    const double kap = 1.0 - dot3(n, bx, by, bz);
-    const double na = dot3(n, ax, ay, az);
-    const double sc = dtp / (kap * kap);
-    const double g1 = -(na * dot3(e1, bx, by, bz) + kap * dot3(e1, ax, ay, az)) * sc;
-    const double g2 = -(na * dot3(e2, bx, by, bz) + kap * dot3(e2, ax, ay, az)) * sc;
-    const double taup = retarded_time(a.b, idx, t0 + (double)k * dtp, n) - tau0;
-    const bool ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(taup) && isfinite(g1) && isfinite(g2);
-    if (!ok) atomicMin(a.err, (unsigned long long)p);
-    const double x = bd.wc_turn * taup;
-    const float fr = (float)(x - rint(x));
-    const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
-    double u = taup * inv_h + 0.5 * kW;
-    // keep the staged coordinates sorted and bounded even for invalid samples
-    u = ok ? fmin(fmax(u, 0.0), 1.0e9) : 1.0e9;
-    const double iu = floor(u);
-    st.iu[tid] = (int)iu;
-    st.fu[tid] = (float)(u - iu);
-    const float G1 = ok ? (float)g1 : 0.f, G2 = ok ? (float)g2 : 0.f;
-    st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
-  }
+// One sample's trajectory data, loaded a chunk ahead of its use.
+struct RawSample {
+  double x, y, z, bx, by, bz;
+  float ax, ay, az;
+};
+
+__device__ __forceinline__ void load_raw(const BatchView& b, int64_t o, int64_t len, int64_t kc,
+                                         RawSample& r) {
+  const int64_t k = kc + threadIdx.x;
+  if (k >= len) return;
+  const int64_t idx = o + k;
+  r.x = b.x[idx];
+  r.y = b.y[idx];
+  r.z = b.z[idx];
+  r.bx = b.bx[idx];
+  r.by = b.by[idx];
+  r.bz = b.bz[idx];
+  r.ax = b.ax[idx];
+  r.ay = b.ay[idx];
+  r.az = b.az[idx];
 }
 
-// number of staged samples (of cnt) with u <= x
-__device__ __forceinline__ int count_le(const SpreadStage& st, int cnt, float x_int, float x_frac) {
-  int lo = 0, hi = cnt;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    const float d = ((float)st.iu[mid] - x_int) + st.fu[mid] - x_frac;  // u_mid - x
-    if (d > 0.0f) hi = mid; else lo = mid + 1;
-  }
-  return lo;
+__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage& st,
+                                              const RawSample& r, const double* n, const double* e1,
+                                              const double* e2, int64_t p, int64_t len, int64_t kc,
+                                              double t0, double dtp, double tau0, double inv_h,
+                                              double umax) {
+  const int tid = threadIdx.x;
+  const int64_t k = kc + tid;
+  if (k >= len) return;
+  const double bx = r.bx, by = r.by, bz = r.bz;
+  const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
+  const double kap = 1.0 - dot3(n, bx, by, bz);
+  const double na = dot3(n, ax, ay, az);
+  const double sc = dtp / (kap * kap);
+  const double g1 = -(na * dot3(e1, bx, by, bz) + kap * dot3(e1, ax, ay, az)) * sc;
+  const double g2 = -(na * dot3(e2, bx, by, bz) + kap * dot3(e2, ax, ay, az)) * sc;
+  const double taup = (t0 + (double)k * dtp - dot3(n, r.x, r.y, r.z)) - tau0;
+  const bool ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(taup) && isfinite(g1) && isfinite(g2);
+  if (!ok) atomicMin(a.err, (unsigned long long)p);
+  const double x = bd.wc_turn * taup;
+  const float fr = (float)(x - rint(x));
+  const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+  // grid coordinate, kept within the grid even for invalid samples (those add nothing)
+  double u = taup * inv_h + 0.5 * kW;
+  u = ok ? fmin(fmax(u, 0.5 * kW), umax) : 0.5 * kW;
+  const double iu = floor(u);
+  const float fu = (float)(u - iu);
+  st.lo[tid] = (int)iu - (kW / 2 - 1);
+#pragma unroll
+  for (int i = 0; i < kW; ++i) st.w[i][tid] = es_kernel((float)(i - (kW / 2 - 1)) - fu);  // q - u
+  const float G1 = ok ? (float)g1 : 0.f, G2 = ok ? (float)g2 : 0.f;
+  st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
 
 __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
@@ -263,6 +289,8 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   const int ncol = 2 * a.n_local;
   const int db = d * a.nb + bi;
   float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
+  float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
+  float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
   double n[3], e1[3], e2[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -285,39 +313,57 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     Q = (int)fmin(ceil(span / bd.h) + kW + 1, (double)bd.qmax);
   }
   const double inv_h = 1.0 / bd.h;
+  // no tap may pass the grid allotment (samples beyond it only add to unwritten points)
+  const double umax = (double)bd.qmax + 0.5 * kW;
+  for (int x = tid; x < kRing; x += kSpreadWin) st.acc[x] = make_float4(0.f, 0.f, 0.f, 0.f);
   float wmax = 0.0f;
-  int64_t kc = -1;     // first sample of the staged chunk (-1: none)
-  int cnt = 0;         // samples in the staged chunk
-  int64_t cursor = 0;  // first sample that can reach the current window
-
-  for (int q0 = 0; q0 < Q; q0 += kSpreadWin) {
-    // G grid points in this window; when G is small each grid point's samples are split
-    // over S consecutive threads (slices k = s mod S) and summed with shuffles.
-    const int G = min(kSpreadWin, Q - q0);
+  int qdone = 0;  // grid points [0, qdone) are written
+  int64_t kc = 0;
+  // the chunk after this one usually starts one sample before this one ends: its data
+  // is requested while this chunk is processed
+  RawSample raw, next;
+  int64_t k_next = 0;
+  load_raw(a.b, o, len, 0, next);
+  while (kc < len) {
+    if (k_next != kc) load_raw(a.b, o, len, kc, next);  // the guess missed: load now
+    raw = next;
+    const int cnt = (int)min((int64_t)kSpreadWin, len - kc);
+    k_next = kc + (kc + cnt < len ? cnt - 1 : cnt);
+    if (k_next < len) load_raw(a.b, o, len, k_next, next);
+    __syncthreads();  // the previous chunk's LDS is no longer read
+    stage_samples(a, bd, st, raw, n, e1, e2, p, len, kc, t0, dtp, tau0, inv_h, umax);
+    __syncthreads();
+    const int base = st.lo[0];
+    // samples whose taps fit the ring; the chunk's last sample waits for the next chunk
+    // unless it ends the trajectory, so that the next chunk's first tap is known here
+    const bool more = kc + cnt < len;
+    const int fits = __syncthreads_count(tid < cnt && st.lo[tid] - base <= kRing - kW);
+    int take = min(fits, more ? cnt - 1 : cnt);
+    take = max(take, 1);
+    const int top = st.lo[take - 1] + kW - 1;  // highest grid point touched
+    const int G = min(top - base + 1, kRing);
+    // first sample reaching each grid point of the chunk
+    if (tid < take) {
+      const int prev = tid == 0 ? base - 1 : st.lo[tid - 1] + kW - 1;
+      const int mine = st.lo[tid] + kW - 1;
+      for (int x = max(prev + 1, base) - base; x <= min(mine - base, G - 1); ++x) st.first[x] = tid;
+    }
+    if (tid < kW) st.first[max(G, 0) + tid] = take;  // past the last point: no sample
+    __syncthreads();
     int S = 1;
     while (S < 64 && 2 * S * G <= kSpreadWin) S *= 2;
-    const int g = tid / S, sl = tid % S;
-    const bool active = g < G;
-    const int q = q0 + g;
-    float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-    int64_t next_cursor = -1;
-    int64_t k = cursor;
-    while (k < len) {
-      if (kc < 0 || k < kc || k >= kc + cnt) {
-        __syncthreads();  // the previous chunk is no longer read
-        stage_samples(a, bd, st, n, e1, e2, p, o, len, k, t0, dtp, tau0, inv_h);
-        kc = k;
-        cnt = (int)min((int64_t)kSpreadWin, len - k);
-        __syncthreads();
-      }
-      if (active) {
-        // staged samples with q - W/2 < u < q + W/2, this thread taking every S-th
-        int s0 = count_le(st, cnt, (float)q, -0.5f * kW);
-        s0 += (sl - s0 % S + S) % S;
-        for (int s = s0; s < cnt; s += S) {
-          const float dx = ((float)(q - st.iu[s])) - st.fu[s];  // q - u
-          if (dx <= -0.5f * kW) break;
-          const float w = es_kernel(dx);
+    const int per_pass = kSpreadWin / S;
+    for (int xb = 0; xb < G; xb += per_pass) {
+      const int x = xb + tid / S, sl = tid % S;
+      float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
+      if (x < G) {
+        const int q = base + x;
+        // (clamped, and the tap index masked: on invalid, unsorted data an entry may be stale)
+        const int s_begin = min(max(st.first[x], 0), take);
+        const int s_end = min(max(st.first[x + kW], s_begin), take);
+        for (int s = s_begin + sl; s < s_end; s += S) {
+          const int i = (q - st.lo[s]) & (kW - 1);
+          const float w = st.w[i][s];
           const float4 gv = st.g[s];
           acc0 = fmaf(w, gv.x, acc0);
           acc1 = fmaf(w, gv.y, acc1);
@@ -325,34 +371,37 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
           acc3 = fmaf(w, gv.w, acc3);
         }
       }
-      // the next window needs samples with u > q0 + win - W/2
-      if (next_cursor < 0) {
-        const int nle = count_le(st, cnt, (float)(q0 + kSpreadWin), -0.5f * kW);
-        if (nle < cnt) next_cursor = kc + nle;
+      for (int off = S >> 1; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off);
+        acc1 += __shfl_xor(acc1, off);
+        acc2 += __shfl_xor(acc2, off);
+        acc3 += __shfl_xor(acc3, off);
       }
-      // does this window need samples beyond the staged chunk?
-      const int last = cnt - 1;
-      const float dlast = ((float)st.iu[last] - (float)(q0 + G - 1)) + st.fu[last] - 0.5f * kW;
-      if (kc + cnt < len && dlast < 0.0f) {
-        k = kc + cnt;
-        continue;
+      if (x < G && sl == 0) {
+        float4& r = st.acc[(base + x) & (kRing - 1)];
+        r.x += acc0;
+        r.y += acc1;
+        r.z += acc2;
+        r.w += acc3;
       }
-      break;
     }
-    cursor = next_cursor >= 0 ? next_cursor : len;
-    for (int off = S >> 1; off > 0; off >>= 1) {
-      acc0 += __shfl_xor(acc0, off);
-      acc1 += __shfl_xor(acc1, off);
-      acc2 += __shfl_xor(acc2, off);
-      acc3 += __shfl_xor(acc3, off);
+    __syncthreads();
+    // grid points below the next chunk's first tap are final
+    int qfin = Q;
+    if (kc + take < len) qfin = min(Q, take < cnt ? st.lo[take] : top + 1);
+    for (int q = qdone + tid; q < qfin; q += kSpreadWin) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (q <= top) {  // beyond it nothing was added (and the slot may hold a newer point)
+        float4& r = st.acc[q & (kRing - 1)];
+        v = r;
+        r = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      *(float2*)(c0 + 2 * q) = make_float2(v.x, v.y);
+      *(float2*)(c1 + 2 * q) = make_float2(v.z, v.w);
+      wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
     }
-    if (active && sl == 0) {
-      float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
-      float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
-      *(float2*)(c0 + 2 * q) = make_float2(acc0, acc1);
-      *(float2*)(c1 + 2 * q) = make_float2(acc2, acc3);
-      wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(acc0), fabsf(acc1)), fmaxf(fabsf(acc2), fabsf(acc3))));
-    }
+    qdone = max(qdone, qfin);
+    kc += take;
   }
   // column maximum (one value for both polarisation columns keeps them on one scale)
   for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off));
