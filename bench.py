@@ -266,6 +266,23 @@ def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
     el = time.perf_counter() - t0
     S_coh = c.read_spectra()
     res["coherent_terms_per_s"] = terms_per_step * steps / el
+    # the same on the matrix-core path (FP16 hi/lo), checked against the FP32 coherent pass
+    c.set_mfma_options(1, 3, 3)
+    wsm = c.workspace(batch, "mfma_f16")
+    c.reset()
+    c.accumulate(batch, "mfma_f16", workspace=wsm)  # warm-up
+    torch.cuda.synchronize()
+    c.reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.accumulate(batch, "mfma_f16", workspace=wsm)
+    torch.cuda.synchronize()
+    el_m = time.perf_counter() - t0
+    res["coherent_mfma_f16x3_terms_per_s"] = terms_per_step * steps / el_m
+    res["coherent_mfma_vs_fp32_band_err"] = float(np.max(band_integrated_error(c.read_spectra(), S_coh, om)))
+    del wsm
+    log(f"[bench] coherent mfma_f16x3: {res['coherent_mfma_f16x3_terms_per_s']:.3e} terms/s, band error vs "
+        f"coherent fp32 {res['coherent_mfma_vs_fp32_band_err']:.2e}")
     res["coherent_over_incoherent_peak"] = float(S_coh.max() / (steps * steps) / S_fp32.max())
     log(f"[bench] coherent: {res['coherent_terms_per_s']:.3e} terms/s")
     del ws
@@ -320,6 +337,28 @@ def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
     log(f"[bench] in-situ ({a.windows} windows, snapshot after each): {res['insitu_terms_per_s']:.3e} "
         f"terms/s, snapshot {ms:.2f} ms ({gbs:.0f} GB/s), last vs one pass "
         f"{res['last_snapshot_vs_one_pass_band_err']:.2e}")
+    # the same recording with the windows' amplitudes from the matrix-core path (FP16 hi/lo)
+    c.set_mfma_options(1, 3, 3)
+    wsm = c.workspace(wins[0], "mfma_f16")
+    state.zero_()
+    c.accumulate_amplitudes(wins[0], state, "mfma_f16", wsm)  # warm-up
+    torch.cuda.synchronize()
+    state.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in wins:
+        c.accumulate_amplitudes(w, state, "mfma_f16", wsm)
+        c.reset()
+        c.spectrum_from_amplitudes(batch, state, ws)
+        last = c.read_spectra()
+    torch.cuda.synchronize()
+    el_m = time.perf_counter() - t0
+    res["insitu_mfma_f16x3_terms_per_s"] = terms_per_step / el_m
+    res["insitu_mfma_last_snapshot_vs_one_pass_band_integrated_err"] = float(
+        band_integrated_error(last, S_fp32, om))
+    log(f"[bench] in-situ on mfma_f16x3: {res['insitu_mfma_f16x3_terms_per_s']:.3e} terms/s, last vs FP32 "
+        f"one pass (band-integrated) {res['insitu_mfma_last_snapshot_vs_one_pass_band_integrated_err']:.2e}")
+    del wsm
     del state, ws, wins
     c.close()
     return res

@@ -158,8 +158,8 @@ lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
  * is the orthonormal right-handed basis of lw_get_basis (A is perpendicular to n).
  *
  * lw_set_coherent: 1 = coherent, 0 = incoherent synthesis.  Resets S (and A).
- * In coherent mode lw_accumulate (FP32 path; LW_EUNSUPPORTED for the
- * matrix-core paths, which drop each particle's absolute phase) and
+ * In coherent mode lw_accumulate (every path; the matrix-core paths restore each
+ * column's phase e^{i w tau_0} in the contraction's epilogue) and
  * lw_accumulate_subset add w_p q_p A_p into A_s; time windows of a run passed as
  * successive batches (each particle's t0 is the window's first sample time)
  * therefore build the integral over the whole run; lw_read_spectra returns
@@ -178,8 +178,11 @@ lw_status lw_load_amplitudes(lw_ctx* ctx, const double* host_in);
  * amplitude A_p (without w_p q_p) of every particle into its own row, so
  * windows of one run must list the particles in the same order.  Leaves S and
  * A_s alone; samples with |beta| >= 1 or non-finite values are recorded for the
- * next read as in lw_accumulate.  FP32 path, asynchronous, no workspace. */
-lw_status lw_accumulate_amplitudes(lw_ctx* ctx, const lw_batch* batch, double* amp);
+ * next read as in lw_accumulate.  Any path: the FP32 path needs no workspace
+ * (workspace may be NULL), the matrix-core paths the lw_workspace_size bytes of
+ * the same batch and path.  Asynchronous on the FP32 path. */
+lw_status lw_accumulate_amplitudes(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
+                                   size_t workspace_bytes, double* amp);
 /* Device workspace (bytes) of lw_spectrum_from_amplitudes for n_particles. */
 lw_status lw_amplitude_workspace_size(lw_ctx* ctx, int64_t n_particles, size_t* bytes);
 /* Add the spectrum of a per-particle amplitude state into the accumulator:

@@ -315,10 +315,6 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
   st = check_batch(c, b);
   if (st != LW_OK) return st;
   if (b->n_particles == 0) return LW_OK;
-  if (c->coherent && path != LW_PATH_FP32)
-    return fail(c, LW_EUNSUPPORTED,
-                "coherent synthesis runs on the FP32 path (the matrix-core path drops each "
-                "particle's absolute phase)");
   size_t need = 0;
   st = lw_workspace_size(c, b, path, &need);
   if (st != LW_OK) return st;
@@ -723,7 +719,8 @@ lw_status lw_load_amplitudes(lw_ctx* c, const double* in) {
   return LW_OK;
 }
 
-lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, double* amp) {
+lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, lw_path path, void* ws,
+                                   size_t ws_bytes, double* amp) {
   if (!c) return LW_EINVAL;
   lw_status st = check_grids(c);
   if (st != LW_OK) return st;
@@ -733,6 +730,19 @@ lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, double* amp) {
   if (!amp) return fail(c, LW_EINVAL, "amplitude state is NULL");
   if (((uintptr_t)amp & 15) != 0) return fail(c, LW_EINVAL, "amplitude state must be 16-byte aligned");
   DeviceGuard g(c->device);
+  if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    size_t need = 0;
+    st = lw_workspace_size(c, b, path, &need);
+    if (st != LW_OK) return st;
+    if (!ws || ws_bytes < need)
+      return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
+    if (((uintptr_t)ws & 255) != 0) return fail(c, LW_EINVAL, "workspace must be 256-byte aligned");
+    st = lw::mfma_accumulate(c, b, path, ws, ws_bytes, nullptr, amp);
+    if (st != LW_OK) return st;
+    c->calls += 1;
+    return LW_OK;
+  }
+  if (path != LW_PATH_FP32) return fail(c, LW_EINVAL, "unknown path %d", (int)path);
   const DirectShape s = direct_shape(c, b->n_particles);
   lw::DirectArgs a;
   a.b = {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,

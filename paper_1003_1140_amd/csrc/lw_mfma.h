@@ -11,7 +11,9 @@ lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_
 lw_status mfma_set_bands(lw_ctx* c, int bands);
 lw_status mfma_set_tile(lw_ctx* c, int tile);
 lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);
+// amp: null, or a per-particle amplitude state [P][nd][nw][4] the columns' amplitudes are
+// added to (then S and the summed amplitudes are left alone)
 lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
-                          float* per_particle);
+                          float* per_particle, double* amp = nullptr);
 
 }  // namespace lw

@@ -52,6 +52,7 @@ constexpr int kTileN = 128;        // GEMM columns per work-group (64 particles 
 constexpr int kTileK = 32;         // inner-dimension step staged in LDS
 constexpr int kPad = 8;            // LDS row padding (halves)
 constexpr int kSpreadWin = 256;    // grid points per spreading window (one per thread)
+constexpr int kTapCoef = 9;        // tap weight polynomials: degree 8 in z = 2 frac(u) - 1
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -85,6 +86,7 @@ struct MfmaPlanCache {
   void* e_hi = nullptr;
   void* e_lo = nullptr;
   double* rowfac = nullptr;  // [nw] 1 / (4 pi^2 Phi(nu h)^2)
+  double* rowc = nullptr;    // [nw][2] e^{-i nu W h / 2} / Phi(nu h): amplitude factor of a row pair
   int32_t* row_of_j = nullptr;  // [nw] stacked row of (j, re)
   double* d_span = nullptr;  // device scratch for the span reduction
 };
@@ -105,6 +107,9 @@ struct SpreadArgs {
   int32_t ns;            // species count (a species outside [0, ns) is a data error)
   unsigned long long* err;
   unsigned long long* flops;  // null, or useful FLOPs of one product of the contraction
+  // phi(i - W/2 + 1 - f) = sum_k tapc[i][k] z^k, z = 2 f - 1: the W tap weights of a sample
+  // with fractional grid coordinate f (Chebyshev interpolants, within 2e-8 of phi)
+  float tapc[kW][kTapCoef];
 };
 
 struct GemmArgs {
@@ -124,8 +129,17 @@ struct GemmArgs {
   const unsigned* colmax;
   const int32_t* colq;
   const int32_t* perm;   // [nd][nb][n_local] particles of each (direction, band) by decreasing q
-  double* partial;       // [nd][n_ftile][ns][rows]
+  double* partial;       // [nd][n_ftile][ns][rows], or [nd][n_ftile][ns][rows][2] when coherent
   int32_t ns, rows;
+  // coherent synthesis: columns keep their phase e^{i w tau_0} and add w q A per species
+  int32_t coherent;
+  const double* dirs;    // [nd][kDirStride]
+  const double* wturn;   // [nw] omega / (2 pi)
+  // amplitude state: each column's amplitude is added to amp[p][d][j][2 pol + (re, im)]
+  // (no partial sums); rowc [nw][2] is the row factor the reduction applies otherwise
+  double* amp;
+  const double* rowc;
+  int32_t wturn_n;       // nw
 };
 
 // ------------------------------------------------------------------ helpers
@@ -138,13 +152,6 @@ __device__ __forceinline__ double retarded_time(const BatchView& b, int64_t idx,
   return t - dot3(n, b.x[idx], b.y[idx], b.z[idx]);
 }
 
-__device__ __forceinline__ float es_kernel(float x) {
-  // exp(beta (sqrt(1 - (2x/W)^2) - 1)) for |x| < W/2, else 0
-  const float y = x * (2.0f / kW);
-  const float r = 1.0f - y * y;
-  if (!(r > 0.0f)) return 0.0f;
-  return __expf((float)kBeta * (__builtin_sqrtf(r) - 1.0f));
-}
 
 // ------------------------------------------------------------------ span of every (particle, direction)
 __global__ void lw_span_kernel(BatchView b, const double* dirs, int nd, double* out_max) {
@@ -267,8 +274,14 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
   const double iu = floor(u);
   const float fu = (float)(u - iu);
   st.lo[tid] = (int)iu - (kW / 2 - 1);
+  const float z = 2.0f * fu - 1.0f;
 #pragma unroll
-  for (int i = 0; i < kW; ++i) st.w[i][tid] = es_kernel((float)(i - (kW / 2 - 1)) - fu);  // q - u
+  for (int i = 0; i < kW; ++i) {  // phi(q - u) for q = lo + i, Horner in z
+    float w = a.tapc[i][kTapCoef - 1];
+#pragma unroll
+    for (int c = kTapCoef - 2; c >= 0; --c) w = fmaf(w, z, a.tapc[i][c]);
+    st.w[i][tid] = w;
+  }
   const float G1 = ok ? (float)g1 : 0.f, G2 = ok ? (float)g2 : 0.f;
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
@@ -594,6 +607,7 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
     const int c = col0 + tid;
     float sc = 1.0f;
     int q2 = 0, fc = -1;
+    double tau0 = 0.0;
     for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
     if (c < ncol) {
       const int pl = a.perm[db * a.n_local + c / 2];  // columns in decreasing-length order
@@ -730,6 +744,103 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 // one chunk) and the staging writes (four rows, four chunks) both do.
 __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
 
+// Amplitude-state epilogue of a 128-row tile: each (column, frequency) amplitude
+// C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own state row.  A state
+// row belongs to one column of one tile, so the adds do not race.
+__device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[2][2],
+                                                   const int* s_fcol, const float* s_scale,
+                                                   const double* s_tau0, const Band& bd, int d,
+                                                   int row0, int wr, int wc, int lane) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int rp = 0; rp < 8; ++rp) {
+      const int r = 4 * (rp >> 1) + 2 * (rp & 1);
+      const int rl = i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+      const int jl = (row0 + wr * 64 + rl) >> 1;
+      if (jl >= bd.nj) continue;
+      const int j = bd.j0 + jl;
+      const double wt = a.wturn[j], fr_c = a.rowc[2 * j], fi_c = a.rowc[2 * j + 1];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const int cc = wc * 64 + jb * 32 + (lane & 31);
+        const int fc = s_fcol[cc];
+        if (fc < 0) continue;
+        const double x = wt * s_tau0[cc];
+        const float fr = (float)(x - rint(x));
+        const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+        const float inv = 1.0f / s_scale[cc];
+        const float zr = acc[i][jb][r], zi = acc[i][jb][r + 1];
+        const double ur = (double)((zr * cs - zi * sn) * inv), ui = (double)((zr * sn + zi * cs) * inv);
+        const int64_t p = a.p_begin + (fc >> 1);
+        double* o = a.amp + (((size_t)p * a.nd + d) * (size_t)a.wturn_n + j) * 4 + 2 * (fc & 1);
+        o[0] += ur * fr_c - ui * fi_c;
+        o[1] += ur * fi_c + ui * fr_c;
+      }
+    }
+}
+
+// Coherent epilogue of a 128-row tile.  A lane holds, for one column (particle p,
+// polarisation = column parity), the real and imaginary rows of a frequency in adjacent
+// accumulator registers.  The column's amplitude up to the row factor applied by the
+// reduction is C e^{i w_j tau_0p} (phase reduced to a turn fraction in FP64, hardware
+// sin/cos in turns); w_p q_p / scale times it is summed over the tile's columns of each
+// species and polarisation and written as partial[...][row][polarisation], the real part
+// on the row of (j, re) and the imaginary part on the row of (j, im).
+template <int WN>
+__device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[2][2],
+                                                  const float (*s_colw)[64 * WN],
+                                                  const double* s_tau0, double (*s_rows)[128],
+                                                  const Band& bd, int d, int nt, int row0, int wr,
+                                                  int wc, int lane, int wave, int tid) {
+  constexpr int TM = 128;
+  for (int s = 0; s < a.ns; ++s) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int rp = 0; rp < 8; ++rp) {
+        const int r = 4 * (rp >> 1) + 2 * (rp & 1);                     // the (j, re) register
+        const int rl = i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // row within the wave
+        const int jl = (row0 + wr * 64 + rl) >> 1;
+        float vr = 0.0f, vi = 0.0f;
+        if (jl < bd.nj) {
+          const double wt = a.wturn[bd.j0 + jl];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int cc = wc * 64 + j * 32 + (lane & 31);
+            const float wq = s_colw[s][cc];
+            const double x = wt * s_tau0[cc];
+            const float fr = (float)(x - rint(x));
+            const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+            const float zr = acc[i][j][r], zi = acc[i][j][r + 1];
+            vr = fmaf(wq, zr * cs - zi * sn, vr);
+            vi = fmaf(wq, zr * sn + zi * cs, vi);
+          }
+        }
+        // sum the columns of equal polarisation (lanes of equal parity in each half-wave)
+        for (int off = 16; off > 1; off >>= 1) {
+          vr += __shfl_xor(vr, off);
+          vi += __shfl_xor(vi, off);
+        }
+        if ((lane & 31) < 2) {
+          const int pol = lane & 1;
+          s_rows[wave][2 * rl + pol] = (double)vr;
+          s_rows[wave][2 * (rl + 1) + pol] = (double)vi;
+        }
+      }
+    __syncthreads();
+    if (tid < 2 * TM) {
+      const int row = tid >> 1, pol = tid & 1;
+      const int g = row / 64, rr = row % 64;
+      double v = 0.0;
+#pragma unroll
+      for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][2 * rr + pol];
+      a.partial[((((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + row) * 2 + pol] = v;
+    }
+  }
+}
+
 template <typename T, int PRODUCTS, int WN>
 __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
@@ -743,8 +854,9 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   __shared__ float s_scale[TN];
   __shared__ int s_q2[TN];
   __shared__ int s_fcol[TN];
-  __shared__ float s_colw[kMaxSpecies][TN];
-  __shared__ double s_rows[NW][64];
+  __shared__ float s_colw[kMaxSpecies][TN];  // w q^2 / scale^2 (w q / scale when coherent)
+  __shared__ double s_tau0[TN];              // first retarded time of each column (coherent)
+  __shared__ double s_rows[NW][128];
   __shared__ int s_kmax;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -775,6 +887,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     const int c = col0 + tid;
     float sc = 1.0f;
     int q2 = 0, fc = -1;
+    double tau0 = 0.0;
     for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
     if (c < ncol) {
       const int pl = a.perm[db * a.n_local + c / 2];
@@ -791,12 +904,20 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
       const int sp = a.b.species ? a.b.species[p] : 0;
       if (sp >= 0 && sp < a.ns) {
         const float qq = a.b.charge[p];
-        s_colw[sp][tid] = a.b.weight[p] * qq * qq / (sc * sc);
+        s_colw[sp][tid] = a.coherent ? a.b.weight[p] * qq / sc : a.b.weight[p] * qq * qq / (sc * sc);
+      }
+      if (a.coherent || a.amp) {  // as the spreading kernel measures tau' from it
+        const int64_t o = a.b.offsets[p];
+        if (a.b.offsets[p + 1] > o) {
+          const double* n = a.dirs + kDirStride * d;
+          tau0 = a.b.t0[p] - (n[0] * a.b.x[o] + n[1] * a.b.y[o] + n[2] * a.b.z[o]);
+        }
       }
     }
     s_scale[tid] = sc;
     s_q2[tid] = q2;
     s_fcol[tid] = fc;
+    s_tau0[tid] = tau0;
   }
   __syncthreads();
   const int kend = min(((s_kmax + kTileK - 1) / kTileK) * kTileK, bd.kp);
@@ -927,6 +1048,14 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     __syncthreads();
   }
 
+  if (a.amp) {
+    amplitude_epilogue(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
+    return;
+  }
+  if (a.coherent) {
+    coherent_epilogue<WN>(a, acc, s_colw, s_tau0, s_rows, bd, d, nt, row0, wr, wc, lane, wave, tid);
+    return;
+  }
   for (int s = 0; s < a.ns; ++s) {
     __syncthreads();
 #pragma unroll
@@ -972,6 +1101,34 @@ __global__ void lw_mfma_reduce_kernel(const double* partial, int n_ftile, int ns
   S[((size_t)s * nd + d) * nw + j] += acc * rowfac[j];
 }
 
+// A[s][d][j][2 pol + (re, im)] += rowc[j] * sum over column tiles of the row pair (j, re), (j, im)
+__global__ void lw_mfma_reduce_coherent_kernel(const double* partial, int n_ftile, int ns, int rows,
+                                               const int32_t* row_of_j, const double* rowc, int nw,
+                                               int nd, double* A) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nd * ns * nw) return;
+  const int j = i % nw;
+  const int s = (i / nw) % ns;
+  const int d = i / (nw * ns);
+  const int r = row_of_j[j];
+  double re[2] = {0.0, 0.0}, im[2] = {0.0, 0.0};
+  for (int t = 0; t < n_ftile; ++t) {
+    const double* pr = partial + (((size_t)d * n_ftile + t) * ns + s) * rows * 2;
+#pragma unroll
+    for (int pol = 0; pol < 2; ++pol) {
+      re[pol] += pr[2 * r + pol];
+      im[pol] += pr[2 * (r + 1) + pol];
+    }
+  }
+  const double fr = rowc[2 * j], fi = rowc[2 * j + 1];
+  double* out = A + (((size_t)s * nd + d) * nw + j) * 4;
+#pragma unroll
+  for (int pol = 0; pol < 2; ++pol) {
+    out[2 * pol] += re[pol] * fr - im[pol] * fi;
+    out[2 * pol + 1] += re[pol] * fi + im[pol] * fr;
+  }
+}
+
 // ------------------------------------------------------------------ host side
 namespace {
 
@@ -979,6 +1136,35 @@ double es_phi_host(double x) {
   const double y = 2.0 * x / kW;
   const double r = 1.0 - y * y;
   return r > 0.0 ? exp(kBeta * (sqrt(r) - 1.0)) : 0.0;
+}
+
+// Tap weight polynomials of the spreading kernel: for tap i and z = 2 f - 1 in [-1, 1],
+// g_i(z) = phi(i - W/2 + 1 - (z + 1) / 2) interpolated at the kTapCoef Chebyshev points of
+// the first kind, then rewritten in powers of z for Horner evaluation.  The sqrt edge of
+// phi limits the interpolant to ~1.6e-8 of phi's peak; the coefficients sum to ~1.25 in
+// absolute value, so FP32 evaluation adds < 1e-7.
+void tap_polynomials(float out[kW][kTapCoef]) {
+  constexpr int N = kTapCoef;
+  double T[N][N] = {};  // T[j] = power coefficients of the Chebyshev polynomial T_j
+  T[0][0] = 1.0;
+  T[1][1] = 1.0;
+  for (int j = 2; j < N; ++j)
+    for (int k = 0; k < N; ++k) T[j][k] = (k > 0 ? 2.0 * T[j - 1][k - 1] : 0.0) - T[j - 2][k];
+  for (int i = 0; i < kW; ++i) {
+    double g[N], zk[N];
+    for (int k = 0; k < N; ++k) {
+      zk[k] = cos((2 * k + 1) * M_PI / (2.0 * N));
+      g[k] = es_phi_host((double)(i - (kW / 2 - 1)) - 0.5 * (zk[k] + 1.0));
+    }
+    double mono[N] = {};
+    for (int j = 0; j < N; ++j) {
+      double cj = 0.0;
+      for (int k = 0; k < N; ++k) cj += g[k] * cos(j * (2 * k + 1) * M_PI / (2.0 * N));
+      cj *= (j == 0 ? 1.0 : 2.0) / N;
+      for (int k = 0; k < N; ++k) mono[k] += cj * T[j][k];
+    }
+    for (int k = 0; k < N; ++k) out[i][k] = (float)mono[k];
+  }
 }
 
 // Fourier transform of the kernel, Phi(xi) = int phi(x) cos(xi x) dx, by composite
@@ -1054,7 +1240,7 @@ WsLayout ws_layout(const lw_ctx* c, const MfmaPlanCache* pc, int64_t P) {
   w.perm = off;
   off += al((size_t)nd * nb * w.chunk * sizeof(int32_t));
   w.partial = off;
-  off += al((size_t)nd * w.n_ftile * c->ns * pc->rows * sizeof(double));
+  off += al((size_t)nd * w.n_ftile * c->ns * pc->rows * (c->coherent ? 2 : 1) * sizeof(double));
   w.total = off;
   return w;
 }
@@ -1063,9 +1249,11 @@ void free_tables(MfmaPlanCache* pc) {
   if (pc->e_hi) (void)hipFree(pc->e_hi);
   if (pc->e_lo) (void)hipFree(pc->e_lo);
   if (pc->rowfac) (void)hipFree(pc->rowfac);
+  if (pc->rowc) (void)hipFree(pc->rowc);
   if (pc->row_of_j) (void)hipFree(pc->row_of_j);
   pc->e_hi = pc->e_lo = nullptr;
   pc->rowfac = nullptr;
+  pc->rowc = nullptr;
   pc->row_of_j = nullptr;
   pc->valid = false;
 }
@@ -1148,17 +1336,24 @@ lw_status build_plan(lw_ctx* c, double span, int dtype) {
                          (__bf16*)pc->e_lo, c->d_omega, bd);
     MF_HIP(hipGetLastError(), "launch etable");
   }
-  std::vector<double> rf(c->nw);
+  std::vector<double> rf(c->nw), rcx(2 * (size_t)c->nw);
   std::vector<int32_t> rj(c->nw);
   for (int b = 0; b < nb; ++b) {
     const Band& bd = pc->band[b];
     for (int jl = 0; jl < bd.nj; ++jl) {
       const int j = bd.j0 + jl;
-      const double ph = es_ft_host((w[j] - bd.wc) * bd.h);
+      const double nu = w[j] - bd.wc;
+      const double ph = es_ft_host(nu * bd.h);
       rf[j] = 1.0 / (4.0 * M_PI * M_PI * ph * ph);
       rj[j] = bd.row_off + 2 * jl;
+      // grid point q sits at retarded time (q - W/2) h after the first sample
+      rcx[2 * j] = cos(-nu * 0.5 * kW * bd.h) / ph;
+      rcx[2 * j + 1] = sin(-nu * 0.5 * kW * bd.h) / ph;
     }
   }
+  MF_HIP(hipMalloc(&pc->rowc, 2 * (size_t)c->nw * sizeof(double)), "hipMalloc(rowc)");
+  MF_HIP(hipMemcpy(pc->rowc, rcx.data(), 2 * (size_t)c->nw * sizeof(double), hipMemcpyHostToDevice),
+         "copy rowc");
   MF_HIP(hipMalloc(&pc->rowfac, c->nw * sizeof(double)), "hipMalloc(rowfac)");
   MF_HIP(hipMalloc(&pc->row_of_j, c->nw * sizeof(int32_t)), "hipMalloc(rows)");
   MF_HIP(hipMemcpy(pc->rowfac, rf.data(), c->nw * sizeof(double), hipMemcpyHostToDevice), "copy rowfac");
@@ -1236,7 +1431,7 @@ lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t
 }
 
 lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,
-                          float* per_particle) {
+                          float* per_particle, double* amp) {
   if (per_particle)
     return set_err(c, LW_EUNSUPPORTED, "per-particle output is available on the FP32 path only");
   lw_status st = ensure_plan(c, b, path);
@@ -1274,12 +1469,19 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   sa.err = c->d_err;
   sa.ns = c->ns;
   sa.flops = c->prof ? c->d_flops : nullptr;
+  tap_polynomials(sa.tapc);
   c->flop_mult = products;
   ga.e_hi = pc->e_hi;
   ga.e_lo = pc->e_lo;
   ga.partial = partial;
   ga.ns = c->ns;
   ga.rows = pc->rows;
+  ga.coherent = c->coherent && !amp ? 1 : 0;
+  ga.dirs = c->d_dirs;
+  ga.wturn = c->d_wturn;
+  ga.wturn_n = c->nw;
+  ga.amp = amp;
+  ga.rowc = pc->rowc;
   // bands by decreasing work (grid points per particle), so the long tiles start first
   for (int i = 0; i < pc->nb; ++i) ga.order[i] = i;
   std::sort(ga.order, ga.order + pc->nb,
@@ -1287,6 +1489,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   int tile = pc->tile;  // 256-row tiles need every band's rows to be a multiple of 256
   for (int i = 0; i < pc->nb; ++i)
     if (tile == 2 && pc->band[i].m % 256 != 0) tile = 1;
+  if (tile == 2 && (c->coherent || amp)) tile = 3;  // those epilogues are written for 128-row tiles
   const int tm = tile == 2 ? 256 : 128;
   const int tn = tile == 3 ? 256 : 128;
   const bool bf = path == LW_PATH_MFMA_BF16;
@@ -1329,11 +1532,15 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
 #undef LW_GEMM
     MF_HIP(hipGetLastError(), "launch dft_mfma");
     MF_HIP(prof_end(c), "profile");
-    {
+    if (!amp) {
       const int n = c->nd * c->ns * c->nw;
       dim3 grid((unsigned)((n + 255) / 256)), block(256);
-      hipLaunchKernelGGL(lw_mfma_reduce_kernel, grid, block, 0, c->stream, partial, nft, c->ns,
-                         pc->rows, pc->row_of_j, pc->rowfac, c->nw, c->nd, c->d_S);
+      if (c->coherent)
+        hipLaunchKernelGGL(lw_mfma_reduce_coherent_kernel, grid, block, 0, c->stream, partial, nft,
+                           c->ns, pc->rows, pc->row_of_j, pc->rowc, c->nw, c->nd, c->d_A);
+      else
+        hipLaunchKernelGGL(lw_mfma_reduce_kernel, grid, block, 0, c->stream, partial, nft, c->ns,
+                           pc->rows, pc->row_of_j, pc->rowfac, c->nw, c->nd, c->d_S);
       MF_HIP(hipGetLastError(), "launch mfma reduce");
     }
   }

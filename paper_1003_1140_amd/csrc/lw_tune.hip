@@ -55,10 +55,6 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
   (void)hipGetDevice(&prev);
   if (prev != c->device) (void)hipSetDevice(c->device);
 
-  if (c->coherent && path != LW_PATH_FP32) {
-    c->err = "coherent synthesis runs on the FP32 path only";
-    return LW_EUNSUPPORTED;
-  }
   // the accumulator the timed runs add into: S, or the summed amplitudes in coherent synthesis
   double* acc = c->coherent ? c->d_A : c->d_S;
   const size_t nS = (size_t)c->ns * c->nd * c->nw * (c->coherent ? 4 : 1);

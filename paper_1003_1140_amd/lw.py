@@ -115,7 +115,7 @@ def load_library():
             "lw_get_basis": (ctypes.c_int, [P, P]),
             "lw_read_amplitudes": (ctypes.c_int, [P, P]),
             "lw_load_amplitudes": (ctypes.c_int, [P, P]),
-            "lw_accumulate_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
+            "lw_accumulate_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int, P, SZ, P]),
             "lw_amplitude_workspace_size": (ctypes.c_int, [P, I64, ctypes.POINTER(SZ)]),
             "lw_spectrum_from_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, SZ]),
             "lw_spectral_diagnostics": (ctypes.c_int, [P, P, P, P, P, P]),
@@ -298,11 +298,17 @@ class Context:
         return torch.zeros((n_particles, self.nd, self.nw, 4), dtype=torch.float64,
                            device=f"cuda:{self.device}")
 
-    def accumulate_amplitudes(self, batch: DeviceBatch, state):
+    def accumulate_amplitudes(self, batch: DeviceBatch, state, path="fp32", workspace=None):
         assert state.dtype == torch.float64 and state.is_contiguous()
         assert state.numel() == batch.n_particles * self.nd * self.nw * 4
-        self._check(self.lib.lw_accumulate_amplitudes(self.h, ctypes.byref(batch.struct),
+        path = PATHS.get(path, path)
+        if workspace is None and path != LW_PATH_FP32:
+            workspace = self.workspace(batch, path)
+        wp = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+        nb = workspace.numel() if workspace is not None else 0
+        self._check(self.lib.lw_accumulate_amplitudes(self.h, ctypes.byref(batch.struct), path, wp, nb,
                                                       ctypes.c_void_p(state.data_ptr())))
+        return workspace
 
     def amplitude_workspace_size(self, n_particles) -> int:
         n = ctypes.c_size_t()

@@ -12,7 +12,8 @@ amplitude is bounded by TOL times the root sum of squares of the terms,
 R = sqrt(sum_p |w_p q_p A_p|^2).  Summed amplitudes are compared against that
 scale on bins whose R^2 is at least 1e-4 of the direction's largest; where the
 particles add in phase (identical copies) the coherent power itself is held to
-the incoherent bar.
+the incoherent bar.  The matrix-core path is held to its incoherent band-integrated
+bars on the coherent power (FP16 hi/lo 1e-5, BF16 hi/lo 1e-4).
 """
 import numpy as np
 import pytest
@@ -25,6 +26,10 @@ from _parity import band_relative_error
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+# matrix-core path: the band-integrated bars of its incoherent parity (FP16 hi/lo 1e-5,
+# BF16 hi/lo 1e-4) on the coherent power, and a per-bin sanity bar on the amplitude
+MFMA_BAND_TOL = {"mfma_f16": 1e-5, "mfma_bf16": 1e-4}
+MFMA_AMP_SANITY = 1e-3
 
 
 def _ctx(dirs, omega, ns=1, coherent=True):
@@ -159,8 +164,10 @@ def test_coherent_time_windows_and_snapshot_differences():
     assert np.max(np.abs(d_gpu - d_ref)[~empty] / scale[~empty][:, None]) <= 4 * TOL
 
 
-def test_incoherent_amplitude_state_over_windows():
+@pytest.mark.parametrize("path", ["fp32", "mfma_f16"])
+def test_incoherent_amplitude_state_over_windows(path):
     from paper_1003_1140_amd import DeviceBatch
+    from _parity import band_integrated_errors
 
     b = workloads.generate(configs.uneven_recipe(), 200, 16)
     dirs, om = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 600)
@@ -170,7 +177,7 @@ def test_incoherent_amplitude_state_over_windows():
     naive = np.zeros((3, len(dirs), len(om)))
     for w in wins:
         dw = DeviceBatch.from_host(w)
-        c.accumulate_amplitudes(dw, state)
+        c.accumulate_amplitudes(dw, state, path)
         c.reset()
         c.accumulate(dw)
         naive += c.read_spectra()
@@ -178,9 +185,15 @@ def test_incoherent_amplitude_state_over_windows():
     c.spectrum_from_amplitudes(DeviceBatch.from_host(b), state)
     S = c.read_spectra()
     ref = oracle.spectrum(b, dirs, om, n_species=3)
-    print(f"[in-situ] incoherent state: band error {band_relative_error(S, ref):.3e}, "
-          f"per-window sum off by {band_relative_error(naive, ref):.3e}", flush=True)
-    assert band_relative_error(S, ref) <= TOL
+    live = [r for r in range(3 * len(dirs)) if ref.reshape(-1, len(om))[r].max() > 0]
+    band = band_integrated_errors(S.reshape(-1, len(om))[live], ref.reshape(-1, len(om))[live], om).max()
+    print(f"[in-situ] {path} incoherent state: band error {band_relative_error(S, ref):.3e}, "
+          f"band-integrated {band:.3e}, per-window sum off by {band_relative_error(naive, ref):.3e}",
+          flush=True)
+    if path == "fp32":
+        assert band_relative_error(S, ref) <= TOL
+    else:
+        assert band <= MFMA_BAND_TOL[path]
     # squaring each window alone drops the cross terms between windows
     assert band_relative_error(naive, ref) > 100 * TOL
     # each particle's state row is its own amplitude
@@ -192,7 +205,7 @@ def test_incoherent_amplitude_state_over_windows():
         one.species = np.zeros(1, dtype=np.int32)
         _, a_ref = oracle.coherent_spectrum(one, dirs, om, n_species=1, with_amplitude=True)
         e = _amp_error(st[p][None], a_ref, np.sum(np.abs(a_ref) ** 2, axis=-1))
-        assert e <= TOL, (p, e)
+        assert e <= (TOL if path == "fp32" else MFMA_AMP_SANITY), (p, e)
     c.close()
 
 
@@ -238,6 +251,35 @@ def test_graph_replays_in_coherent_mode():
     c.close()
 
 
+@pytest.mark.parametrize("path,case", [("mfma_f16", "jitter"), ("mfma_f16", "uneven_species"),
+                                       ("mfma_bf16", "jitter")])
+def test_coherent_matrix_core_path(path, case):
+    """The matrix-core path keeps each column's phase e^{i w tau_0} in its epilogue."""
+    from paper_1003_1140_amd import DeviceBatch
+    from _parity import band_integrated_errors
+
+    if case == "jitter":
+        b = workloads.generate(configs.jitter_recipe(), 0, 40)
+        dirs, om, ns = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024), 1
+    else:
+        b = workloads.generate(configs.uneven_recipe(), 0, 18)
+        dirs, om, ns = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 700), 3
+    S_ref, A_ref = oracle.coherent_spectrum(b, dirs, om, n_species=ns, with_amplitude=True)
+    c = _ctx(dirs, om, ns)
+    c.accumulate(DeviceBatch.from_host(b), path)
+    S = c.read_spectra()
+    A = _xyz(c.read_amplitudes(), c.get_basis())
+    c.close()
+    rss2 = _rss2(b, dirs, om, ns)
+    e = _amp_error(A, A_ref, rss2)
+    live = [r for r in range(S.shape[0] * S.shape[1]) if S_ref.reshape(-1, S.shape[-1])[r].max() > 0]
+    band = band_integrated_errors(S.reshape(-1, S.shape[-1])[live], S_ref.reshape(-1, S.shape[-1])[live], om)
+    print(f"[coherent] {path} {case}: amplitude error / R = {e:.3e}, band-integrated {band.max():.3e}",
+          flush=True)
+    assert band.max() <= MFMA_BAND_TOL[path]
+    assert e <= MFMA_AMP_SANITY
+
+
 def test_coherent_mode_errors_and_resume():
     from paper_1003_1140_amd import DeviceBatch, LWError
 
@@ -245,9 +287,6 @@ def test_coherent_mode_errors_and_resume():
     dirs, om = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 128)
     db = DeviceBatch.from_host(b)
     c = _ctx(dirs, om)
-    with pytest.raises(LWError) as ei:
-        c.accumulate(db, "mfma_f16")
-    assert ei.value.status == -6
     with pytest.raises(LWError) as ei:
         c.load_accumulator(np.zeros((1, len(dirs), len(om))))
     assert ei.value.status == -4
