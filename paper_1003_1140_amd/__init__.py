@@ -5,3 +5,4 @@ spectrum surrogate (``surrogate``) that runs on the library's own kernels.
 """
 from .lw import (LIB_PATH, PATHS, MLP, Context, DeviceBatch, Graph, LWError, load_library,  # noqa: F401
                  LW_OK, LW_EINVAL, LW_ENOMEM, LW_EDEVICE, LW_ESTATE, LW_ERANGE, LW_EUNSUPPORTED)
+from .insitu import Recorder  # noqa: F401

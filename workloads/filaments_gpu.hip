@@ -1,4 +1,6 @@
-// filaments_gpu.hip -- device twin of filaments.c (workload generator, not the method).
+// filaments_gpu.hip -- device twin of filaments.c (workload generator, not the method),
+// and the in-situ stand-in that advances the same particles window by window in a field
+// of evolving amplitude.
 //
 // One thread per particle: the same Philox4x32-10 draws, beam initial conditions,
 // random-filament field and Boris push as filaments.c, writing the same
@@ -124,24 +126,9 @@ __device__ double field_by(const Field& f, double x, double z) {
   return by;
 }
 
-__global__ void wl_generate_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n,
-                                   const int64_t* offsets, Field f, double* x, double* y, double* z,
-                                   double* bx, double* by, double* bz, float* ax, float* ay,
-                                   float* az, double* t0, double* dtp, float* charge, float* weight,
-                                   int32_t* species, int* status) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint64_t id = (uint64_t)(first_id + i);
-  int32_t len, s;
-  double g0;
-  float q, m;
-  meta(r, id, &len, &s, &g0, &q, &m);
-  const int64_t o = offsets[i] - offsets[0];
-  const int64_t L = offsets[i + 1] - offsets[i];
-  if (L != len) {
-    atomicExch(status, -1);
-    return;
-  }
+// Initial position and momentum of particle `id` (beam of its species, thermal spread).
+__device__ void initial_state(const wl_recipe_gpu& r, uint64_t id, double g0, float m, double* pos,
+                              double* u) {
   uint32_t w[4];
   draws(r.seed, id, 1u, w);
   double px = r.box * u01(w[0], w[1]);
@@ -161,12 +148,25 @@ __global__ void wl_generate_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n,
   const double gp = sqrt(1.0 + upx * upx + upy * upy + upz * upz);
   const double sgn = (id & 1u) ? -1.0 : 1.0;
   const double b0 = sgn * sqrt(1.0 - 1.0 / (g0 * g0));
-  double ux = g0 * (upx + b0 * gp), uy = upy, uz = upz;
-  const double qm = (double)q / (double)m;
-  const double dt = r.dt;
-  for (int64_t k = 0; k < L; ++k) {
+  pos[0] = px;
+  pos[1] = py;
+  pos[2] = pz;
+  u[0] = g0 * (upx + b0 * gp);
+  u[1] = upy;
+  u[2] = upz;
+}
+
+// One Boris step of length dt in B = (0, Bf(pos), 0) scaled by amp, writing the sample
+// (position before the step, mean velocity, velocity change over dt) at idx.
+__device__ inline void boris_sample(const Field& f, double amp, double qm, double dt, double* pos,
+                                    double* u, int64_t idx, double* x, double* y, double* z,
+                                    double* bx, double* by, double* bz, float* ax, float* ay,
+                                    float* az) {
+  const double px = pos[0], py = pos[1], pz = pos[2];
+  const double ux = u[0], uy = u[1], uz = u[2];
+  {
     const double gm = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-    const double Bf = field_by(f, px, pz);
+    const double Bf = amp * field_by(f, px, pz);
     const double ty = qm * Bf * dt / (2.0 * gm);
     const double sy = 2.0 * ty / (1.0 + ty * ty);
     const double vx = ux - uz * ty, vz = uz + ux * ty;
@@ -174,7 +174,6 @@ __global__ void wl_generate_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n,
     const double gpl = sqrt(1.0 + nx * nx + ny * ny + nz * nz);
     const double bmx = ux / gm, bmy = uy / gm, bmz = uz / gm;
     const double bpx = nx / gpl, bpy = ny / gpl, bpz = nz / gpl;
-    const int64_t idx = o + k;
     x[idx] = px;
     y[idx] = py;
     z[idx] = pz;
@@ -184,18 +183,107 @@ __global__ void wl_generate_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n,
     ax[idx] = (float)((bpx - bmx) / dt);
     ay[idx] = (float)((bpy - bmy) / dt);
     az[idx] = (float)((bpz - bmz) / dt);
-    px += bpx * dt;
-    py += bpy * dt;
-    pz += bpz * dt;
-    ux = nx;
-    uy = ny;
-    uz = nz;
+    pos[0] = px + bpx * dt;
+    pos[1] = py + bpy * dt;
+    pos[2] = pz + bpz * dt;
+    u[0] = nx;
+    u[1] = ny;
+    u[2] = nz;
   }
+}
+
+__global__ void wl_generate_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n,
+                                   const int64_t* offsets, Field f, double* x, double* y, double* z,
+                                   double* bx, double* by, double* bz, float* ax, float* ay,
+                                   float* az, double* t0, double* dtp, float* charge, float* weight,
+                                   int32_t* species, int* status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t id = (uint64_t)(first_id + i);
+  int32_t len, s;
+  double g0;
+  float q, m;
+  meta(r, id, &len, &s, &g0, &q, &m);
+  const int64_t o = offsets[i] - offsets[0];
+  const int64_t L = offsets[i + 1] - offsets[i];
+  if (L != len) {
+    atomicExch(status, -1);
+    return;
+  }
+  double pos[3], u[3];
+  initial_state(r, id, g0, m, pos, u);
+  const double qm = (double)q / (double)m;
+  const double dt = r.dt;
+  for (int64_t k = 0; k < L; ++k)
+    boris_sample(f, 1.0, qm, dt, pos, u, o + k, x, y, z, bx, by, bz, ax, ay, az);
   t0[i] = 0.0;
   dtp[i] = dt;
   charge[i] = q;
   weight[i] = 1.0f;
   species[i] = s;
+}
+
+// ---- in-situ stand-in: persistent particles in a field whose amplitude evolves in time
+// State [6][n]: x, y, z, ux, uy, uz (FP64), advanced window by window.
+__global__ void wl_insitu_init_kernel(wl_recipe_gpu r, int64_t first_id, int64_t n, double* state,
+                                      float* charge, float* mass) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t id = (uint64_t)(first_id + i);
+  int32_t len, s;
+  double g0;
+  float q, m;
+  meta(r, id, &len, &s, &g0, &q, &m);
+  double pos[3], u[3];
+  initial_state(r, id, g0, m, pos, u);
+  for (int c = 0; c < 3; ++c) {
+    state[c * n + i] = pos[c];
+    state[(3 + c) * n + i] = u[c];
+  }
+  charge[i] = q;
+  mass[i] = m;
+}
+
+// One window: n_steps simulation steps, each sub-cycled n_sub times with synthesis step dt.
+// The field amplitude is given at the n_steps + 1 simulation step boundaries and
+// interpolated linearly inside a step (as a PIC code's particle sub-cycling interpolates
+// its fields in time).  Writes n_steps * n_sub samples per particle, particle-major, and
+// per particle t0 = t_start, dt, charge, weight 1 and the collection region: the z-slab
+// (of n_regions equal slabs of the periodic box, across the beams) holding the particle at
+// the window start.
+__global__ void wl_insitu_push_kernel(Field f, int64_t n, double* state, const float* charge_in,
+                                      const float* mass, const double* amp, int32_t n_steps,
+                                      int32_t n_sub, double dt, double t_start, double box,
+                                      int32_t n_regions, double* x, double* y, double* z,
+                                      double* bx, double* by, double* bz, float* ax, float* ay,
+                                      float* az, double* t0, double* dtp, float* charge,
+                                      float* weight, int32_t* species) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double pos[3], u[3];
+  for (int c = 0; c < 3; ++c) {
+    pos[c] = state[c * n + i];
+    u[c] = state[(3 + c) * n + i];
+  }
+  const double zm = pos[2] - box * floor(pos[2] / box);
+  const int reg = min(n_regions - 1, max(0, (int)(zm / box * n_regions)));
+  const double qm = (double)charge_in[i] / (double)mass[i];
+  const int64_t L = (int64_t)n_steps * n_sub;
+  for (int32_t st = 0; st < n_steps; ++st) {
+    const double a0 = amp[st], da = amp[st + 1] - amp[st];
+    for (int32_t k = 0; k < n_sub; ++k)
+      boris_sample(f, a0 + da * ((double)k / (double)n_sub), qm, dt, pos, u,
+                   i * L + (int64_t)st * n_sub + k, x, y, z, bx, by, bz, ax, ay, az);
+  }
+  for (int c = 0; c < 3; ++c) {
+    state[c * n + i] = pos[c];
+    state[(3 + c) * n + i] = u[c];
+  }
+  t0[i] = t_start;
+  dtp[i] = dt;
+  charge[i] = charge_in[i];
+  weight[i] = 1.0f;
+  species[i] = reg;
 }
 
 }  // namespace
@@ -218,6 +306,38 @@ int wl_generate_gpu(const wl_recipe_gpu* r, int64_t first_id, int64_t n, const i
   hipLaunchKernelGGL(wl_generate_kernel, grid, block, 0, (hipStream_t)stream, *r, first_id, n,
                      offsets, f, x, y, z, bx, by, bz, ax, ay, az, t0, dtp, charge, weight, species,
                      status);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// In-situ stand-in, initial state of particles first_id .. first_id+n-1: state [6][n]
+// device FP64 (positions, momenta), charge and mass [n] device FP32.
+int wl_insitu_init_gpu(const wl_recipe_gpu* r, int64_t first_id, int64_t n, double* state,
+                       float* charge, float* mass, void* stream) {
+  if (!r || n < 0) return -1;
+  if (n == 0) return 0;
+  dim3 grid((unsigned)((n + 63) / 64)), block(64);
+  hipLaunchKernelGGL(wl_insitu_init_kernel, grid, block, 0, (hipStream_t)stream, *r, first_id, n,
+                     state, charge, mass);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// Advance the state by one window (see wl_insitu_push_kernel) and write its samples into
+// device arrays of n * n_steps * n_sub samples; amp: device [n_steps + 1].
+int wl_insitu_push_gpu(int32_t imax, double k0, const double* cre, const double* cim, int64_t n,
+                       double* state, const float* charge_in, const float* mass, const double* amp,
+                       int32_t n_steps, int32_t n_sub, double dt, double t_start, double box,
+                       int32_t n_regions, double* x, double* y, double* z, double* bx, double* by,
+                       double* bz, float* ax, float* ay, float* az, double* t0, double* dtp,
+                       float* charge, float* weight, int32_t* species, void* stream) {
+  if (imax != kI || n < 0 || n_steps < 1 || n_sub < 1 || n_regions < 1 || !(dt > 0.0) ||
+      !(box > 0.0))
+    return -1;
+  if (n == 0) return 0;
+  Field f{k0, cre, cim};
+  dim3 grid((unsigned)((n + 63) / 64)), block(64);
+  hipLaunchKernelGGL(wl_insitu_push_kernel, grid, block, 0, (hipStream_t)stream, f, n, state,
+                     charge_in, mass, amp, n_steps, n_sub, dt, t_start, box, n_regions, x, y, z, bx,
+                     by, bz, ax, ay, az, t0, dtp, charge, weight, species);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -4,6 +4,13 @@
 first_id .. first_id+n-1 straight into device tensors (the structure-of-arrays
 layout of ``workloads.Batch``), for ensembles too large to pass through the host.
 The host generator remains the source of every oracle input.
+
+``InsituSim`` is the in-situ stand-in: the same particles kept on the device and
+advanced window by window through the filament field with an amplitude that grows
+and saturates in time (linear filamentation growth, then saturation, Section 3.1),
+each simulation step sub-cycled for the synthesis (Section 2.2).  Its windows are
+what a PIC code would hand the diagnostic between two recordings; ``to_host`` copies
+one back so that the oracle sees exactly the trajectories the device produced.
 """
 from __future__ import annotations
 
@@ -47,6 +54,8 @@ def _load():
 
         _lib = ctypes.CDLL(_SO)
         _lib.wl_generate_gpu.restype = ctypes.c_int
+        _lib.wl_insitu_init_gpu.restype = ctypes.c_int
+        _lib.wl_insitu_push_gpu.restype = ctypes.c_int
     return _lib
 
 
@@ -103,3 +112,100 @@ def generate_device(recipe, first_id, n, device="cuda"):
     if int(status.item()) != 0:
         raise RuntimeError("device generator: particle lengths disagree with the offsets")
     return t, ns
+
+
+def to_host(tensors):
+    """A workloads.Batch (numpy) copy of device tensors in the Batch layout."""
+    from . import Batch
+
+    h = {k: v.cpu().numpy() for k, v in tensors.items()}
+    return Batch(offsets=h["offsets"] - h["offsets"][0], x=h["x"], y=h["y"], z=h["z"], bx=h["bx"],
+                 by=h["by"], bz=h["bz"], ax=h["ax"], ay=h["ay"], az=h["az"], t0=h["t0"], dt=h["dt"],
+                 charge=h["charge"], weight=h["weight"], species=h["species"])
+
+
+def growth_amplitude(t, a0=0.01, gamma=0.4, a_sat=1.0):
+    """Filament field amplitude: exponential growth at rate gamma from a0, saturating at a_sat
+    (a_sat / sqrt(1 + (a_sat^2 / a0^2 - 1) e^{-2 gamma t}))."""
+    t = np.asarray(t, dtype=np.float64)
+    return a_sat / np.sqrt(1.0 + (a_sat**2 / a0**2 - 1.0) * np.exp(-2.0 * gamma * t))
+
+
+class InsituSim:
+    """Particles first_id .. first_id+n-1 of ``recipe`` advanced window by window on the device.
+
+    ``window(n_steps, n_sub, amplitude)`` advances n_steps simulation steps of n_sub
+    synthesis steps of recipe.dt each, with the field amplitude ``amplitude(t)`` taken at
+    the simulation step boundaries, and returns the window's samples as device tensors in
+    the Batch layout (species = collection region, the z-slab at the window start).  The
+    tensors are reused by the next window of the same shape.
+    """
+
+    def __init__(self, recipe, first_id, n, device="cuda", n_regions=1):
+        import torch
+
+        self.lib = _load()
+        self.recipe = recipe
+        self.n = int(n)
+        self.dev = torch.device(device)
+        self.n_regions = int(n_regions)
+        self.imax, self.k0, cre, cim = field_coeffs(recipe)
+        self.cre = torch.from_numpy(cre).to(self.dev)
+        self.cim = torch.from_numpy(cim).to(self.dev)
+        self.state = torch.empty((6, self.n), dtype=torch.float64, device=self.dev)
+        self.charge = torch.empty(self.n, dtype=torch.float32, device=self.dev)
+        self.mass = torch.empty(self.n, dtype=torch.float32, device=self.dev)
+        self.t = 0.0
+        self._buf = None
+        st = self.lib.wl_insitu_init_gpu(ctypes.byref(recipe), ctypes.c_int64(first_id),
+                                         ctypes.c_int64(self.n), self._p(self.state),
+                                         self._p(self.charge), self._p(self.mass), self._stream())
+        if st != 0:
+            raise RuntimeError(f"wl_insitu_init_gpu failed ({st})")
+
+    @staticmethod
+    def _p(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _stream(self):
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def _buffers(self, L):
+        import torch
+
+        if self._buf is not None and self._buf[0] == L:
+            return self._buf[1]
+        n, dev = self.n, self.dev
+        t = {"offsets": torch.arange(n + 1, dtype=torch.int64, device=dev) * L}
+        for k in ("x", "y", "z", "bx", "by", "bz"):
+            t[k] = torch.empty(n * L, dtype=torch.float64, device=dev)
+        for k in ("ax", "ay", "az"):
+            t[k] = torch.empty(n * L, dtype=torch.float32, device=dev)
+        for k, dt in (("t0", torch.float64), ("dt", torch.float64), ("charge", torch.float32),
+                      ("weight", torch.float32), ("species", torch.int32)):
+            t[k] = torch.empty(n, dtype=dt, device=dev)
+        self._buf = (L, t)
+        return t
+
+    def window(self, n_steps, n_sub, amplitude=growth_amplitude):
+        import torch
+
+        dt = self.recipe.dt
+        L = int(n_steps) * int(n_sub)
+        t = self._buffers(L)
+        bounds = self.t + dt * n_sub * np.arange(n_steps + 1)
+        amp = torch.from_numpy(np.ascontiguousarray(amplitude(bounds), dtype=np.float64)).to(self.dev)
+        st = self.lib.wl_insitu_push_gpu(
+            ctypes.c_int32(self.imax), ctypes.c_double(self.k0), self._p(self.cre), self._p(self.cim),
+            ctypes.c_int64(self.n), self._p(self.state), self._p(self.charge), self._p(self.mass),
+            self._p(amp), ctypes.c_int32(n_steps), ctypes.c_int32(n_sub), ctypes.c_double(dt),
+            ctypes.c_double(self.t), ctypes.c_double(self.recipe.box), ctypes.c_int32(self.n_regions),
+            *[self._p(t[k]) for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az", "t0", "dt",
+                                       "charge", "weight", "species")],
+            self._stream())
+        if st != 0:
+            raise RuntimeError(f"wl_insitu_push_gpu failed ({st})")
+        self.t += dt * L
+        return t  # (amp is freed in stream order: the caching allocator reuses it only after)
