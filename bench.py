@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-insitu", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--coupled-windows", type=int, default=10)
+    ap.add_argument("--coupled-steps", type=int, default=40, help="simulation steps per window")
     ap.add_argument("--windows", type=int, default=4, help="time windows of the in-situ leg")
     ap.add_argument("--batched-particles", type=int, default=8000,
                     help="particles of the uneven three-species workload in the batched leg")
@@ -364,6 +367,63 @@ def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
     return res
 
 
+def coupled_leg(a, dirs, om, log):
+    """In-situ coupling: a device pusher advances the jitter ensemble window by window
+    (simulation steps of 10 synthesis steps, growing filament amplitude) and every window
+    goes straight into the recorder (per-particle amplitude state) with a snapshot after
+    each window.  Times the pusher and the recording separately with HIP events on the
+    stream both use."""
+    import torch
+
+    from paper_1003_1140_amd import Context, DeviceBatch, Recorder
+    from workloads import configs
+    from workloads.gpu import InsituSim
+
+    n, n_steps, n_sub, n_win = a.particles, a.coupled_steps, 10, a.coupled_windows
+    res = {"workload": f"{n} particles of the jitter recipe advanced in situ: {n_win} windows of "
+                       f"{n_steps} simulation steps x {n_sub} synthesis steps (dt_synth = "
+                       f"{configs.DT}), filament amplitude growing 0.01 -> 1 at rate 0.4; 4 dirs, "
+                       f"{len(om)} log omega; snapshot after every window",
+           "terms": float(n) * n_steps * n_sub * n_win * len(dirs) * len(om)}
+    for path in ("fp32", "mfma_f16"):
+        sim = InsituSim(configs.jitter_recipe(), 0, n, "cuda")
+        c = Context(0)
+        c.set_directions(dirs)
+        c.set_frequencies(om)
+        c.set_mfma_options(1, 3, 3)
+        rec = Recorder(c, n, coherent=False, path=path)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_win)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for w in range(n_win):
+            e = ev[w]
+            e[0].record()
+            t = sim.window(n_steps, n_sub)
+            e[1].record()
+            rec.record(DeviceBatch(t, n))
+            e[2].record()
+            S = rec.snapshot()
+            e[3].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        push = sum(e[0].elapsed_time(e[1]) for e in ev)
+        record = sum(e[1].elapsed_time(e[2]) for e in ev)
+        snap = sum(e[2].elapsed_time(e[3]) for e in ev)
+        assert np.all(np.isfinite(S))
+        sim_steps = n_win * n_steps
+        res[path] = {"wall_s": wall, "push_ms": push, "record_ms": record, "snapshot_ms": snap,
+                     "recording_terms_per_s": res["terms"] / ((record + snap) * 1e-3),
+                     "synthesis_ms_per_simulation_step": (record + snap) / sim_steps,
+                     "push_ms_per_simulation_step": push / sim_steps}
+        log(f"[bench] coupled in situ ({path}): push {push:.0f} ms, recording {record:.0f} ms, snapshots "
+            f"{snap:.0f} ms over {sim_steps} simulation steps; recording "
+            f"{res[path]['recording_terms_per_s']:.3e} terms/s")
+        del rec, sim
+        c.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def band_relative(S, ref, floor=1e-4):
     S = np.asarray(S).reshape(-1, np.shape(S)[-1])
     ref = np.asarray(ref).reshape(-1, np.shape(ref)[-1])
@@ -608,6 +668,8 @@ def main():
                                    lambda m: print(m, file=sys.stderr, flush=True))
     del batch
     torch.cuda.empty_cache()
+    if not a.no_coupled:
+        out["coupled"] = coupled_leg(a, dirs, om, lambda m: print(m, file=sys.stderr, flush=True))
     if not a.no_batched:
         out["batched"] = batched_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
         torch.cuda.empty_cache()
