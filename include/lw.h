@@ -212,6 +212,26 @@ lw_status lw_spectrum_from_amplitudes(lw_ctx* ctx, const lw_batch* batch, const 
 lw_status lw_spectral_diagnostics(lw_ctx* ctx, const double* S, const double* host_weights,
                                   const double* ranges, double* avg_out, double* diag_out);
 
+/* ---- pitch-cone selection (Section 3.2) ----
+ * Particles whose momentum lies in narrow cones about inclinations theta_c[m] from the
+ * streaming axis, against the whole ensemble, in gamma^2 bins:
+ *   cos theta = |u . a| / |u| (u = gamma beta, a = host_axis normalised; the pitch angle
+ *   folded to [0, pi/2], so both beams count; a particle at rest counts as on-axis);
+ *   in cone m when cos(min(pi/2, theta_c[m] + dtheta)) <= cos theta <= cos(max(0,
+ *   theta_c[m] - dtheta)); gamma^2 = 1 + |u|^2 in bin b when edges[b] <= gamma^2 <
+ *   edges[b + 1] (outside the edges: not counted).
+ * ux, uy, uz: device FP64 [n_particles].  host_theta_c [n_cones] (1..16 cones), dtheta > 0,
+ * host_edges [n_bins + 1] increasing (1..256 bins).  Outputs (host): counts_out int64
+ * [n_cones + 1][n_bins] (row n_cones: all particles); dev_out [n_cones][n_bins], the
+ * relative deviation from isotropy (count share / isotropic share cos theta_lo -
+ * cos theta_hi; NaN for an empty bin); member: NULL or device int32 [n_particles], the
+ * first cone holding each particle or -1 (e.g. to synthesise one cone with
+ * lw_accumulate_subset).  Counts are exact.  Synchronous. */
+lw_status lw_pitch_cones(lw_ctx* ctx, int64_t n_particles, const double* ux, const double* uy,
+                         const double* uz, const double* host_axis, const double* host_theta_c,
+                         int32_t n_cones, double dtheta, const double* host_edges, int32_t n_bins,
+                         int64_t* counts_out, double* dev_out, int32_t* member);
+
 /* ---- batched launches (uneven lengths, several species) ----
  * Plan a batch for the persistent launch (synchronous; reads the batch offsets).
  * FP32 path: particles are ordered by decreasing trajectory length and grouped

@@ -859,6 +859,60 @@ lw_status lw_spectral_diagnostics(lw_ctx* c, const double* S, const double* weig
   return LW_OK;
 }
 
+lw_status lw_pitch_cones(lw_ctx* c, int64_t n, const double* ux, const double* uy, const double* uz,
+                         const double* axis, const double* theta_c, int32_t n_cones, double dtheta,
+                         const double* edges, int32_t n_bins, int64_t* counts_out, double* dev_out,
+                         int32_t* member) {
+  if (!c) return LW_EINVAL;
+  if (n < 0 || (n > 0 && (!ux || !uy || !uz))) return fail(c, LW_EINVAL, "bad momentum arrays");
+  if (!axis || !theta_c || !edges || !counts_out || !dev_out) return fail(c, LW_EINVAL, "NULL argument");
+  if (n_cones < 1 || n_cones > lw::kMaxCones) return fail(c, LW_EINVAL, "1 to %d cones", lw::kMaxCones);
+  if (n_bins < 1 || n_bins > lw::kMaxPitchBins) return fail(c, LW_EINVAL, "1 to %d bins", lw::kMaxPitchBins);
+  if (!(dtheta > 0.0) || !isfinite(dtheta)) return fail(c, LW_EINVAL, "dtheta must be > 0");
+  for (int i = 0; i < n_bins; ++i)
+    if (!(edges[i] < edges[i + 1]) || !isfinite(edges[i + 1])) return fail(c, LW_EINVAL, "edges must increase");
+  const double an = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+  if (!(an > 0.0) || !isfinite(an)) return fail(c, LW_EINVAL, "axis is zero or not finite");
+  const double a[3] = {axis[0] / an, axis[1] / an, axis[2] / an};
+  std::vector<double> host(2 * (size_t)n_cones + n_bins + 1);
+  for (int m = 0; m < n_cones; ++m) {
+    if (!isfinite(theta_c[m])) return fail(c, LW_EINVAL, "cone %d is not finite", m);
+    const double lo = std::max(0.0, theta_c[m] - dtheta), hi = std::min(0.5 * M_PI, theta_c[m] + dtheta);
+    host[2 * m] = cos(hi);
+    host[2 * m + 1] = cos(lo);
+  }
+  std::copy(edges, edges + n_bins + 1, host.begin() + 2 * n_cones);
+  DeviceGuard g(c->device);
+  const size_t rows = (size_t)(n_cones + 1) * n_bins;
+  const size_t need = host.size() * sizeof(double) + rows * (sizeof(unsigned long long) + sizeof(double));
+  if (c->diag_cap * sizeof(double) < need) {
+    LW_HIP(hipStreamSynchronize(c->stream), "sync");
+    free_dev(c->d_diag);
+    c->d_diag = nullptr;
+    c->diag_cap = 0;
+    const size_t words = (need + sizeof(double) - 1) / sizeof(double);
+    LW_HIP(hipMalloc(&c->d_diag, words * sizeof(double)), "hipMalloc(pitch)");
+    c->diag_cap = words;
+  }
+  double* d_bounds = c->d_diag;
+  double* d_edges = d_bounds + 2 * n_cones;
+  unsigned long long* d_counts = (unsigned long long*)(d_edges + n_bins + 1);
+  double* d_dev = (double*)(d_counts + rows);
+  LW_HIP(hipMemcpyAsync(d_bounds, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice, c->stream),
+         "copy cones");
+  LW_HIP(lw::launch_fill_u64(d_counts, (int64_t)rows, 0ull, c->stream), "zero counts");
+  LW_HIP(lw::launch_pitch_cones(n, ux, uy, uz, a, d_bounds, n_cones, d_edges, n_bins, d_counts, d_dev,
+                                member, c->stream),
+         "launch pitch cones");
+  LW_HIP(hipMemcpyAsync(counts_out, d_counts, rows * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream),
+         "copy counts");
+  LW_HIP(hipMemcpyAsync(dev_out, d_dev, (size_t)n_cones * n_bins * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream),
+         "copy deviation");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  return LW_OK;
+}
+
 lw_status lw_stats(const lw_ctx* c, int64_t* calls) {
   if (!c || !calls) return LW_EINVAL;
   *calls = c->calls;

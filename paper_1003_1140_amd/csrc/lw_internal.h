@@ -75,6 +75,13 @@ hipError_t launch_coherent_power(const double* A, int64_t n, double* S, hipStrea
 // (sum a_sum), then per (species, row) [k, w_k, w_peak, S_k, alpha, n_alpha, beta, n_beta]
 // into out [ns][nd + 1][8]; ranges = alpha_lo, alpha_hi, beta_lo, beta_hi.
 constexpr int kDiagFields = 8;
+// Pitch cones (lw_pitch.hip): counts [nc + 1][nb] (zeroed by the caller), deviation
+// [nc][nb], member [n] or null; bounds [nc][2] = (cos theta_hi, cos theta_lo); axis unit.
+constexpr int kMaxCones = 16, kMaxPitchBins = 256;
+hipError_t launch_pitch_cones(int64_t n, const double* ux, const double* uy, const double* uz,
+                              const double axis[3], const double* bounds, int nc, const double* edges,
+                              int nb, unsigned long long* counts, double* dev, int32_t* member,
+                              hipStream_t stream);
 hipError_t launch_spectral_diagnostics(const double* S, const double* a, double a_sum, int ns, int nd,
                                        int nw, const double* omega, const double ranges[4],
                                        double* avg, double* out, hipStream_t stream);

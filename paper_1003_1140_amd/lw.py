@@ -33,7 +33,7 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets",
             "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
             "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes",
-            "lw_spectral_diagnostics")
+            "lw_spectral_diagnostics", "lw_pitch_cones")
 
 
 class LWError(RuntimeError):
@@ -119,6 +119,7 @@ def load_library():
             "lw_amplitude_workspace_size": (ctypes.c_int, [P, I64, ctypes.POINTER(SZ)]),
             "lw_spectrum_from_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, SZ]),
             "lw_spectral_diagnostics": (ctypes.c_int, [P, P, P, P, P, P]),
+            "lw_pitch_cones": (ctypes.c_int, [P, I64, P, P, P, P, P, I32, D, P, I32, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -347,6 +348,24 @@ class Context:
             rp = _np_ptr(ra)
         self._check(self.lib.lw_spectral_diagnostics(self.h, sp, wp, rp, _np_ptr(avg), _np_ptr(diag)))
         return avg, diag
+
+    def pitch_cones(self, ux, uy, uz, axis, theta_c, dtheta, edges, member=False):
+        """(counts [n_cones + 1][n_bins], deviation [n_cones][n_bins], member or None) for device
+        FP64 momenta ux, uy, uz (u = gamma beta)."""
+        n = int(ux.numel())
+        for t in (ux, uy, uz):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n
+        ax = np.ascontiguousarray(axis, dtype=np.float64)
+        th = np.ascontiguousarray(theta_c, dtype=np.float64)
+        ed = np.ascontiguousarray(edges, dtype=np.float64)
+        counts = np.zeros((th.size + 1, ed.size - 1), dtype=np.int64)
+        dev = np.zeros((th.size, ed.size - 1), dtype=np.float64)
+        mem = torch.empty(n, dtype=torch.int32, device=ux.device) if member else None
+        self._check(self.lib.lw_pitch_cones(self.h, n, ctypes.c_void_p(ux.data_ptr()), ctypes.c_void_p(uy.data_ptr()),
+                                            ctypes.c_void_p(uz.data_ptr()), _np_ptr(ax), _np_ptr(th), th.size,
+                                            float(dtheta), _np_ptr(ed), ed.size - 1, _np_ptr(counts), _np_ptr(dev),
+                                            ctypes.c_void_p(mem.data_ptr()) if member else None))
+        return counts, dev, mem
 
     def set_mfma_options(self, bands=1, products_f16=3, products_bf16=3):
         self._check(self.lib.lw_set_mfma_options(self.h, bands, products_f16, products_bf16))
