@@ -418,6 +418,16 @@ def coupled_leg(a, dirs, om, log):
         log(f"[bench] coupled in situ ({path}): push {push:.0f} ms, recording {record:.0f} ms, snapshots "
             f"{snap:.0f} ms over {sim_steps} simulation steps; recording "
             f"{res[path]['recording_terms_per_s']:.3e} terms/s")
+        if path == "fp32":  # pitch cones of the final momenta (Section 3.2 analysis)
+            ux, uy, uz = (sim.state[3 + k].contiguous() for k in range(3))
+            theta = [m * np.pi / 8 for m in range(5)]
+            edges = np.exp(np.linspace(0.0, np.log(2500.0), 41))
+            c.pitch_cones(ux, uy, uz, [1.0, 0.0, 0.0], theta, 1.0 / 3.0, edges, member=True)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            counts, dev, _ = c.pitch_cones(ux, uy, uz, [1.0, 0.0, 0.0], theta, 1.0 / 3.0, edges, member=True)
+            res["pitch_cones_ms"] = (time.perf_counter() - t1) * 1e3
+            res["pitch_cone_counts"] = [int(x) for x in counts.sum(axis=1)]
         del rec, sim
         c.close()
         torch.cuda.empty_cache()

@@ -87,3 +87,27 @@ def test_direction_sets():
         np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, rtol=1e-15)
     ea = configs.dirs_equal_area()
     assert np.abs(ea.sum(0)).max() < 1e-12  # symmetric cell centres
+
+
+def test_two_d_motion_stays_in_the_field_plane():
+    """2D2V: no y momentum and y = 0 at start; B along y keeps every sample in the x-z plane."""
+    from workloads import configs
+
+    b = workloads.generate(configs.jitter_2d_recipe(steps=600), 0, 8)
+    assert np.all(b.y == 0.0) and np.all(b.by == 0.0) and np.all(b.ay == 0.0)
+    assert np.all(np.abs(b.bx[b.offsets[:-1]]) > 0.9)  # they start in the counter-streaming beams
+    b3 = workloads.generate(configs.jitter_recipe(steps=600), 0, 8)
+    assert np.any(b3.by != 0.0)  # the 3D recipe is unchanged
+
+
+def test_two_d_radiation_has_no_out_of_plane_field_in_plane():
+    """In-plane motion seen from an in-plane observer radiates no field along y."""
+    import oracle
+    from workloads import configs
+
+    b = workloads.generate(configs.jitter_2d_recipe(steps=300), 0, 3)
+    dirs = configs.dirs_paper(two_d=True)
+    assert np.all(dirs[:, 1] == 0.0)
+    _, A = oracle.coherent_spectrum(b, dirs, configs.log_grid(0.1, 100.0, 64), n_species=1,
+                                    with_amplitude=True)
+    assert np.all(A[..., 1] == 0.0) and np.abs(A).max() > 0

@@ -168,12 +168,13 @@ class Recipe(ctypes.Structure):
         ("ion_mass", ctypes.c_double),
         ("len_min", ctypes.c_int32),
         ("len_max", ctypes.c_int32),
+        ("two_d", ctypes.c_int32),
     ]
 
 
 def make_recipe(seed, steps=4096, gammas=(3.0,), dt=0.005, kT=0.01, delta=0.3,
                 box=4.0 * np.pi, kmin=0.5, kmax=8.0, frac_pos=0.0, frac_ion=0.0,
-                ion_mass=16.0, len_range=None) -> Recipe:
+                ion_mass=16.0, len_range=None, two_d=False) -> Recipe:
     r = Recipe()
     r.seed = int(seed)
     r.dt = dt
@@ -191,6 +192,7 @@ def make_recipe(seed, steps=4096, gammas=(3.0,), dt=0.005, kT=0.01, delta=0.3,
     lo, hi = len_range if len_range is not None else (steps, steps)
     r.len_min = int(lo)
     r.len_max = int(hi)
+    r.two_d = 1 if two_d else 0
     return r
 
 

@@ -86,6 +86,21 @@ def jitter_recipe(seed=SEEDS["jitter"], steps=4096):
     return make_recipe(seed, steps=steps, gammas=(3.0,), dt=DT)
 
 
+def jitter_2d_recipe(seed=SEEDS["jitter"], steps=4096):
+    """The jitter ensemble in 2D2V: motion confined to the x-z plane of the field."""
+    return make_recipe(seed, steps=steps, gammas=(3.0,), dt=DT, two_d=True)
+
+
+def dirs_paper(two_d=False):
+    """Six far observers spread uniformly in angle from head-on (along the stream, +x) to
+    edge-on (Section 2.2): in the x-z plane of the motion for 2D runs, in the x-y plane
+    otherwise (the paper gives no azimuth for 3D)."""
+    th = np.linspace(0.0, 0.5 * np.pi, 6)
+    side = np.stack([np.cos(th), np.zeros(6), np.sin(th)], axis=1) if two_d else \
+        np.stack([np.cos(th), np.sin(th), np.zeros(6)], axis=1)
+    return unit(side)
+
+
 def wide_recipe(seed=SEEDS["jitter_wide"], steps=2048):
     return make_recipe(seed, steps=steps, gammas=(3.0,), dt=DT)
 

@@ -97,6 +97,7 @@ typedef struct {
   double frac_ion;    /* fraction of ions (charge +1) */
   double ion_mass;    /* ion mass in m_e */
   int32_t len_min, len_max; /* trajectory length, uniform integers in [min, max] */
+  int32_t two_d;      /* 2D2V: motion in the x-z plane (y = 0, no y momentum) */
 } wl_recipe;
 
 #define WL_SPECIES_ELECTRON 0
@@ -303,7 +304,7 @@ int wl_generate(const wl_recipe* r, int64_t first_id, int64_t n, const int64_t* 
       double px = r->box * u01(w[0], w[1]);
       double pz = r->box * u01(w[2], w[3]);
       draws(r->seed, id, 5u, w);
-      double py = r->box * u01(w[0], w[1]);
+      double py = r->two_d ? 0.0 : r->box * u01(w[0], w[1]);
       /* rest-frame thermal four-velocity, then boost along +-x */
       double nrm[4];
       draws(r->seed, id, 2u, w);
@@ -311,7 +312,7 @@ int wl_generate(const wl_recipe* r, int64_t first_id, int64_t n, const int64_t* 
       draws(r->seed, id, 3u, w);
       normals2(w, nrm + 2);
       double sig = sqrt(r->kT / (double)m);
-      double upx = sig * nrm[0], upy = sig * nrm[1], upz = sig * nrm[2];
+      double upx = sig * nrm[0], upy = r->two_d ? 0.0 : sig * nrm[1], upz = sig * nrm[2];
       double gp = sqrt(1.0 + upx * upx + upy * upy + upz * upz);
       double sgn = (id & 1u) ? -1.0 : 1.0;
       double b0 = sgn * sqrt(1.0 - 1.0 / (g0 * g0));

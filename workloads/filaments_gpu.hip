@@ -20,6 +20,7 @@ typedef struct {
   double gamma0[4];
   double frac_pos, frac_ion, ion_mass;
   int32_t len_min, len_max;
+  int32_t two_d;
 } wl_recipe_gpu;
 }
 
@@ -134,7 +135,7 @@ __device__ void initial_state(const wl_recipe_gpu& r, uint64_t id, double g0, fl
   double px = r.box * u01(w[0], w[1]);
   double pz = r.box * u01(w[2], w[3]);
   draws(r.seed, id, 5u, w);
-  double py = r.box * u01(w[0], w[1]);
+  double py = r.two_d ? 0.0 : r.box * u01(w[0], w[1]);
   double nrm[4];
   for (int h = 0; h < 2; ++h) {
     draws(r.seed, id, 2u + h, w);
@@ -144,7 +145,7 @@ __device__ void initial_state(const wl_recipe_gpu& r, uint64_t id, double g0, fl
     nrm[2 * h + 1] = rr * sin(2.0 * M_PI * u2);
   }
   const double sig = sqrt(r.kT / (double)m);
-  const double upx = sig * nrm[0], upy = sig * nrm[1], upz = sig * nrm[2];
+  const double upx = sig * nrm[0], upy = r.two_d ? 0.0 : sig * nrm[1], upz = sig * nrm[2];
   const double gp = sqrt(1.0 + upx * upx + upy * upy + upz * upz);
   const double sgn = (id & 1u) ? -1.0 : 1.0;
   const double b0 = sgn * sqrt(1.0 - 1.0 / (g0 * g0));
