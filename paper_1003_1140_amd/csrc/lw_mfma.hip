@@ -16,7 +16,7 @@
 //  * Then, by the Poisson summation formula, for |w - w_c| <= D
 //        A(w) e^{-i w tau_0} = sum_q F(q) e^{i (w - w_c) t_q} / Phi((w - w_c) h),
 //    Phi the Fourier transform of phi, up to aliasing terms suppressed by the
-//    kernel (sigma = 2, W = 8: ~1e-7 of sum |g|).
+//    kernel (~4e-7 of the signal at a band edge; W and sigma below).
 //  * sum_q F(q) e^{i nu_j q h} is a complex matrix product C = E F with the
 //    table E[j, q] = e^{i nu_j q h} (nu_j = w_j - w_c) shared by every particle
 //    and direction.  Written as a real product it has rows (j, re|im), inner
@@ -43,9 +43,20 @@
 
 namespace lw {
 
-constexpr int kW = 8;              // kernel width in grid points
-constexpr double kSigma = 2.0;     // grid oversampling relative to the band half-width
-constexpr double kBeta = 2.30 * kW;
+// Kernel width W, oversampling sigma and shape beta, chosen by the precision of the
+// contraction.  The worst alias-to-signal ratio at a band edge, the sum over m != 0 of
+// |Phi(xi + 2 pi m)| / Phi(xi) at xi = pi / sigma, is 8.5e-8 for (10, 1.6, 20.5) and 4.1e-7
+// for (8, 2, 18.4).  The first makes the contraction's inner dimension a fifth shorter for
+// a quarter more spreading taps, but its deconvolution 1 / Phi grows 10x from the band
+// centre to the edge (against 2.8x): harmless when the operands are split into hi + lo
+// parts (rounding ~2^-22), not when a single FP16 or BF16 product carries ~2^-11.
+struct KernelShape {
+  int w;
+  double sigma, beta;
+};
+constexpr KernelShape kShapeSplit = {10, 1.6, 20.5};   // hi/lo operands, three products
+constexpr KernelShape kShapeSingle = {8, 2.0, 18.4};   // one product
+constexpr int kWMax = 10;
 constexpr int kMaxBands = 16;
 constexpr int kTileM = 128;        // GEMM rows per work-group
 constexpr int kTileN = 128;        // GEMM columns per work-group (64 particles x 2 polarisations)
@@ -77,6 +88,7 @@ struct MfmaPlanCache {
   int bands_req = 1;
   int products_f16 = 3, products_bf16 = 3;
   int tile = 3;          // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256
+  KernelShape shape = kShapeSplit;  // spreading kernel the tables were built for
   int nb = 0;
   Band band[kMaxBands];
   double span = 0.0;     // span the tables were sized for
@@ -109,7 +121,7 @@ struct SpreadArgs {
   unsigned long long* flops;  // null, or useful FLOPs of one product of the contraction
   // phi(i - W/2 + 1 - f) = sum_k tapc[i][k] z^k, z = 2 f - 1: the W tap weights of a sample
   // with fractional grid coordinate f (Chebyshev interpolants, within 2e-8 of phi)
-  float tapc[kW][kTapCoef];
+  float tapc[kWMax][kTapCoef];
 };
 
 struct GemmArgs {
@@ -217,6 +229,7 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 // of a chunk lies within kRing of the oldest pending one.
 constexpr int kRing = 1024;  // grid points held in LDS (power of two)
 
+template <int kW>
 struct SpreadStage {
   int lo[kSpreadWin];             // first grid point of each sample's taps
   float w[kW][kSpreadWin];        // tap weights
@@ -247,7 +260,8 @@ __device__ __forceinline__ void load_raw(const BatchView& b, int64_t o, int64_t 
   r.az = b.az[idx];
 }
 
-__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage& st,
+template <int kW>
+__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage<kW>& st,
                                               const RawSample& r, const double* n, const double* e1,
                                               const double* e2, int64_t p, int64_t len, int64_t kc,
                                               double t0, double dtp, double tau0, double inv_h,
@@ -286,8 +300,9 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
 
+template <int kW>
 __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
-  __shared__ SpreadStage st;
+  __shared__ SpreadStage<kW> st;
   __shared__ float s_wmax[kSpreadWin / 64];
 
   const int tid = threadIdx.x;
@@ -371,11 +386,11 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
       float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
       if (x < G) {
         const int q = base + x;
-        // (clamped, and the tap index masked: on invalid, unsorted data an entry may be stale)
+        // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale)
         const int s_begin = min(max(st.first[x], 0), take);
         const int s_end = min(max(st.first[x + kW], s_begin), take);
         for (int s = s_begin + sl; s < s_end; s += S) {
-          const int i = (q - st.lo[s]) & (kW - 1);
+          const int i = min(max(q - st.lo[s], 0), kW - 1);
           const float w = st.w[i][s];
           const float4 gv = st.g[s];
           acc0 = fmaf(w, gv.x, acc0);
@@ -1132,10 +1147,10 @@ __global__ void lw_mfma_reduce_coherent_kernel(const double* partial, int n_ftil
 // ------------------------------------------------------------------ host side
 namespace {
 
-double es_phi_host(double x) {
-  const double y = 2.0 * x / kW;
+double es_phi_host(double x, const KernelShape& k) {
+  const double y = 2.0 * x / k.w;
   const double r = 1.0 - y * y;
-  return r > 0.0 ? exp(kBeta * (sqrt(r) - 1.0)) : 0.0;
+  return r > 0.0 ? exp(k.beta * (sqrt(r) - 1.0)) : 0.0;
 }
 
 // Tap weight polynomials of the spreading kernel: for tap i and z = 2 f - 1 in [-1, 1],
@@ -1143,18 +1158,20 @@ double es_phi_host(double x) {
 // the first kind, then rewritten in powers of z for Horner evaluation.  The sqrt edge of
 // phi limits the interpolant to ~1.6e-8 of phi's peak; the coefficients sum to ~1.25 in
 // absolute value, so FP32 evaluation adds < 1e-7.
-void tap_polynomials(float out[kW][kTapCoef]) {
+void tap_polynomials(float out[kWMax][kTapCoef], const KernelShape& ks) {
   constexpr int N = kTapCoef;
   double T[N][N] = {};  // T[j] = power coefficients of the Chebyshev polynomial T_j
   T[0][0] = 1.0;
   T[1][1] = 1.0;
   for (int j = 2; j < N; ++j)
     for (int k = 0; k < N; ++k) T[j][k] = (k > 0 ? 2.0 * T[j - 1][k - 1] : 0.0) - T[j - 2][k];
-  for (int i = 0; i < kW; ++i) {
+  for (int i = 0; i < kWMax; ++i)
+    for (int k = 0; k < N; ++k) out[i][k] = 0.0f;
+  for (int i = 0; i < ks.w; ++i) {
     double g[N], zk[N];
     for (int k = 0; k < N; ++k) {
       zk[k] = cos((2 * k + 1) * M_PI / (2.0 * N));
-      g[k] = es_phi_host((double)(i - (kW / 2 - 1)) - 0.5 * (zk[k] + 1.0));
+      g[k] = es_phi_host((double)(i - (ks.w / 2 - 1)) - 0.5 * (zk[k] + 1.0), ks);
     }
     double mono[N] = {};
     for (int j = 0; j < N; ++j) {
@@ -1167,23 +1184,37 @@ void tap_polynomials(float out[kW][kTapCoef]) {
   }
 }
 
-// Fourier transform of the kernel, Phi(xi) = int phi(x) cos(xi x) dx, by composite
-// Gauss-Legendre quadrature (the kernel is smooth inside its support).
-double es_ft_host(double xi) {
+// The kernel as the spreading applies it: at x = i - W/2 + 1 - f (f in [0, 1)) the
+// polynomial of tap i at z = 2 f - 1, from the same FP32 coefficients.
+double applied_phi_host(double x, const KernelShape& k, const float (*tapc)[kTapCoef]) {
+  const double t = x + (double)(k.w / 2 - 1);
+  const double i = ceil(t);
+  if (i < 0.0 || i > (double)(k.w - 1)) return 0.0;
+  const double z = 2.0 * (i - t) - 1.0;
+  const float* c = tapc[(int)i];
+  double v = c[kTapCoef - 1];
+  for (int m = kTapCoef - 2; m >= 0; --m) v = v * z + (double)c[m];
+  return v;
+}
+
+// Fourier transform of the applied kernel, Phi(xi) = int phi(x) cos(xi x) dx, by 8-point
+// Gauss-Legendre on every unit interval between tap breakpoints (a polynomial on each), so
+// that the deconvolution divides out exactly what the spreading put in.
+double es_ft_host(double xi, const KernelShape& k) {
   static const double gx[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290,
                                -0.1834346424956498, 0.1834346424956498,  0.5255324099163290,
                                0.7966664774136267,  0.9602898564975363};
   static const double gw[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873,
                                0.3626837833783620, 0.3626837833783620, 0.3137066458778873,
                                0.2223810344533745, 0.1012285362903763};
-  const int panels = 64;
-  const double a = -0.5 * kW, w = (double)kW / panels;
+  float tapc[kWMax][kTapCoef];
+  tap_polynomials(tapc, k);
   double s = 0.0;
-  for (int p = 0; p < panels; ++p) {
-    const double c = a + (p + 0.5) * w;
+  for (int p = 0; p < k.w; ++p) {  // unit panels [-W/2 + p, -W/2 + p + 1]
+    const double c = -0.5 * k.w + p + 0.5;
     for (int i = 0; i < 8; ++i) {
-      const double x = c + 0.5 * w * gx[i];
-      s += 0.5 * w * gw[i] * es_phi_host(x) * cos(xi * x);
+      const double x = c + 0.5 * gx[i];
+      s += 0.5 * gw[i] * applied_phi_host(x, k, tapc) * cos(xi * x);
     }
   }
   return s;
@@ -1282,9 +1313,10 @@ lw_status batch_span(lw_ctx* c, const lw_batch* b, double* span) {
   return LW_OK;
 }
 
-lw_status build_plan(lw_ctx* c, double span, int dtype) {
+lw_status build_plan(lw_ctx* c, double span, int dtype, const KernelShape& ks) {
   MfmaPlanCache* pc = c->mfma;
   free_tables(pc);
+  pc->shape = ks;
   const int nb = std::max(1, std::min(pc->bands_req, std::min(kMaxBands, c->nw)));
   pc->nb = nb;
   pc->span = span;
@@ -1305,9 +1337,9 @@ lw_status build_plan(lw_ctx* c, double span, int dtype) {
     bd.wc = 0.5 * (lo + hi);
     double D = 0.5 * (hi - lo);
     D = std::max(D, 1e-6 * std::max(bd.wc, 1e-300));
-    bd.h = M_PI / (kSigma * D);
+    bd.h = M_PI / (ks.sigma * D);
     bd.wc_turn = bd.wc / (2.0 * M_PI);
-    const double qd = ceil(span / bd.h) + kW + 1;
+    const double qd = ceil(span / bd.h) + ks.w + 1;
     if (qd > 4.0e6) return set_err(c, LW_EUNSUPPORTED, "retarded-time span too long for the matrix-core grid");
     bd.qmax = (int)qd;
     bd.m = ((2 * bd.nj + kTileM - 1) / kTileM) * kTileM;
@@ -1343,12 +1375,12 @@ lw_status build_plan(lw_ctx* c, double span, int dtype) {
     for (int jl = 0; jl < bd.nj; ++jl) {
       const int j = bd.j0 + jl;
       const double nu = w[j] - bd.wc;
-      const double ph = es_ft_host(nu * bd.h);
+      const double ph = es_ft_host(nu * bd.h, ks);
       rf[j] = 1.0 / (4.0 * M_PI * M_PI * ph * ph);
       rj[j] = bd.row_off + 2 * jl;
       // grid point q sits at retarded time (q - W/2) h after the first sample
-      rcx[2 * j] = cos(-nu * 0.5 * kW * bd.h) / ph;
-      rcx[2 * j + 1] = sin(-nu * 0.5 * kW * bd.h) / ph;
+      rcx[2 * j] = cos(-nu * 0.5 * ks.w * bd.h) / ph;
+      rcx[2 * j + 1] = sin(-nu * 0.5 * ks.w * bd.h) / ph;
     }
   }
   MF_HIP(hipMalloc(&pc->rowc, 2 * (size_t)c->nw * sizeof(double)), "hipMalloc(rowc)");
@@ -1368,16 +1400,19 @@ lw_status build_plan(lw_ctx* c, double span, int dtype) {
 lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path) {
   MfmaPlanCache* pc = c->mfma;
   const int dtype = path == LW_PATH_MFMA_BF16 ? 1 : 0;
+  const int products = dtype ? pc->products_bf16 : pc->products_f16;
+  const KernelShape& ks = products > 1 ? kShapeSplit : kShapeSingle;
+  const bool same = pc->valid && pc->dtype == dtype && pc->shape.w == ks.w;
   if (c->capturing) {
-    if (pc->valid && pc->dtype == dtype) return LW_OK;
+    if (same) return LW_OK;
     return set_err(c, LW_ESTATE, "matrix-core tables must be planned before graph capture");
   }
   double span = 0.0;
   lw_status st = batch_span(c, b, &span);
   if (st != LW_OK) return st;
-  if (pc->valid && pc->dtype == dtype && span <= pc->span) return LW_OK;
-  const double want = std::max(span * 1.25, pc->valid ? pc->span : 0.0);
-  return build_plan(c, want, dtype);
+  if (same && span <= pc->span) return LW_OK;
+  const double want = std::max(span * 1.25, same ? pc->span : 0.0);
+  return build_plan(c, want, dtype, ks);
 }
 
 }  // namespace
@@ -1469,7 +1504,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   sa.err = c->d_err;
   sa.ns = c->ns;
   sa.flops = c->prof ? c->d_flops : nullptr;
-  tap_polynomials(sa.tapc);
+  tap_polynomials(sa.tapc, pc->shape);
   c->flop_mult = products;
   ga.e_hi = pc->e_hi;
   ga.e_lo = pc->e_lo;
@@ -1501,8 +1536,12 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     sa.n_local = ga.n_local = nl;
     sa.n_ftile = ga.n_ftile = nft;
     MF_HIP(prof_begin(c, kProfSpread), "profile");
-    hipLaunchKernelGGL(lw_spread_kernel, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)), dim3(kSpreadWin),
-                       0, c->stream, sa);
+    if (pc->shape.w == kShapeSplit.w)
+      hipLaunchKernelGGL(lw_spread_kernel<kShapeSplit.w>, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)),
+                         dim3(kSpreadWin), 0, c->stream, sa);
+    else
+      hipLaunchKernelGGL(lw_spread_kernel<kShapeSingle.w>, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)),
+                         dim3(kSpreadWin), 0, c->stream, sa);
     MF_HIP(hipGetLastError(), "launch spread");
     MF_HIP(prof_end(c), "profile");
     hipLaunchKernelGGL(lw_sort_columns_kernel, dim3((unsigned)(c->nd * pc->nb)), dim3(1024), 0, c->stream,
