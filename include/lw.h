@@ -264,9 +264,14 @@ lw_status lw_tune(lw_ctx* ctx, const lw_batch* batch, lw_path path, int32_t repe
 /* HIP graph of one lw_accumulate(batch, path, workspace): captured on a
  * private stream (so it also works when the context uses the null stream),
  * replayed on the context's stream by lw_graph_launch; each replay adds the
- * batch's spectrum into S like lw_accumulate.  The batch, workspace and the
- * context's grids must stay unchanged while the graph is in use.  The
- * graph clears its counters with kernels, not memset nodes. */
+ * batch's spectrum into S like lw_accumulate.  The batch and workspace must
+ * stay unchanged while the graph is in use.  The graph clears its counters with
+ * kernels, not memset nodes.  lw_graph_launch returns LW_ESTATE (and launches
+ * nothing) once the context's device buffers the graph refers to have been
+ * freed or refilled since the capture: new grids or species (lw_set_directions,
+ * lw_set_frequencies, lw_set_species, lw_set_coherent), a new lw_plan_batch
+ * (also run by lw_tune), or rebuilt matrix-core tables (a batch with a longer
+ * retarded-time span, other bands or products); capture again then. */
 typedef struct lw_graph lw_graph;
 lw_status lw_graph_capture(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
                            size_t workspace_bytes, lw_graph** out);

@@ -61,6 +61,7 @@ void free_dev(void* p) {
 
 // S [ns][nd][nw], and in coherent synthesis the summed amplitudes A [ns][nd][nw][4]; both zeroed.
 lw_status alloc_accumulator(lw_ctx* c) {
+  c->epoch += 1;
   free_dev(c->d_S);
   free_dev(c->d_A);
   c->d_S = nullptr;
@@ -477,6 +478,7 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   if (path != LW_PATH_FP32) return fail(c, LW_EINVAL, "unknown path %d", (int)path);
   auto& pl = c->plan;
   pl.valid = false;
+  c->epoch += 1;  // the plan's buffers are refilled (and may move)
   const int64_t P = b->n_particles;
   if (P == 0) return LW_OK;
   std::vector<int64_t> off(P + 1);
@@ -646,6 +648,8 @@ lw_status lw_graph_capture(lw_ctx* c, const lw_batch* b, lw_path path, void* ws,
   lw_graph* gr = new lw_graph();
   gr->ctx = c;
   gr->graph = graph;
+  gr->epoch = c->epoch;
+  gr->mfma_epoch = lw::mfma_epoch(c->mfma);
   e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(graph);
@@ -659,6 +663,10 @@ lw_status lw_graph_capture(lw_ctx* c, const lw_batch* b, lw_path path, void* ws,
 lw_status lw_graph_launch(lw_graph* gr) {
   if (!gr || !gr->ctx) return LW_EINVAL;
   lw_ctx* c = gr->ctx;
+  if (gr->epoch != c->epoch || gr->mfma_epoch != lw::mfma_epoch(c->mfma))
+    return fail(c, LW_ESTATE,
+                "the context's accumulators, grids, tables or plan changed since this graph was "
+                "captured: capture it again");
   DeviceGuard g(c->device);
   LW_HIP(hipGraphLaunch(gr->exec, c->stream), "launch graph");
   c->calls += 1;

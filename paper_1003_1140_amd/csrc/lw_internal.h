@@ -134,10 +134,14 @@ struct lw_ctx {
   } plan;
   unsigned* d_ticket = nullptr;
   bool capturing = false;  // inside lw_graph_capture: no synchronisation allowed
+  // bumped whenever a device buffer that captured work refers to is freed, moved or refilled
+  // for another batch (accumulators, grids, persistent plan); a graph records it at capture
+  uint64_t epoch = 0;
 };
 
 struct lw_graph {
   lw_ctx* ctx = nullptr;
+  uint64_t epoch = 0, mfma_epoch = 0;  // the context's buffers the graph was captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };

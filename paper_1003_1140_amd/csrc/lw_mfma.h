@@ -7,6 +7,8 @@ namespace lw {
 MfmaPlanCache* mfma_cache_create();
 void mfma_cache_destroy(MfmaPlanCache* c);
 void mfma_cache_invalidate(MfmaPlanCache* c);
+// Counts table rebuilds: captured work that read older tables must not run.
+uint64_t mfma_epoch(const MfmaPlanCache* c);
 lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16);
 lw_status mfma_set_bands(lw_ctx* c, int bands);
 lw_status mfma_set_tile(lw_ctx* c, int tile);

@@ -89,6 +89,7 @@ struct MfmaPlanCache {
   int products_f16 = 3, products_bf16 = 3;
   int tile = 3;          // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256
   KernelShape shape = kShapeSplit;  // spreading kernel the tables were built for
+  uint64_t epoch = 0;               // bumped when the tables are freed
   int nb = 0;
   Band band[kMaxBands];
   double span = 0.0;     // span the tables were sized for
@@ -1277,6 +1278,7 @@ WsLayout ws_layout(const lw_ctx* c, const MfmaPlanCache* pc, int64_t P) {
 }
 
 void free_tables(MfmaPlanCache* pc) {
+  pc->epoch += 1;
   if (pc->e_hi) (void)hipFree(pc->e_hi);
   if (pc->e_lo) (void)hipFree(pc->e_lo);
   if (pc->rowfac) (void)hipFree(pc->rowfac);
@@ -1425,6 +1427,8 @@ void mfma_cache_destroy(MfmaPlanCache* pc) {
   if (pc->d_span) (void)hipFree(pc->d_span);
   delete pc;
 }
+
+uint64_t mfma_epoch(const MfmaPlanCache* pc) { return pc ? pc->epoch : 0; }
 
 void mfma_cache_invalidate(MfmaPlanCache* pc) {
   if (pc) free_tables(pc);

@@ -139,3 +139,43 @@ def test_autotuner_leaves_spectra_unchanged_and_picks_a_shape(uneven_small, tmp_
     rep = c.tune(db, "mfma_f16", repeats=1)
     print("[tune] mfma best", json.dumps(rep["best"]), flush=True)
     assert rep["best"] is not None
+
+
+def test_stale_graphs_are_refused(uneven_small):
+    """A graph whose accumulators or tables were reallocated is refused on the host (it is never
+    launched); a fresh capture works again."""
+    from paper_1003_1140_amd import DeviceBatch, LWError
+
+    b, dirs, om = uneven_small
+    db = DeviceBatch.from_host(b.select(range(8)))
+    c = ctx_for(dirs, om)
+    g = c.graph_capture(db, "fp32")
+    g.launch()
+    c.set_species(3)  # reallocates S
+    with pytest.raises(LWError) as ei:
+        g.launch()
+    assert ei.value.status == -4
+    g.close()
+    # matrix-core: a products change switches the kernel shape and rebuilds the tables
+    c.reset()
+    c.set_mfma_options(1, 3, 3)
+    c.plan_batch(db, "mfma_f16")
+    ws = c.workspace(db, "mfma_f16")
+    g = c.graph_capture(db, "mfma_f16", workspace=ws)
+    g.launch()
+    first = c.read_spectra()
+    c.set_mfma_options(1, 1, 3)
+    c.accumulate(db, "mfma_f16", workspace=c.workspace(db, "mfma_f16"))
+    with pytest.raises(LWError) as ei:
+        g.launch()
+    assert ei.value.status == -4
+    g.close()
+    c.set_mfma_options(1, 3, 3)
+    c.reset()
+    c.plan_batch(db, "mfma_f16")
+    ws = c.workspace(db, "mfma_f16")
+    g = c.graph_capture(db, "mfma_f16", workspace=ws)
+    g.launch()
+    np.testing.assert_allclose(c.read_spectra(), first, rtol=1e-12, atol=0)
+    g.close()
+    c.close()
