@@ -214,10 +214,10 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 
 // ------------------------------------------------------------------ spreading
 // One work-group per (particle of the chunk, direction, band).  Samples are sorted in
-// tau because dtau/dt = kappa > 0, so each sample's W = 8 taps cover grid points
-// lo_s .. lo_s + 7 with lo_s = floor(u_s) - 3 nondecreasing in s.  The trajectory is
-// walked in chunks of 256 samples, each staged once:
-//   1. one thread per sample: prepass, demodulation, grid coordinate and its 8 tap
+// tau because dtau/dt = kappa > 0, so each sample's W taps (W even) cover grid points
+// lo_s .. lo_s + W - 1 with lo_s = floor(u_s) - W/2 + 1 nondecreasing in s.  The trajectory
+// is walked in chunks of 256 samples, each staged once:
+//   1. one thread per sample: prepass, demodulation, grid coordinate and its W tap
 //      weights phi(lo_s + i - u_s), kept in LDS;
 //   2. first[x] = the first sample of the chunk whose taps reach grid point base + x
 //      (built by the samples themselves, no search); the samples reaching q are then
@@ -232,6 +232,7 @@ constexpr int kRing = 1024;  // grid points held in LDS (power of two)
 
 template <int kW>
 struct SpreadStage {
+  static_assert(kW % 2 == 0 && kW <= kWMax, "even widths: the tap window must not depend on frac(u)");
   int lo[kSpreadWin];             // first grid point of each sample's taps
   float w[kW][kSpreadWin];        // tap weights
   float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2)
