@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "lw_mfma.h"
@@ -984,15 +985,27 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
       const float scl = sclv[v];
       const int lim = q2v[v] - (k0 + sc4 * 8);  // valid elements of these eight
       typedef T t8 __attribute__((ext_vector_type(8)));
-      t8 hv, lv;
+      typedef float f32x8 __attribute__((ext_vector_type(8)));
+      if constexpr (std::is_same<T, _Float16>::value) {
+        f32x8 x = __builtin_shufflevector(rb[v][0], rb[v][1], 0, 1, 2, 3, 4, 5, 6, 7) * scl;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = e < lim ? (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl : 0.0f;
-        hv[e] = (T)x;
-        if (NP > 1) lv[e] = (T)(x - (float)hv[e]);
+        for (int e = 0; e < 8; ++e) x[e] = e < lim ? x[e] : 0.0f;  // past the column's end
+        // split x = hi + lo, both rounded to FP16, converting pairs of lanes at once
+        const t8 hv = __builtin_convertvector(x, t8);
+        *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
+        if (NP > 1)
+          *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = __builtin_convertvector(x - __builtin_convertvector(hv, f32x8), t8);
+      } else {  // BF16: lane by lane schedules better around the conversions (measured)
+        t8 hv, lv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = e < lim ? (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl : 0.0f;
+          hv[e] = (T)x;
+          if (NP > 1) lv[e] = (T)(x - (float)hv[e]);
+        }
+        *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
+        if (NP > 1) *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = lv;
       }
-      *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
-      if (NP > 1) *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = lv;
     }
   };
 
@@ -1052,13 +1065,15 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   // fill a buffer nobody reads), so the loop body has no branches around memory
   // operations and the wait counters stay exact: a stage's loads are waited for only
   // when that stage is stored, two compute phases later.
+  // Stages go in pairs with no exit in between (an exit there makes the compiler copy the
+  // accumulators every iteration): with an odd count the last pair's second stage lies
+  // past every column's end, so its F operand is stored as zeros and it adds nothing.
   for (int st = 0; st < nst; st += 2) {
     // buffer 0 holds stage st, register set 1 stage st + 1
     load(ra0, rb0, min((st + 2) * kTileK, last));
     compute(0);
     store(ra1, rb1, 1, (st + 1) * kTileK);
     __syncthreads();
-    if (st + 1 >= nst) break;
     load(ra1, rb1, min((st + 3) * kTileK, last));
     compute(1);
     store(ra0, rb0, 0, (st + 2) * kTileK);
