@@ -434,6 +434,13 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     qdone = max(qdone, qfin);
     kc += take;
   }
+  // The inner dimension is read in groups of eight floats: clear the rest of the column's
+  // last group (at most three grid points, within kp), so that the contraction loads whole
+  // groups and needs no mask.
+  if (tid < ((2 * Q + 7) / 8 * 8 - 2 * Q) / 2) {
+    *(float2*)(c0 + 2 * (Q + tid)) = make_float2(0.f, 0.f);
+    *(float2*)(c1 + 2 * (Q + tid)) = make_float2(0.f, 0.f);
+  }
   // column maximum (one value for both polarisation columns keeps them on one scale)
   for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off));
   if ((tid & 63) == 0) s_wmax[tid >> 6] = wmax;
@@ -762,6 +769,9 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 // one chunk) and the staging writes (four rows, four chunks) both do.
 __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
 
+// A group of eight zeros: the source of every F group that lies wholly past its column's end.
+__device__ __attribute__((aligned(16))) float lw_zero_group[8];
+
 // Amplitude-state epilogue of a 128-row tile: each (column, frequency) amplitude
 // C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own state row.  A state
 // row belongs to one column of one tile, so the adds do not race.
@@ -944,10 +954,13 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   // register sets keep two stages in flight, so a stage's global loads have two
   // compute phases to arrive before they are written to LDS.
   const int sr = tid >> 2, sc4 = tid & 3;
+  // stage s of the inner dimension covers [32 s, 32 s + 32); LDS buffer s % 2
+  const int nst = kend / kTileK;
+  const int last = max(nst - 1, 0) * kTileK;
   typedef u32x4 RegA[AV][NP];
   typedef f32x4 RegB[BV][2];
-  // the thread's two columns: F offset (column 0 stands in past the chunk, masked at
-  // store time), length and scale stay fixed over the inner loop
+  // the thread's two columns: F offset (column 0 stands in past the chunk, with length 0),
+  // length and scale stay fixed over the inner loop
   size_t fofs[BV];
   int q2v[BV];
   float sclv[BV];
@@ -958,21 +971,25 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     q2v[v] = s_fcol[col] >= 0 ? s_q2[col] : 0;
     sclv[v] = s_scale[col];
   }
+  // stage k0 (past the end: the table re-reads the last stage, F reads zeros)
   auto load = [&](RegA& ra, RegB& rb, int k0) {
+    const int ke = min(k0, last);
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
-      const size_t g = (size_t)(row0 + sr + (NT / 4) * v) * bd.kp + k0 + sc4 * 8;
+      const size_t g = (size_t)(row0 + sr + (NT / 4) * v) * bd.kp + ke + sc4 * 8;
       ra[v][0] = *(const u32x4*)(E_hi + g);
       if (NP > 1) ra[v][NP - 1] = *(const u32x4*)(E_lo + g);
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
-      const float* src = Fb + fofs[v] + k0;
+      // groups past the column's end read zeros; the group that holds the end was cleared
+      // past it by the spreading kernel
+      const float* src = k0 + sc4 * 8 < q2v[v] ? Fb + fofs[v] + k0 : lw_zero_group;
       rb[v][0] = *(const f32x4*)src;
       rb[v][1] = *(const f32x4*)(src + 4);
     }
   };
-  auto store = [&](const RegA& ra, const RegB& rb, int buf, int k0) {
+  auto store = [&](const RegA& ra, const RegB& rb, int buf) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int r = sr + (NT / 4) * v;
@@ -983,13 +1000,10 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     for (int v = 0; v < BV; ++v) {
       const int r = sr + (NT / 4) * v;
       const float scl = sclv[v];
-      const int lim = q2v[v] - (k0 + sc4 * 8);  // valid elements of these eight
       typedef T t8 __attribute__((ext_vector_type(8)));
       typedef float f32x8 __attribute__((ext_vector_type(8)));
       if constexpr (std::is_same<T, _Float16>::value) {
-        f32x8 x = __builtin_shufflevector(rb[v][0], rb[v][1], 0, 1, 2, 3, 4, 5, 6, 7) * scl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = e < lim ? x[e] : 0.0f;  // past the column's end
+        const f32x8 x = __builtin_shufflevector(rb[v][0], rb[v][1], 0, 1, 2, 3, 4, 5, 6, 7) * scl;
         // split x = hi + lo, both rounded to FP16, converting pairs of lanes at once
         const t8 hv = __builtin_convertvector(x, t8);
         *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
@@ -999,7 +1013,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
         t8 hv, lv;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const float x = e < lim ? (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl : 0.0f;
+          const float x = (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl;
           hv[e] = (T)x;
           if (NP > 1) lv[e] = (T)(x - (float)hv[e]);
         }
@@ -1050,33 +1064,30 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     }
   };
 
-  // stage s of the inner dimension covers [32 s, 32 s + 32); LDS buffer s % 2
-  const int nst = kend / kTileK;
-  const int last = max(nst - 1, 0) * kTileK;
   RegA ra0, ra1;
   RegB rb0, rb1;
   if (nst > 0) {
     load(ra0, rb0, 0);
-    load(ra1, rb1, min(kTileK, last));
-    store(ra0, rb0, 0, 0);
+    load(ra1, rb1, kTileK);
+    store(ra0, rb0, 0);
   }
   __syncthreads();
-  // Loads and stores run unconditionally (stages past the end re-read the last one and
-  // fill a buffer nobody reads), so the loop body has no branches around memory
-  // operations and the wait counters stay exact: a stage's loads are waited for only
-  // when that stage is stored, two compute phases later.
+  // Loads and stores run unconditionally (stages past the end re-read the table's last
+  // stage, read zeros for F and fill a buffer nobody reads), so the loop body has no
+  // branches around memory operations and the wait counters stay exact: a stage's loads
+  // are waited for only when that stage is stored, two compute phases later.
   // Stages go in pairs with no exit in between (an exit there makes the compiler copy the
   // accumulators every iteration): with an odd count the last pair's second stage lies
-  // past every column's end, so its F operand is stored as zeros and it adds nothing.
+  // past every column's end, so its F operand is zero and it adds nothing.
   for (int st = 0; st < nst; st += 2) {
     // buffer 0 holds stage st, register set 1 stage st + 1
-    load(ra0, rb0, min((st + 2) * kTileK, last));
+    load(ra0, rb0, (st + 2) * kTileK);
     compute(0);
-    store(ra1, rb1, 1, (st + 1) * kTileK);
+    store(ra1, rb1, 1);
     __syncthreads();
-    load(ra1, rb1, min((st + 3) * kTileK, last));
+    load(ra1, rb1, (st + 3) * kTileK);
     compute(1);
-    store(ra0, rb0, 0, (st + 2) * kTileK);
+    store(ra0, rb0, 0);
     __syncthreads();
   }
 
