@@ -70,7 +70,8 @@ def parse():
                     help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
     ap.add_argument("--bands", type=int, default=1)
     ap.add_argument("--tile", type=int, default=0,
-                    help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256 (0: library default)")
+                    help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256, 4 = 256x256 "
+                         "(0: library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -112,7 +113,7 @@ def profiled_traffic(path, tile, particles):
     configuration, or None when the kernel source changed since it was taken."""
     import hashlib
 
-    if path != "mfma_f16x3" or tile not in (0, 3) or particles != 100_000:
+    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000:
         return None
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -126,10 +127,11 @@ def profiled_traffic(path, tile, particles):
     return float(fields["traffic_bytes_per_launch"])
 
 
-TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4> (128 x 256 tiles)",
-                1: "lw_dft_mfma_r128_kernel<WN=2> (128 x 128 tiles)",
+TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4, MI=4> (256 x 256 tiles)",
+                1: "lw_dft_mfma_r128_kernel<WN=2, MI=2> (128 x 128 tiles)",
                 2: "lw_dft_mfma_kernel (256 x 128 tiles)",
-                3: "lw_dft_mfma_r128_kernel<WN=4> (128 x 256 tiles)"}
+                3: "lw_dft_mfma_r128_kernel<WN=4, MI=2> (128 x 256 tiles)",
+                4: "lw_dft_mfma_r128_kernel<WN=4, MI=4> (256 x 256 tiles)"}
 
 
 def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):

@@ -596,8 +596,9 @@ lw_status lw_set_tuning(lw_ctx* c, int32_t wpt, int32_t pb, int32_t persistent, 
   if (wpt != 0 && wpt != 1 && wpt != 2 && wpt != 4 && wpt != 8)
     return fail(c, LW_EINVAL, "frequencies per thread must be 0 (automatic), 1, 2, 4 or 8");
   if (pb < 0 || pb > 4096) return fail(c, LW_EINVAL, "particles per item must be in [0, 4096]");
-  if (tile < 0 || tile > 3)
-    return fail(c, LW_EINVAL, "contraction tile must be 0 (keep), 1 (128x128), 2 (256x128) or 3 (128x256)");
+  if (tile < 0 || tile > 4)
+    return fail(c, LW_EINVAL,
+                "contraction tile must be 0 (keep), 1 (128x128), 2 (256x128), 3 (128x256) or 4 (256x256)");
   c->tune_wpt = wpt;
   c->tune_pb = pb;
   c->tune_persistent = persistent ? 1 : 0;

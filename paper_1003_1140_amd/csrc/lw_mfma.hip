@@ -88,7 +88,7 @@ struct MfmaPlanCache {
   bool valid = false;
   int bands_req = 1;
   int products_f16 = 3, products_bf16 = 3;
-  int tile = 3;          // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256
+  int tile = 4;  // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256, 4 = 256 x 256
   KernelShape shape = kShapeSplit;  // spreading kernel the tables were built for
   uint64_t epoch = 0;               // bumped when the tables are freed
   int nb = 0;
@@ -757,11 +757,14 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   }
 }
 
-// ------------------------------------------------------------------ 128-row variants
-// 128 x (64 WN) tiles: 2 x WN waves, each 64 x 64 as 2 x 2 MFMA blocks.  WN = 2 gives
-// 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4 gives 128 x 256
-// tiles of eight waves, which halve the phase-table bytes per product: the table
-// tiles are re-read by every column group, so they set the memory traffic.  LDS rows
+// ------------------------------------------------------------------ swizzled variants
+// (64 MI) x (64 WN) tiles: 2 x WN waves, each (32 MI) x 64 as MI x 2 MFMA blocks.  WN = 2,
+// MI = 2 gives 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4 gives
+// tiles of eight waves 256 columns wide, which halve the phase-table bytes per product:
+// the table tiles are re-read by every column group.  MI = 4 (256 x 256) halves the F
+// bytes per product as well (F tiles are re-read by every row tile) and reads 0.5 LDS
+// bytes per MFMA operand byte instead of 0.67; it needs every band's row count to be a
+// multiple of 256 and all 256 VGPRs that two waves per SIMD leave each wave.  LDS rows
 // hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored at
 // slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over
 // 64 four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen
@@ -772,20 +775,21 @@ __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 
 // A group of eight zeros: the source of every F group that lies wholly past its column's end.
 __device__ __attribute__((aligned(16))) float lw_zero_group[8];
 
-// Amplitude-state epilogue of a 128-row tile: each (column, frequency) amplitude
+// Amplitude-state epilogue (waves of 32 MI rows): each (column, frequency) amplitude
 // C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own state row.  A state
 // row belongs to one column of one tile, so the adds do not race.
-__device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[2][2],
+template <int MI>
+__device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][2],
                                                    const int* s_fcol, const float* s_scale,
                                                    const double* s_tau0, const Band& bd, int d,
                                                    int row0, int wr, int wc, int lane) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int rp = 0; rp < 8; ++rp) {
       const int r = 4 * (rp >> 1) + 2 * (rp & 1);
       const int rl = i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-      const int jl = (row0 + wr * 64 + rl) >> 1;
+      const int jl = (row0 + wr * 32 * MI + rl) >> 1;
       if (jl >= bd.nj) continue;
       const int j = bd.j0 + jl;
       const double wt = a.wturn[j], fr_c = a.rowc[2 * j], fi_c = a.rowc[2 * j + 1];
@@ -808,29 +812,29 @@ __device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x
     }
 }
 
-// Coherent epilogue of a 128-row tile.  A lane holds, for one column (particle p,
+// Coherent epilogue (waves of 32 MI rows, two rows of waves per tile).  A lane holds, for one column (particle p,
 // polarisation = column parity), the real and imaginary rows of a frequency in adjacent
 // accumulator registers.  The column's amplitude up to the row factor applied by the
 // reduction is C e^{i w_j tau_0p} (phase reduced to a turn fraction in FP64, hardware
 // sin/cos in turns); w_p q_p / scale times it is summed over the tile's columns of each
 // species and polarisation and written as partial[...][row][polarisation], the real part
 // on the row of (j, re) and the imaginary part on the row of (j, im).
-template <int WN>
-__device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[2][2],
+template <int WN, int MI>
+__device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][2],
                                                   const float (*s_colw)[64 * WN],
-                                                  const double* s_tau0, double (*s_rows)[128],
+                                                  const double* s_tau0, double (*s_rows)[64 * MI],
                                                   const Band& bd, int d, int nt, int row0, int wr,
                                                   int wc, int lane, int wave, int tid) {
-  constexpr int TM = 128;
+  constexpr int TM = 64 * MI, WR = 32 * MI;  // tile rows, rows per wave
   for (int s = 0; s < a.ns; ++s) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int rp = 0; rp < 8; ++rp) {
         const int r = 4 * (rp >> 1) + 2 * (rp & 1);                     // the (j, re) register
         const int rl = i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);  // row within the wave
-        const int jl = (row0 + wr * 64 + rl) >> 1;
+        const int jl = (row0 + wr * WR + rl) >> 1;
         float vr = 0.0f, vi = 0.0f;
         if (jl < bd.nj) {
           const double wt = a.wturn[bd.j0 + jl];
@@ -860,7 +864,7 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
     __syncthreads();
     if (tid < 2 * TM) {
       const int row = tid >> 1, pol = tid & 1;
-      const int g = row / 64, rr = row % 64;
+      const int g = row / WR, rr = row % WR;
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][2 * rr + pol];
@@ -869,10 +873,13 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
   }
 }
 
-template <typename T, int PRODUCTS, int WN>
+template <typename T, int PRODUCTS, int WN, int MI>
 __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
-  constexpr int NT = 128 * WN, NW = 2 * WN, TM = 128, TN = 64 * WN, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int NT = 128 * WN, NW = 2 * WN, TN = 64 * WN, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int TM = 64 * MI, WR = 32 * MI;  // tile rows, rows per wave
+  typedef T t8 __attribute__((ext_vector_type(8)));
+  typedef float f32x8 __attribute__((ext_vector_type(8)));
   constexpr int AV = TM * 4 / NT;  // 16-byte table chunks per thread and stage
   constexpr int BV = TN * 4 / NT;  // 8-float F chunks per thread and stage
   static_assert(kTileK == 32, "four 16-byte chunks per LDS row");
@@ -884,8 +891,10 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   __shared__ int s_fcol[TN];
   __shared__ float s_colw[kMaxSpecies][TN];  // w q^2 / scale^2 (w q / scale when coherent)
   __shared__ double s_tau0[TN];              // first retarded time of each column (coherent)
-  __shared__ double s_rows[NW][128];
   __shared__ int s_kmax;
+  // the epilogue's row sums reuse the table buffers (after a barrier that ends the loop)
+  static_assert(sizeof(sA) >= sizeof(double) * NW * 64 * MI, "row sums fit the table buffers");
+  double(*s_rows)[64 * MI] = reinterpret_cast<double(*)[64 * MI]>(&sA[0][0][0]);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int oi = 0;
@@ -1000,16 +1009,15 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     for (int v = 0; v < BV; ++v) {
       const int r = sr + (NT / 4) * v;
       const float scl = sclv[v];
-      typedef T t8 __attribute__((ext_vector_type(8)));
-      typedef float f32x8 __attribute__((ext_vector_type(8)));
-      if constexpr (std::is_same<T, _Float16>::value) {
+      if constexpr (std::is_same<T, _Float16>::value || MI == 4) {
         const f32x8 x = __builtin_shufflevector(rb[v][0], rb[v][1], 0, 1, 2, 3, 4, 5, 6, 7) * scl;
-        // split x = hi + lo, both rounded to FP16, converting pairs of lanes at once
+        // split x = hi + lo, both rounded to T, converting pairs of lanes at once
         const t8 hv = __builtin_convertvector(x, t8);
         *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
         if (NP > 1)
           *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = __builtin_convertvector(x - __builtin_convertvector(hv, f32x8), t8);
-      } else {  // BF16: lane by lane schedules better around the conversions (measured)
+      } else {  // BF16 in 128-row tiles: lane by lane schedules better (measured); in 256-row
+                // tiles it needs more than the 256 VGPRs available
         t8 hv, lv;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -1023,9 +1031,9 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     }
   };
 
-  f32x16 acc[2][2];
+  f32x16 acc[MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -1036,28 +1044,31 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int ch = 2 * ks + (lane >> 5);
-      vec fa[NP][2], fb[NP][2];
+      vec fa[NP][MI], fb[NP][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int r = wr * 64 + i * 32 + (lane & 31);
+      for (int i = 0; i < MI; ++i) {
+        const int r = wr * WR + i * 32 + (lane & 31);
         fa[0][i] = *(const vec*)&sA[buf][0][swz(r, ch)];
         if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[buf][NP - 1][swz(r, ch)];
-        const int cc = wc * 64 + i * 32 + (lane & 31);
-        fb[0][i] = *(const vec*)&sB[buf][0][swz(cc, ch)];
-        if (NP > 1) fb[NP - 1][i] = *(const vec*)&sB[buf][NP - 1][swz(cc, ch)];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int cc = wc * 64 + j * 32 + (lane & 31);
+        fb[0][j] = *(const vec*)&sB[buf][0][swz(cc, ch)];
+        if (NP > 1) fb[NP - 1][j] = *(const vec*)&sB[buf][NP - 1][swz(cc, ch)];
       }
       // products outermost: consecutive MFMAs write different accumulators
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
       if (PRODUCTS > 1) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
       }
@@ -1074,8 +1085,9 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   __syncthreads();
   // Loads and stores run unconditionally (stages past the end re-read the table's last
   // stage, read zeros for F and fill a buffer nobody reads), so the loop body has no
-  // branches around memory operations and the wait counters stay exact: a stage's loads
-  // are waited for only when that stage is stored, two compute phases later.
+  // branches around memory operations.  A stage's loads are waited for when that stage is
+  // stored; the compiler issues them at the end of the phase before (their registers are
+  // not free earlier), so they have one compute phase to arrive.
   // Stages go in pairs with no exit in between (an exit there makes the compiler copy the
   // accumulators every iteration): with an odd count the last pair's second stage lies
   // past every column's end, so its F operand is zero and it adds nothing.
@@ -1092,17 +1104,17 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   }
 
   if (a.amp) {
-    amplitude_epilogue(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
+    amplitude_epilogue<MI>(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
     return;
   }
   if (a.coherent) {
-    coherent_epilogue<WN>(a, acc, s_colw, s_tau0, s_rows, bd, d, nt, row0, wr, wc, lane, wave, tid);
+    coherent_epilogue<WN, MI>(a, acc, s_colw, s_tau0, s_rows, bd, d, nt, row0, wr, wc, lane, wave, tid);
     return;
   }
   for (int s = 0; s < a.ns; ++s) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         float v = 0.0f;
@@ -1117,7 +1129,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
       }
     __syncthreads();
     if (tid < TM) {
-      const int g = tid / 64, rr = tid % 64;
+      const int g = tid / WR, rr = tid % WR;
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][rr];
@@ -1479,7 +1491,7 @@ lw_status mfma_set_bands(lw_ctx* c, int bands) {
 }
 
 lw_status mfma_set_tile(lw_ctx* c, int tile) {
-  if (tile < 1 || tile > 3) return set_err(c, LW_EINVAL, "tile shape must be 1, 2 or 3");
+  if (tile < 1 || tile > 4) return set_err(c, LW_EINVAL, "tile shape must be 1, 2, 3 or 4");
   c->mfma->tile = tile;
   return LW_OK;
 }
@@ -1554,10 +1566,10 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
             [&](int x, int y) { return pc->band[x].qmax * pc->band[x].m > pc->band[y].qmax * pc->band[y].m; });
   int tile = pc->tile;  // 256-row tiles need every band's rows to be a multiple of 256
   for (int i = 0; i < pc->nb; ++i)
-    if (tile == 2 && pc->band[i].m % 256 != 0) tile = 1;
-  if (tile == 2 && (c->coherent || amp)) tile = 3;  // those epilogues are written for 128-row tiles
-  const int tm = tile == 2 ? 256 : 128;
-  const int tn = tile == 3 ? 256 : 128;
+    if (pc->band[i].m % 256 != 0) tile = tile == 2 ? 1 : tile == 4 ? 3 : tile;
+  if (tile == 2 && (c->coherent || amp)) tile = 3;  // that kernel has no such epilogues
+  const int tm = tile == 2 || tile == 4 ? 256 : 128;
+  const int tn = tile >= 3 ? 256 : 128;
   const bool bf = path == LW_PATH_MFMA_BF16;
 
   for (int64_t p0 = 0; p0 < b->n_particles; p0 += L.chunk) {
@@ -1590,10 +1602,12 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   do {                                                                                           \
     if (tile == 2)                                                                               \
       hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+    else if (tile == 4)                                                                          \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else if (tile == 3)                                                                          \
-      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else                                                                                         \
-      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
   } while (0)
     if (!bf && products == 1) LW_GEMM(_Float16, 1);
     else if (!bf) LW_GEMM(_Float16, 3);

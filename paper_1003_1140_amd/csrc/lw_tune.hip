@@ -90,7 +90,7 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
                 cands.end());
   } else {
     for (int bands : {1, 2})
-      for (int tile : {1, 2, 3}) cands.push_back({0, 0, 1, bands, tile, 0.0});
+      for (int tile : {1, 2, 3, 4}) cands.push_back({0, 0, 1, bands, tile, 0.0});
   }
 
   hipEvent_t e0, e1;

@@ -383,7 +383,7 @@ class Context:
         self._check(self.lib.lw_plan_batch(self.h, ctypes.byref(batch.struct), PATHS.get(path, path)))
 
     def set_tuning(self, wpt=0, pb=0, persistent=1, bands=0, tile=0):
-        """tile: 0 keep, 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256 contraction tiles."""
+        """tile: 0 keep, 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256, 4 = 256 x 256 contraction tiles."""
         self._check(self.lib.lw_set_tuning(self.h, wpt, pb, persistent, bands, tile))
 
     def tune(self, batch: DeviceBatch, path="fp32", repeats=2, cache_json=None) -> dict:

@@ -251,10 +251,14 @@ def test_graph_replays_in_coherent_mode():
     c.close()
 
 
-@pytest.mark.parametrize("path,case", [("mfma_f16", "jitter"), ("mfma_f16", "uneven_species"),
-                                       ("mfma_bf16", "jitter")])
-def test_coherent_matrix_core_path(path, case):
-    """The matrix-core path keeps each column's phase e^{i w tau_0} in its epilogue."""
+@pytest.mark.parametrize("path,case,tile", [("mfma_f16", "jitter", 3), ("mfma_f16", "jitter", 4),
+                                            ("mfma_f16", "uneven_species", 3),
+                                            ("mfma_f16", "uneven_species", 4),
+                                            ("mfma_bf16", "jitter", 4)])
+def test_coherent_matrix_core_path(path, case, tile):
+    """The matrix-core path keeps each column's phase e^{i w tau_0} in its epilogue (128- and
+    256-row contraction tiles: 1024 and 640 frequencies give row counts that are multiples
+    of 256)."""
     from paper_1003_1140_amd import DeviceBatch
     from _parity import band_integrated_errors
 
@@ -263,9 +267,10 @@ def test_coherent_matrix_core_path(path, case):
         dirs, om, ns = configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024), 1
     else:
         b = workloads.generate(configs.uneven_recipe(), 0, 18)
-        dirs, om, ns = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 700), 3
+        dirs, om, ns = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 640), 3
     S_ref, A_ref = oracle.coherent_spectrum(b, dirs, om, n_species=ns, with_amplitude=True)
     c = _ctx(dirs, om, ns)
+    c.set_tuning(tile=tile)
     c.accumulate(DeviceBatch.from_host(b), path)
     S = c.read_spectra()
     A = _xyz(c.read_amplitudes(), c.get_basis())
@@ -274,7 +279,8 @@ def test_coherent_matrix_core_path(path, case):
     e = _amp_error(A, A_ref, rss2)
     live = [r for r in range(S.shape[0] * S.shape[1]) if S_ref.reshape(-1, S.shape[-1])[r].max() > 0]
     band = band_integrated_errors(S.reshape(-1, S.shape[-1])[live], S_ref.reshape(-1, S.shape[-1])[live], om)
-    print(f"[coherent] {path} {case}: amplitude error / R = {e:.3e}, band-integrated {band.max():.3e}",
+    print(f"[coherent] {path} {case} tile {tile}: amplitude error / R = {e:.3e}, "
+          f"band-integrated {band.max():.3e}",
           flush=True)
     assert band.max() <= MFMA_BAND_TOL[path]
     assert e <= MFMA_AMP_SANITY

@@ -80,10 +80,12 @@ def test_bf16_three_products_wide(wide):
     assert report("mfma bf16 x3, wide 6 particles", S, ref, om).max() <= 1e-4
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_contraction_tile_shapes(wide, tile):
     """Every contraction tile (1: 128 x 128 of four waves, 2: 256 x 128 of eight, 3: 128 x 256
-    of eight) meets the bounds of the default operands, and one FP16 product with 8 bands."""
+    of eight, 4: 256 x 256 of eight) meets the bounds of the default operands, and one FP16
+    product with 8 bands (where a band's rows are not a multiple of 256, tiles 2 and 4 fall
+    back to 1 and 3)."""
     b, dirs, om, ref = wide
     S = run(b, dirs, om, "mfma_f16", tile=tile)
     assert report(f"mfma f16 x3, tile {tile}", S, ref, om).max() <= 1e-5
