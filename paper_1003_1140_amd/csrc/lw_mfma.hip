@@ -122,6 +122,7 @@ struct SpreadArgs {
   unsigned long long* err;
   unsigned long long* flops;  // null, or useful FLOPs of one product of the contraction
   // phi(i - W/2 + 1 - f) = sum_k tapc[i][k] z^k, z = 2 f - 1: the W tap weights of a sample
+  // (mirror-symmetric: tapc[W - 1 - i][k] = (-1)^k tapc[i][k])
   // with fractional grid coordinate f (Chebyshev interpolants, within 2e-8 of phi)
   float tapc[kWMax][kTapCoef];
 };
@@ -263,22 +264,30 @@ __device__ __forceinline__ void load_raw(const BatchView& b, int64_t o, int64_t 
   r.az = b.az[idx];
 }
 
+__device__ __forceinline__ float dot3f(const float a[3], float x, float y, float z) {
+  return fmaf(a[0], x, fmaf(a[1], y, a[2] * z));
+}
+
 template <int kW>
 __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage<kW>& st,
-                                              const RawSample& r, const double* n, const double* e1,
-                                              const double* e2, int64_t p, int64_t len, int64_t kc,
+                                              const RawSample& r, const double* n, const float* nf,
+                                              const float* e1f, const float* e2f,
+                                              const float (*tap)[kTapCoef], int64_t p, int64_t len,
+                                              int64_t kc,
                                               double t0, double dtp, double tau0, double inv_h,
                                               double umax) {
   const int tid = threadIdx.x;
   const int64_t k = kc + tid;
   if (k >= len) return;
   const double bx = r.bx, by = r.by, bz = r.bz;
-  const double ax = (double)r.ax, ay = (double)r.ay, az = (double)r.az;
+  // kappa = 1 - n.beta cancels as |beta| -> 1 and stays FP64; the integrand is used in FP32
+  // and is formed in FP32 from it (e.(n x ((n - beta) x a)) = -(e.beta)(n.a) - kappa (e.a))
   const double kap = 1.0 - dot3(n, bx, by, bz);
-  const double na = dot3(n, ax, ay, az);
-  const double sc = dtp / (kap * kap);
-  const double g1 = -(na * dot3(e1, bx, by, bz) + kap * dot3(e1, ax, ay, az)) * sc;
-  const double g2 = -(na * dot3(e2, bx, by, bz) + kap * dot3(e2, ax, ay, az)) * sc;
+  const float kf = (float)kap, bxf = (float)bx, byf = (float)by, bzf = (float)bz;
+  const float na = dot3f(nf, r.ax, r.ay, r.az);
+  const float sc = (float)dtp * __builtin_amdgcn_rcpf(kf * kf);
+  const float g1 = -(na * dot3f(e1f, bxf, byf, bzf) + kf * dot3f(e1f, r.ax, r.ay, r.az)) * sc;
+  const float g2 = -(na * dot3f(e2f, bxf, byf, bzf) + kf * dot3f(e2f, r.ax, r.ay, r.az)) * sc;
   const double taup = (t0 + (double)k * dtp - dot3(n, r.x, r.y, r.z)) - tau0;
   const bool ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(taup) && isfinite(g1) && isfinite(g2);
   if (!ok) atomicMin(a.err, (unsigned long long)p);
@@ -291,15 +300,21 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
   const double iu = floor(u);
   const float fu = (float)(u - iu);
   st.lo[tid] = (int)iu - (kW / 2 - 1);
-  const float z = 2.0f * fu - 1.0f;
+  const float z = 2.0f * fu - 1.0f, z2 = z * z;
+  // phi(q - u) for q = lo + i: tap i is E(z^2) + z O(z^2) and tap W - 1 - i is E - z O, with
+  // E and O the even and odd parts of tap i's polynomial, each by Horner in z^2
+  static_assert(kTapCoef % 2 == 1, "the highest power is even");
 #pragma unroll
-  for (int i = 0; i < kW; ++i) {  // phi(q - u) for q = lo + i, Horner in z
-    float w = a.tapc[i][kTapCoef - 1];
+  for (int i = 0; i < kW / 2; ++i) {
+    float e = tap[i][kTapCoef - 1], o = tap[i][kTapCoef - 2];
 #pragma unroll
-    for (int c = kTapCoef - 2; c >= 0; --c) w = fmaf(w, z, a.tapc[i][c]);
-    st.w[i][tid] = w;
+    for (int c = kTapCoef - 3; c >= 0; c -= 2) e = fmaf(e, z2, tap[i][c]);
+#pragma unroll
+    for (int c = kTapCoef - 4; c >= 1; c -= 2) o = fmaf(o, z2, tap[i][c]);
+    st.w[i][tid] = fmaf(z, o, e);
+    st.w[kW - 1 - i][tid] = fmaf(-z, o, e);
   }
-  const float G1 = ok ? (float)g1 : 0.f, G2 = ok ? (float)g2 : 0.f;
+  const float G1 = ok ? g1 : 0.f, G2 = ok ? g2 : 0.f;
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
 
@@ -307,6 +322,9 @@ template <int kW>
 __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   __shared__ SpreadStage<kW> st;
   __shared__ float s_wmax[kSpreadWin / 64];
+  // the first W/2 tap polynomials, read at one address by all lanes (held as kernel
+  // arguments they would crowd the scalar registers)
+  __shared__ float s_tap[kW / 2][kTapCoef];
 
   const int tid = threadIdx.x;
   // block -> (particle, direction, band); bands fastest so one particle's work is adjacent
@@ -322,12 +340,14 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
   float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
   float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
-  double n[3], e1[3], e2[3];
+  double n[3];
+  float nf[3], e1f[3], e2f[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     n[c] = a.dirs[kDirStride * d + c];
-    e1[c] = a.dirs[kDirStride * d + 3 + c];
-    e2[c] = a.dirs[kDirStride * d + 6 + c];
+    nf[c] = (float)n[c];
+    e1f[c] = (float)a.dirs[kDirStride * d + 3 + c];
+    e2f[c] = (float)a.dirs[kDirStride * d + 6 + c];
   }
 
   if (tid == 0 && bi == 0 && d == 0 && a.b.species) {
@@ -347,6 +367,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   // no tap may pass the grid allotment (samples beyond it only add to unwritten points)
   const double umax = (double)bd.qmax + 0.5 * kW;
   for (int x = tid; x < kRing; x += kSpreadWin) st.acc[x] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (tid < (kW / 2) * kTapCoef) s_tap[tid / kTapCoef][tid % kTapCoef] = a.tapc[tid / kTapCoef][tid % kTapCoef];
   float wmax = 0.0f;
   int qdone = 0;  // grid points [0, qdone) are written
   int64_t kc = 0;
@@ -362,7 +383,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     k_next = kc + (kc + cnt < len ? cnt - 1 : cnt);
     if (k_next < len) load_raw(a.b, o, len, k_next, next);
     __syncthreads();  // the previous chunk's LDS is no longer read
-    stage_samples(a, bd, st, raw, n, e1, e2, p, len, kc, t0, dtp, tau0, inv_h, umax);
+    stage_samples(a, bd, st, raw, n, nf, e1f, e2f, s_tap, p, len, kc, t0, dtp, tau0, inv_h, umax);
     __syncthreads();
     const int base = st.lo[0];
     // samples whose taps fit the ring; the chunk's last sample waits for the next chunk
@@ -1197,7 +1218,9 @@ double es_phi_host(double x, const KernelShape& k) {
 // g_i(z) = phi(i - W/2 + 1 - (z + 1) / 2) interpolated at the kTapCoef Chebyshev points of
 // the first kind, then rewritten in powers of z for Horner evaluation.  The sqrt edge of
 // phi limits the interpolant to ~1.6e-8 of phi's peak; the coefficients sum to ~1.25 in
-// absolute value, so FP32 evaluation adds < 1e-7.
+// absolute value, so FP32 evaluation adds < 1e-7.  phi is even, so g_{W-1-i}(z) = g_i(-z):
+// the last W/2 taps are stored as the mirror images of the first (odd powers change sign),
+// and the device evaluates each mirrored pair from one even and one odd part.
 void tap_polynomials(float out[kWMax][kTapCoef], const KernelShape& ks) {
   constexpr int N = kTapCoef;
   double T[N][N] = {};  // T[j] = power coefficients of the Chebyshev polynomial T_j
@@ -1207,7 +1230,7 @@ void tap_polynomials(float out[kWMax][kTapCoef], const KernelShape& ks) {
     for (int k = 0; k < N; ++k) T[j][k] = (k > 0 ? 2.0 * T[j - 1][k - 1] : 0.0) - T[j - 2][k];
   for (int i = 0; i < kWMax; ++i)
     for (int k = 0; k < N; ++k) out[i][k] = 0.0f;
-  for (int i = 0; i < ks.w; ++i) {
+  for (int i = 0; i < ks.w / 2; ++i) {  // taps W - 1 - i are the mirror images
     double g[N], zk[N];
     for (int k = 0; k < N; ++k) {
       zk[k] = cos((2 * k + 1) * M_PI / (2.0 * N));
@@ -1220,7 +1243,10 @@ void tap_polynomials(float out[kWMax][kTapCoef], const KernelShape& ks) {
       cj *= (j == 0 ? 1.0 : 2.0) / N;
       for (int k = 0; k < N; ++k) mono[k] += cj * T[j][k];
     }
-    for (int k = 0; k < N; ++k) out[i][k] = (float)mono[k];
+    for (int k = 0; k < N; ++k) {
+      out[i][k] = (float)mono[k];
+      out[ks.w - 1 - i][k] = (k % 2 ? -1.0f : 1.0f) * out[i][k];
+    }
   }
 }
 
