@@ -127,11 +127,11 @@ def profiled_traffic(path, tile, particles):
     return float(fields["traffic_bytes_per_launch"])
 
 
-TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4, MI=4> (256 x 256 tiles)",
-                1: "lw_dft_mfma_r128_kernel<WN=2, MI=2> (128 x 128 tiles)",
+TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4, MI=4, NJ=2> (256 x 256 tiles, eight waves)",
+                1: "lw_dft_mfma_r128_kernel<WN=2, MI=2, NJ=2> (128 x 128 tiles)",
                 2: "lw_dft_mfma_kernel (256 x 128 tiles)",
-                3: "lw_dft_mfma_r128_kernel<WN=4, MI=2> (128 x 256 tiles)",
-                4: "lw_dft_mfma_r128_kernel<WN=4, MI=4> (256 x 256 tiles)"}
+                3: "lw_dft_mfma_r128_kernel<WN=4, MI=2, NJ=2> (128 x 256 tiles)",
+                4: "lw_dft_mfma_r128_kernel<WN=4, MI=4, NJ=2> (256 x 256 tiles, eight waves)"}
 
 
 def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):

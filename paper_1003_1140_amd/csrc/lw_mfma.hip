@@ -779,13 +779,15 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 }
 
 // ------------------------------------------------------------------ swizzled variants
-// (64 MI) x (64 WN) tiles: 2 x WN waves, each (32 MI) x 64 as MI x 2 MFMA blocks.  WN = 2,
-// MI = 2 gives 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4 gives
-// tiles of eight waves 256 columns wide, which halve the phase-table bytes per product:
-// the table tiles are re-read by every column group.  MI = 4 (256 x 256) halves the F
-// bytes per product as well (F tiles are re-read by every row tile) and reads 0.5 LDS
-// bytes per MFMA operand byte instead of 0.67; it needs every band's row count to be a
-// multiple of 256 and all 256 VGPRs that two waves per SIMD leave each wave.  LDS rows
+// (64 MI) x (32 NJ WN) tiles: 2 x WN waves, each (32 MI) x (32 NJ) as MI x NJ MFMA blocks.
+// WN = 2, MI = 2 gives 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4
+// gives tiles of eight waves 256 columns wide, which halve the phase-table bytes per
+// product: the table tiles are re-read by every column group.  MI = 4 (256 x 256) halves
+// the F bytes per product as well (F tiles are re-read by every row tile) and issues 0.5
+// fragment reads per MFMA instead of 0.67; it needs every band's row count to be a
+// multiple of 256 and all 256 VGPRs that two waves per SIMD leave each wave.  (Four waves
+// of 128 x 128, NJ = 4, one wave per SIMD with the accumulators in AGPRs, measured 15 %
+// slower: no second wave covers the fragment-read latency.)  The launches use NJ = 2.  LDS rows
 // hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored at
 // slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over
 // 64 four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen
@@ -799,8 +801,8 @@ __device__ __attribute__((aligned(16))) float lw_zero_group[8];
 // Amplitude-state epilogue (waves of 32 MI rows): each (column, frequency) amplitude
 // C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own state row.  A state
 // row belongs to one column of one tile, so the adds do not race.
-template <int MI>
-__device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][2],
+template <int MI, int NJ>
+__device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][NJ],
                                                    const int* s_fcol, const float* s_scale,
                                                    const double* s_tau0, const Band& bd, int d,
                                                    int row0, int wr, int wc, int lane) {
@@ -815,8 +817,8 @@ __device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x
       const int j = bd.j0 + jl;
       const double wt = a.wturn[j], fr_c = a.rowc[2 * j], fi_c = a.rowc[2 * j + 1];
 #pragma unroll
-      for (int jb = 0; jb < 2; ++jb) {
-        const int cc = wc * 64 + jb * 32 + (lane & 31);
+      for (int jb = 0; jb < NJ; ++jb) {
+        const int cc = wc * 32 * NJ + jb * 32 + (lane & 31);
         const int fc = s_fcol[cc];
         if (fc < 0) continue;
         const double x = wt * s_tau0[cc];
@@ -840,9 +842,9 @@ __device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x
 // sin/cos in turns); w_p q_p / scale times it is summed over the tile's columns of each
 // species and polarisation and written as partial[...][row][polarisation], the real part
 // on the row of (j, re) and the imaginary part on the row of (j, im).
-template <int WN, int MI>
-__device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][2],
-                                                  const float (*s_colw)[64 * WN],
+template <int WN, int MI, int NJ>
+__device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][NJ],
+                                                  const float (*s_colw)[32 * NJ * WN],
                                                   const double* s_tau0, double (*s_rows)[64 * MI],
                                                   const Band& bd, int d, int nt, int row0, int wr,
                                                   int wc, int lane, int wave, int tid) {
@@ -860,8 +862,8 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
         if (jl < bd.nj) {
           const double wt = a.wturn[bd.j0 + jl];
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const int cc = wc * 64 + j * 32 + (lane & 31);
+          for (int j = 0; j < NJ; ++j) {
+            const int cc = wc * 32 * NJ + j * 32 + (lane & 31);
             const float wq = s_colw[s][cc];
             const double x = wt * s_tau0[cc];
             const float fr = (float)(x - rint(x));
@@ -883,8 +885,8 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
         }
       }
     __syncthreads();
-    if (tid < 2 * TM) {
-      const int row = tid >> 1, pol = tid & 1;
+    for (int t = tid; t < 2 * TM; t += 2 * 64 * WN) {
+      const int row = t >> 1, pol = t & 1;
       const int g = row / WR, rr = row % WR;
       double v = 0.0;
 #pragma unroll
@@ -894,10 +896,10 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
   }
 }
 
-template <typename T, int PRODUCTS, int WN, int MI>
-__global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
+template <typename T, int PRODUCTS, int WN, int MI, int NJ>
+__global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
-  constexpr int NT = 128 * WN, NW = 2 * WN, TN = 64 * WN, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int NT = 128 * WN, NW = 2 * WN, TN = 32 * NJ * WN, NP = PRODUCTS > 1 ? 2 : 1;
   constexpr int TM = 64 * MI, WR = 32 * MI;  // tile rows, rows per wave
   typedef T t8 __attribute__((ext_vector_type(8)));
   typedef float f32x8 __attribute__((ext_vector_type(8)));
@@ -1052,11 +1054,11 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
     }
   };
 
-  f32x16 acc[MI][2];
+  f32x16 acc[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
@@ -1065,7 +1067,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int ch = 2 * ks + (lane >> 5);
-      vec fa[NP][MI], fb[NP][2];
+      vec fa[NP][MI], fb[NP][NJ];
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
         const int r = wr * WR + i * 32 + (lane & 31);
@@ -1073,8 +1075,8 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
         if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[buf][NP - 1][swz(r, ch)];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int cc = wc * 64 + j * 32 + (lane & 31);
+      for (int j = 0; j < NJ; ++j) {
+        const int cc = wc * 32 * NJ + j * 32 + (lane & 31);
         fb[0][j] = *(const vec*)&sB[buf][0][swz(cc, ch)];
         if (NP > 1) fb[NP - 1][j] = *(const vec*)&sB[buf][NP - 1][swz(cc, ch)];
       }
@@ -1082,16 +1084,16 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
+        for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
       if (PRODUCTS > 1) {
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
+          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
+          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
       }
     }
   };
@@ -1125,11 +1127,11 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
   }
 
   if (a.amp) {
-    amplitude_epilogue<MI>(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
+    amplitude_epilogue<MI, NJ>(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
     return;
   }
   if (a.coherent) {
-    coherent_epilogue<WN, MI>(a, acc, s_colw, s_tau0, s_rows, bd, d, nt, row0, wr, wc, lane, wave, tid);
+    coherent_epilogue<WN, MI, NJ>(a, acc, s_colw, s_tau0, s_rows, bd, d, nt, row0, wr, wc, lane, wave, tid);
     return;
   }
   for (int s = 0; s < a.ns; ++s) {
@@ -1140,8 +1142,8 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
       for (int r = 0; r < 16; ++r) {
         float v = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int cc = wc * 64 + j * 32 + (lane & 31);
+        for (int j = 0; j < NJ; ++j) {
+          const int cc = wc * 32 * NJ + j * 32 + (lane & 31);
           const float c = acc[i][j][r];
           v = fmaf(c * c, s_colw[s][cc], v);
         }
@@ -1149,12 +1151,12 @@ __global__ __launch_bounds__(128 * WN, WN == 2 ? 2 : 1) void lw_dft_mfma_r128_ke
         if ((lane & 31) == 0) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
       }
     __syncthreads();
-    if (tid < TM) {
-      const int g = tid / WR, rr = tid % WR;
+    for (int t = tid; t < TM; t += NT) {
+      const int g = t / WR, rr = t % WR;
       double v = 0.0;
 #pragma unroll
       for (int w = 0; w < WN; ++w) v += s_rows[g * WN + w][rr];
-      a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + tid] = v;
+      a.partial[(((size_t)d * a.n_ftile + nt) * a.ns + s) * a.rows + bd.row_off + row0 + t] = v;
     }
   }
 }
@@ -1629,11 +1631,11 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     if (tile == 2)                                                                               \
       hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else if (tile == 4)                                                                          \
-      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 4, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else if (tile == 3)                                                                          \
-      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 2, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else                                                                                         \
-      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
+      hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2, 2, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
   } while (0)
     if (!bf && products == 1) LW_GEMM(_Float16, 1);
     else if (!bf) LW_GEMM(_Float16, 3);
