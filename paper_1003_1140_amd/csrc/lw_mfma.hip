@@ -798,41 +798,70 @@ __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 
 // A group of eight zeros: the source of every F group that lies wholly past its column's end.
 __device__ __attribute__((aligned(16))) float lw_zero_group[8];
 
-// Amplitude-state epilogue (waves of 32 MI rows): each (column, frequency) amplitude
-// C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own state row.  A state
-// row belongs to one column of one tile, so the adds do not race.
+// Amplitude-state epilogue (waves of 32 MI rows and 32 NJ columns): each (column,
+// frequency) amplitude C e^{i w_j tau_0p} rowc_j / scale is added to the particle's own
+// state row.  A state row belongs to one column pair of one tile, so the adds do not race.
+// A lane's accumulators hold one column (one polarisation of one particle) at 8 of every
+// 16 frequencies, while a particle's state runs along frequency with both polarisations
+// side by side.  Each wave therefore passes its values through its own 2 KB of LDS, 16
+// particles x 8 frequencies at a time, and then adds them lane by frequency: 8 consecutive
+// lanes update 256 contiguous bytes of one particle's state.
 template <int MI, int NJ>
 __device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][NJ],
                                                    const int* s_fcol, const float* s_scale,
-                                                   const double* s_tau0, const Band& bd, int d,
-                                                   int row0, int wr, int wc, int lane) {
+                                                   const double* s_tau0, float* s_x, const Band& bd,
+                                                   int d, int row0, int wr, int wc, int lane) {
+  // s_x: [16 particles][8 frequencies][2 polarisations][re, im] floats
+  const int h = lane >> 5, cl = lane & 31;
 #pragma unroll
-  for (int i = 0; i < MI; ++i)
+  for (int i = 0; i < MI; ++i) {
+    const int jbase = (row0 + wr * 32 * MI + i * 32) >> 1;  // first frequency of the block
 #pragma unroll
-    for (int rp = 0; rp < 8; ++rp) {
-      const int r = 4 * (rp >> 1) + 2 * (rp & 1);
-      const int rl = i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
-      const int jl = (row0 + wr * 32 * MI + rl) >> 1;
-      if (jl >= bd.nj) continue;
-      const int j = bd.j0 + jl;
-      const double wt = a.wturn[j], fr_c = a.rowc[2 * j], fi_c = a.rowc[2 * j + 1];
+    for (int jb = 0; jb < NJ; ++jb) {
+      const int c0 = wc * 32 * NJ + jb * 32;  // the wave's first column in this block
+      const double tau0 = s_tau0[c0 + cl];
+      const float inv = 1.0f / s_scale[c0 + cl];
 #pragma unroll
-      for (int jb = 0; jb < NJ; ++jb) {
-        const int cc = wc * 32 * NJ + jb * 32 + (lane & 31);
-        const int fc = s_fcol[cc];
-        if (fc < 0) continue;
-        const double x = wt * s_tau0[cc];
-        const float fr = (float)(x - rint(x));
-        const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
-        const float inv = 1.0f / s_scale[cc];
-        const float zr = acc[i][jb][r], zi = acc[i][jb][r + 1];
-        const double ur = (double)((zr * cs - zi * sn) * inv), ui = (double)((zr * sn + zi * cs) * inv);
-        const int64_t p = a.p_begin + (fc >> 1);
-        double* o = a.amp + (((size_t)p * a.nd + d) * (size_t)a.wturn_n + j) * 4 + 2 * (fc & 1);
-        o[0] += ur * fr_c - ui * fi_c;
-        o[1] += ur * fi_c + ui * fr_c;
+      for (int hq = 0; hq < 2; ++hq) {
+        // register 4 q + 2 e (re) and + 1 (im) of block i is frequency 4 q + 2 h + e
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int r = 4 * (2 * hq + qq) + 2 * e, jh = 4 * qq + 2 * h + e;
+            const int jl = max(min(jbase + 8 * hq + jh, bd.nj - 1), 0);  // rows past the band are dropped below
+            const double x = a.wturn[bd.j0 + jl] * tau0;
+            const float fr = (float)(x - rint(x));
+            const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+            const float zr = acc[i][jb][r], zi = acc[i][jb][r + 1];
+            *(float2*)&s_x[(((cl >> 1) * 8 + jh) * 2 + (cl & 1)) * 2] =
+                make_float2((zr * cs - zi * sn) * inv, (zr * sn + zi * cs) * inv);
+          }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int t = lane + 64 * k, pp = t >> 3, jh = t & 7;
+          const int jl = jbase + 8 * hq + jh;
+          const int fc = s_fcol[c0 + 2 * pp];  // polarisation 0; polarisation 1 is fc + 1
+          const f32x4 v = *(const f32x4*)&s_x[(pp * 8 + jh) * 4];
+          if (fc >= 0 && jl < bd.nj) {
+            const int j = bd.j0 + jl;
+            const double fr_c = a.rowc[2 * j], fi_c = a.rowc[2 * j + 1];
+            double* o = a.amp + (((size_t)(a.p_begin + (fc >> 1)) * a.nd + d) * (size_t)a.wturn_n + j) * 4;
+#pragma unroll
+            for (int pol = 0; pol < 2; ++pol) {
+              const double ur = (double)v[2 * pol], ui = (double)v[2 * pol + 1];
+              o[2 * pol] += ur * fr_c - ui * fi_c;
+              o[2 * pol + 1] += ur * fi_c + ui * fr_c;
+            }
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // reads done before the next writes
+        __builtin_amdgcn_wave_barrier();
       }
     }
+  }
 }
 
 // Coherent epilogue (waves of 32 MI rows, two rows of waves per tile).  A lane holds, for one column (particle p,
@@ -1127,7 +1156,9 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
   }
 
   if (a.amp) {
-    amplitude_epilogue<MI, NJ>(a, acc, s_fcol, s_scale, s_tau0, bd, d, row0, wr, wc, lane);
+    static_assert(sizeof(sA) >= NW * 512 * sizeof(float), "2 KB of the table buffers per wave");
+    amplitude_epilogue<MI, NJ>(a, acc, s_fcol, s_scale, s_tau0, reinterpret_cast<float*>(&sA[0][0][0]) + wave * 512,
+                               bd, d, row0, wr, wc, lane);
     return;
   }
   if (a.coherent) {
