@@ -164,8 +164,11 @@ def test_coherent_time_windows_and_snapshot_differences():
     assert np.max(np.abs(d_gpu - d_ref)[~empty] / scale[~empty][:, None]) <= 4 * TOL
 
 
-@pytest.mark.parametrize("path", ["fp32", "mfma_f16"])
-def test_incoherent_amplitude_state_over_windows(path):
+@pytest.mark.parametrize("path,tile", [("fp32", 0), ("mfma_f16", 4), ("mfma_f16", 3), ("mfma_f16", 1)])
+def test_incoherent_amplitude_state_over_windows(path, tile):
+    """Windows added into the per-particle state reproduce the whole trajectory's spectrum;
+    on the matrix-core path with every tile shape whose epilogue writes the state (four
+    waves of 64 x 64, eight of 64 x 64 and eight of 128 x 64)."""
     from paper_1003_1140_amd import DeviceBatch
     from _parity import band_integrated_errors
 
@@ -173,6 +176,8 @@ def test_incoherent_amplitude_state_over_windows(path):
     dirs, om = configs.dirs_equal_area()[::4], configs.log_grid(0.1, 1e3, 600)
     wins = _windows(b, [300, 1100, 1101])
     c = _ctx(dirs, om, 3, coherent=False)
+    if tile:
+        c.set_tuning(tile=tile)
     state = c.amplitude_state(b.n_particles)
     naive = np.zeros((3, len(dirs), len(om)))
     for w in wins:
@@ -187,7 +192,7 @@ def test_incoherent_amplitude_state_over_windows(path):
     ref = oracle.spectrum(b, dirs, om, n_species=3)
     live = [r for r in range(3 * len(dirs)) if ref.reshape(-1, len(om))[r].max() > 0]
     band = band_integrated_errors(S.reshape(-1, len(om))[live], ref.reshape(-1, len(om))[live], om).max()
-    print(f"[in-situ] {path} incoherent state: band error {band_relative_error(S, ref):.3e}, "
+    print(f"[in-situ] {path} tile {tile} incoherent state: band error {band_relative_error(S, ref):.3e}, "
           f"band-integrated {band:.3e}, per-window sum off by {band_relative_error(naive, ref):.3e}",
           flush=True)
     if path == "fp32":
