@@ -247,10 +247,11 @@ lw_status lw_plan_batch(lw_ctx* ctx, const lw_batch* batch, lw_path path);
  * 1, 2, 4, 8); pb = particles per work item (0 automatic); persistent = use a
  * matching lw_plan_batch plan (1) or always the plain grid (0); bands and the
  * contraction tile (rows x columns per work-group: LW_TILE_128x128,
- * LW_TILE_256x128, LW_TILE_128x256, LW_TILE_256x256) for the matrix-core path;
- * 0 = unchanged.  A 256-row tile needs every band's row count (2 x its
- * frequencies, rounded up to 128) to be a multiple of 256; otherwise the
- * launch takes the 128-row tile of the same width. */
+ * LW_TILE_256x128, LW_TILE_128x256, LW_TILE_256x256, the default) for the
+ * matrix-core path; 0 = unchanged.  A 256-row tile needs every band's row count
+ * (2 x its frequencies, rounded up to 128) to be a multiple of 256; otherwise
+ * the launch takes the 128-row tile of the same width.  LW_TILE_256x128 has no
+ * coherent or amplitude-state epilogue: those launches take LW_TILE_128x256. */
 enum { LW_TILE_128x128 = 1, LW_TILE_256x128 = 2, LW_TILE_128x256 = 3, LW_TILE_256x256 = 4 };
 lw_status lw_set_tuning(lw_ctx* ctx, int32_t wpt, int32_t pb, int32_t persistent, int32_t bands,
                         int32_t tile);
