@@ -108,21 +108,29 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md")
 
 
+def kernel_code_digest(src):
+    """SHA-256 of a source file's code: line comments and all whitespace removed (the file
+    has no block comments and no "//" inside string literals)."""
+    import hashlib
+    import re
+
+    code = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256(re.sub(r"\s+", "", code).encode()).hexdigest()
+
+
 def profiled_traffic(path, tile, particles):
     """HBM bytes per contraction launch from the committed counter profile of this exact
-    configuration, or None when the kernel source changed since it was taken."""
-    import hashlib
-
+    configuration, or None when the kernel code changed since it was taken."""
     if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000:
         return None
     try:
         text = open(TRAFFIC_PROFILE).read()
-        src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip"), "rb").read()
+        src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip")).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch:", "kernel_source_sha256:")))
-    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:")))
+    if fields.get("kernel_code_sha256", "").strip() != kernel_code_digest(src):
         return None
     return float(fields["traffic_bytes_per_launch"])
 

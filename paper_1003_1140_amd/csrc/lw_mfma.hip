@@ -1011,16 +1011,15 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
   __syncthreads();
   const int kend = min(((s_kmax + kTileK - 1) / kTileK) * kTileK, bd.kp);
 
-  // staging: thread t moves chunk t % 4 of rows (columns) t / 4 + (NT / 4) v.  Two
-  // register sets keep two stages in flight, so a stage's global loads have two
-  // compute phases to arrive before they are written to LDS.
+  // staging: thread t moves chunk t % 4 of rows (columns) t / 4 + (NT / 4) v, through two
+  // register sets (one filled while the other waits to be stored).
   const int sr = tid >> 2, sc4 = tid & 3;
   // stage s of the inner dimension covers [32 s, 32 s + 32); LDS buffer s % 2
   const int nst = kend / kTileK;
   const int last = max(nst - 1, 0) * kTileK;
   typedef u32x4 RegA[AV][NP];
   typedef f32x4 RegB[BV][2];
-  // the thread's two columns: F offset (column 0 stands in past the chunk, with length 0),
+  // the thread's BV columns: F offset (column 0 stands in past the chunk, with length 0),
   // length and scale stay fixed over the inner loop
   size_t fofs[BV];
   int q2v[BV];
