@@ -230,7 +230,10 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 //      (FP32) and their ring slots cleared.
 // The next chunk starts with the sample that did not fit the ring, so every grid point
 // of a chunk lies within kRing of the oldest pending one.
-constexpr int kRing = 1024;  // grid points held in LDS (power of two)
+// Grid points held in LDS.  768 covers the grid points of a 256-sample chunk at the
+// oversamplings used, and keeps a work-group near 31 KB of LDS so that five share a CU
+// (1024 allowed four: measured 12 % slower).
+constexpr int kRing = 768;
 
 template <int kW>
 struct SpreadStage {
@@ -389,7 +392,10 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     // samples whose taps fit the ring; the chunk's last sample waits for the next chunk
     // unless it ends the trajectory, so that the next chunk's first tap is known here
     const bool more = kc + cnt < len;
-    const int fits = __syncthreads_count(tid < cnt && st.lo[tid] - base <= kRing - kW);
+    // The ring holds every grid point from the oldest unwritten one (qdone) to the highest
+    // one touched.  qdone is this chunk's first tap except in the first chunk, where it is 0
+    // while the first tap is 1: measuring from it keeps point qdone + kRing out of qdone's slot.
+    const int fits = __syncthreads_count(tid < cnt && st.lo[tid] - qdone <= kRing - kW);
     int take = min(fits, more ? cnt - 1 : cnt);
     take = max(take, 1);
     const int top = st.lo[take - 1] + kW - 1;  // highest grid point touched
@@ -430,7 +436,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
         acc3 += __shfl_xor(acc3, off);
       }
       if (x < G && sl == 0) {
-        float4& r = st.acc[(base + x) & (kRing - 1)];
+        float4& r = st.acc[(base + x) % kRing];
         r.x += acc0;
         r.y += acc1;
         r.z += acc2;
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     for (int q = qdone + tid; q < qfin; q += kSpreadWin) {
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (q <= top) {  // beyond it nothing was added (and the slot may hold a newer point)
-        float4& r = st.acc[q & (kRing - 1)];
+        float4& r = st.acc[q % kRing];
         v = r;
         r = make_float4(0.f, 0.f, 0.f, 0.f);
       }
