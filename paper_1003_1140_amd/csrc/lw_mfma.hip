@@ -788,17 +788,17 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
 // (64 MI) x (32 NJ WN) tiles: 2 x WN waves, each (32 MI) x (32 NJ) as MI x NJ MFMA blocks.
 // WN = 2, MI = 2 gives 128 x 128 tiles of four waves (two work-groups share a CU); WN = 4
 // gives tiles of eight waves 256 columns wide, which halve the phase-table bytes per
-// product: the table tiles are re-read by every column group.  MI = 4 (256 x 256) halves
-// the F bytes per product as well (F tiles are re-read by every row tile) and issues 0.5
-// fragment reads per MFMA instead of 0.67; it needs every band's row count to be a
-// multiple of 256 and all 256 VGPRs that two waves per SIMD leave each wave.  (Four waves
-// of 128 x 128, NJ = 4, one wave per SIMD with the accumulators in AGPRs, measured 15 %
-// slower: no second wave covers the fragment-read latency.)  The launches use NJ = 2.  LDS rows
-// hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored at
-// slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over
-// 64 four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen
-// distinct 16-byte slots modulo 256 bytes: the fragment reads (sixteen consecutive rows,
-// one chunk) and the staging writes (four rows, four chunks) both do.
+// product: the table tiles are re-read by every column group.  MI = 4 (256 x 256) halves the
+// F bytes per product as well (F tiles are re-read by every row tile) and issues 0.5
+// fragment reads per MFMA instead of 0.67; it needs every band's row count to be a multiple
+// of 256 and all 256 VGPRs that two waves per SIMD leave each wave.  (Four waves of 128 x
+// 128, NJ = 4, one wave per SIMD with the accumulators in AGPRs, measured 15 % slower: no
+// second wave covers the fragment-read latency.)  The launches use NJ = 2.
+// LDS rows hold 32 halves (four 16-byte chunks) without padding; chunk c of row r is stored
+// at slot c ^ ((r >> 2) & 3).  A 16-byte access is served sixteen lanes at a time over 64
+// four-byte banks (256 bytes), so each group of sixteen lanes must touch sixteen distinct
+// 16-byte slots modulo 256 bytes: the fragment reads (sixteen consecutive rows, one chunk)
+// and the staging writes (four rows, four chunks) both do.
 __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
 
 // A group of eight zeros: the source of every F group that lies wholly past its column's end.
@@ -870,13 +870,13 @@ __device__ __forceinline__ void amplitude_epilogue(const GemmArgs& a, const f32x
   }
 }
 
-// Coherent epilogue (waves of 32 MI rows, two rows of waves per tile).  A lane holds, for one column (particle p,
-// polarisation = column parity), the real and imaginary rows of a frequency in adjacent
-// accumulator registers.  The column's amplitude up to the row factor applied by the
-// reduction is C e^{i w_j tau_0p} (phase reduced to a turn fraction in FP64, hardware
-// sin/cos in turns); w_p q_p / scale times it is summed over the tile's columns of each
-// species and polarisation and written as partial[...][row][polarisation], the real part
-// on the row of (j, re) and the imaginary part on the row of (j, im).
+// Coherent epilogue (waves of 32 MI rows, two rows of waves per tile).  A lane holds, for one
+// column (particle p, polarisation = column parity), the real and imaginary rows of a frequency
+// in adjacent accumulator registers.  The column's amplitude up to the row factor applied by
+// the reduction is C e^{i w_j tau_0p} (phase reduced to a turn fraction in FP64, hardware
+// sin/cos in turns); w_p q_p / scale times it is summed over the tile's columns of each species
+// and polarisation and written as partial[...][row][polarisation], the real part on the row of
+// (j, re) and the imaginary part on the row of (j, im).
 template <int WN, int MI, int NJ>
 __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x16 (&acc)[MI][NJ],
                                                   const float (*s_colw)[32 * NJ * WN],
