@@ -65,10 +65,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--particles", type=int, default=100_000)
+    ap.add_argument("--workload", choices=("jitter", "wide"), default="jitter",
+                    help="jitter: 4096 steps, 4 directions, 1024 frequencies (the benchmark); wide: "
+                         "the mixed-precision form, 2048 steps, 16 directions, 2048 frequencies")
     ap.add_argument("--chunk", type=int, default=8192, help="particles generated per host chunk")
     ap.add_argument("--paths", default="fp32,mfma_f16x1,mfma_bf16x3,mfma_f16x3",
                     help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
-    ap.add_argument("--bands", type=int, default=1)
+    ap.add_argument("--bands", type=int, default=2,
+                    help="frequency bands of the matrix-core paths (2 measured fastest on the benchmark "
+                         "workload: the upper band keeps the grid, the lower one is 100x coarser)")
     ap.add_argument("--tile", type=int, default=0,
                     help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256, 4 = 256x256 "
                          "(0: library default)")
@@ -118,10 +123,10 @@ def kernel_code_digest(src):
     return hashlib.sha256(re.sub(r"\s+", "", code).encode()).hexdigest()
 
 
-def profiled_traffic(path, tile, particles):
+def profiled_traffic(path, tile, particles, workload="jitter", bands=2):
     """HBM bytes per contraction launch from the committed counter profile of this exact
-    configuration, or None when the kernel code changed since it was taken."""
-    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000:
+    configuration (the default launch), or None when the kernel code changed since it was taken."""
+    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload != "jitter" or bands != 2:
         return None
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -280,7 +285,7 @@ def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
     S_coh = c.read_spectra()
     res["coherent_terms_per_s"] = terms_per_step * steps / el
     # the same on the matrix-core path (FP16 hi/lo), checked against the FP32 coherent pass
-    c.set_mfma_options(1, 3, 3)
+    c.set_mfma_options(a.bands, 3, 3)
     wsm = c.workspace(batch, "mfma_f16")
     c.reset()
     c.accumulate(batch, "mfma_f16", workspace=wsm)  # warm-up
@@ -351,7 +356,7 @@ def insitu_leg(a, batch, terms_per_step, dirs, om, S_fp32, log):
         f"terms/s, snapshot {ms:.2f} ms ({gbs:.0f} GB/s), last vs one pass "
         f"{res['last_snapshot_vs_one_pass_band_err']:.2e}")
     # the same recording with the windows' amplitudes from the matrix-core path (FP16 hi/lo)
-    c.set_mfma_options(1, 3, 3)
+    c.set_mfma_options(a.bands, 3, 3)
     wsm = c.workspace(wins[0], "mfma_f16")
     state.zero_()
     c.accumulate_amplitudes(wins[0], state, "mfma_f16", wsm)  # warm-up
@@ -400,7 +405,7 @@ def coupled_leg(a, dirs, om, log):
         c = Context(0)
         c.set_directions(dirs)
         c.set_frequencies(om)
-        c.set_mfma_options(1, 3, 3)
+        c.set_mfma_options(a.bands, 3, 3)
         rec = Recorder(c, n, coherent=False, path=path)
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(n_win)]
         torch.cuda.synchronize()
@@ -646,9 +651,10 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] copy probe: {n} bytes read and {n} bytes written", file=sys.stderr, flush=True)
         del src, dst
-    recipe = configs.jitter_recipe()
-    dirs = configs.dirs_jitter()
-    om = configs.log_grid(0.1, 1e3, 1024)
+    if a.workload == "wide":
+        recipe, dirs, om = configs.wide_recipe(), configs.dirs_wide(), configs.log_grid(0.1, 1e3, 2048)
+    else:
+        recipe, dirs, om = configs.jitter_recipe(), configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024)
     t = time.perf_counter()
     batch = upload_ensemble(recipe, a.particles, a.chunk, dev, host=a.host_generator)
     terms_per_step = float(batch.n_samples_host) * len(dirs) * len(om)
@@ -674,7 +680,7 @@ def main():
                     spectra[path], spectra["fp32"], om)
     head = paths[-1]
     r = results[head]
-    r["roofline"]["traffic"] = profiled_traffic(head, a.tile, a.particles)
+    r["roofline"]["traffic"] = profiled_traffic(head, a.tile, a.particles, a.workload, a.bands)
     out = {
         "metric": "LW spectral terms/s (particle x step x omega x n)",
         "value": r["terms_per_s"],
@@ -689,11 +695,16 @@ def main():
         "dtype": {"fp32": "f32 (f64 phase)", "mfma_f16": "f16 / f32 acc",
                   "mfma_bf16": "bf16 / f32 acc"}[split_path(head)[0]] + " x%d" % split_path(head)[1],
         "data": "synthetic",
-        "config": {"workload": f"filamentation-jitter ensemble: {a.particles} e- of gamma0=3 "
-                               "counter-streaming beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), "
-                               "1024 log omega in [0.1,1e3]; 1 step = the whole ensemble",
-                   "particles": a.particles, "samples_per_particle": 4096, "directions": 4,
-                   "frequencies": 1024, "path": head, "bands": a.bands},
+        "config": ({"workload": f"filamentation-jitter ensemble: {a.particles} e- of gamma0=3 "
+                                "counter-streaming beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), "
+                                "1024 log omega in [0.1,1e3]; 1 step = the whole ensemble",
+                    "particles": a.particles, "samples_per_particle": 4096, "directions": 4,
+                    "frequencies": 1024, "path": head, "bands": a.bands} if a.workload == "jitter" else
+                   {"workload": f"mixed-precision form: {a.particles} particles of the jitter generator, "
+                                "2048 Boris steps, 16 dirs (head-on, 15/30/45 deg, perpendicular), 2048 log "
+                                "omega in [0.1,1e3]; 1 step = the whole ensemble",
+                    "particles": a.particles, "samples_per_particle": 2048, "directions": len(dirs),
+                    "frequencies": 2048, "path": head, "bands": a.bands}),
         "roofline": r["roofline"],
         "paths": results,
     }

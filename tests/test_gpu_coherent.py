@@ -256,11 +256,12 @@ def test_graph_replays_in_coherent_mode():
     c.close()
 
 
-@pytest.mark.parametrize("path,case,tile", [("mfma_f16", "jitter", 3), ("mfma_f16", "jitter", 4),
-                                            ("mfma_f16", "uneven_species", 3),
-                                            ("mfma_f16", "uneven_species", 4),
-                                            ("mfma_bf16", "jitter", 4)])
-def test_coherent_matrix_core_path(path, case, tile):
+@pytest.mark.parametrize("path,case,tile,bands", [("mfma_f16", "jitter", 3, 1), ("mfma_f16", "jitter", 4, 1),
+                                                  ("mfma_f16", "jitter", 4, 2),
+                                                  ("mfma_f16", "uneven_species", 3, 1),
+                                                  ("mfma_f16", "uneven_species", 4, 1),
+                                                  ("mfma_bf16", "jitter", 4, 1)])
+def test_coherent_matrix_core_path(path, case, tile, bands):
     """The matrix-core path keeps each column's phase e^{i w tau_0} in its epilogue (128- and
     256-row contraction tiles: 1024 and 640 frequencies give row counts that are multiples
     of 256)."""
@@ -276,6 +277,7 @@ def test_coherent_matrix_core_path(path, case, tile):
     S_ref, A_ref = oracle.coherent_spectrum(b, dirs, om, n_species=ns, with_amplitude=True)
     c = _ctx(dirs, om, ns)
     c.set_tuning(tile=tile)
+    c.set_mfma_options(bands, 3, 3)
     c.accumulate(DeviceBatch.from_host(b), path)
     S = c.read_spectra()
     A = _xyz(c.read_amplitudes(), c.get_basis())
@@ -284,7 +286,7 @@ def test_coherent_matrix_core_path(path, case, tile):
     e = _amp_error(A, A_ref, rss2)
     live = [r for r in range(S.shape[0] * S.shape[1]) if S_ref.reshape(-1, S.shape[-1])[r].max() > 0]
     band = band_integrated_errors(S.reshape(-1, S.shape[-1])[live], S_ref.reshape(-1, S.shape[-1])[live], om)
-    print(f"[coherent] {path} {case} tile {tile}: amplitude error / R = {e:.3e}, "
+    print(f"[coherent] {path} {case} tile {tile}, {bands} band(s): amplitude error / R = {e:.3e}, "
           f"band-integrated {band.max():.3e}",
           flush=True)
     assert band.max() <= MFMA_BAND_TOL[path]

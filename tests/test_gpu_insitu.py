@@ -71,8 +71,11 @@ def test_pusher_preserves_the_lorentz_factor():
     assert np.max(np.abs(u1 - u0)) > 1e-3  # the field did deflect them
 
 
-@pytest.mark.parametrize("path", ["fp32", "mfma_f16"])
-def test_recorder_incoherent_windows(path):
+@pytest.mark.parametrize("path,bands", [("fp32", 1), ("mfma_f16", 1), ("mfma_f16", 2)])
+def test_recorder_incoherent_windows(path, bands):
+    """Snapshots of pusher windows recorded into the per-particle state match the oracle on
+    the trajectory so far; on the matrix-core path with one band and with the two bands the
+    benchmark's in-situ legs use."""
     from paper_1003_1140_amd import Context, DeviceBatch, Recorder
     from _parity import band_integrated_errors
 
@@ -81,6 +84,7 @@ def test_recorder_incoherent_windows(path):
     c = Context(0)
     c.set_directions(dirs)
     c.set_frequencies(om)
+    c.set_mfma_options(bands, 3, 3)
     rec = Recorder(c, n, coherent=False, path=path)
     host, snaps = [], []
     for _ in range(3):  # 3 windows of 16 simulation steps x 10 sub-steps
@@ -96,7 +100,7 @@ def test_recorder_incoherent_windows(path):
         else:
             err = band_integrated_errors(snaps[i].reshape(-1, len(om)), ref.reshape(-1, len(om)), om).max()
             assert err <= 1e-5, (i, err)
-        print(f"[insitu] {path} incoherent snapshot {i}: error {err:.3e}", flush=True)
+        print(f"[insitu] {path}, {bands} band(s), incoherent snapshot {i}: error {err:.3e}", flush=True)
     c.close()
 
 
