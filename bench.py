@@ -125,8 +125,9 @@ def kernel_code_digest(src):
 
 def profiled_traffic(path, tile, particles, workload="jitter", bands=2):
     """HBM bytes per contraction launch from the committed counter profile of this exact
-    configuration (the default launch), or None when the kernel code changed since it was taken."""
-    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload != "jitter" or bands != 2:
+    configuration (the default launch), or None when the kernel code or the band count
+    differs from the profiled run."""
+    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload != "jitter":
         return None
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -134,8 +135,10 @@ def profiled_traffic(path, tile, particles, workload="jitter", bands=2):
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:")))
+                  if line.startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:", "bands:")))
     if fields.get("kernel_code_sha256", "").strip() != kernel_code_digest(src):
+        return None
+    if fields.get("bands", "").strip() != str(bands):
         return None
     return float(fields["traffic_bytes_per_launch"])
 
