@@ -1,0 +1,45 @@
+"""Host logic of bench.py that decides what its JSON line reports (no GPU).
+
+The roofline's traffic comes from the committed counter profile only while the contraction
+kernel's code and the band count match what was profiled; these tests pin that rule.
+"""
+import importlib.util
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_code_digest_ignores_comments_and_whitespace_only():
+    b = _bench()
+    src = "int f(int x) {\n  return x + 1;  // add one\n}\n"
+    same = "int f(int x){return x+1;}\n// a note\n"
+    changed = "int f(int x) {\n  return x + 2;  // add one\n}\n"
+    assert b.kernel_code_digest(src) == b.kernel_code_digest(same)
+    assert b.kernel_code_digest(src) != b.kernel_code_digest(changed)
+
+
+def test_traffic_is_reported_only_for_the_profiled_launch():
+    b = _bench()
+    text = open(b.TRAFFIC_PROFILE).read()
+    fields = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
+    profiled_bands = int(fields["bands"])
+    src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip")).read()
+    if fields["kernel_code_sha256"].strip() != b.kernel_code_digest(src):
+        # the kernel changed after the counters were taken: nothing may be reported
+        assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands) is None
+        return
+    got = b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands)
+    assert got == float(fields["traffic_bytes_per_launch"])
+    # any other launch gets none
+    assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands + 1) is None
+    assert b.profiled_traffic("mfma_bf16x3", 0, 100_000, "jitter", profiled_bands) is None
+    assert b.profiled_traffic("mfma_f16x3", 1, 100_000, "jitter", profiled_bands) is None
+    assert b.profiled_traffic("mfma_f16x3", 0, 50_000, "jitter", profiled_bands) is None
+    assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "wide", profiled_bands) is None
