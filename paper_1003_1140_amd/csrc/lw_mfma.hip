@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <limits>
 #include <type_traits>
 #include <vector>
 
@@ -1418,6 +1419,65 @@ lw_status batch_span(lw_ctx* c, const lw_batch* b, double* span) {
   return LW_OK;
 }
 
+// Band boundaries (frequency indices jb[0] = 0 < ... < jb[nb] = nw) that minimise the
+// contraction's work, the sum over bands of rows x grid points: 2 nj rounded up to a row
+// tile, times span / h + W + 1 with h = pi / (sigma D) and D the band's half-width.  The
+// spread costs the same for any split (every band spreads every sample).  On a log grid
+// the upper band keeps a wide D however it is cut, so it should hold few frequencies.
+// Boundaries fall on multiples of 128 frequencies when there are enough (so that every
+// band's row count suits 256-row tiles), on a coarser step when the grid is long (at most
+// 256 candidate positions), and anywhere on short grids.
+std::vector<int> band_bounds(const std::vector<double>& w, int nb, double span, const KernelShape& ks) {
+  const int nw = (int)w.size();
+  std::vector<int> jb(nb + 1);
+  for (int b = 0; b <= nb; ++b) jb[b] = (int)((int64_t)nw * b / nb);  // equal counts
+  if (nb < 2) return jb;
+  int g = nw >= 128 * nb ? 128 : 1;
+  while (nw / g > 256) g *= 2;
+  std::vector<int> pos;
+  for (int j = 0; j < nw; j += g) pos.push_back(j);
+  pos.push_back(nw);
+  const int np = (int)pos.size();
+  if (np - 1 < nb) return jb;
+  // cost of one band over [pos[k], pos[l])
+  std::vector<double> cost((size_t)np * np, 0.0);
+  for (int k = 0; k + 1 < np; ++k) {
+    double lo = w[pos[k]], hi = w[pos[k]];
+    for (int l = k + 1; l < np; ++l) {
+      for (int j = pos[l - 1]; j < pos[l]; ++j) {
+        lo = std::min(lo, w[j]);
+        hi = std::max(hi, w[j]);
+      }
+      const double wc = 0.5 * (lo + hi);
+      const double D = std::max(0.5 * (hi - lo), 1e-6 * std::max(wc, 1e-300));
+      const double rows = (double)(((2 * (pos[l] - pos[k]) + kTileM - 1) / kTileM) * kTileM);
+      cost[(size_t)k * np + l] = rows * (span * ks.sigma * D / M_PI + ks.w + 1);
+    }
+  }
+  // best[b][l]: least cost of b bands covering [0, pos[l]); from[b][l]: start of the last one
+  const double inf = std::numeric_limits<double>::infinity();
+  std::vector<double> best((size_t)(nb + 1) * np, inf);
+  std::vector<int> from((size_t)(nb + 1) * np, -1);
+  best[0] = 0.0;
+  for (int b = 1; b <= nb; ++b)
+    for (int l = b; l < np; ++l)
+      for (int k = b - 1; k < l; ++k) {
+        const double v = best[(size_t)(b - 1) * np + k] + cost[(size_t)k * np + l];
+        if (v < best[(size_t)b * np + l]) {
+          best[(size_t)b * np + l] = v;
+          from[(size_t)b * np + l] = k;
+        }
+      }
+  if (!(best[(size_t)nb * np + np - 1] < inf)) return jb;
+  int l = np - 1;
+  for (int b = nb; b >= 1; --b) {
+    jb[b] = pos[l];
+    l = from[(size_t)b * np + l];
+  }
+  jb[0] = 0;
+  return jb;
+}
+
 lw_status build_plan(lw_ctx* c, double span, int dtype, const KernelShape& ks) {
   MfmaPlanCache* pc = c->mfma;
   free_tables(pc);
@@ -1427,12 +1487,13 @@ lw_status build_plan(lw_ctx* c, double span, int dtype, const KernelShape& ks) {
   pc->span = span;
   pc->dtype = dtype;
   const std::vector<double>& w = c->h_omega;
+  const std::vector<int> jb = band_bounds(w, nb, span, ks);
   int row = 0;
   int64_t eoff = 0, foff = 0;
   for (int b = 0; b < nb; ++b) {
     Band& bd = pc->band[b];
-    bd.j0 = (int)((int64_t)c->nw * b / nb);
-    const int j1 = (int)((int64_t)c->nw * (b + 1) / nb);
+    bd.j0 = jb[b];
+    const int j1 = jb[b + 1];
     bd.nj = j1 - bd.j0;
     double lo = w[bd.j0], hi = w[bd.j0];
     for (int j = bd.j0; j < j1; ++j) {
