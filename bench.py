@@ -48,6 +48,27 @@ def fp32_term_peak():
 
 PEAK_MFMA_TFLOPS = 2500.0  # dense FP16/BF16 matrix peak of one MI355X
 PEAK_HBM_GBS = 8000.0  # HBM3E bandwidth of one MI355X
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # FP32 vector peak of one MI355X (with packed FP32 math)
+
+
+def spread_width(products):
+    """Taps W of the spreading kernel: 10 for the hi/lo operand split, 8 for one product."""
+    return 10 if products == 3 else 8
+
+
+def spread_flops_per_unit(w):
+    """Arithmetic of the spreading step for one (sample, direction, band) with W taps.
+
+    FP32: the W tap weights times the demodulated integrand into 2 polarisations x
+    (re, im), 4W FMAs = 8W; the tap weights, W/2 mirrored pairs of degree-8 polynomials in
+    z = 2 frac(u) - 1 evaluated as even and odd parts in z^2 (4 + 3 Horner FMAs and 2 FMAs
+    to combine), 9W, plus 3 for z and z^2; the integrand e.(n x ((n - beta) x a)) / kappa^2
+    for both polarisations, 35; the demodulation of both by (cos, sin), 4.
+    FP64: kappa 6, retarded time 9, the turn fraction of w_c tau 2, the grid coordinate
+    and its fraction 4.
+    Sine, cosine and reciprocal are not counted.  Total 17 W + 63 (233 at W = 10).
+    """
+    return 17 * w + 63
 
 
 def split_path(name):
@@ -111,6 +132,7 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md")
+TRAFFIC_FIELDS = {"contraction": "traffic_bytes_per_launch", "spread": "spread_traffic_bytes_per_launch"}
 
 
 def kernel_code_digest(src):
@@ -123,10 +145,10 @@ def kernel_code_digest(src):
     return hashlib.sha256(re.sub(r"\s+", "", code).encode()).hexdigest()
 
 
-def profiled_traffic(path, tile, particles, workload="jitter", bands=2):
-    """HBM bytes per contraction launch from the committed counter profile of this exact
-    configuration (the default launch), or None when the kernel code or the band count
-    differs from the profiled run."""
+def profiled_traffic(path, tile, particles, workload="jitter", bands=2, kernel="contraction"):
+    """HBM bytes per launch of the contraction (or the spreading kernel) from the committed
+    counter profile of this exact configuration (the default launch), or None when the
+    kernel code or the band count differs from the profiled run."""
     if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload != "jitter":
         return None
     try:
@@ -135,12 +157,14 @@ def profiled_traffic(path, tile, particles, workload="jitter", bands=2):
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines()
-                  if line.startswith(("traffic_bytes_per_launch:", "kernel_code_sha256:", "bands:")))
+                  if line.startswith(tuple(f + ":" for f in (*TRAFFIC_FIELDS.values(), "kernel_code_sha256",
+                                                             "bands"))))
     if fields.get("kernel_code_sha256", "").strip() != kernel_code_digest(src):
         return None
     if fields.get("bands", "").strip() != str(bands):
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    value = fields.get(TRAFFIC_FIELDS[kernel])
+    return float(value) if value is not None else None
 
 
 TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4, MI=4, NJ=2> (256 x 256 tiles, eight waves)",
@@ -182,10 +206,23 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
     else:
         ach = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
         peak = PEAK_MFMA_TFLOPS
-        res["roofline"] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                           "frac": ach / peak, "traffic": None, "kernel": TILE_KERNELS[tile],
-                           "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
-                           "launches_per_step": prof["gemm_launches"] / steps}
+        contraction = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                       "frac": ach / peak, "traffic": None, "kernel": TILE_KERNELS[tile],
+                       "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
+                       "launches_per_step": prof["gemm_launches"] / steps}
+        # every band spreads every sample once per direction
+        w = spread_width(products)
+        units = float(batch.n_samples_host) * ctx.nd * bands * steps
+        ach = units * spread_flops_per_unit(w) / (prof["spread_ms"] * 1e-3) / 1e12
+        spread = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                  "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": f"lw_spread_kernel<{w}>",
+                  "avg_launch_ms": prof["spread_ms"] / max(prof["spread_launches"], 1),
+                  "launches_per_step": prof["spread_launches"] / steps,
+                  "flops_per_sample_direction_band": spread_flops_per_unit(w)}
+        res["roofline_contraction"] = contraction
+        res["roofline_spread"] = spread
+        # the headline roofline is the kernel that takes longer in the step
+        res["roofline"] = dict(spread if prof["spread_ms"] > prof["gemm_ms"] else contraction)
     return res, S
 
 
@@ -683,7 +720,11 @@ def main():
                     spectra[path], spectra["fp32"], om)
     head = paths[-1]
     r = results[head]
-    r["roofline"]["traffic"] = profiled_traffic(head, a.tile, a.particles, a.workload, a.bands)
+    if "roofline_contraction" in r:
+        for kernel in ("contraction", "spread"):
+            r["roofline_" + kernel]["traffic"] = profiled_traffic(head, a.tile, a.particles, a.workload,
+                                                                  a.bands, kernel)
+        r["roofline"] = dict(r["roofline_spread" if r["roofline"]["bound"] == "alu" else "roofline_contraction"])
     out = {
         "metric": "LW spectral terms/s (particle x step x omega x n)",
         "value": r["terms_per_s"],
@@ -709,6 +750,8 @@ def main():
                     "particles": a.particles, "samples_per_particle": 2048, "directions": len(dirs),
                     "frequencies": 2048, "path": head, "bands": a.bands}),
         "roofline": r["roofline"],
+        **({"roofline_contraction": r["roofline_contraction"], "roofline_spread": r["roofline_spread"]}
+           if "roofline_contraction" in r else {}),
         "paths": results,
     }
     if not a.no_insitu and "fp32" in spectra:

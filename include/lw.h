@@ -365,10 +365,10 @@ lw_status lw_mlp_train_head_step(lw_mlp* net, const float* x, const float* err_t
  * accumulation kernel launch (enable != 0 turns it on; off by default). */
 lw_status lw_set_profiling(lw_ctx* ctx, int32_t enable);
 /* Synchronise, then report and clear the timings gathered since the last read:
- * host_out[6] = {FP32 accumulation kernel ms, spreading kernel ms, matrix-core
+ * host_out[7] = {FP32 accumulation kernel ms, spreading kernel ms, matrix-core
  * contraction kernel ms, useful contraction FLOPs (2 x rows x columns x inner
  * length per particle, direction and band, times the number of products),
- * FP32 kernel launches, contraction kernel launches}. */
+ * FP32 kernel launches, contraction kernel launches, spreading kernel launches}. */
 lw_status lw_profile_read(lw_ctx* ctx, double* host_out);
 
 /* Number of successful lw_accumulate calls since creation. */

@@ -459,6 +459,7 @@ lw_status lw_profile_read(lw_ctx* c, double* out) {
   out[3] = (double)fl * c->flop_mult;
   out[4] = n[lw::kProfDirect];
   out[5] = n[lw::kProfGemm];
+  out[6] = n[lw::kProfSpread];
   c->ev_marks.clear();
   c->ev_used = 0;
   return LW_OK;

@@ -226,9 +226,10 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 //      (built by the samples themselves, no search); the samples reaching q are then
 //      exactly first[x] .. first[x + W] - 1, since each covers W consecutive points;
 //   3. one thread (or S threads taking every S-th sample, summed with shuffles) per grid
-//      point adds w g over its samples into a ring of running grid sums in LDS;
-//   4. grid points below the next chunk's first tap are final: they are written to F
-//      (FP32) and their ring slots cleared.
+//      point adds w g over its samples to the point's running sum, held in a ring in LDS;
+//   4. a point below the next chunk's first tap is then final: that thread writes it to F
+//      (FP32) and clears its ring slot; the chunk's points that no sample reached are
+//      written as zeros.
 // The next chunk starts with the sample that did not fit the ring, so every grid point
 // of a chunk lies within kRing of the oldest pending one.
 // Grid points held in LDS.  768 covers the grid points of a 256-sample chunk at the
@@ -401,6 +402,9 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     take = max(take, 1);
     const int top = st.lo[take - 1] + kW - 1;  // highest grid point touched
     const int G = min(top - base + 1, kRing);
+    // grid points below the next chunk's first tap are final after this chunk
+    int qfin = Q;
+    if (kc + take < len) qfin = min(Q, take < cnt ? st.lo[take] : top + 1);
     // first sample reaching each grid point of the chunk
     if (tid < take) {
       const int prev = tid == 0 ? base - 1 : st.lo[tid - 1] + kW - 1;
@@ -412,6 +416,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     int S = 1;
     while (S < 64 && 2 * S * G <= kSpreadWin) S *= 2;
     const int per_pass = kSpreadWin / S;
+    const int ring0 = base % kRing;  // slot of grid point base (base >= 1)
     for (int xb = 0; xb < G; xb += per_pass) {
       const int x = xb + tid / S, sl = tid % S;
       float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
@@ -437,27 +442,30 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
         acc3 += __shfl_xor(acc3, off);
       }
       if (x < G && sl == 0) {
-        float4& r = st.acc[(base + x) % kRing];
-        r.x += acc0;
-        r.y += acc1;
-        r.z += acc2;
-        r.w += acc3;
+        const int slot = ring0 + x < kRing ? ring0 + x : ring0 + x - kRing;  // x < G <= kRing
+        float4& r = st.acc[slot];
+        const float4 v = make_float4(r.x + acc0, r.y + acc1, r.z + acc2, r.w + acc3);
+        const int q = base + x;  // >= qdone: the chunk starts at or after the oldest pending point
+        if (q < qfin) {
+          *(float2*)(c0 + 2 * q) = make_float2(v.x, v.y);
+          *(float2*)(c1 + 2 * q) = make_float2(v.z, v.w);
+          wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+          r = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          r = v;
+        }
       }
     }
-    __syncthreads();
-    // grid points below the next chunk's first tap are final
-    int qfin = Q;
-    if (kc + take < len) qfin = min(Q, take < cnt ? st.lo[take] : top + 1);
-    for (int q = qdone + tid; q < qfin; q += kSpreadWin) {
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (q <= top) {  // beyond it nothing was added (and the slot may hold a newer point)
-        float4& r = st.acc[q % kRing];
-        v = r;
-        r = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-      *(float2*)(c0 + 2 * q) = make_float2(v.x, v.y);
-      *(float2*)(c1 + 2 * q) = make_float2(v.z, v.w);
-      wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    // final points outside [base, base + G) were reached by no sample: below the first
+    // chunk's first tap, in a gap between two samples wider than the kernel, or past the
+    // last tap of the trajectory
+    for (int q = qdone + tid; q < min(base, qfin); q += kSpreadWin) {
+      *(float2*)(c0 + 2 * q) = make_float2(0.f, 0.f);
+      *(float2*)(c1 + 2 * q) = make_float2(0.f, 0.f);
+    }
+    for (int q = max(base + G, qdone) + tid; q < qfin; q += kSpreadWin) {
+      *(float2*)(c0 + 2 * q) = make_float2(0.f, 0.f);
+      *(float2*)(c1 + 2 * q) = make_float2(0.f, 0.f);
     }
     qdone = max(qdone, qfin);
     kc += take;

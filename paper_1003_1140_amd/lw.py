@@ -374,10 +374,11 @@ class Context:
         self._check(self.lib.lw_set_profiling(self.h, 1 if enable else 0))
 
     def profile_read(self) -> dict:
-        out = np.zeros(6, dtype=np.float64)
+        out = np.zeros(7, dtype=np.float64)
         self._check(self.lib.lw_profile_read(self.h, _np_ptr(out)))
         return {"direct_ms": out[0], "spread_ms": out[1], "gemm_ms": out[2], "gemm_flops": out[3],
-                "direct_launches": int(out[4]), "gemm_launches": int(out[5])}
+                "direct_launches": int(out[4]), "gemm_launches": int(out[5]),
+                "spread_launches": int(out[6])}
 
     def plan_batch(self, batch: DeviceBatch, path="fp32"):
         self._check(self.lib.lw_plan_batch(self.h, ctypes.byref(batch.struct), PATHS.get(path, path)))

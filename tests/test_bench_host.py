@@ -37,9 +37,20 @@ def test_traffic_is_reported_only_for_the_profiled_launch():
         return
     got = b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands)
     assert got == float(fields["traffic_bytes_per_launch"])
+    got = b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands, "spread")
+    assert got == float(fields["spread_traffic_bytes_per_launch"])
     # any other launch gets none
     assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands + 1) is None
     assert b.profiled_traffic("mfma_bf16x3", 0, 100_000, "jitter", profiled_bands) is None
     assert b.profiled_traffic("mfma_f16x3", 1, 100_000, "jitter", profiled_bands) is None
     assert b.profiled_traffic("mfma_f16x3", 0, 50_000, "jitter", profiled_bands) is None
     assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "wide", profiled_bands) is None
+
+
+def test_spread_flop_model():
+    b = _bench()
+    # 8W accumulation + 9W tap polynomials + 3 (z, z^2) + 35 integrand + 4 demodulation
+    # + 21 FP64 prepass
+    for w in (8, 10):
+        assert b.spread_flops_per_unit(w) == 8 * w + 9 * w + 3 + 35 + 4 + 21
+    assert b.spread_width(3) == 10 and b.spread_width(1) == 8
