@@ -425,6 +425,8 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
         // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale)
         const int s_begin = min(max(st.first[x], 0), take);
         const int s_end = min(max(st.first[x + kW], s_begin), take);
+        // two samples per trip: half the loop control (2 % of the kernel; 4 gained less)
+#pragma unroll 2
         for (int s = s_begin + sl; s < s_end; s += S) {
           const int i = min(max(q - st.lo[s], 0), kW - 1);
           const float w = st.w[i][s];
@@ -445,7 +447,9 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
         const int slot = ring0 + x < kRing ? ring0 + x : ring0 + x - kRing;  // x < G <= kRing
         float4& r = st.acc[slot];
         const float4 v = make_float4(r.x + acc0, r.y + acc1, r.z + acc2, r.w + acc3);
-        const int q = base + x;  // >= qdone: the chunk starts at or after the oldest pending point
+        // q >= qdone on valid data (the chunk starts at or after the oldest pending point); on
+        // invalid data, which is reported, a point may be rewritten, still within [1, Q)
+        const int q = base + x;
         if (q < qfin) {
           *(float2*)(c0 + 2 * q) = make_float2(v.x, v.y);
           *(float2*)(c1 + 2 * q) = make_float2(v.z, v.w);
