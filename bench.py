@@ -210,9 +210,11 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
                        "frac": ach / peak, "traffic": None, "kernel": TILE_KERNELS[tile],
                        "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
                        "launches_per_step": prof["gemm_launches"] / steps}
-        # every band spreads every sample once per direction
+        # every band spreads every sample once per direction (the plan holds 1 to 16 bands,
+        # at most one per frequency)
         w = spread_width(products)
-        units = float(batch.n_samples_host) * ctx.nd * bands * steps
+        nb = max(1, min(bands, 16, ctx.nw))
+        units = float(batch.n_samples_host) * ctx.nd * nb * steps
         ach = units * spread_flops_per_unit(w) / (prof["spread_ms"] * 1e-3) / 1e12
         spread = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                   "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": f"lw_spread_kernel<{w}>",
