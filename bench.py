@@ -200,9 +200,12 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
         per_launch_ms = prof["direct_ms"] / max(prof["direct_launches"], 1)
         ach = terms_per_step * steps / prof["direct_launches"] / (per_launch_ms * 1e-3)
         peak = fp32_term_peak()
+        # the same rate as counted arithmetic: four FP32 FMAs (8 FLOPs) per term
         res["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "Tterm/s",
                            "frac": ach / peak, "traffic": None, "kernel": "lw_direct_f32_kernel<4>",
-                           "avg_launch_ms": per_launch_ms}
+                           "avg_launch_ms": per_launch_ms,
+                           "counted_tflops": 8 * ach / 1e12,
+                           "frac_of_fp32_vector_peak": 8 * ach / 1e12 / PEAK_FP32_VECTOR_TFLOPS}
     else:
         ach = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
         peak = PEAK_MFMA_TFLOPS
