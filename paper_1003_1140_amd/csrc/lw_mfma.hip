@@ -1352,11 +1352,13 @@ lw_status set_err(lw_ctx* c, lw_status st, const char* msg) {
   } while (0)
 
 int chunk_particles(const MfmaPlanCache* pc, int nd, int64_t P) {
-  // particles per chunk bounded so that F (all directions) stays near 6 GiB
+  // particles per chunk bounded so that F (all directions) stays near 12 GiB: fewer, larger
+  // launches (with two bands 12 GiB made the spreading kernel 8 % faster than 6 GiB and left
+  // the contraction as it was; with one band it slowed the contraction by 4 %)
   int64_t per = 0;
   for (int b = 0; b < pc->nb; ++b) per += 2 * (int64_t)pc->band[b].kp * sizeof(float);
   per *= nd;
-  int64_t n = per > 0 ? (int64_t)(6LL << 30) / per : 8192;
+  int64_t n = per > 0 ? (int64_t)(12LL << 30) / per : 8192;
   n = std::max<int64_t>(64, std::min<int64_t>(n, kMaxChunk));
   n = (n / 64) * 64;
   return (int)std::min<int64_t>(n, ((P + 63) / 64) * 64);
