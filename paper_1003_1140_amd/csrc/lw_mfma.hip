@@ -497,22 +497,27 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
 }
 
 // ------------------------------------------------------------------ column order
-// One work-group per (direction, band): the chunk's particles ordered by decreasing
-// grid length q (ties by index), so that each contraction tile holds columns of
-// similar inner length and stops where its longest column ends.  Bitonic sort of
-// 64-bit keys in LDS: deterministic.
-constexpr int kMaxChunk = 16384;
+// One work-group per (direction, band, block of up to kSortBlock particles): the block's
+// particles ordered by decreasing grid length q (ties by index), so that each contraction
+// tile holds columns of similar inner length and stops where its longest column ends.  A
+// tile (64 or 128 particles) never straddles two blocks; the contraction takes each tile's
+// length as the maximum over its columns, so any order is correct and the sort only saves
+// work.  Bitonic sort of 64-bit keys in LDS: deterministic.
+constexpr int kSortBlock = 16384;
 
 __global__ __launch_bounds__(1024) void lw_sort_columns_kernel(const int32_t* colq, int n_local,
                                                                int32_t* perm) {
-  __shared__ unsigned long long key[kMaxChunk];
-  const int seg = blockIdx.x;
+  __shared__ unsigned long long key[kSortBlock];
+  const int nblk = (n_local + kSortBlock - 1) / kSortBlock;
+  const int seg = blockIdx.x / nblk;
+  const int i0 = (blockIdx.x % nblk) * kSortBlock;
+  const int n = min(kSortBlock, n_local - i0);
   const int32_t* q = colq + (size_t)seg * n_local;
   int n2 = 1;
-  while (n2 < n_local) n2 <<= 1;
+  while (n2 < n) n2 <<= 1;
   for (int i = threadIdx.x; i < n2; i += blockDim.x)
-    key[i] = i < n_local ? ((unsigned long long)(0x7fffffffu - (unsigned)q[i]) << 32) | (unsigned)i
-                         : ~0ull;
+    key[i] = i < n ? ((unsigned long long)(0x7fffffffu - (unsigned)q[i0 + i]) << 32) | (unsigned)(i0 + i)
+                   : ~0ull;
   __syncthreads();
   for (int k = 2; k <= n2; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
@@ -529,8 +534,8 @@ __global__ __launch_bounds__(1024) void lw_sort_columns_kernel(const int32_t* co
       }
       __syncthreads();
     }
-  for (int i = threadIdx.x; i < n_local; i += blockDim.x)
-    perm[(size_t)seg * n_local + i] = (int32_t)(key[i] & 0xffffffffull);
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    perm[(size_t)seg * n_local + i0 + i] = (int32_t)(key[i] & 0xffffffffull);
 }
 
 // ------------------------------------------------------------------ DFT contraction on MFMA
@@ -1352,14 +1357,17 @@ lw_status set_err(lw_ctx* c, lw_status st, const char* msg) {
   } while (0)
 
 int chunk_particles(const MfmaPlanCache* pc, int nd, int64_t P) {
-  // particles per chunk bounded so that F (all directions) stays near 12 GiB: fewer, larger
-  // launches (with two bands 12 GiB made the spreading kernel 8 % faster than 6 GiB and left
-  // the contraction as it was; with one band it slowed the contraction by 4 %)
+  // particles per chunk bounded so that F (all directions) stays near 24 GiB: fewer, larger
+  // launches.  With two bands on 1e5 particles, 12 GiB (7 chunks) made the spreading kernel
+  // 8 % faster than 6 GiB (13); 24 GiB (4) saved 1.6 % more of the step, and 48 or 96 GiB
+  // no more (the contraction slows as the spread gains)
   int64_t per = 0;
   for (int b = 0; b < pc->nb; ++b) per += 2 * (int64_t)pc->band[b].kp * sizeof(float);
   per *= nd;
-  int64_t n = per > 0 ? (int64_t)(12LL << 30) / per : 8192;
-  n = std::max<int64_t>(64, std::min<int64_t>(n, kMaxChunk));
+  int64_t n = per > 0 ? (int64_t)(24LL << 30) / per : 8192;
+  // column indices (direction, band, 2 x particle) stay within int32
+  n = std::min<int64_t>(n, ((int64_t)1 << 30) / ((int64_t)nd * pc->nb));
+  n = std::max<int64_t>(64, n);
   n = (n / 64) * 64;
   return (int)std::min<int64_t>(n, ((P + 63) / 64) * 64);
 }
@@ -1726,8 +1734,9 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
                          dim3(kSpreadWin), 0, c->stream, sa);
     MF_HIP(hipGetLastError(), "launch spread");
     MF_HIP(prof_end(c), "profile");
-    hipLaunchKernelGGL(lw_sort_columns_kernel, dim3((unsigned)(c->nd * pc->nb)), dim3(1024), 0, c->stream,
-                       colq, nl, perm);
+    hipLaunchKernelGGL(lw_sort_columns_kernel,
+                       dim3((unsigned)(c->nd * pc->nb * ((nl + kSortBlock - 1) / kSortBlock))), dim3(1024), 0,
+                       c->stream, colq, nl, perm);
     MF_HIP(hipGetLastError(), "launch column sort");
     int tiles = 0;
     for (int oi = 0; oi < pc->nb; ++oi) {
