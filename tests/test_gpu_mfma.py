@@ -181,3 +181,17 @@ def test_agrees_with_fp32_path_on_a_large_batch():
     for tile in (1, 2):
         S16 = run(b, dirs, om, "mfma_f16", tile=tile)
         assert report(f"mfma f16 x3 (tile {tile}) vs fp32, 4096 jitter particles", S16, S32, om).max() <= 1e-5
+
+
+def test_chunk_sorted_in_several_blocks():
+    """40000 short trajectories fit one chunk, whose columns are ordered by grid length in
+    three blocks of particles (16384, 16384 and a ragged 7232), each sorted on its own: a
+    wrong block offset would drop or repeat columns.  The FP32 path judges."""
+    b = workloads.generate(workloads.make_recipe(11, steps=128), 0, 40_000)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 256)
+    S32 = gpu_spectrum(b, dirs, om, path="fp32")
+    for bands in (1, 2):
+        S16 = run(b, dirs, om, "mfma_f16", bands=bands)
+        assert report(f"mfma f16 x3 vs fp32, 40000 particles in one chunk, {bands} band(s)",
+                      S16, S32, om).max() <= 1e-5
