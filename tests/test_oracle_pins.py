@@ -11,8 +11,9 @@ computed by means independent of the oracle's own arithmetic:
 * for uniformly spaced retarded times the discrete sum obeys an exact
   Parseval identity;
 * uniform circular motion at integer harmonics equals the Bessel closed form
-  m^2 beta^2 J'_m(m beta)^2 (Jacobi-Anger), with its in-plane K_{2/3}
-  asymptotics;
+  m^2 beta^2 J'_m(m beta)^2 (Jacobi-Anger) in the orbit plane and Schott's
+  angular distribution out of it, with its in-plane K_{2/3} asymptotics and,
+  integrated over solid angle, the synchrotron x int K_{5/3} form;
 * the solid-angle and frequency integral of a smooth orbit equals the
   Lienard (relativistic Larmor) energy;
 * rotations, time shifts, translations, charge sign, weights, permutations,
@@ -165,6 +166,88 @@ def test_synchrotron_in_plane_k23_asymptotics():
     asym = (m * rho) ** 2 / (3 * np.pi**2) / g**4 * sp.kv(2 / 3, xi) ** 2
     ratio = S / asym
     assert np.all(np.abs(ratio - 1) < 0.08), ratio
+
+
+def _circular_fine(gamma=10.0, n=100_000):
+    """One period of the config-1 orbit on a fine step (T / 1e5): the discrete sum equals
+    the continuous integral to ~1e-9 at the harmonics used below."""
+    return orbits.circular(gamma, 1.0, n, 2 * np.pi / n)
+
+
+def _elevated(psi):
+    """Unit directions at elevation psi above the orbit plane (x-y), azimuth 0."""
+    psi = np.atleast_1d(psi)
+    return np.stack([np.cos(psi), np.zeros_like(psi), np.sin(psi)], 1)
+
+
+def test_synchrotron_harmonics_out_of_plane_schott():
+    """Every elevation, not only the orbit plane: at harmonic m of one period the spectrum is
+    m^2 [cot^2(th) J_m(m beta sin th)^2 + beta^2 J'_m(m beta sin th)^2] (Schott's angular
+    distribution of the harmonics; th the polar angle from the orbit normal), exact."""
+    g = 10.0
+    b = _circular_fine(g)
+    beta = np.sqrt(1 - 1 / g**2)
+    psi = np.array([-0.9, -0.3, -0.05, 0.0, 0.02, 0.1, 0.45, 1.2])
+    th = np.pi / 2 - psi
+    m = np.array([1.0, 3.0, 10.0, 40.0, 150.0, 600.0])
+    S = spectrum_of(b, _elevated(psi), m)
+    for i, t in enumerate(th):
+        x = m * beta * np.sin(t)
+        exact = m**2 * ((np.cos(t) / np.sin(t)) ** 2 * sp.jv(m, x) ** 2 + beta**2 * sp.jvp(m, x) ** 2)
+        big = exact >= 1e-12 * exact.max()
+        np.testing.assert_allclose(S[i][big], exact[big], rtol=1e-8)
+
+
+def _synchrotron_F(x):
+    """F(x) = x int_x^inf K_{5/3}(s) ds, by adaptive quadrature of scipy's K_nu."""
+    from scipy.integrate import quad
+
+    return x * quad(lambda s: sp.kv(5.0 / 3.0, s), x, np.inf, limit=200)[0]
+
+
+def test_synchrotron_function_integral():
+    """int_0^inf F(x) dx = 8 pi / (9 sqrt 3), which fixes the total of the x int K_{5/3} form
+    (per revolution (8 pi / 9) gamma omega_c, the Larmor energy up to O(1/gamma^2))."""
+    from scipy.integrate import quad
+
+    total = quad(_synchrotron_F, 0.0, 1.0, limit=200)[0] + quad(_synchrotron_F, 1.0, 60.0, limit=200)[0]
+    assert abs(total / (8 * np.pi / (9 * np.sqrt(3))) - 1) < 1e-7
+
+
+def _angle_integrated(gamma, n, ratio_x):
+    """2 pi int cos(psi) S(psi) dpsi over |psi| <= 8 / gamma (96-node Gauss-Legendre) at the
+    harmonics nearest ratio_x * w_c, and sqrt(3) gamma F(w / w_c) there."""
+    b = orbits.circular(gamma, 1.0, n, 2 * np.pi / n)
+    beta = np.sqrt(1 - 1 / gamma**2)
+    wc = 1.5 * gamma**3 / beta
+    xg, wg = np.polynomial.legendre.leggauss(96)
+    half = 8.0 / gamma
+    psi = half * xg
+    m = np.round(np.asarray(ratio_x) * wc)
+    S = spectrum_of(b, _elevated(psi), m)
+    dW = 2 * np.pi * half * np.sum((wg * np.cos(psi))[:, None] * S, axis=0)
+    form = np.array([np.sqrt(3) * gamma * _synchrotron_F(w / wc) for w in m])
+    return dW, form
+
+
+def test_synchrotron_angle_integrated_x_int_k53():
+    """Solid-angle integral of one period's spectrum against the synchrotron form.
+
+    The harmonics of a whole period do not depend on azimuth, so the solid-angle integral is
+    2 pi int cos(psi) S(psi) dpsi over the elevation psi.  At harmonics w = m w0 near
+    0.1 ... 2 w_c it must equal sqrt(3) gamma F(w / w_c), w_c = (3/2) gamma^3 w0 / beta
+    (Rybicki-Lightman; Jackson 14.91), up to the O(1/gamma^2) corrections of that
+    ultra-relativistic form: at most 2.5 % at gamma = 10 (the config-1 orbit) and 0.4 % at
+    gamma = 30, and the deviation must shrink by at least 5x between the two (1/gamma^2
+    predicts 9x).  A wrong power of kappa, prefactor, cross product or phase in the oracle
+    moves these ratios by far more."""
+    x = np.array([0.1, 0.3, 1.0, 2.0])
+    dw10, f10 = _angle_integrated(10.0, 100_000, x)
+    dw30, f30 = _angle_integrated(30.0, 400_000, x)
+    r10, r30 = dw10 / f10, dw30 / f30
+    assert np.all(np.abs(r10 - 1) < 0.025), r10
+    assert np.all(np.abs(r30 - 1) < 0.004), r30
+    assert np.all(np.abs(r10 - 1) > 5 * np.abs(r30 - 1)), (r10, r30)
 
 
 # ---------------------------------------------------------------- P4 / P6

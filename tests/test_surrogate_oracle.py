@@ -1,5 +1,6 @@
 """Pins of the FP64 surrogate-network reference and of the feature reference (CPU)."""
 import numpy as np
+import pytest
 import scipy.special as sp
 
 import oracle
@@ -85,3 +86,80 @@ def test_energy_feature_of_straight_motion_is_zero():
     b = orbits.straight([0.3, 0.4, 0.0], [0, 0, 0], 50, 0.1)
     f = feat.features(b, [[0.0, 0.0, 1.0], [0.6, 0.8, 0.0]])[0]
     assert np.all(f[:, 11] == np.log(1e-30))
+
+
+# ---------------------------------------------------------------- features 3, 6, 7, 8, 9, 12
+# A constant-speed zigzag, beta = beta0 (cos phi, sin phi, 0) with phi = phi_m sin(W t), fixes
+# these features in closed form: gamma is constant, |a_perp| = beta0 |phi'| exactly, over
+# whole periods the mean unit velocity is x and the deflection angle is |phi|, and the force
+# reverses at every zero of cos(W t).
+ZZ_BETA, ZZ_PHI, ZZ_W = 0.8, 0.3, 2.0
+
+
+def _zigzag(periods, spp, t0_frac):
+    dt = 2 * np.pi / ZZ_W / spp
+    return orbits.zigzag(ZZ_BETA, ZZ_PHI, ZZ_W, periods * spp, dt, t0=t0_frac * dt), dt
+
+
+def test_feature_rms_aperp_and_deflection_of_a_zigzag():
+    """Samples at t_k = k T / spp over whole periods (spp divisible by 4): the discrete means
+    of cos^2 and sin^2 are exactly 1/2 and a sample sits on each turning point, so
+    rms |a_perp| = beta0 phi_m W / sqrt 2, gamma theta_rms = gamma phi_m / sqrt 2 and
+    gamma theta_max = gamma phi_m."""
+    b, dt = _zigzag(periods=5, spp=400, t0_frac=0.0)
+    g = 1 / np.sqrt(1 - ZZ_BETA**2)
+    f = feat.features(b, [[0.0, 0.0, 1.0]])[0, 0]
+    assert abs(f[0] - np.log(g)) < 1e-12
+    assert abs(f[3] - np.log(ZZ_BETA * ZZ_PHI * ZZ_W / np.sqrt(2) + feat.EPS)) < 1e-10
+    assert abs(f[6] - g * ZZ_PHI / np.sqrt(2)) < 1e-10
+    assert abs(f[7] - g * ZZ_PHI) < 1e-10
+
+
+@pytest.mark.parametrize("periods,spp", [(3, 500), (7, 130)])
+def test_feature_reversal_rate_of_a_zigzag(periods, spp):
+    """With the first sample a third of a step after t = 0, no sample sits on a zero of
+    cos(W t) and every one of the 2 P zeros inside the record falls between two samples:
+    exactly 2 P reversals, so rate = 2 P / (N dt) (per unit time, not per sample) and
+    feature 9 = ln(gamma^2 rate + 1e-6)."""
+    b, dt = _zigzag(periods, spp, t0_frac=1.0 / 3.0)
+    n = periods * spp
+    g = 1 / np.sqrt(1 - ZZ_BETA**2)
+    f = feat.features(b, [[1.0, 0.0, 0.0]])[0, 0]
+    rate = 2 * periods / (n * dt)
+    assert abs(f[8] / rate - 1) < 1e-13
+    assert abs(f[9] - np.log(g * g * rate + 1e-6)) < 1e-12
+    # circular motion never reverses the force (consecutive accelerations turn by w0 dt)
+    c = feat.features(orbits.circular(3.0, 1.0, 800, 0.01), [[1.0, 0.0, 0.0]])[0, 0]
+    assert c[8] == 0.0 and c[9] == np.log(1e-6)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.05, 0.4, 1.3, np.pi - 0.2])
+def test_feature_observer_angle_to_the_mean_beam(alpha):
+    """Feature 12 is gamma times the angle between n and the mean beam direction (x here),
+    not a mean of the angles between n and the instantaneous velocity: with n tilted by
+    alpha out of the plane of the swing it is gamma alpha exactly, while the velocity itself
+    is never at angle alpha from n except at the zero crossings of phi."""
+    b, _ = _zigzag(periods=4, spp=400, t0_frac=0.0)
+    g = 1 / np.sqrt(1 - ZZ_BETA**2)
+    n = [np.cos(alpha), 0.0, np.sin(alpha)]
+    f = feat.features(b, [n])[0, 0]
+    assert abs(f[12] - g * alpha) < 1e-10
+    # straight motion: the mean direction is the velocity itself
+    s = feat.features(orbits.straight([0.6 * np.cos(0.7), 0.6 * np.sin(0.7), 0.0], [0, 0, 0], 20, 0.1),
+                      [[1.0, 0.0, 0.0]])[0, 0]
+    assert abs(s[12] - 1.25 * 0.7) < 1e-12
+
+
+def test_feature_gamma_spread_of_a_two_speed_record():
+    """Feature 1 (std / mean of gamma) of a record spending equal numbers of samples at
+    gamma1 and gamma2 is |gamma2 - gamma1| / (gamma2 + gamma1)."""
+    n = 200
+    beta = np.zeros((n, 3))
+    beta[: n // 2, 0] = 0.6   # gamma 1.25
+    beta[n // 2:, 0] = 0.8    # gamma 5/3
+    bdot = np.zeros((n, 3))
+    bdot[:, 1] = 0.01
+    f = feat.features_one(beta, bdot, 0.05, [0.0, 1.0, 0.0])
+    g1, g2 = 1.25, 5.0 / 3.0
+    assert abs(f[1] - (g2 - g1) / (g2 + g1)) < 1e-13
+    assert abs(f[0] - np.log(0.5 * (g1 + g2))) < 1e-13

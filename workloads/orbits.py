@@ -80,6 +80,36 @@ def gaussian_oscillator(amp, omega0, sigma, beta_d, n, dt, t0=None, charge=-1.0,
                            t0=t0, dt=dt, charge=charge, weight=weight, accel_dtype=accel_dtype)
 
 
+def zigzag(beta0, phi_m, big_omega, n, dt, t0=0.0, charge=-1.0, weight=1.0,
+           accel_dtype=np.float64):
+    """Constant speed beta0 with a velocity direction that swings in the x-y plane.
+
+    beta = beta0 (cos phi, sin phi, 0), phi = phi_m sin(W t) (W = big_omega), so gamma is
+    constant and d(beta)/dt = beta0 phi' (-sin phi, cos phi, 0) is perpendicular to beta.
+    Positions are the exact integrals of beta, from the Bessel expansions
+    cos(a sin x) = J0(a) + 2 sum_k J_2k(a) cos(2k x) and
+    sin(a sin x) = 2 sum_k J_(2k+1)(a) sin((2k+1) x), truncated where the terms
+    fall below 1e-18.
+    """
+    import scipy.special as sp
+
+    t = _times(n, dt, t0)
+    ph = phi_m * np.sin(big_omega * t)
+    dph = phi_m * big_omega * np.cos(big_omega * t)
+    x = beta0 * sp.jv(0, phi_m) * t
+    y = np.zeros(n)
+    for k in range(1, 40):
+        je, jo = sp.jv(2 * k, phi_m), sp.jv(2 * k - 1, phi_m)
+        x = x + beta0 * 2 * je * np.sin(2 * k * big_omega * t) / (2 * k * big_omega)
+        y = y - beta0 * 2 * jo * np.cos((2 * k - 1) * big_omega * t) / ((2 * k - 1) * big_omega)
+        if abs(je) < 1e-18 and abs(jo) < 1e-18:
+            break
+    zero = np.zeros(n)
+    return single_particle(x, y, zero, beta0 * np.cos(ph), beta0 * np.sin(ph), zero,
+                           -beta0 * dph * np.sin(ph), beta0 * dph * np.cos(ph), zero, t0=t0,
+                           dt=dt, charge=charge, weight=weight, accel_dtype=accel_dtype)
+
+
 def rotate(batch, R):
     """Rotate positions, velocities and accelerations of a batch by the 3x3 matrix R."""
     from . import Batch
