@@ -1,23 +1,29 @@
 """Throughput of the radiation spectral synthesis on one MI355X.
 
-Workload: the filamentation-jitter ensemble -- electrons of two gamma0 = 3
-counter-streaming beams (kT = 0.01 rest-frame spread), 4096 Boris samples
-each through a static random-filament field (k^-2 over [0.5, 8], deflection
-parameter 0.3), observed along +x, -x, +y, +z on 1024 log-spaced frequencies
-over [0.1, 1e3] omega_p.  One step = one lw_accumulate over the whole
-1e5-particle ensemble (prepass, accumulation, particle reduction) with its
-trajectories (25 GB) already resident in HBM.
+Headline workload: the mixed-precision form -- particles of the filamentation-
+jitter generator (electrons of two gamma0 = 3 counter-streaming beams, kT = 0.01
+rest-frame spread, Boris-pushed through a static random-filament field, k^-2 over
+[0.5, 8], deflection parameter 0.3), 2048 samples each, seen from 16 directions
+(head-on, 15/30/45 degrees oblique at four azimuths, three perpendicular) on 2048
+log-spaced frequencies over [0.1, 1e3] omega_p.  The full ensemble has 1e6
+particles (6.87e16 terms, 123 GB of trajectories); one step is one lw_accumulate
+over a slice of it (1e5 particles by default) with the trajectories already
+resident in HBM, and the full-ensemble time is extrapolated linearly.
 
 metric: terms/s, a term being one (particle, sample, direction, frequency)
-product of the spectral sum.
+product of the spectral sum.  The headline path is the matrix-core contraction
+with FP16 hi/lo operands; its band-integrated error against the FP64 oracle is
+measured on 8 particles of the same workload.
 
-A second leg measures the learned surrogate on its own workload (one ensemble
-of the same generator, 256 log frequencies): training on 1.25e5 particles'
-exact spectra, then inference on 1e6 particles with the error-head fallback and
-a 1 % held-out judge, against the exact FP32 path on the same particles.
+Legs (each its own JSON object): the FP32 path on the 1e5-particle, 4096-sample,
+4-direction, 1024-frequency jitter ensemble, with coherent, in-situ and coupled
+recording on it; the batched uneven three-species workload (64 directions) with
+per-CU busy spread; the learned surrogate (training on 1.25e5 particles' exact
+spectra, inference on 1e6 particles with fallback and a 1 % held-out judge); and
+the FP64 oracle on the host cores.
 
 Prints one JSON line.  Options: --steps K --warmup W --particles P --paths ...
---no-surrogate.
+--no-surrogate and the other --no-* switches.
 """
 from __future__ import annotations
 
@@ -57,7 +63,7 @@ def spread_width(products):
 
 
 def spread_flops_per_unit(w):
-    """Arithmetic of the spreading step for one (sample, direction, band) with W taps.
+    """Counted arithmetic of the spreading step for one (sample, direction, band) with W taps.
 
     FP32: the W tap weights times the demodulated integrand into 2 polarisations x
     (re, im), 4W FMAs = 8W; the tap weights, W/2 mirrored pairs of degree-8 polynomials in
@@ -66,9 +72,18 @@ def spread_flops_per_unit(w):
     for both polarisations, 35; the demodulation of both by (cos, sin), 4.
     FP64: kappa 6, retarded time 9, the turn fraction of w_c tau 2, the grid coordinate
     and its fraction 4.
-    Sine, cosine and reciprocal are not counted.  Total 17 W + 63 (233 at W = 10).
+    Sine, cosine and reciprocal are not counted.  Total 17 W + 63 (233 at W = 10).  This
+    is instruction work, reported beside the algorithmic figure below.
     """
     return 17 * w + 63
+
+
+# Algorithmic work of the spread per (sample, direction, band): 8 taps x 2 polarisations
+# multiply-adds, 32 FLOP (the figure the roofline's frac uses); the contraction's
+# algorithmic work is one product's multiply-adds, however many hi/lo products run.
+SPREAD_ALGO_FLOPS = 32
+C3_PARTICLES = 1_000_000
+C3_TERMS = C3_PARTICLES * 2048 * 16 * 2048  # the full mixed-precision ensemble: 6.7e13 terms
 
 
 def split_path(name):
@@ -85,22 +100,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--particles", type=int, default=100_000)
-    ap.add_argument("--workload", choices=("jitter", "wide"), default="jitter",
-                    help="jitter: 4096 steps, 4 directions, 1024 frequencies (the benchmark); wide: "
-                         "the mixed-precision form, 2048 steps, 16 directions, 2048 frequencies")
+    ap.add_argument("--workload", choices=("c3", "c2"), default="c3",
+                    help="headline workload: c3 = the mixed-precision form (2048 steps, 16 directions, "
+                         "2048 frequencies; a slice of its 1e6 particles per step); c2 = the jitter "
+                         "ensemble (4096 steps, 4 directions, 1024 frequencies)")
+    ap.add_argument("--particles", type=int, default=0,
+                    help="particles per step of the headline workload (default: all of it, 1e6 for c3 and "
+                         "1e5 for c2)")
+    ap.add_argument("--other-path-steps", type=int, default=3,
+                    help="timed steps of the non-headline paths on the headline workload")
+    ap.add_argument("--fp32-particles", type=int, default=50_000,
+                    help="particles of the headline workload timed on the FP32 path (speedup at equal shape)")
+    ap.add_argument("--c2-particles", type=int, default=100_000, help="particles of the jitter (c2) leg")
+    ap.add_argument("--c2-steps", type=int, default=3, help="timed steps of the FP32 path on the c2 leg")
     ap.add_argument("--chunk", type=int, default=8192, help="particles generated per host chunk")
-    ap.add_argument("--paths", default="fp32,mfma_f16x1,mfma_bf16x3,mfma_f16x3",
-                    help="comma list of fp32, mfma_f16[x3], mfma_bf16[x3]; the last one is the headline")
+    ap.add_argument("--paths", default="mfma_f16x1,mfma_bf16x3,mfma_f16x3",
+                    help="comma list of fp32, mfma_f16[x1|x3], mfma_bf16[x1|x3]; the last one is the headline")
     ap.add_argument("--bands", type=int, default=2,
-                    help="frequency bands of the matrix-core paths (2 measured fastest on the benchmark "
-                         "workload: the upper band keeps the grid, the lower one is 100x coarser)")
+                    help="frequency bands of the matrix-core paths (2 measured fastest on both workloads: "
+                         "the upper band keeps the grid, the lower one is ~9x coarser)")
     ap.add_argument("--tile", type=int, default=0,
                     help="contraction tile: 1 = 128x128, 2 = 256x128, 3 = 128x256, 4 = 256x256 "
                          "(0: library default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-insitu", action="store_true")
@@ -108,8 +134,10 @@ def parse():
     ap.add_argument("--coupled-windows", type=int, default=10)
     ap.add_argument("--coupled-steps", type=int, default=40, help="simulation steps per window")
     ap.add_argument("--windows", type=int, default=4, help="time windows of the in-situ leg")
-    ap.add_argument("--batched-particles", type=int, default=8000,
+    ap.add_argument("--batched-particles", type=int, default=50_000,
                     help="particles of the uneven three-species workload in the batched leg")
+    ap.add_argument("--batched-tune-particles", type=int, default=8000,
+                    help="the first particles of the batched leg the autotuner times its candidates on")
     ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
     ap.add_argument("--surrogate-chunk", type=int, default=100_000)
     ap.add_argument("--surrogate-steps", type=int, default=1500)
@@ -131,7 +159,10 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
     return worst
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md")
+TRAFFIC_PROFILES = {
+    "c2": os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md"),
+    "c3": os.path.join(ROOT, "profiles", "lw_mfma__c3_slice_1e5x2048_16dir_2048w.md"),
+}
 TRAFFIC_FIELDS = {"contraction": "traffic_bytes_per_launch", "spread": "spread_traffic_bytes_per_launch"}
 
 
@@ -145,14 +176,15 @@ def kernel_code_digest(src):
     return hashlib.sha256(re.sub(r"\s+", "", code).encode()).hexdigest()
 
 
-def profiled_traffic(path, tile, particles, workload="jitter", bands=2, kernel="contraction"):
+def profiled_traffic(path, tile, particles, workload="c3", bands=2, kernel="contraction"):
     """HBM bytes per launch of the contraction (or the spreading kernel) from the committed
-    counter profile of this exact configuration (the default launch), or None when the
-    kernel code or the band count differs from the profiled run."""
-    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload != "jitter":
+    counter profile of this exact configuration (the default launch of the workload), or None
+    when there is no such profile or the kernel code or the band count differs from the
+    profiled run."""
+    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload not in TRAFFIC_PROFILES:
         return None
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILES[workload]).read()
         src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip")).read()
     except OSError:
         return None
@@ -165,6 +197,10 @@ def profiled_traffic(path, tile, particles, workload="jitter", bands=2, kernel="
         return None
     value = fields.get(TRAFFIC_FIELDS[kernel])
     return float(value) if value is not None else None
+
+
+def SPREAD_KERNEL(w):
+    return f"lw_spread_kernel<{w}>"
 
 
 TILE_KERNELS = {0: "lw_dft_mfma_r128_kernel<WN=4, MI=4, NJ=2> (256 x 256 tiles, eight waves)",
@@ -207,23 +243,32 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
                            "counted_tflops": 8 * ach / 1e12,
                            "frac_of_fp32_vector_peak": 8 * ach / 1e12 / PEAK_FP32_VECTOR_TFLOPS}
     else:
-        ach = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
+        # the library counts each product's multiply-adds; one product is the useful work
+        executed = prof["gemm_flops"] / (prof["gemm_ms"] * 1e-3) / 1e12
+        ach = executed / products
         peak = PEAK_MFMA_TFLOPS
         contraction = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                        "frac": ach / peak, "traffic": None, "kernel": TILE_KERNELS[tile],
                        "avg_launch_ms": prof["gemm_ms"] / max(prof["gemm_launches"], 1),
-                       "launches_per_step": prof["gemm_launches"] / steps}
+                       "launches_per_step": prof["gemm_launches"] / steps,
+                       "products": products, "executed_tflops": executed,
+                       "executed_frac": executed / peak}
         # every band spreads every sample once per direction (the plan holds 1 to 16 bands,
         # at most one per frequency)
         w = spread_width(products)
         nb = max(1, min(bands, 16, ctx.nw))
         units = float(batch.n_samples_host) * ctx.nd * nb * steps
-        ach = units * spread_flops_per_unit(w) / (prof["spread_ms"] * 1e-3) / 1e12
+        sec = prof["spread_ms"] * 1e-3
+        ach = units * SPREAD_ALGO_FLOPS / sec / 1e12
+        counted = units * spread_flops_per_unit(w) / sec / 1e12
         spread = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                  "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": f"lw_spread_kernel<{w}>",
+                  "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": SPREAD_KERNEL(w),
                   "avg_launch_ms": prof["spread_ms"] / max(prof["spread_launches"], 1),
                   "launches_per_step": prof["spread_launches"] / steps,
-                  "flops_per_sample_direction_band": spread_flops_per_unit(w)}
+                  "algorithmic_flops_per_sample_direction_band": SPREAD_ALGO_FLOPS,
+                  "units_per_step": units / steps,
+                  "counted_flops_per_sample_direction_band": spread_flops_per_unit(w),
+                  "counted_tflops": counted, "counted_frac": counted / PEAK_FP32_VECTOR_TFLOPS}
         res["roofline_contraction"] = contraction
         res["roofline_spread"] = spread
         # the headline roofline is the kernel that takes longer in the step
@@ -231,7 +276,20 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
     return res, S
 
 
-def cpu_baseline(recipe, dirs, om, target_s):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(recipe, dirs, om, target_s, label):
     import oracle
     import workloads
 
@@ -249,8 +307,39 @@ def cpu_baseline(recipe, dirs, om, target_s):
     el = time.perf_counter() - t
     terms = sample.n_samples * len(dirs) * len(om)
     return {"value": terms / el, "unit": "terms/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{n} jitter particles x {sample.n_samples // n} samples x {len(dirs)} dirs x "
+            "cpu_model": cpu_model(), "logical_cpus_visible": os.cpu_count(),
+            "sample": f"{n} particles of the {label} x {sample.n_samples // n} samples x {len(dirs)} dirs x "
                       f"{len(om)} freqs, FP64 libm sin/cos, {el:.1f} s"}
+
+
+def oracle_check(recipe, dirs, om, paths, bands, n_particles=8):
+    """The first particles of the headline workload, generated on the host (the same bytes
+    go to the device): every path's spectrum against the FP64 oracle -- band-integrated
+    error (16 log bands per direction, bands holding >= 1e-4 of the strongest) and the
+    largest per-bin error over bins >= 1e-4 of the direction's peak."""
+    import oracle
+    import workloads
+    from paper_1003_1140_amd import Context, DeviceBatch
+
+    host = workloads.generate(recipe, 0, n_particles)
+    t = time.perf_counter()
+    ref = oracle.spectrum(host, dirs, om, n_species=1)
+    t_oracle = time.perf_counter() - t
+    dev = DeviceBatch.from_host(host)
+    out = {"particles": n_particles, "directions": len(dirs), "frequencies": len(om),
+           "samples": int(host.n_samples), "oracle_seconds": t_oracle}
+    for name in paths:
+        path, products = split_path(name)
+        c = Context(0)
+        c.set_directions(dirs)
+        c.set_frequencies(om)
+        c.set_mfma_options(bands, products, products)
+        c.accumulate(dev, path, workspace=c.workspace(dev, path))
+        S = c.read_spectra()
+        c.close()
+        out[name] = {"band_integrated_err": band_integrated_error(S, ref, om),
+                     "per_bin_max_err": band_relative(S, ref)}
+    return out
 
 
 def upload_ensemble(recipe, n, chunk, dev, host=False):
@@ -506,8 +595,10 @@ def band_relative(S, ref, floor=1e-4):
 
 
 def batched_leg(a, log):
-    """Uneven multi-species workload: plain grid vs persistent launch vs autotuned shape,
-    and a captured graph of the tuned launch (FP32 path), plus the tuned matrix-core path."""
+    """Uneven multi-species workload: plain grid vs persistent launch vs autotuned shape, and
+    a captured graph of the tuned launch (FP32 path), plus the tuned matrix-core path.  The
+    tuner times its candidates on the first particles; the chosen shape then runs the whole
+    slice.  The persistent launch records each compute unit's busy time (load balance)."""
     import torch
 
     from paper_1003_1140_amd import Context, DeviceBatch
@@ -518,6 +609,8 @@ def batched_leg(a, log):
     rec = configs.uneven_recipe()
     t, ns = generate_device(rec, 0, n)
     b = DeviceBatch(t, n)
+    nt = min(n, a.batched_tune_particles)
+    bt = b.head(nt)
     dirs, om = configs.dirs_equal_area(), configs.log_grid(0.1, 1e3, 1024)
     terms = float(ns) * len(dirs) * len(om)
     ctx = Context(0)
@@ -526,7 +619,7 @@ def batched_leg(a, log):
     ctx.set_species(3)
     ctx.set_profiling(True)
 
-    def timed(fn, reps=2):
+    def timed(fn, reps=1):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -535,43 +628,57 @@ def batched_leg(a, log):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps
 
-    out = {"workload": f"{n} particles of the uneven workload (47.5 % e-, 47.5 % e+, 5 % ions of mass 16; "
-                       f"gamma0 2/5/15; lengths U[256, 8192]; {ns} samples), 64 equal-area directions, "
-                       f"1024 log omega in [0.1, 1e3], 3 species", "terms": terms}
+    out = {"workload": f"{n} of the 4e5 particles of the uneven workload (47.5 % e-, 47.5 % e+, 5 % ions of "
+                       f"mass 16; gamma0 2/5/15; lengths U[256, 8192]; {ns} samples), 64 equal-area "
+                       f"directions, 1024 log omega in [0.1, 1e3], 3 species; tuner candidates timed on the "
+                       f"first {nt} particles", "terms": terms}
     ws = ctx.workspace(b, "fp32")
     ctx.set_tuning(persistent=0)
     s_plain = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
-    S_plain = ctx.read_spectra() / 3.0
+    S_plain = ctx.read_spectra() / 2.0
     ctx.reset()
     ctx.set_tuning(persistent=1)
     ctx.plan_batch(b, "fp32")
     s_pers = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
+    busy_default = ctx.profile_cu_busy()
     t0 = time.perf_counter()
-    rep_fp32 = ctx.tune(b, "fp32", repeats=1)
+    rep_fp32 = ctx.tune(bt, "fp32", repeats=1)
     t_tune = time.perf_counter() - t0
+    if rep_fp32["best"].get("persistent"):
+        ctx.plan_batch(b, "fp32")  # the tuned shape, planned for the whole slice
     ws = ctx.workspace(b, "fp32")  # the tuned shape may need a different workspace
     ctx.reset()
     ctx.profile_read()
     s_tuned = timed(lambda: ctx.accumulate(b, "fp32", workspace=ws))
     prof = ctx.profile_read()
-    S_tuned = ctx.read_spectra() / 3.0
+    busy_tuned = ctx.profile_cu_busy() if rep_fp32["best"].get("persistent") else None
+    S_tuned = ctx.read_spectra() / 2.0
     m = S_plain > 1e-4 * S_plain.max(axis=-1, keepdims=True)
     tuned_vs_plain = float(np.max(np.abs(S_tuned - S_plain)[m] / S_plain[m]))
     g = ctx.graph_capture(b, "fp32", workspace=ws)
     s_graph = timed(g.launch)
     g.close()
-    rep_mfma = ctx.tune(b, "mfma_f16", repeats=1)
+    rep_mfma = ctx.tune(bt, "mfma_f16", repeats=1)
     wsm = ctx.workspace(b, "mfma_f16")
+    ctx.reset()
     s_mfma = timed(lambda: ctx.accumulate(b, "mfma_f16", workspace=wsm))
-    ctx.read_spectra()
+    S_mfma = ctx.read_spectra() / 2.0
     out.update({"fp32_plain_grid_terms_per_s": terms / s_plain, "fp32_persistent_terms_per_s": terms / s_pers,
                 "fp32_tuned_terms_per_s": terms / s_tuned, "fp32_tuned_graph_terms_per_s": terms / s_graph,
                 "mfma_f16x3_tuned_terms_per_s": terms / s_mfma, "tuner_seconds_fp32": t_tune,
                 "tuned_fp32": rep_fp32["best"], "tuned_mfma": rep_mfma["best"],
                 "fp32_tuned_kernel_ms": prof["direct_ms"] / max(prof["direct_launches"], 1),
-                "fp32_tuned_vs_plain_max_rel": tuned_vs_plain})
+                "fp32_tuned_vs_plain_max_rel": tuned_vs_plain,
+                "mfma_vs_fp32_band_integrated": band_integrated_error(S_mfma, S_plain, om),
+                "cu_busy_persistent_default": busy_default,
+                "cu_busy_spread_persistent_default": (busy_default["max_ms"] - busy_default["min_ms"])
+                / busy_default["mean_ms"],
+                "cu_busy_persistent_tuned": busy_tuned})
+    if busy_tuned:
+        out["cu_busy_spread_persistent_tuned"] = (busy_tuned["max_ms"] - busy_tuned["min_ms"]) / busy_tuned["mean_ms"]
     log(f"[bench] batched: plain {terms / s_plain:.3e}, persistent {terms / s_pers:.3e}, tuned "
-        f"{terms / s_tuned:.3e}, graph {terms / s_graph:.3e}, mfma {terms / s_mfma:.3e} terms/s")
+        f"{terms / s_tuned:.3e}, graph {terms / s_graph:.3e}, mfma {terms / s_mfma:.3e} terms/s; per-CU busy "
+        f"{busy_default['min_ms']:.1f}..{busy_default['max_ms']:.1f} ms over {busy_default['cus']} CUs")
     return out
 
 
@@ -675,6 +782,64 @@ def surrogate_leg(a, log):
     }
 
 
+def headline_workload(name):
+    from workloads import configs
+
+    if name == "c3":
+        return configs.wide_recipe(), configs.dirs_wide(), configs.log_grid(0.1, 1e3, 2048), 2048
+    return configs.jitter_recipe(), configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024), 4096
+
+
+def time_paths(ctx, batch, paths, steps, warmup, terms_per_step, a, log):
+    results, spectra = {}, {}
+    for path in paths:
+        results[path], spectra[path] = time_path(ctx, batch, path, steps, warmup, terms_per_step,
+                                                 a.bands, a.tile)
+        log(f"[bench] {path}: {results[path]['terms_per_s']:.3e} terms/s")
+    return results, spectra
+
+
+def c2_leg(a, log):
+    """The jitter ensemble (1e5 particles x 4096 samples, 4 directions, 1024 frequencies): the
+    FP32 path's own configuration, the headline matrix-core path on it, and the coherent,
+    in-situ and coupled recording legs."""
+    import torch
+
+    from paper_1003_1140_amd import Context
+
+    dev = torch.device("cuda:0")
+    recipe, dirs, om, steps_per_particle = headline_workload("c2")
+    batch = upload_ensemble(recipe, a.c2_particles, a.chunk, dev, host=a.host_generator)
+    terms = float(batch.n_samples_host) * len(dirs) * len(om)
+    ctx = Context(0)
+    ctx.set_directions(dirs)
+    ctx.set_frequencies(om)
+    ctx.set_profiling(True)
+    if a.tile:
+        ctx.set_tuning(tile=a.tile)
+    out = {"workload": f"filamentation-jitter ensemble: {a.c2_particles} e- of gamma0=3 counter-streaming "
+                       "beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), 1024 log omega in [0.1,1e3]",
+           "terms_per_step": terms}
+    res, spec = time_paths(ctx, batch, ["fp32"], a.c2_steps, 1, terms, a, log)
+    res2, spec2 = time_paths(ctx, batch, ["mfma_f16x3"], max(a.steps, 2), 1, terms, a, log)
+    res.update(res2)
+    spec.update(spec2)
+    res["mfma_f16x3"]["band_integrated_err_vs_fp32"] = band_integrated_error(spec["mfma_f16x3"], spec["fp32"], om)
+    res["mfma_f16x3"]["speedup_vs_fp32"] = res["mfma_f16x3"]["terms_per_s"] / res["fp32"]["terms_per_s"]
+    for kernel in ("contraction", "spread"):
+        res["mfma_f16x3"]["roofline_" + kernel]["traffic"] = profiled_traffic(
+            "mfma_f16x3", a.tile, a.c2_particles, "c2", a.bands, kernel)
+    out["paths"] = res
+    ctx.close()
+    if not a.no_insitu:
+        out["insitu"] = insitu_leg(a, batch, terms, dirs, om, spec["fp32"], log)
+    del batch
+    torch.cuda.empty_cache()
+    if not a.no_coupled:
+        out["coupled"] = coupled_leg(a, dirs, om, log)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -682,9 +847,10 @@ def main():
         sys.exit(2)
     import torch
 
-    import workloads
-    from workloads import configs
-    from paper_1003_1140_amd import Context, DeviceBatch
+    from paper_1003_1140_amd import Context
+
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
@@ -694,17 +860,16 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] copy probe: {n} bytes read and {n} bytes written", file=sys.stderr, flush=True)
+        log(f"[bench] copy probe: {n} bytes read and {n} bytes written")
         del src, dst
-    if a.workload == "wide":
-        recipe, dirs, om = configs.wide_recipe(), configs.dirs_wide(), configs.log_grid(0.1, 1e3, 2048)
-    else:
-        recipe, dirs, om = configs.jitter_recipe(), configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 1024)
+    recipe, dirs, om, n_steps = headline_workload(a.workload)
+    if a.particles <= 0:
+        a.particles = C3_PARTICLES if a.workload == "c3" else 100_000
     t = time.perf_counter()
     batch = upload_ensemble(recipe, a.particles, a.chunk, dev, host=a.host_generator)
     terms_per_step = float(batch.n_samples_host) * len(dirs) * len(om)
-    print(f"[bench] generated and uploaded {a.particles} particles ({batch.n_samples_host} samples) "
-          f"in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    log(f"[bench] generated and uploaded {a.particles} particles ({batch.n_samples_host} samples) "
+        f"in {time.perf_counter() - t:.1f} s")
 
     ctx = Context(0)
     ctx.set_directions(dirs)
@@ -713,23 +878,60 @@ def main():
     if a.tile:
         ctx.set_tuning(tile=a.tile)
     paths = [p for p in a.paths.split(",") if p]
-    results, spectra = {}, {}
-    for path in paths:
-        results[path], spectra[path] = time_path(ctx, batch, path, a.steps, a.warmup, terms_per_step,
-                                                 a.bands, a.tile)
-        print(f"[bench] {path}: {results[path]['terms_per_s']:.3e} terms/s", file=sys.stderr, flush=True)
-    if "fp32" in spectra:
-        for path in paths:
-            if path != "fp32":
-                results[path]["band_integrated_err_vs_fp32"] = band_integrated_error(
-                    spectra[path], spectra["fp32"], om)
     head = paths[-1]
+    results, spectra = {}, {}
+    for path in paths:  # the headline path gets the requested steps, the others a few
+        st, wu = (a.steps, a.warmup) if path == head else (min(a.steps, a.other_path_steps), 1)
+        r_, s_ = time_paths(ctx, batch, [path], st, wu, terms_per_step, a, log)
+        results.update(r_)
+        spectra.update(s_)
     r = results[head]
+    # the FP32 path on the first particles of the same workload: speedup at equal shape, and
+    # every matrix-core path's spectrum on those particles against it
+    fp32_cmp = None
+    if "fp32" not in results and a.fp32_particles > 0:
+        sub = batch.head(min(a.fp32_particles, a.particles))
+        sub.n_samples_host = int(sub.t["offsets"][sub.n_particles].item() - sub.t["offsets"][0].item())
+        terms_sub = float(sub.n_samples_host) * len(dirs) * len(om)
+        rf, sf = time_path(ctx, sub, "fp32", 2, 1, terms_sub, a.bands, a.tile)
+        fp32_cmp = {"particles": sub.n_particles, "terms_per_s": rf["terms_per_s"],
+                    "ms_per_step": rf["ms_per_step"], "roofline": rf["roofline"]}
+        for name in paths:
+            path, products = split_path(name)
+            ctx.set_mfma_options(a.bands, products, products)
+            ctx.reset()
+            ctx.accumulate(sub, path, workspace=ctx.workspace(sub, path))
+            fp32_cmp[name + "_band_integrated_err_vs_fp32"] = band_integrated_error(ctx.read_spectra(), sf, om)
+            results[name]["speedup_vs_fp32_same_workload"] = results[name]["terms_per_s"] / rf["terms_per_s"]
+        log(f"[bench] fp32 on {sub.n_particles} particles of the same workload: {rf['terms_per_s']:.3e} terms/s")
+        del sub
     if "roofline_contraction" in r:
         for kernel in ("contraction", "spread"):
             r["roofline_" + kernel]["traffic"] = profiled_traffic(head, a.tile, a.particles, a.workload,
                                                                   a.bands, kernel)
         r["roofline"] = dict(r["roofline_spread" if r["roofline"]["bound"] == "alu" else "roofline_contraction"])
+    ctx.close()
+    del batch
+    torch.cuda.empty_cache()
+    path_dtype = {"fp32": "f32 (f64 phase)", "mfma_f16": "f16 hi/lo operands, f32 acc",
+                  "mfma_bf16": "bf16 hi/lo operands, f32 acc"}[split_path(head)[0]]
+    if split_path(head)[1] == 1 and head != "fp32":
+        path_dtype = path_dtype.replace(" hi/lo", "")
+    if a.workload == "c3":
+        whole = a.particles == C3_PARTICLES
+        config = {"workload": ("mixed-precision form: " + ("all of its" if whole else f"a slice of {a.particles} of its")
+                               + " 1e6 particles per step, jitter generator (gamma0=3 counter-streaming e- beams, "
+                               "kT=0.01, static random-filament B_y, deflection 0.3), 2048 Boris steps, 16 dirs "
+                               "(head-on, 15/30/45 deg at 4 azimuths, 3 perpendicular), 2048 log omega in [0.1,1e3]"),
+                  "particles_per_step": a.particles, "full_ensemble_particles": C3_PARTICLES,
+                  "samples_per_particle": 2048, "directions": len(dirs), "frequencies": 2048,
+                  "path": head, "bands": a.bands}
+    else:
+        config = {"workload": f"filamentation-jitter ensemble: {a.particles} e- of gamma0=3 counter-streaming "
+                              "beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), 1024 log omega in [0.1,1e3]; "
+                              "1 step = the whole ensemble",
+                  "particles": a.particles, "samples_per_particle": 4096, "directions": 4,
+                  "frequencies": 1024, "path": head, "bands": a.bands}
     out = {
         "metric": "LW spectral terms/s (particle x step x omega x n)",
         "value": r["terms_per_s"],
@@ -741,43 +943,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32 (f64 phase)", "mfma_f16": "f16 / f32 acc",
-                  "mfma_bf16": "bf16 / f32 acc"}[split_path(head)[0]] + " x%d" % split_path(head)[1],
+        "dtype": path_dtype,
         "data": "synthetic",
-        "config": ({"workload": f"filamentation-jitter ensemble: {a.particles} e- of gamma0=3 "
-                                "counter-streaming beams, 4096 Boris steps, 4 dirs (+x,-x,+y,+z), "
-                                "1024 log omega in [0.1,1e3]; 1 step = the whole ensemble",
-                    "particles": a.particles, "samples_per_particle": 4096, "directions": 4,
-                    "frequencies": 1024, "path": head, "bands": a.bands} if a.workload == "jitter" else
-                   {"workload": f"mixed-precision form: {a.particles} particles of the jitter generator, "
-                                "2048 Boris steps, 16 dirs (head-on, 15/30/45 deg, perpendicular), 2048 log "
-                                "omega in [0.1,1e3]; 1 step = the whole ensemble",
-                    "particles": a.particles, "samples_per_particle": 2048, "directions": len(dirs),
-                    "frequencies": 2048, "path": head, "bands": a.bands}),
+        "config": config,
         "roofline": r["roofline"],
         **({"roofline_contraction": r["roofline_contraction"], "roofline_spread": r["roofline_spread"]}
            if "roofline_contraction" in r else {}),
         "paths": results,
     }
-    if not a.no_insitu and "fp32" in spectra:
-        out["insitu"] = insitu_leg(a, batch, terms_per_step, dirs, om, spectra["fp32"],
-                                   lambda m: print(m, file=sys.stderr, flush=True))
-    del batch
-    torch.cuda.empty_cache()
-    if not a.no_coupled:
-        out["coupled"] = coupled_leg(a, dirs, om, lambda m: print(m, file=sys.stderr, flush=True))
+    if a.workload == "c3":
+        out["full_c3_seconds"] = C3_TERMS / r["terms_per_s"]
+    if fp32_cmp is not None:
+        out["fp32_same_workload"] = fp32_cmp
+    if not a.no_oracle_check:
+        out["oracle_check"] = oracle_check(recipe, dirs, om, ["fp32"] + [p for p in paths if p != "fp32"], a.bands)
+        log(f"[bench] oracle check on 8 particles: " + ", ".join(
+            f"{k} {v['band_integrated_err']:.2e}" for k, v in out["oracle_check"].items() if isinstance(v, dict)))
+    if not a.no_c2 and a.workload == "c3":
+        out["c2"] = c2_leg(a, log)
+        torch.cuda.empty_cache()
     if not a.no_batched:
-        out["batched"] = batched_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
+        out["batched"] = batched_leg(a, log)
         torch.cuda.empty_cache()
     if not a.no_surrogate:
         torch.cuda.empty_cache()
-        out["surrogate"] = surrogate_leg(a, lambda m: print(m, file=sys.stderr, flush=True))
-        print(f"[bench] surrogate: {out['surrogate']['equivalent_terms_per_s']:.3e} equivalent terms/s, "
-              f"gain {out['surrogate']['gain_vs_exact']:.2f}x over exact FP32, "
-              f"{out['surrogate']['gain_vs_exact_mfma']:.2f}x over exact MFMA", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_leg(a, log)
+        log(f"[bench] surrogate: {out['surrogate']['equivalent_terms_per_s']:.3e} equivalent terms/s, "
+            f"gain {out['surrogate']['gain_vs_exact']:.2f}x over exact FP32, "
+            f"{out['surrogate']['gain_vs_exact_mfma']:.2f}x over exact MFMA")
     if not a.no_cpu_baseline:
-        print("[bench] running CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(recipe, dirs, om, a.cpu_seconds)
+        log("[bench] running CPU oracle baseline")
+        label = "mixed-precision form" if a.workload == "c3" else "jitter ensemble"
+        out["cpu_baseline"] = cpu_baseline(recipe, dirs, om, a.cpu_seconds, label)
     print(json.dumps(out), flush=True)
 
 

@@ -60,14 +60,27 @@ typedef enum {
  *     contraction on the matrix cores -- each particle's integrand is spread
  *     onto a uniform retarded-time grid per frequency band, contracted with
  *     a shared table of phase factors e^{i w q h} in FP16 (BF16), FP32
- *     accumulation, then deconvolved (see lw_set_mfma_options). */
-typedef enum { LW_PATH_FP32 = 0, LW_PATH_MFMA_F16 = 1, LW_PATH_MFMA_BF16 = 2 } lw_path;
+ *     accumulation, then deconvolved (see lw_set_mfma_options).
+ *   LW_PATH_AUTO: the library picks one of the above per call: the FP16
+ *     matrix-core path (hi/lo operands unless lw_set_mfma_options chose one
+ *     product) when no per-particle output is asked for and the frequency
+ *     list has at least LW_AUTO_MIN_FREQUENCIES points (where that path
+ *     measured faster than the FP32 path), the FP32 path otherwise.  Each of
+ *     the two keeps its own stated error. */
+typedef enum { LW_PATH_FP32 = 0, LW_PATH_MFMA_F16 = 1, LW_PATH_MFMA_BF16 = 2, LW_PATH_AUTO = 3 } lw_path;
+#define LW_AUTO_MIN_FREQUENCIES 256
 
 /* Particle batch (structure of arrays, device pointers, borrowed).
  * Particle p owns samples offsets[p] .. offsets[p+1]-1 (offsets non-decreasing,
- * offsets[0] may be > 0); sample k of particle p is at time t0[p] + k*dt[p].
- * beta = (bx,by,bz) = v/c, betadot = (ax,ay,az) = d(beta)/dt, r = (x,y,z).
- * species may be NULL (all particles in species 0). */
+ * offsets[0] may be > 0, every offset within the sample arrays); sample k of
+ * particle p is at time t0[p] + k*dt[p].  beta = (bx,by,bz) = v/c,
+ * betadot = (ax,ay,az) = d(beta)/dt, r = (x,y,z).  species may be NULL (all
+ * particles in species 0).  flags: 0, or LW_BATCH_F64_ACCEL when ax, ay, az
+ * point to double arrays (they are then read as FP64; the FP32 path keeps the
+ * integrand in FP64 up to its final rounding).  A particle whose offsets
+ * decrease is a data error (recorded like |beta| >= 1; it adds nothing); the
+ * sample arrays are not bounds-checked. */
+#define LW_BATCH_F64_ACCEL 1u
 typedef struct {
   int64_t n_particles;
   const int64_t* offsets; /* [n_particles + 1] */
@@ -78,6 +91,7 @@ typedef struct {
   const float *charge;    /* [n_particles] q_p in units of e */
   const float *weight;    /* [n_particles] w_p (macro-particle weight) */
   const int32_t* species; /* [n_particles] or NULL */
+  uint32_t flags;         /* 0 or LW_BATCH_F64_ACCEL */
 } lw_batch;
 
 typedef struct lw_ctx lw_ctx;
@@ -118,18 +132,26 @@ lw_status lw_set_mfma_options(lw_ctx* ctx, int32_t bands, int32_t products_f16,
                               int32_t products_bf16);
 
 /* Device workspace (bytes) lw_accumulate needs for this batch and path.  For
- * the matrix-core paths this call reads the batch on the device to size the
- * retarded-time grids (it synchronises the stream) and prepares the phase
- * tables; lw_accumulate repeats the check and enlarges the tables if a
- * later batch needs more. */
+ * the matrix-core paths this call plans the batch: it reads the batch on the
+ * device to size the retarded-time grids (it synchronises the stream),
+ * prepares the phase tables (with 25 % headroom in span) and remembers the
+ * batch (its offsets pointer and particle count) as planned, as
+ * lw_plan_batch does.  LW_PATH_AUTO sizes the path lw_accumulate would pick. */
 lw_status lw_workspace_size(lw_ctx* ctx, const lw_batch* batch, lw_path path, size_t* bytes);
 
-/* Add the batch's spectrum into S (asynchronous for the FP32 path; the
- * matrix-core paths synchronise once to size their grids).  workspace: device memory
- * of at least lw_workspace_size bytes, 256-byte aligned.  per_particle: NULL
- * or device float [n_particles][nd][nw] receiving each particle's own
- * w_p q_p^2 |A_p|^2 / (4 pi^2) (FP32 path only; LW_EUNSUPPORTED otherwise).  Host-side checks (sizes, NULL pointers,
- * workspace size and alignment) fail before any launch. */
+/* Add the batch's spectrum into S.  Asynchronous and stream-ordered: the FP32
+ * path never synchronises; the matrix-core paths do not for a planned batch
+ * (the last batch lw_workspace_size or lw_plan_batch saw, identified by its
+ * offsets pointer and particle count, on the same grids and options), whose
+ * samples are checked against the plan on the device instead: a particle whose
+ * retarded-time span outgrew the plan is recorded, and the next lw_read_spectra
+ * (or lw_read_amplitudes) returns LW_ESTATE naming it -- plan the batch again and
+ * redo the call.  Any other batch is planned first, which synchronises once.
+ * workspace: device memory of at least lw_workspace_size bytes, 256-byte aligned.
+ * per_particle: NULL or device float [n_particles][nd][nw] receiving each
+ * particle's own w_p q_p^2 |A_p|^2 / (4 pi^2) (FP32 path only; LW_EUNSUPPORTED
+ * otherwise).  Host-side checks (sizes, NULL pointers, flags, workspace size and
+ * alignment) fail before any launch. */
 lw_status lw_accumulate(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
                         size_t workspace_bytes, float* per_particle);
 
@@ -141,6 +163,19 @@ lw_status lw_read_spectra(lw_ctx* ctx, double* host_out);
 lw_status lw_reset(lw_ctx* ctx);
 /* Replace S with host_in [n_species][nd][nw] (resume from a saved state). */
 lw_status lw_load_accumulator(lw_ctx* ctx, const double* host_in);
+/* Periodic recording (Section 2.2 records the accumulated spectra as the run
+ * goes): write the accumulator to the file at `path` -- a 64-byte header
+ * ("LWACC001", species, directions, frequencies, coherent flag, payload length,
+ * FNV-1a 64 checksum of everything after the header), the directions [nd][3]
+ * and frequencies [nw] (FP64), then S [n_species][nd][nw] (incoherent) or A_s
+ * [n_species][nd][nw][4] (coherent), little-endian FP64.  Synchronises; does
+ * not report device data errors (lw_read_spectra does). */
+lw_status lw_save_accumulator(lw_ctx* ctx, const char* path);
+/* Resume from such a file: the context's species count, directions,
+ * frequencies and mode must equal the file's (bitwise for the grids), else
+ * LW_EINVAL; a short or corrupted file (checksum) is LW_EINVAL and leaves the
+ * accumulator unchanged.  Synchronises. */
+lw_status lw_load_accumulator_file(lw_ctx* ctx, const char* path);
 
 /* ---- coherent synthesis and in-situ recording (Section 2.2, recording scheme) ----
  * The observed power is the squared modulus of the time integral of the summed
@@ -360,6 +395,16 @@ lw_status lw_mlp_train_step(lw_mlp* net, const float* x, const float* t, int64_t
 /* One AdamW step of the error head towards err_target [rows] (main net frozen). */
 lw_status lw_mlp_train_head_step(lw_mlp* net, const float* x, const float* err_target, int64_t rows,
                                  float lr, double* loss);
+/* Write the network to `path`: a header ("LWMLP001", n_in, hidden, n_hidden, n_out,
+ * parameter count, FNV-1a 64 checksum of what follows), then FP32 master
+ * parameters, error-head parameters, AdamW first and second moments of both and
+ * their step counts, the input normalisation (flag, shift, scale) and the output
+ * skip (index, coefficient): everything a later process needs to infer or to
+ * continue training.  Synchronises. */
+lw_status lw_mlp_save(lw_mlp* net, const char* path);
+/* Restore such a file into a network of the same shape (LW_EINVAL otherwise, or on
+ * a short or corrupted file, leaving the network unchanged). */
+lw_status lw_mlp_load(lw_mlp* net, const char* path);
 
 /* Kernel timing with HIP events recorded on the context's stream around each
  * accumulation kernel launch (enable != 0 turns it on; off by default). */
@@ -370,6 +415,13 @@ lw_status lw_set_profiling(lw_ctx* ctx, int32_t enable);
  * length per particle, direction and band, times the number of products),
  * FP32 kernel launches, contraction kernel launches, spreading kernel launches}. */
 lw_status lw_profile_read(lw_ctx* ctx, double* host_out);
+
+/* Load balance of the last persistent FP32 launch made with profiling on (lw_plan_batch
+ * plan in use): each work-group records the compute unit it ran on (XCC and hardware ids)
+ * and its start and end on the device's real-time counter; a compute unit's busy time is
+ * the sum over its work-groups of (end - start).  Synchronises.  host_out[4] = {compute
+ * units seen, min, mean, max busy ms}.  LW_ESTATE if no such launch was made. */
+lw_status lw_profile_cu_busy(lw_ctx* ctx, double* host_out);
 
 /* Number of successful lw_accumulate calls since creation. */
 lw_status lw_stats(const lw_ctx* ctx, int64_t* calls);

@@ -109,6 +109,7 @@ lw_status check_batch(lw_ctx* c, const lw_batch* b) {
                          "t0", "dt", "charge", "weight"};
   for (int i = 0; i < 14; ++i)
     if (!need[i]) return fail(c, LW_EINVAL, "batch.%s is NULL", names[i]);
+  if (b->flags & ~LW_BATCH_F64_ACCEL) return fail(c, LW_EINVAL, "unknown batch flags 0x%x", b->flags);
   return LW_OK;
 }
 
@@ -120,6 +121,28 @@ lw_status check_grids(lw_ctx* c) {
 
 using lw::DirectShape;
 using lw::direct_shape;
+
+// Wait for the stream, then turn the device's records into a status: a batch that outgrew
+// the matrix-core plan first (its result is incomplete), then bad data.
+lw_status read_device_errors(lw_ctx* c) {
+  unsigned long long e[2] = {kNoError, kNoError};
+  LW_HIP(hipMemcpyAsync(e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy error records");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  if (e[1] != kNoError)
+    return fail(c, LW_ESTATE,
+                "particle %llu: retarded-time span outgrew the matrix-core plan (plan the batch again with "
+                "lw_workspace_size or lw_plan_batch and redo the accumulation)", e[1]);
+  if (e[0] != kNoError)
+    return fail(c, LW_ERANGE, "particle %llu has |beta| >= 1, a non-finite sample or decreasing offsets", e[0]);
+  return LW_OK;
+}
+
+// LW_PATH_AUTO: the matrix-core FP16 path where it measured faster (long frequency lists) and
+// can serve the call (no per-particle output), else the FP32 path.
+lw_path resolve_path(const lw_ctx* c, lw_path path, bool per_particle) {
+  if (path != LW_PATH_AUTO) return path;
+  return (!per_particle && c->nw >= LW_AUTO_MIN_FREQUENCIES) ? LW_PATH_MFMA_F16 : LW_PATH_FP32;
+}
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
@@ -167,11 +190,12 @@ lw_status lw_create(lw_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = (hipStream_t)stream;
   DeviceGuard g(device);
-  if (hipMalloc(&c->d_err, sizeof(unsigned long long)) != hipSuccess) {
+  if (hipMalloc(&c->d_err, 2 * sizeof(unsigned long long)) != hipSuccess) {
     delete c;
     return LW_ENOMEM;
   }
-  if (lw::launch_fill_u64(c->d_err, 1, kNoError, c->stream) != hipSuccess) {
+  c->d_overflow = c->d_err + 1;  // one allocation: both records are cleared and read together
+  if (lw::launch_fill_u64(c->d_err, 2, kNoError, c->stream) != hipSuccess) {
     (void)hipFree(c->d_err);
     delete c;
     return LW_EDEVICE;
@@ -189,6 +213,7 @@ void lw_destroy(lw_ctx* c) {
   free_dev(c->plan.d_perm);
   free_dev(c->plan.d_order);
   free_dev(c->d_ticket);
+  free_dev(c->d_wgtime);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   free_dev(c->d_flops);
   free_dev(c->d_dirs);
@@ -293,6 +318,7 @@ lw_status lw_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* 
   if (!c || !bytes) return LW_EINVAL;
   lw_status st = check_grids(c);
   if (st != LW_OK) return st;
+  path = resolve_path(c, path, false);
   if (!b || b->n_particles < 0) return fail(c, LW_EINVAL, "bad batch");
   *bytes = 0;
   if (path == LW_PATH_FP32) {
@@ -316,8 +342,14 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
   st = check_batch(c, b);
   if (st != LW_OK) return st;
   if (b->n_particles == 0) return LW_OK;
+  path = resolve_path(c, path, per_particle != nullptr);
   size_t need = 0;
-  st = lw_workspace_size(c, b, path, &need);
+  if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
+    DeviceGuard g0(c->device);
+    st = lw::mfma_workspace_need(c, b, path, &need);  // no synchronisation for a planned batch
+  } else {
+    st = lw_workspace_size(c, b, path, &need);
+  }
   if (st != LW_OK) return st;
   if (need > 0 && (!ws || ws_bytes < need))
     return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
@@ -326,8 +358,7 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
   if (path == LW_PATH_FP32) {
     DirectShape s = direct_shape(c, b->n_particles);
     lw::DirectArgs a;
-    a.b = {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
-           b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+    a.b = lw::view_of(b);
     a.dirs = c->d_dirs;
     a.wturn = c->d_wturn;
     a.nd = c->nd;
@@ -356,6 +387,17 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
       a.order = pl.d_order;
       a.ticket = c->d_ticket;
       a.n_items = pl.n_items;
+      if (c->prof && !c->capturing) {
+        if (c->wgtime_cap < pl.workgroups) {
+          free_dev(c->d_wgtime);
+          c->wgtime_cap = 0;
+          LW_HIP(hipMalloc(&c->d_wgtime, 3 * sizeof(unsigned long long) * (size_t)pl.workgroups),
+                 "hipMalloc(work-group timing)");
+          c->wgtime_cap = pl.workgroups;
+        }
+        a.wg_time = c->d_wgtime;
+        c->wgtime_n = pl.workgroups;
+      }
       LW_HIP(lw::launch_fill_u32(c->d_ticket, 1, 0u, c->stream), "reset ticket");
       LW_HIP(lw::launch_direct_f32_persistent(a, s.wpt, pl.workgroups, c->stream),
              "launch lw_direct_f32 (persistent)");
@@ -383,15 +425,10 @@ lw_status lw_read_spectra(lw_ctx* c, double* out) {
   if (st != LW_OK) return st;
   DeviceGuard g(c->device);
   size_t n = (size_t)c->ns * c->nd * c->nw;
-  unsigned long long e = kNoError;
   if (c->coherent)
     LW_HIP(lw::launch_coherent_power(c->d_A, (int64_t)n, c->d_S, c->stream), "launch coherent power");
   LW_HIP(hipMemcpyAsync(out, c->d_S, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy S");
-  LW_HIP(hipMemcpyAsync(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy err");
-  LW_HIP(hipStreamSynchronize(c->stream), "sync");
-  if (e != kNoError)
-    return fail(c, LW_ERANGE, "particle %llu has |beta| >= 1 or a non-finite sample", e);
-  return LW_OK;
+  return read_device_errors(c);
 }
 
 lw_status lw_reset(lw_ctx* c) {
@@ -401,7 +438,7 @@ lw_status lw_reset(lw_ctx* c) {
     LW_HIP(lw::launch_fill_f64(c->d_S, (int64_t)c->ns * c->nd * c->nw, 0.0, c->stream), "zero S");
   if (c->d_A)
     LW_HIP(lw::launch_fill_f64(c->d_A, (int64_t)4 * c->ns * c->nd * c->nw, 0.0, c->stream), "zero A");
-  LW_HIP(lw::launch_fill_u64(c->d_err, 1, kNoError, c->stream), "reset error");
+  LW_HIP(lw::launch_fill_u64(c->d_err, 2, kNoError, c->stream), "reset error records");
   return LW_OK;
 }
 
@@ -414,6 +451,61 @@ lw_status lw_load_accumulator(lw_ctx* c, const double* in) {
   DeviceGuard g(c->device);
   size_t n = (size_t)c->ns * c->nd * c->nw;
   LW_HIP(hipMemcpyAsync(c->d_S, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "load S");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  return LW_OK;
+}
+
+lw_status lw_save_accumulator(lw_ctx* c, const char* path) {
+  if (!c || !path) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  const size_t n = (size_t)c->ns * c->nd * c->nw * (c->coherent ? 4 : 1);
+  std::vector<double> acc(n);
+  LW_HIP(hipMemcpyAsync(acc.data(), c->coherent ? c->d_A : c->d_S, n * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream),
+         "copy accumulator");
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  lw::Bytes b;
+  for (int d = 0; d < c->nd; ++d) b.put(&c->h_dirs[(size_t)lw::kDirStride * d], 3 * sizeof(double));
+  b.put(c->h_omega.data(), c->nw * sizeof(double));
+  b.put(acc.data(), n * sizeof(double));
+  const int64_t f[5] = {c->ns, c->nd, c->nw, c->coherent ? 1 : 0, 0};
+  if (!lw::write_lw_file(path, "LWACC001", f, b)) return fail(c, LW_EINVAL, "cannot write %s", path);
+  return LW_OK;
+}
+
+lw_status lw_load_accumulator_file(lw_ctx* c, const char* path) {
+  if (!c || !path) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  lw::FileHeader h;
+  lw::Bytes b;
+  std::string why;
+  if (!lw::read_lw_file(path, "LWACC001", &h, &b, &why)) return fail(c, LW_EINVAL, "%s: %s", path, why.c_str());
+  if (h.f[0] != c->ns || h.f[1] != c->nd || h.f[2] != c->nw || h.f[3] != (c->coherent ? 1 : 0))
+    return fail(c, LW_EINVAL, "%s holds %lld species x %lld directions x %lld frequencies (%s), the context "
+                "%d x %d x %d (%s)", path, (long long)h.f[0], (long long)h.f[1], (long long)h.f[2],
+                h.f[3] ? "coherent" : "incoherent", c->ns, c->nd, c->nw, c->coherent ? "coherent" : "incoherent");
+  const size_t n = (size_t)c->ns * c->nd * c->nw * (c->coherent ? 4 : 1);
+  if (b.v.size() != (3 * (size_t)c->nd + c->nw + n) * sizeof(double))
+    return fail(c, LW_EINVAL, "%s: payload length does not match its header", path);
+  for (int d = 0; d < c->nd; ++d) {
+    double nv[3];
+    b.get(nv, sizeof(nv));
+    if (memcmp(nv, &c->h_dirs[(size_t)lw::kDirStride * d], sizeof(nv)) != 0)
+      return fail(c, LW_EINVAL, "%s: direction %d differs from the context's", path, d);
+  }
+  std::vector<double> om(c->nw);
+  b.get(om.data(), c->nw * sizeof(double));
+  if (memcmp(om.data(), c->h_omega.data(), c->nw * sizeof(double)) != 0)
+    return fail(c, LW_EINVAL, "%s: frequencies differ from the context's", path);
+  std::vector<double> acc(n);
+  b.get(acc.data(), n * sizeof(double));
+  DeviceGuard g(c->device);
+  LW_HIP(hipMemcpyAsync(c->coherent ? c->d_A : c->d_S, acc.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                        c->stream),
+         "load accumulator");
   LW_HIP(hipStreamSynchronize(c->stream), "sync");
   return LW_OK;
 }
@@ -465,6 +557,42 @@ lw_status lw_profile_read(lw_ctx* c, double* out) {
   return LW_OK;
 }
 
+lw_status lw_profile_cu_busy(lw_ctx* c, double* out) {
+  if (!c || !out) return LW_EINVAL;
+  if (c->wgtime_n <= 0 || !c->d_wgtime)
+    return fail(c, LW_ESTATE, "no persistent FP32 launch was made with profiling on");
+  DeviceGuard g(c->device);
+  std::vector<unsigned long long> h(3 * (size_t)c->wgtime_n);
+  LW_HIP(hipStreamSynchronize(c->stream), "sync");
+  LW_HIP(hipMemcpy(h.data(), c->d_wgtime, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost),
+         "copy work-group timing");
+  int khz = 0;
+  LW_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device), "wall clock rate");
+  if (khz <= 0) return fail(c, LW_EDEVICE, "device reports no wall clock rate");
+  std::vector<double> busy(1u << 12, 0.0);
+  std::vector<char> seen(1u << 12, 0);
+  for (int w = 0; w < c->wgtime_n; ++w) {
+    const unsigned key = (unsigned)(h[3 * w] & 0xfffu);
+    const unsigned long long t0 = h[3 * w + 1], t1 = h[3 * w + 2];
+    busy[key] += t1 > t0 ? (double)(t1 - t0) : 0.0;
+    seen[key] = 1;
+  }
+  double n = 0, lo = 0, hi = 0, sum = 0;
+  for (size_t k = 0; k < busy.size(); ++k) {
+    if (!seen[k]) continue;
+    const double ms = busy[k] / (double)khz;
+    lo = n == 0 ? ms : std::min(lo, ms);
+    hi = n == 0 ? ms : std::max(hi, ms);
+    sum += ms;
+    n += 1;
+  }
+  out[0] = n;
+  out[1] = lo;
+  out[2] = n > 0 ? sum / n : 0.0;
+  out[3] = hi;
+  return LW_OK;
+}
+
 lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   if (!c) return LW_EINVAL;
   lw_status st = check_grids(c);
@@ -472,6 +600,7 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   st = check_batch(c, b);
   if (st != LW_OK) return st;
   DeviceGuard g(c->device);
+  path = resolve_path(c, path, false);
   if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
     size_t bytes = 0;
     return lw::mfma_workspace_size(c, b, path, &bytes);  // sizes the grids and phase tables
@@ -562,8 +691,8 @@ lw_status lw_accumulate_subset(lw_ctx* c, const lw_batch* b, const int64_t* indi
   DeviceGuard g(c->device);
   lw::DirectArgs a;
   // the kernel walks n_idx positions and maps each through the index list
-  a.b = {n_idx,  b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
-         b->ax,  b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  a.b = lw::view_of(b);
+  a.b.n_particles = n_idx;
   a.dirs = c->d_dirs;
   a.wturn = c->d_wturn;
   a.nd = c->nd;
@@ -618,6 +747,7 @@ lw_status lw_graph_capture(lw_ctx* c, const lw_batch* b, lw_path path, void* ws,
   st = check_batch(c, b);
   if (st != LW_OK) return st;
   DeviceGuard g(c->device);
+  path = resolve_path(c, path, false);
   if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
     size_t bytes = 0;
     st = lw::mfma_workspace_size(c, b, path, &bytes);  // plan the grids outside the capture
@@ -708,13 +838,8 @@ lw_status lw_read_amplitudes(lw_ctx* c, double* out) {
   if (!c->coherent) return fail(c, LW_ESTATE, "amplitudes are kept in coherent synthesis only");
   DeviceGuard g(c->device);
   size_t n = (size_t)4 * c->ns * c->nd * c->nw;
-  unsigned long long e = kNoError;
   LW_HIP(hipMemcpyAsync(out, c->d_A, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy A");
-  LW_HIP(hipMemcpyAsync(&e, c->d_err, sizeof(e), hipMemcpyDeviceToHost, c->stream), "copy err");
-  LW_HIP(hipStreamSynchronize(c->stream), "sync");
-  if (e != kNoError)
-    return fail(c, LW_ERANGE, "particle %llu has |beta| >= 1 or a non-finite sample", e);
-  return LW_OK;
+  return read_device_errors(c);
 }
 
 lw_status lw_load_amplitudes(lw_ctx* c, const double* in) {
@@ -740,9 +865,10 @@ lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, lw_path path, v
   if (!amp) return fail(c, LW_EINVAL, "amplitude state is NULL");
   if (((uintptr_t)amp & 15) != 0) return fail(c, LW_EINVAL, "amplitude state must be 16-byte aligned");
   DeviceGuard g(c->device);
+  path = resolve_path(c, path, false);
   if (path == LW_PATH_MFMA_F16 || path == LW_PATH_MFMA_BF16) {
     size_t need = 0;
-    st = lw_workspace_size(c, b, path, &need);
+    st = lw::mfma_workspace_need(c, b, path, &need);  // no synchronisation for a planned batch
     if (st != LW_OK) return st;
     if (!ws || ws_bytes < need)
       return fail(c, LW_ENOMEM, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
@@ -755,8 +881,7 @@ lw_status lw_accumulate_amplitudes(lw_ctx* c, const lw_batch* b, lw_path path, v
   if (path != LW_PATH_FP32) return fail(c, LW_EINVAL, "unknown path %d", (int)path);
   const DirectShape s = direct_shape(c, b->n_particles);
   lw::DirectArgs a;
-  a.b = {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
-         b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  a.b = lw::view_of(b);
   a.dirs = c->d_dirs;
   a.wturn = c->d_wturn;
   a.nd = c->nd;

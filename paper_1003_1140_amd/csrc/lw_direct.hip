@@ -46,7 +46,8 @@ __device__ __forceinline__ Staged prepass(const BatchView& b, int64_t idx, doubl
                                           const double n[3], const double e1[3],
                                           const double e2[3], bool* bad) {
   const double bx = b.bx[idx], by = b.by[idx], bz = b.bz[idx];
-  const double ax = (double)b.ax[idx], ay = (double)b.ay[idx], az = (double)b.az[idx];
+  double ax, ay, az;
+  load_accel(b, idx, ax, ay, az);
   const double rx = b.x[idx], ry = b.y[idx], rz = b.z[idx];
   const double b2 = bx * bx + by * by + bz * bz;
   const double kappa = 1.0 - (n[0] * bx + n[1] * by + n[2] * bz);
@@ -104,6 +105,10 @@ __device__ __forceinline__ void direct_item(const DirectArgs& a, int64_t item, S
     const int64_t p = a.perm ? a.perm[pi] : pi;
     const int64_t base = a.b.offsets[p];
     const int64_t len = a.b.offsets[p + 1] - base;
+    if (len < 0) {  // decreasing offsets: reported, contributes nothing
+      if (tid == 0) record_error(a.err, p);
+      continue;
+    }
     const double t0 = a.b.t0[p], dtp = a.b.dt[p];
 
     double acc[WPT][4];
@@ -207,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void lw_direct_f32_persistent_kernel(Dire
   __shared__ Staged stage[kThreads];
   __shared__ int64_t s_item;
   extern __shared__ double sacc[];  // [ns][ncomp][WPT][kThreads]
+  const unsigned long long t_start = a.wg_time ? __builtin_amdgcn_s_memrealtime() : 0ull;
   for (;;) {
     __syncthreads();  // the previous item's LDS use is over
     if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.ticket, 1u);
@@ -214,6 +220,15 @@ __global__ __launch_bounds__(kThreads) void lw_direct_f32_persistent_kernel(Dire
     const int64_t i = s_item;
     if (i >= a.n_items) break;
     direct_item<WPT>(a, a.order ? a.order[i] : i, stage, sacc);
+  }
+  if (a.wg_time && threadIdx.x == 0) {
+    // compute unit of this work-group: XCC id, then HW_ID bits 8..15 (CU, shader array, engine)
+    const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_REG_HW_ID, 32 bits
+    const unsigned xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // HW_REG_XCC_ID, 32 bits
+    unsigned long long* r = a.wg_time + 3 * (size_t)blockIdx.x;
+    r[0] = ((unsigned long long)(xcc & 0xfu) << 8) | ((hw >> 8) & 0xffu);
+    r[1] = t_start;
+    r[2] = __builtin_amdgcn_s_memrealtime();
   }
 }
 

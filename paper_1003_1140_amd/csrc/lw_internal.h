@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <string.h>
 
 #include <string>
 #include <vector>
@@ -23,11 +25,40 @@ struct BatchView {
   int64_t n_particles;
   const int64_t* offsets;
   const double *x, *y, *z, *bx, *by, *bz;
-  const float *ax, *ay, *az;
+  const float *ax, *ay, *az;      // FP32 d(beta)/dt, or null when adx.. are set
   const double *t0, *dt;
   const float *charge, *weight;
   const int32_t* species;
+  const double *adx, *ady, *adz;  // FP64 d(beta)/dt (LW_BATCH_F64_ACCEL), or null
 };
+
+// The device view of a caller's batch.
+inline BatchView view_of(const lw_batch* b) {
+  const bool f64 = (b->flags & LW_BATCH_F64_ACCEL) != 0;
+  BatchView v{b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
+              b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species,
+              nullptr,        nullptr,    nullptr};
+  if (f64) {
+    v.adx = (const double*)(const void*)b->ax;
+    v.ady = (const double*)(const void*)b->ay;
+    v.adz = (const double*)(const void*)b->az;
+    v.ax = v.ay = v.az = nullptr;
+  }
+  return v;
+}
+
+// d(beta)/dt of sample i in FP64, whatever the batch stores.
+__device__ __forceinline__ void load_accel(const BatchView& b, int64_t i, double& ax, double& ay, double& az) {
+  if (b.adx) {
+    ax = b.adx[i];
+    ay = b.ady[i];
+    az = b.adz[i];
+  } else {
+    ax = (double)b.ax[i];
+    ay = (double)b.ay[i];
+    az = (double)b.az[i];
+  }
+}
 
 struct DirectArgs {
   BatchView b;
@@ -47,6 +78,9 @@ struct DirectArgs {
   const int64_t* order;  // item order for the ticket queue, or null
   unsigned* ticket;      // queue head, zeroed before the launch
   int64_t n_items;
+  // persistent launch with profiling: per work-group {compute-unit key, start, end} of the
+  // real-time counter, [workgroups][3], or null
+  unsigned long long* wg_time = nullptr;
 };
 
 // Launchers (lw_direct.hip).
@@ -88,6 +122,86 @@ hipError_t launch_spectral_diagnostics(const double* S, const double* a, double 
 
 struct MfmaPlanCache;
 
+// ---- the library's binary files (accumulator and network snapshots) ----
+// 64-byte header: 8-byte magic, five int64 fields, payload length, FNV-1a 64 checksum of the
+// payload; then the payload.  Host byte order (little-endian on every supported host).
+struct FileHeader {
+  char magic[8];
+  int64_t f[5];
+  uint64_t payload;
+  uint64_t sum;
+};
+static_assert(sizeof(FileHeader) == 64, "file header is 64 bytes");
+
+inline uint64_t fnv1a64(const void* data, size_t n) {
+  const unsigned char* p = (const unsigned char*)data;
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// Byte buffer with typed appends and reads (the payload of a file).
+struct Bytes {
+  std::vector<char> v;
+  size_t at = 0;
+  void put(const void* p, size_t n) { v.insert(v.end(), (const char*)p, (const char*)p + n); }
+  bool get(void* p, size_t n) {
+    if (at + n > v.size()) return false;
+    memcpy(p, v.data() + at, n);
+    at += n;
+    return true;
+  }
+};
+
+inline bool write_lw_file(const char* path, const char magic[8], const int64_t f[5], const Bytes& b) {
+  FileHeader h;
+  memcpy(h.magic, magic, 8);
+  for (int i = 0; i < 5; ++i) h.f[i] = f[i];
+  h.payload = b.v.size();
+  h.sum = fnv1a64(b.v.data(), b.v.size());
+  FILE* fp = fopen(path, "wb");
+  if (!fp) return false;
+  bool ok = fwrite(&h, sizeof(h), 1, fp) == 1 && (b.v.empty() || fwrite(b.v.data(), b.v.size(), 1, fp) == 1);
+  ok = (fclose(fp) == 0) && ok;
+  return ok;
+}
+
+// Reads the whole file; false with a reason on a missing, short, foreign or corrupted file.
+inline bool read_lw_file(const char* path, const char magic[8], FileHeader* h, Bytes* b, std::string* why) {
+  FILE* fp = fopen(path, "rb");
+  if (!fp) {
+    *why = "cannot open the file";
+    return false;
+  }
+  bool ok = fread(h, sizeof(*h), 1, fp) == 1;
+  if (!ok) *why = "file shorter than its header";
+  if (ok && memcmp(h->magic, magic, 8) != 0) {
+    ok = false;
+    *why = "not a file of this kind (magic)";
+  }
+  if (ok && h->payload > ((uint64_t)1 << 40)) {
+    ok = false;
+    *why = "implausible payload length";
+  }
+  if (ok) {
+    b->v.resize(h->payload);
+    b->at = 0;
+    if (h->payload && fread(b->v.data(), h->payload, 1, fp) != 1) {
+      ok = false;
+      *why = "file shorter than its payload";
+    }
+  }
+  fclose(fp);
+  if (ok && fnv1a64(b->v.data(), b->v.size()) != h->sum) {
+    ok = false;
+    *why = "checksum mismatch";
+  }
+  return ok;
+}
+
 }  // namespace lw
 
 // Context state (opaque behind the C ABI).
@@ -108,6 +222,8 @@ struct lw_ctx {
   double* d_diag = nullptr;
   size_t diag_cap = 0;
   unsigned long long* d_err = nullptr;
+  // lowest particle index whose retarded-time span outgrew the matrix-core plan
+  unsigned long long* d_overflow = nullptr;
   std::string err;
   int64_t calls = 0;
   lw::MfmaPlanCache* mfma = nullptr;
@@ -133,6 +249,9 @@ struct lw_ctx {
     size_t order_cap = 0;
   } plan;
   unsigned* d_ticket = nullptr;
+  // per work-group timing of the last persistent FP32 launch made with profiling on
+  unsigned long long* d_wgtime = nullptr;
+  int wgtime_cap = 0, wgtime_n = 0;
   bool capturing = false;  // inside lw_graph_capture: no synchronisation allowed
   // bumped whenever a device buffer that captured work refers to is freed, moved or refilled
   // for another batch (accumulators, grids, persistent plan); a graph records it at capture

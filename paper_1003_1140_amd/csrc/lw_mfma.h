@@ -12,7 +12,11 @@ uint64_t mfma_epoch(const MfmaPlanCache* c);
 lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16);
 lw_status mfma_set_bands(lw_ctx* c, int bands);
 lw_status mfma_set_tile(lw_ctx* c, int tile);
+// Plans the batch: measures its retarded-time span (synchronises), grows the tables if
+// needed and remembers the batch as planned.
 lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);
+// The same size without measuring a planned batch again (no synchronisation then).
+lw_status mfma_workspace_need(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);
 // amp: null, or a per-particle amplitude state [P][nd][nw][4] the columns' amplitudes are
 // added to (then S and the summed amplitudes are left alone)
 lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, size_t ws_bytes,

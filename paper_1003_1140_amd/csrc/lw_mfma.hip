@@ -104,6 +104,12 @@ struct MfmaPlanCache {
   double* rowc = nullptr;    // [nw][2] e^{-i nu W h / 2} / Phi(nu h): amplitude factor of a row pair
   int32_t* row_of_j = nullptr;  // [nw] stacked row of (j, re)
   double* d_span = nullptr;  // device scratch for the span reduction
+  // the last batch whose span was measured against these tables (lw_workspace_size,
+  // lw_plan_batch, or an accumulation that planned): later calls on it need no measurement,
+  // the spreading kernel reports a particle that outgrew the plan instead
+  const void* planned_offsets = nullptr;
+  int64_t planned_n = -1;
+  uint64_t planned_epoch = ~0ull;
 };
 
 struct SpreadArgs {
@@ -121,6 +127,7 @@ struct SpreadArgs {
   int32_t n_ftile;       // column tiles per band
   int32_t ns;            // species count (a species outside [0, ns) is a data error)
   unsigned long long* err;
+  unsigned long long* overflow;  // lowest particle whose span needs more grid points than planned
   unsigned long long* flops;  // null, or useful FLOPs of one product of the contraction
   // phi(i - W/2 + 1 - f) = sum_k tapc[i][k] z^k, z = 2 f - 1: the W tap weights of a sample
   // (mirror-symmetric: tapc[W - 1 - i][k] = (-1)^k tapc[i][k])
@@ -264,9 +271,15 @@ __device__ __forceinline__ void load_raw(const BatchView& b, int64_t o, int64_t 
   r.bx = b.bx[idx];
   r.by = b.by[idx];
   r.bz = b.bz[idx];
-  r.ax = b.ax[idx];
-  r.ay = b.ay[idx];
-  r.az = b.az[idx];
+  if (b.adx) {
+    r.ax = (float)b.adx[idx];
+    r.ay = (float)b.ady[idx];
+    r.az = (float)b.adz[idx];
+  } else {
+    r.ax = b.ax[idx];
+    r.ay = b.ay[idx];
+    r.az = b.az[idx];
+  }
 }
 
 __device__ __forceinline__ float dot3f(const float a[3], float x, float y, float z) {
@@ -359,6 +372,7 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     const int sp = a.b.species[p];
     if (sp < 0 || sp >= a.ns) atomicMin(a.err, (unsigned long long)p);
   }
+  if (tid == 0 && bi == 0 && d == 0 && len < 0) atomicMin(a.err, (unsigned long long)p);
   int Q = 0;
   double tau0 = 0.0;
   if (len > 0) {
@@ -366,7 +380,10 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
     const double taul = retarded_time(a.b, o + len - 1, t0 + (double)(len - 1) * dtp, n);
     double span = taul - tau0;
     if (!(span >= 0.0) || !isfinite(span)) span = 0.0;
-    Q = (int)fmin(ceil(span / bd.h) + kW + 1, (double)bd.qmax);
+    const double qneed = ceil(span / bd.h) + kW + 1;
+    // a batch that outgrew the plan is reported, not silently clipped
+    if (tid == 0 && qneed > (double)bd.qmax) atomicMin(a.overflow, (unsigned long long)p);
+    Q = (int)fmin(qneed, (double)bd.qmax);
   }
   const double inv_h = 1.0 / bd.h;
   // no tap may pass the grid allotment (samples beyond it only add to unwritten points)
@@ -1417,11 +1434,6 @@ void free_tables(MfmaPlanCache* pc) {
   pc->valid = false;
 }
 
-BatchView view_of(const lw_batch* b) {
-  return {b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
-          b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
-}
-
 // Largest retarded-time span over the batch and directions (synchronous).
 lw_status batch_span(lw_ctx* c, const lw_batch* b, double* span) {
   MfmaPlanCache* pc = c->mfma;
@@ -1583,9 +1595,12 @@ lw_status build_plan(lw_ctx* c, double span, int dtype, const KernelShape& ks) {
   return LW_OK;
 }
 
-// Make sure the tables cover the batch; grows the span with headroom.  Inside a graph
-// capture nothing may synchronise: the plan made before the capture is used as is.
-lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path) {
+// Make sure the tables cover the batch; grows the span with headroom.  With measure = false a
+// planned batch (same offsets pointer and particle count, tables unchanged since) is taken as
+// covered without a synchronisation: the spreading kernel records any particle that needs
+// more grid points than planned, and the next read reports it.  Inside a graph capture
+// nothing may synchronise: the plan made before the capture is used as is.
+lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path, bool measure) {
   MfmaPlanCache* pc = c->mfma;
   const int dtype = path == LW_PATH_MFMA_BF16 ? 1 : 0;
   const int products = dtype ? pc->products_bf16 : pc->products_f16;
@@ -1595,12 +1610,21 @@ lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path) {
     if (same) return LW_OK;
     return set_err(c, LW_ESTATE, "matrix-core tables must be planned before graph capture");
   }
+  if (!measure && same && pc->planned_offsets == (const void*)b->offsets &&
+      pc->planned_n == b->n_particles && pc->planned_epoch == pc->epoch)
+    return LW_OK;
   double span = 0.0;
   lw_status st = batch_span(c, b, &span);
   if (st != LW_OK) return st;
-  if (same && span <= pc->span) return LW_OK;
-  const double want = std::max(span * 1.25, same ? pc->span : 0.0);
-  return build_plan(c, want, dtype, ks);
+  if (!(same && span <= pc->span)) {
+    const double want = std::max(span * 1.25, same ? pc->span : 0.0);
+    st = build_plan(c, want, dtype, ks);
+    if (st != LW_OK) return st;
+  }
+  pc->planned_offsets = (const void*)b->offsets;
+  pc->planned_n = b->n_particles;
+  pc->planned_epoch = pc->epoch;
+  return LW_OK;
 }
 
 }  // namespace
@@ -1649,7 +1673,19 @@ lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t
     *bytes = 0;
     return LW_OK;
   }
-  lw_status st = ensure_plan(c, b, path);
+  lw_status st = ensure_plan(c, b, path, true);
+  if (st != LW_OK) return st;
+  *bytes = ws_layout(c, c->mfma, b->n_particles).total;
+  return LW_OK;
+}
+
+lw_status mfma_workspace_need(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes) {
+  if (!b || b->n_particles < 0) return set_err(c, LW_EINVAL, "bad batch");
+  if (b->n_particles == 0) {
+    *bytes = 0;
+    return LW_OK;
+  }
+  lw_status st = ensure_plan(c, b, path, false);
   if (st != LW_OK) return st;
   *bytes = ws_layout(c, c->mfma, b->n_particles).total;
   return LW_OK;
@@ -1659,7 +1695,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
                           float* per_particle, double* amp) {
   if (per_particle)
     return set_err(c, LW_EUNSUPPORTED, "per-particle output is available on the FP32 path only");
-  lw_status st = ensure_plan(c, b, path);
+  lw_status st = ensure_plan(c, b, path, false);
   if (st != LW_OK) return st;
   MfmaPlanCache* pc = c->mfma;
   const WsLayout L = ws_layout(c, pc, b->n_particles);
@@ -1692,6 +1728,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   ga.colq = colq;
   ga.perm = perm;
   sa.err = c->d_err;
+  sa.overflow = c->d_overflow;
   sa.ns = c->ns;
   sa.flops = c->prof ? c->d_flops : nullptr;
   tap_polynomials(sa.tapc, pc->shape);

@@ -67,7 +67,8 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   for (int64_t k = tid; k < len; k += 256) {
     const int64_t i = o + k;
     const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
-    const double ax = b.ax[i], ay = b.ay[i], az = b.az[i];
+    double ax, ay, az;
+    lw::load_accel(b, i, ax, ay, az);
     const double b2 = bx * bx + by * by + bz * bz;
     if (!(b2 < 1.0)) {
       atomicMin(err, (unsigned long long)p);
@@ -86,7 +87,9 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
     q[3] += ap * ap;
     q[4] += ap * ap * ap * ap;
     if (k > 0) {
-      const double dot = ax * (double)b.ax[i - 1] + ay * (double)b.ay[i - 1] + az * (double)b.az[i - 1];
+      double px0, py0, pz0;
+      lw::load_accel(b, i - 1, px0, py0, pz0);
+      const double dot = ax * px0 + ay * py0 + az * pz0;
       if (dot < 0.0) q[5] += 1.0;
     }
     q[6] = fmax(q[6], ap);
@@ -613,8 +616,7 @@ lw_status lw_features(lw_ctx* c, const lw_batch* b, float* feats) {
     c->err = "batch pointer is NULL";
     return LW_EINVAL;
   }
-  lw::BatchView v{b->n_particles, b->offsets, b->x,  b->y,  b->z,      b->bx,     b->by,     b->bz,
-                  b->ax,          b->ay,      b->az, b->t0, b->dt,     b->charge, b->weight, b->species};
+  lw::BatchView v = lw::view_of(b);
   const int64_t blocks = b->n_particles * (int64_t)((c->nd + lw::kDirGroup - 1) / lw::kDirGroup);
   if (blocks > 0x7fffffffLL) {
     c->err = "too many particles for one feature launch";
@@ -789,6 +791,78 @@ lw_status lw_mlp_set_params(lw_mlp* n, const float* host, int64_t count, const f
   MLP_HIP(hipMemcpy(n->p, host, count * sizeof(float), hipMemcpyHostToDevice), "copy params");
   if (host_head) MLP_HIP(hipMemcpy(n->hp, host_head, (n->hidden + 1) * sizeof(float), hipMemcpyHostToDevice), "copy head");
   return LW_OK;
+}
+
+lw_status lw_mlp_save(lw_mlp* n, const char* path) {
+  if (!n || !path) return LW_EINVAL;
+  MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+  const int64_t np = n->n_params, nh = n->hidden + 1;
+  std::vector<float> buf((size_t)std::max(np, nh));
+  lw::Bytes b;
+  const float* main_arrays[3] = {n->p, n->m, n->v};
+  const float* head_arrays[3] = {n->hp, n->hm, n->hv};
+  for (const float* a : main_arrays) {
+    MLP_HIP(hipMemcpy(buf.data(), a, np * sizeof(float), hipMemcpyDeviceToHost), "copy network");
+    b.put(buf.data(), np * sizeof(float));
+  }
+  for (const float* a : head_arrays) {
+    MLP_HIP(hipMemcpy(buf.data(), a, nh * sizeof(float), hipMemcpyDeviceToHost), "copy error head");
+    b.put(buf.data(), nh * sizeof(float));
+  }
+  b.put(&n->step, sizeof(int64_t));
+  b.put(&n->head_step, sizeof(int64_t));
+  const int64_t has_norm = n->norm ? 1 : 0;
+  b.put(&has_norm, sizeof(has_norm));
+  if (has_norm) {
+    std::vector<float> nm(2 * (size_t)n->n_in);
+    MLP_HIP(hipMemcpy(nm.data(), n->norm, nm.size() * sizeof(float), hipMemcpyDeviceToHost), "copy norm");
+    b.put(nm.data(), nm.size() * sizeof(float));
+  }
+  const int64_t skip = n->skip_index;
+  b.put(&skip, sizeof(skip));
+  b.put(&n->skip_coeff, sizeof(float));
+  const int64_t f[5] = {n->n_in, n->hidden, n->n_hidden, n->n_out, np};
+  if (!lw::write_lw_file(path, "LWMLP001", f, b)) return mlp_fail(n, LW_EINVAL, std::string("cannot write ") + path);
+  return LW_OK;
+}
+
+lw_status lw_mlp_load(lw_mlp* n, const char* path) {
+  if (!n || !path) return LW_EINVAL;
+  lw::FileHeader h;
+  lw::Bytes b;
+  std::string why;
+  if (!lw::read_lw_file(path, "LWMLP001", &h, &b, &why)) return mlp_fail(n, LW_EINVAL, std::string(path) + ": " + why);
+  const int64_t np = n->n_params, nh = n->hidden + 1;
+  if (h.f[0] != n->n_in || h.f[1] != n->hidden || h.f[2] != n->n_hidden || h.f[3] != n->n_out || h.f[4] != np)
+    return mlp_fail(n, LW_EINVAL, std::string(path) + ": network shape differs");
+  std::vector<float> arr[6];
+  for (int i = 0; i < 6; ++i) {
+    arr[i].resize(i < 3 ? np : nh);
+    if (!b.get(arr[i].data(), arr[i].size() * sizeof(float))) return mlp_fail(n, LW_EINVAL, std::string(path) + ": short payload");
+  }
+  int64_t step = 0, head_step = 0, has_norm = 0, skip = -1;
+  float coeff = 0.0f;
+  std::vector<float> nm;
+  bool ok = b.get(&step, 8) && b.get(&head_step, 8) && b.get(&has_norm, 8);
+  if (ok && has_norm) {
+    nm.resize(2 * (size_t)n->n_in);
+    ok = b.get(nm.data(), nm.size() * sizeof(float));
+  }
+  ok = ok && b.get(&skip, 8) && b.get(&coeff, sizeof(float)) && b.at == b.v.size();
+  if (!ok || skip < -1 || skip >= n->n_in) return mlp_fail(n, LW_EINVAL, std::string(path) + ": malformed payload");
+  MLP_HIP(hipStreamSynchronize(n->c->stream), "sync");
+  float* main_arrays[3] = {n->p, n->m, n->v};
+  float* head_arrays[3] = {n->hp, n->hm, n->hv};
+  for (int i = 0; i < 3; ++i) {
+    MLP_HIP(hipMemcpy(main_arrays[i], arr[i].data(), np * sizeof(float), hipMemcpyHostToDevice), "load network");
+    MLP_HIP(hipMemcpy(head_arrays[i], arr[3 + i].data(), nh * sizeof(float), hipMemcpyHostToDevice), "load head");
+  }
+  n->step = step;
+  n->head_step = head_step;
+  lw_status st = has_norm ? lw_mlp_set_input_norm(n, nm.data(), nm.data() + n->n_in)
+                          : lw_mlp_set_input_norm(n, nullptr, nullptr);
+  if (st != LW_OK) return st;
+  return lw_mlp_set_output_skip(n, (int32_t)skip, coeff);
 }
 
 lw_status lw_mlp_set_input_norm(lw_mlp* n, const float* shift, const float* scale) {

@@ -51,6 +51,8 @@ extern "C" lw_status lw_tune(lw_ctx* c, const lw_batch* b, lw_path path, int32_t
     return LW_EINVAL;
   }
   if (repeats < 1) repeats = 1;
+  if (path == LW_PATH_AUTO)  // tune the path lw_accumulate would pick
+    path = c->nw >= LW_AUTO_MIN_FREQUENCIES ? LW_PATH_MFMA_F16 : LW_PATH_FP32;
   int prev = -1;
   (void)hipGetDevice(&prev);
   if (prev != c->device) (void)hipSetDevice(c->device);

@@ -18,8 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblw.so")
 
 LW_OK, LW_EINVAL, LW_ENOMEM, LW_EDEVICE, LW_ESTATE, LW_ERANGE, LW_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-LW_PATH_FP32, LW_PATH_MFMA_F16, LW_PATH_MFMA_BF16 = 0, 1, 2
-PATHS = {"fp32": LW_PATH_FP32, "mfma_f16": LW_PATH_MFMA_F16, "mfma_bf16": LW_PATH_MFMA_BF16}
+LW_PATH_FP32, LW_PATH_MFMA_F16, LW_PATH_MFMA_BF16, LW_PATH_AUTO = 0, 1, 2, 3
+PATHS = {"fp32": LW_PATH_FP32, "mfma_f16": LW_PATH_MFMA_F16, "mfma_bf16": LW_PATH_MFMA_BF16,
+         "auto": LW_PATH_AUTO}
+LW_BATCH_F64_ACCEL = 1
+LW_AUTO_MIN_FREQUENCIES = 256
 
 EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set_directions",
             "lw_set_frequencies", "lw_set_log_frequencies", "lw_get_frequencies", "lw_set_species",
@@ -33,7 +36,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_mlp_train_head_step", "lw_surrogate_accumulate", "lw_surrogate_targets",
             "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
             "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes",
-            "lw_spectral_diagnostics", "lw_pitch_cones")
+            "lw_spectral_diagnostics", "lw_pitch_cones", "lw_profile_cu_busy", "lw_save_accumulator",
+            "lw_load_accumulator_file", "lw_mlp_save", "lw_mlp_load")
 
 
 class LWError(RuntimeError):
@@ -52,6 +56,7 @@ class lw_batch(ctypes.Structure):
         ("t0", ctypes.c_void_p), ("dt", ctypes.c_void_p),
         ("charge", ctypes.c_void_p), ("weight", ctypes.c_void_p),
         ("species", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -120,6 +125,11 @@ def load_library():
             "lw_spectrum_from_amplitudes": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, SZ]),
             "lw_spectral_diagnostics": (ctypes.c_int, [P, P, P, P, P, P]),
             "lw_pitch_cones": (ctypes.c_int, [P, I64, P, P, P, P, P, I32, D, P, I32, P, P, P]),
+            "lw_profile_cu_busy": (ctypes.c_int, [P, P]),
+            "lw_save_accumulator": (ctypes.c_int, [P, ctypes.c_char_p]),
+            "lw_load_accumulator_file": (ctypes.c_int, [P, ctypes.c_char_p]),
+            "lw_mlp_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+            "lw_mlp_load": (ctypes.c_int, [P, ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -148,18 +158,25 @@ class DeviceBatch:
         self.n_particles = int(n_particles)
         self.struct = lw_batch()
         self.struct.n_particles = self.n_particles
-        for name, _ in lw_batch._fields_[1:]:
+        for name, _ in lw_batch._fields_[1:-1]:
             ten = tensors.get(name)
             setattr(self.struct, name, ten.data_ptr() if ten is not None else None)
+        # FP64 accelerations (all three, or none) are passed as such with the batch flag
+        f64 = [tensors[k].dtype == torch.float64 for k in ("ax", "ay", "az") if k in tensors]
+        if any(f64) and not all(f64):
+            raise ValueError("ax, ay, az must share one dtype")
+        self.struct.flags = LW_BATCH_F64_ACCEL if f64 and all(f64) else 0
 
     @classmethod
-    def from_host(cls, host, device="cuda", with_species=True):
+    def from_host(cls, host, device="cuda", with_species=True, f64_accel=False):
+        """f64_accel: pass d(beta)/dt as FP64 (LW_BATCH_F64_ACCEL) instead of rounding it to FP32."""
         dev = torch.device(device)
         t = {"offsets": torch.from_numpy(np.ascontiguousarray(host.offsets, dtype=np.int64)).to(dev)}
         for k in cls.F64:
             t[k] = torch.from_numpy(np.ascontiguousarray(getattr(host, k), dtype=np.float64)).to(dev)
         for k in cls.F32:
-            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(host, k), dtype=np.float32)).to(dev)
+            dt = np.float64 if (f64_accel and k in ("ax", "ay", "az")) else np.float32
+            t[k] = torch.from_numpy(np.ascontiguousarray(getattr(host, k), dtype=dt)).to(dev)
         if with_species:
             t["species"] = torch.from_numpy(np.ascontiguousarray(host.species, dtype=np.int32)).to(dev)
         return cls(t, len(host.offsets) - 1)
@@ -273,6 +290,22 @@ class Context:
         self._check(self.lib.lw_load_accumulator(self.h, _np_ptr(s)))
 
     # ---- coherent synthesis and in-situ recording ----
+    def set_stream(self, stream):
+        """Order later calls on this stream (a torch.cuda.Stream, a raw hipStream_t, or None)."""
+        raw = getattr(stream, "cuda_stream", stream)
+        self._check(self.lib.lw_set_stream(self.h, ctypes.c_void_p(raw) if raw else None))
+
+    def save_accumulator(self, path):
+        self._check(self.lib.lw_save_accumulator(self.h, os.fsencode(path)))
+
+    def load_accumulator_file(self, path):
+        self._check(self.lib.lw_load_accumulator_file(self.h, os.fsencode(path)))
+
+    def profile_cu_busy(self) -> dict:
+        out = np.zeros(4, dtype=np.float64)
+        self._check(self.lib.lw_profile_cu_busy(self.h, _np_ptr(out)))
+        return {"cus": int(out[0]), "min_ms": out[1], "mean_ms": out[2], "max_ms": out[3]}
+
     def set_coherent(self, coherent=True):
         self._check(self.lib.lw_set_coherent(self.h, 1 if coherent else 0))
         self.coherent = bool(coherent)
@@ -568,6 +601,12 @@ class MLP:
         self.ctx._check(self.ctx.lib.lw_mlp_train_step(self.h, self._ptr(x), self._ptr(t), x.shape[0], lr,
                                                        weight_decay, ctypes.byref(loss)))
         return loss.value
+
+    def save(self, path):
+        self.ctx._check(self.ctx.lib.lw_mlp_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self.ctx._check(self.ctx.lib.lw_mlp_load(self.h, os.fsencode(path)))
 
     def train_head_step(self, x, err_target, lr=1e-3):
         loss = ctypes.c_double()

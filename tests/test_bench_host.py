@@ -27,24 +27,28 @@ def test_code_digest_ignores_comments_and_whitespace_only():
 
 def test_traffic_is_reported_only_for_the_profiled_launch():
     b = _bench()
-    text = open(b.TRAFFIC_PROFILE).read()
-    fields = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
-    profiled_bands = int(fields["bands"])
     src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip")).read()
-    if fields["kernel_code_sha256"].strip() != b.kernel_code_digest(src):
-        # the kernel changed after the counters were taken: nothing may be reported
-        assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands) is None
-        return
-    got = b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands)
-    assert got == float(fields["traffic_bytes_per_launch"])
-    got = b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands, "spread")
-    assert got == float(fields["spread_traffic_bytes_per_launch"])
-    # any other launch gets none
-    assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "jitter", profiled_bands + 1) is None
-    assert b.profiled_traffic("mfma_bf16x3", 0, 100_000, "jitter", profiled_bands) is None
-    assert b.profiled_traffic("mfma_f16x3", 1, 100_000, "jitter", profiled_bands) is None
-    assert b.profiled_traffic("mfma_f16x3", 0, 50_000, "jitter", profiled_bands) is None
-    assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "wide", profiled_bands) is None
+    for workload, prof in b.TRAFFIC_PROFILES.items():
+        if not os.path.exists(prof):
+            assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, 2) is None
+            continue
+        text = open(prof).read()
+        fields = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
+        profiled_bands = int(fields["bands"])
+        if fields["kernel_code_sha256"].strip() != b.kernel_code_digest(src):
+            # the kernel changed after the counters were taken: nothing may be reported
+            assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands) is None
+            continue
+        got = b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands)
+        assert got == float(fields["traffic_bytes_per_launch"])
+        got = b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands, "spread")
+        assert got == float(fields["spread_traffic_bytes_per_launch"])
+        # any other launch gets none
+        assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands + 1) is None
+        assert b.profiled_traffic("mfma_bf16x3", 0, 100_000, workload, profiled_bands) is None
+        assert b.profiled_traffic("mfma_f16x3", 1, 100_000, workload, profiled_bands) is None
+        assert b.profiled_traffic("mfma_f16x3", 0, 50_000, workload, profiled_bands) is None
+    assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "other", 2) is None
 
 
 def test_spread_flop_model():
@@ -54,3 +58,11 @@ def test_spread_flop_model():
     for w in (8, 10):
         assert b.spread_flops_per_unit(w) == 8 * w + 9 * w + 3 + 35 + 4 + 21
     assert b.spread_width(3) == 10 and b.spread_width(1) == 8
+
+
+def test_algorithmic_work_of_the_roofline():
+    """frac uses the algorithmic work: 32 FLOP per (sample, direction, band) for the spread and
+    one product's multiply-adds for the contraction, whatever the number of hi/lo products."""
+    b = _bench()
+    assert b.SPREAD_ALGO_FLOPS == 32
+    assert b.C3_TERMS == 1e6 * 2048 * 16 * 2048 and abs(b.C3_TERMS / 6.7e13 - 1) < 0.01
