@@ -1,0 +1,176 @@
+"""CPU emulation of the spreading kernel's index logic (no GPU).
+
+The matrix-core path spreads each (particle, direction, band) column's samples onto a uniform
+grid: sample s adds its W tap values to grid points lo_s .. lo_s + W - 1.  The kernel walks the
+samples in chunks of up to 256 and keeps running sums in a ring of kRing grid points (slot
+q mod kRing).  A chunk takes the samples whose taps stay within kRing of the oldest unwritten
+point (and leaves its last sample to the next chunk, so that the next first tap is known); a
+table gives the first sample reaching each point of the chunk; a point below the next chunk's
+first tap is final, is written and its slot cleared; points no sample reaches are written as
+zeros.  This module re-states that logic step by step, with the kernel's clamps and sizes, and
+checks on random first-tap sequences -- dense, sparse (3 to 7 points per sample), gapped,
+co-located -- at rings of 768 (the kernel's) and 1024 that
+
+* every index stays inside its buffer (first-sample table, ring, column),
+* no ring slot ever holds the running sums of two grid points at once,
+* every grid point below Q is written exactly once and equals the brute-force sum of the taps
+  that land on it,
+
+and that on disordered data (which the kernel reports as a data error) the walk still ends in
+bounds.
+"""
+import numpy as np
+import pytest
+
+CHUNK = 256
+
+
+def emulate(lo_all, vals, Q, W, k_ring, strict=True):
+    """Index logic of one column: returns (F, write counts).  vals[s, i] is sample s's value
+    on tap i (one component stands for the four of the kernel)."""
+    n = len(lo_all)
+    F = np.zeros(Q)
+    writes = np.zeros(Q, dtype=int)
+    ring = np.zeros(k_ring)
+    owner = np.full(k_ring, -1)  # grid point whose running sum a slot holds (-1: none)
+
+    def clamp(v, a, b):
+        return min(max(v, a), b)
+
+    qdone, kc, guard = 0, 0, 0
+    while kc < n:
+        guard += 1
+        assert guard < 10 * n + 10, "chunk walk does not end"
+        cnt = min(CHUNK, n - kc)
+        lo = lo_all[kc:kc + cnt]
+        base = lo[0]
+        more = kc + cnt < n
+        fits = sum(1 for t in range(cnt) if lo[t] - qdone <= k_ring - W)
+        take = max(min(fits, cnt - 1 if more else cnt), 1)
+        top = lo[take - 1] + W - 1
+        G = min(top - base + 1, k_ring)
+        qfin = Q
+        if kc + take < n:
+            qfin = min(Q, lo[take] if take < cnt else top + 1)
+        first = np.full(k_ring + W, -12345)
+        for t in range(take):
+            prev = base - 1 if t == 0 else lo[t - 1] + W - 1
+            mine = lo[t] + W - 1
+            for x in range(max(prev + 1, base) - base, min(mine - base, G - 1) + 1):
+                assert 0 <= x < len(first)
+                first[x] = t
+        for t in range(W):
+            assert 0 <= max(G, 0) + t < len(first)
+            first[max(G, 0) + t] = take
+        ring0 = base % k_ring
+        for x in range(G):
+            q = base + x
+            sb = clamp(first[x], 0, take)
+            se = clamp(first[x + W], sb, take)
+            acc = 0.0
+            for s in range(sb, se):
+                acc += vals[kc + s, clamp(q - lo[s], 0, W - 1)]
+            slot = ring0 + x if ring0 + x < k_ring else ring0 + x - k_ring
+            assert 0 <= slot < k_ring
+            if strict:
+                assert owner[slot] in (-1, q), f"slot {slot} holds point {owner[slot]} and {q}"
+            v = ring[slot] + acc
+            if q < qfin:
+                assert 0 <= q < Q
+                F[q] = v
+                writes[q] += 1
+                ring[slot], owner[slot] = 0.0, -1
+            else:
+                ring[slot], owner[slot] = v, q
+        for q in range(qdone, min(base, qfin)):
+            F[q] = 0.0
+            writes[q] += 1
+        for q in range(max(base + G, qdone), qfin):
+            F[q] = 0.0
+            writes[q] += 1
+        qdone = max(qdone, qfin)
+        kc += take
+    return F, writes
+
+
+def brute(lo, vals, Q, W):
+    F = np.zeros(Q)
+    for s, l in enumerate(lo):
+        for i in range(W):
+            if l + i < Q:
+                F[l + i] += vals[s, i]
+    return F
+
+
+def ordered_case(rng, n, spacing, W):
+    """First taps of n samples with the given per-sample spacing generator, from lo = 1 (the
+    smallest first tap the kernel produces), and the column length the kernel would use."""
+    steps = spacing(rng, n)
+    lo = 1 + np.concatenate([[0], np.cumsum(steps[1:])]).astype(int)
+    Q = int(lo[-1] + W + 1 + rng.integers(0, 3))
+    return lo, Q
+
+
+SPACINGS = {
+    "dense": lambda rng, n: (rng.random(n) < 0.2).astype(int),
+    "sparse_3_7": lambda rng, n: rng.integers(3, 8, n),
+    "mixed": lambda rng, n: np.where(rng.random(n) < 0.5, rng.integers(0, 2, n), rng.integers(2, 6, n)),
+    "gapped": lambda rng, n: np.where(rng.random(n) < 0.01, rng.integers(900, 3000, n), rng.integers(0, 3, n)),
+    "co_located": lambda rng, n: np.zeros(n, dtype=int),
+}
+
+
+@pytest.mark.parametrize("W", [8, 10])
+@pytest.mark.parametrize("k_ring", [768, 1024])
+@pytest.mark.parametrize("kind", sorted(SPACINGS))
+def test_every_point_written_once_and_equal_to_brute_force(kind, k_ring, W):
+    rng = np.random.default_rng(sum(map(ord, kind)) * 7919 + k_ring * 31 + W)
+    for n in (1, 2, 255, 256, 257, 700):
+        lo, Q = ordered_case(rng, n, SPACINGS[kind], W)
+        vals = rng.normal(size=(n, W))
+        F, writes = emulate(lo, vals, Q, W, k_ring)
+        assert np.all(writes == 1), (kind, n, np.flatnonzero(writes != 1)[:10])
+        np.testing.assert_allclose(F, brute(lo, vals, Q, W), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("W", [8, 10])
+def test_column_clipped_by_the_plan(W):
+    """A span past the plan: first taps pile up at qmax + 1 (the kernel clamps the grid
+    coordinate), Q = qmax; points below Q are still written once."""
+    rng = np.random.default_rng(5)
+    lo, _ = ordered_case(rng, 600, SPACINGS["sparse_3_7"], W)
+    qmax = int(lo[300])
+    lo = np.minimum(lo, qmax + 1)
+    vals = rng.normal(size=(600, W))
+    F, writes = emulate(lo, vals, qmax, W, 768)
+    assert np.all(writes == 1)
+    np.testing.assert_allclose(F, brute(lo, vals, qmax, W), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_disordered_data_ends_in_bounds(seed):
+    """Out-of-order first taps (invalid samples are put at lo = 1, other orders come from
+    inconsistent positions): the walk ends and indices stay in their buffers (asserted
+    inside); values and write counts are not checked (the kernel reports such data)."""
+    rng = np.random.default_rng(seed)
+    W = 10
+    lo = rng.integers(1, 3000, 700)
+    lo[rng.random(700) < 0.3] = 1
+    Q = 3000 + W + 1
+    vals = rng.normal(size=(700, W))
+    emulate(lo, vals, Q, W, 768, strict=False)
+
+
+def test_sparse_first_chunk_spanning_the_ring():
+    """The case the ring's origin rule exists for: spacings of 3 to 7 points, so that a first
+    chunk's taps reach past point kRing while point 0 is still unwritten."""
+    rng = np.random.default_rng(12)
+    hit = 0
+    for _ in range(40):
+        lo, Q = ordered_case(rng, 600, SPACINGS["sparse_3_7"], 10)
+        hit += int(lo[min(254, len(lo) - 1)] + 9 >= 768)
+        vals = rng.normal(size=(600, 10))
+        F, writes = emulate(lo, vals, Q, 10, 768)
+        assert np.all(writes == 1)
+        np.testing.assert_allclose(F, brute(lo, vals, Q, 10), rtol=1e-12, atol=1e-12)
+    assert hit > 0
