@@ -758,6 +758,7 @@ def surrogate_leg(a, log):
     S_mfma = exact_m.read_spectra()
     Se, Sp, Ss = judge.spectra()
     held_err = sg.held_out_errors(Se, Sp)
+    floor = sg.split_half_floor(Se, judge.half_spectrum())
     sur_only = sg.held_out_errors(Se, Ss)
     ens = sg.held_out_errors(S_exact, S_pipe)
     sub = {f"{f:.4f}": sg.held_out_errors(S_exact, sc.read_spectra() / f)["per_bin_median"]
@@ -772,6 +773,8 @@ def surrogate_leg(a, log):
         "exact_mfma_vs_fp32_band_integrated": band_integrated_error(S_mfma, S_exact, om),
         "fallback_fraction": fallback / n, "held_out_particles": judge.n,
         "held_out_per_bin_max": held_err["per_bin_max"], "held_out_per_bin_median": held_err["per_bin_median"],
+        "held_out_split_half_floor_per_bin_max": floor["per_bin_max"],
+        "held_out_split_half_floor_per_bin_median": floor["per_bin_median"],
         "held_out_band_integrated_max": band_integrated_error(Sp, Se, om),
         "held_out_surrogate_only_per_bin_max": sur_only["per_bin_max"],
         "held_out_surrogate_only_per_bin_median": sur_only["per_bin_median"],

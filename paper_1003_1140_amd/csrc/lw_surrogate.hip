@@ -21,6 +21,7 @@ namespace lw {
 constexpr int kFeat = 16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16v __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ features
 // One work-group per (particle, group of up to kDirGroup directions): the
@@ -195,11 +196,12 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
 }
 
 // ------------------------------------------------------------------ BF16 MFMA GEMM
-// C[i][j] (ldc) = sum_k A(i,k) B(k,j) (+ bias[j]) (+ row_coeff * row_add[i*row_stride]),
-// A(i,k) = A[i*sai + k*sak],
-// B(k,j) = B[k*sbk + j*sbj]; FP32 operands are rounded to BF16 as they are staged in
-// LDS, products accumulate in FP32 on v_mfma_f32_32x32x16_bf16.  64 x 64 tile per
-// work-group of 4 waves (2 x 2 blocks of 32 x 32), inner steps of 16.
+// C[i][j] = sum_k A(i,k) B(k,j), with A(i,k) = A[i*sai + k*sak] and B(k,j) = B[k*sbk + j*sbj].
+// FP32 operands are rounded to BF16 as they are staged in LDS; products accumulate in FP32 on
+// v_mfma_f32_32x32x16_bf16.  Epilogue (applied when the inner dimension is not split): add
+// bias[j] and row_coeff * row_add[i*row_stride]; write C = v, and also H = GELU(v) when H is
+// given (a layer's pre-activation and activation in one pass), or C = v GELU'(Z[i*ldc + j])
+// when Z is given (the backward of the activation, fused into the product that feeds it).
 struct GemmDesc {
   const float* A;
   int64_t sai, sak;
@@ -212,8 +214,34 @@ struct GemmDesc {
   const float* row_add = nullptr;  // per-row term added to every column, or null
   int64_t row_stride = 0;
   float row_coeff = 0.0f;
+  float* H = nullptr;              // GELU of the result, or null
+  const float* Z = nullptr;        // multiply the result by GELU'(Z), or null
+  float* part = nullptr;           // split inner dimension: partial products [splits][M][N]
+  int splits = 1;
+  int gelu_out = 0;                // 1: write C = GELU(v) instead (inference: no pre-activation kept)
 };
 
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
+  return cdf + z * pdf;
+}
+
+__device__ __forceinline__ float gemm_epilogue(const GemmDesc& g, int64_t ii, int64_t jj, float v) {
+  if (g.bias) v += g.bias[jj];
+  if (g.row_add) v += g.row_coeff * g.row_add[ii * g.row_stride];
+  return v;
+}
+
+__device__ __forceinline__ void gemm_store(const GemmDesc& g, int64_t ii, int64_t jj, float v) {
+  if (g.Z) v *= gelu_grad_f(g.Z[ii * g.ldc + jj]);
+  g.C[ii * g.ldc + jj] = g.gelu_out ? gelu_f(v) : v;
+  if (g.H) g.H[ii * g.ldc + jj] = gelu_f(v);
+}
+
+// General shapes and strides: 64 x 64 tile per work-group of 4 waves (2 x 2 blocks of 32 x 32),
+// inner steps of 16, scalar loads.
 __global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
   constexpr int T = 64, KS = 16, LD = KS + 8;
   __shared__ __attribute__((aligned(16))) __bf16 sA[T * LD];
@@ -224,7 +252,6 @@ __global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
   f32x16v acc;
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   for (int64_t k0 = 0; k0 < g.K; k0 += KS) {
-    // 64 x 16 elements of A and of B: 4 each per thread
     for (int e = tid; e < T * KS; e += 256) {
       const int r = e / KS, kk = e % KS;
       const int64_t ii = i0 + r, k = k0 + kk;
@@ -244,26 +271,183 @@ __global__ __launch_bounds__(256) void lw_gemm_bf16_kernel(GemmDesc g) {
   for (int r = 0; r < 16; ++r) {
     const int64_t ii = i0 + wi + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
     const int64_t jj = j0 + wj + (lane & 31);
-    if (ii < g.M && jj < g.N)
-      g.C[ii * g.ldc + jj] = acc[r] + (g.bias ? g.bias[jj] : 0.0f) +
-                             (g.row_add ? g.row_coeff * g.row_add[ii * g.row_stride] : 0.0f);
+    if (ii < g.M && jj < g.N) gemm_store(g, ii, jj, gemm_epilogue(g, ii, jj, acc[r]));
   }
 }
 
-hipError_t gemm_bf16(const GemmDesc& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64)), block(256);
-  hipLaunchKernelGGL(lw_gemm_bf16_kernel, grid, block, 0, s, g);
+// Tiled form for operands with one unit stride each (A along k or along i, B along k or
+// along j), dimensions that are multiples of 4 and 16-byte aligned rows: 128 x 128 tile per
+// work-group of 4 waves (2 x 2, each 64 x 64 as 2 x 2 MFMA blocks), inner steps of 32 through
+// two LDS buffers -- while the MFMAs of one step run, the next step's operands travel from
+// memory to registers as float4 along the unit-stride index, and then to the other buffer.
+// gridDim.z splits the inner dimension (partial tiles, added in a fixed order afterwards).
+template <bool AK, bool BK>
+__global__ __launch_bounds__(256) void lw_gemm_bf16_tiled_kernel(GemmDesc g) {
+  constexpr int TM = 128, TN = 128, TK = 32, LD = TK + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[2][TM * LD];  // [i][k]
+  __shared__ __attribute__((aligned(16))) __bf16 sB[2][TN * LD];  // [j][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // tile of this work-group: blocks b, b + 8, ... share an XCD (work-groups are dealt to the 8
+  // XCDs in turn); along that sequence the column tiles of one row tile come one after the
+  // other, so the row tile of A is fetched once and reused from the XCD's L2
+  const int ntn = (int)((g.N + TN - 1) / TN), ntm = (int)((g.M + TM - 1) / TM);
+  const int xcd = (int)blockIdx.x % 8, seq = (int)blockIdx.x / 8;
+  const int mt = (seq / ntn) * 8 + xcd, nt = seq % ntn;
+  if (mt >= ntm) return;  // padding of the XCD-aware numbering
+  const int64_t i0 = (int64_t)mt * TM, j0 = (int64_t)nt * TN;
+  const int wi = (wave >> 1) * 64, wj = (wave & 1) * 64;
+  // inner range of this split
+  const int64_t kc = ((g.K + g.splits - 1) / g.splits + TK - 1) / TK * TK;
+  const int64_t kb = (int64_t)blockIdx.z * kc, ke = min(g.K, kb + kc);
+
+  f32x4 ra[4], rb[4];
+  // float4 v of the thread: A (B) element block (row or column, k) of the tile
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int idx = tid + 256 * v;
+      if (AK) {  // 128 rows x 8 float4 along k
+        const int r = idx >> 3, kq = (idx & 7) * 4;
+        const int64_t ii = i0 + r, k = k0 + kq;
+        ra[v] = (ii < g.M && k < ke) ? *(const f32x4*)(g.A + ii * g.sai + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {   // 32 k x 32 float4 along i
+        const int k = idx >> 5, rq = (idx & 31) * 4;
+        const int64_t ii = i0 + rq, kk = k0 + k;
+        ra[v] = (ii < g.M && kk < ke) ? *(const f32x4*)(g.A + ii + kk * g.sak) : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      if (BK) {
+        const int c = idx >> 3, kq = (idx & 7) * 4;
+        const int64_t jj = j0 + c, k = k0 + kq;
+        rb[v] = (jj < g.N && k < ke) ? *(const f32x4*)(g.B + jj * g.sbj + k) : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        const int k = idx >> 5, cq = (idx & 31) * 4;
+        const int64_t jj = j0 + cq, kk = k0 + k;
+        rb[v] = (jj < g.N && kk < ke) ? *(const f32x4*)(g.B + jj + kk * g.sbk) : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  };
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int idx = tid + 256 * v;
+      if (AK) {
+        const int r = idx >> 3, kq = (idx & 7) * 4;
+        *(bf16x4*)&sA[buf][r * LD + kq] = bf16x4{(__bf16)ra[v][0], (__bf16)ra[v][1], (__bf16)ra[v][2], (__bf16)ra[v][3]};
+      } else {
+        const int k = idx >> 5, rq = (idx & 31) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sA[buf][(rq + e) * LD + k] = (__bf16)ra[v][e];
+      }
+      if (BK) {
+        const int c = idx >> 3, kq = (idx & 7) * 4;
+        *(bf16x4*)&sB[buf][c * LD + kq] = bf16x4{(__bf16)rb[v][0], (__bf16)rb[v][1], (__bf16)rb[v][2], (__bf16)rb[v][3]};
+      } else {
+        const int k = idx >> 5, cq = (idx & 31) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sB[buf][(cq + e) * LD + k] = (__bf16)rb[v][e];
+      }
+    }
+  };
+
+  f32x16v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
+    const bool more = k0 + TK < ke;
+    if (more) load(k0 + TK);
+#pragma unroll
+    for (int ks = 0; ks < TK; ks += 16) {
+      const int kk = ks + 8 * (lane >> 5);
+      bf16x8 fa[2], fb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) fa[a] = *(const bf16x8*)&sA[buf][(wi + 32 * a + (lane & 31)) * LD + kk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = *(const bf16x8*)&sB[buf][(wj + 32 * b + (lane & 31)) * LD + kk];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t ii = i0 + wi + 32 * a + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4);
+        const int64_t jj = j0 + wj + 32 * b + (lane & 31);
+        if (ii >= g.M || jj >= g.N) continue;
+        if (g.splits > 1)
+          g.part[((int64_t)blockIdx.z * g.M + ii) * g.N + jj] = acc[a][b][r];
+        else
+          gemm_store(g, ii, jj, gemm_epilogue(g, ii, jj, acc[a][b][r]));
+      }
+}
+
+// Split inner dimension: C = sum over splits in order of the partial products, then the epilogue.
+__global__ void lw_gemm_splitk_reduce_kernel(GemmDesc g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.M * g.N) return;
+  const int64_t ii = e / g.N, jj = e % g.N;
+  float v = 0.0f;
+  for (int z = 0; z < g.splits; ++z) v += g.part[(int64_t)z * g.M * g.N + e];
+  gemm_store(g, ii, jj, gemm_epilogue(g, ii, jj, v));
+}
+
+// Inner-dimension splits of a product whose output alone gives too few tiles to fill the
+// chip (weight gradients: 256 x 256 outputs over many rows).
+constexpr int kMaxSplits = 64;
+inline int gemm_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  int s = 1;
+  while (s < kMaxSplits && tiles * s < 512 && K / (2 * s) >= 256) s *= 2;
+  return s;
+}
+
+hipError_t gemm_bf16(const GemmDesc& g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0) return hipSuccess;
+  GemmDesc g = g0;
+  const bool ak = g.sak == 1, ai = g.sai == 1, bk = g.sbk == 1, bj = g.sbj == 1;
+  const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool tiled = (ak || ai) && (bk || bj) && g.M % 4 == 0 && g.N % 4 == 0 && g.K % 4 == 0 &&
+                     al16(g.A) && al16(g.B) && (ak ? g.sai % 4 == 0 : g.sak % 4 == 0) &&
+                     (bk ? g.sbj % 4 == 0 : g.sbk % 4 == 0);
+  if (!tiled) {
+    dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64)), block(256);
+    hipLaunchKernelGGL(lw_gemm_bf16_kernel, grid, block, 0, s, g);
+    return hipGetLastError();
+  }
+  g.splits = g.part ? gemm_splits(g.M, g.N, g.K) : 1;
+  // row tiles rounded up to a multiple of 8 (one per XCD), times the column tiles
+  const int64_t ntm = (g.M + 127) / 128, ntn = (g.N + 127) / 128;
+  dim3 grid((unsigned)((ntm + 7) / 8 * 8 * ntn), 1, (unsigned)g.splits), block(256);
+  if (ak && bk) hipLaunchKernelGGL((lw_gemm_bf16_tiled_kernel<true, true>), grid, block, 0, s, g);
+  else if (ak) hipLaunchKernelGGL((lw_gemm_bf16_tiled_kernel<true, false>), grid, block, 0, s, g);
+  else if (bk) hipLaunchKernelGGL((lw_gemm_bf16_tiled_kernel<false, true>), grid, block, 0, s, g);
+  else hipLaunchKernelGGL((lw_gemm_bf16_tiled_kernel<false, false>), grid, block, 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.splits == 1) return e;
+  const int64_t n = g.M * g.N;
+  hipLaunchKernelGGL(lw_gemm_splitk_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ elementwise kernels
-__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float z) {
-  const float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
-  const float pdf = 0.39894228040143268f * __expf(-0.5f * z * z);
-  return cdf + z * pdf;
-}
 
 __global__ void lw_normalise_kernel(const float* x, int64_t n, int n_in, const float* norm, float* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,16 +455,6 @@ __global__ void lw_normalise_kernel(const float* x, int64_t n, int n_in, const f
     const int k = (int)(i % n_in);
     out[i] = (x[i] - norm[k]) * norm[n_in + k];
   }
-}
-
-__global__ void lw_gelu_kernel(const float* z, float* h, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) h[i] = gelu_f(z[i]);
-}
-
-__global__ void lw_gelu_back_kernel(const float* z, float* dh, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dh[i] *= gelu_grad_f(z[i]);
 }
 
 // dY = 2 (Y - T) / (rows * cols); per-block partial sums of (Y - T)^2
@@ -443,6 +617,7 @@ struct lw_mlp {
   double* loss_part = nullptr;
   double* col_part = nullptr;  // stage-1 partial column sums [row blocks][max(n_out, hidden + 1)]
   float* err_buf = nullptr;
+  float* splitk = nullptr;     // partial weight gradients [kMaxSplits][largest layer]
   std::vector<int64_t> w_off, b_off;
 };
 
@@ -523,7 +698,9 @@ lw_status input_of(lw_mlp* n, const float* x, int64_t rows, const float** in) {
 }
 
 // forward: fills z_l, h_l and y (into `y` if given, else the workspace)
-lw_status forward(lw_mlp* n, const float* raw, const float* x, int64_t rows, float* y) {
+// keep_pre: also keep each hidden layer's pre-activation z (the backward needs it); inference
+// writes the activations alone.
+lw_status forward(lw_mlp* n, const float* raw, const float* x, int64_t rows, float* y, bool keep_pre = true) {
   hipStream_t s = n->c->stream;
   const float* in = x;
   for (int l = 0; l <= n->n_hidden; ++l) {
@@ -535,13 +712,16 @@ lw_status forward(lw_mlp* n, const float* raw, const float* x, int64_t rows, flo
       g.row_stride = n->n_in;
       g.row_coeff = n->skip_coeff;
     }
-    MLP_HIP(lw::gemm_bf16(g, s), "gemm forward");
-    if (l < n->n_hidden) {
-      dim3 grid((unsigned)((rows * dout + 255) / 256));
-      hipLaunchKernelGGL(lw::lw_gelu_kernel, grid, dim3(256), 0, s, out, h_of(n, l, rows), rows * dout);
-      MLP_HIP(hipGetLastError(), "gelu");
-      in = h_of(n, l, rows);
+    if (l < n->n_hidden) {  // pre-activation and GELU in one pass
+      if (keep_pre) {
+        g.H = h_of(n, l, rows);
+      } else {
+        g.C = h_of(n, l, rows);
+        g.gelu_out = 1;
+      }
     }
+    MLP_HIP(lw::gemm_bf16(g, s), "gemm forward");
+    if (l < n->n_hidden) in = h_of(n, l, rows);
   }
   return LW_OK;
 }
@@ -555,6 +735,7 @@ lw_status backward(lw_mlp* n, const float* x, int64_t rows) {
     const float* in = l == 0 ? x : h_of(n, l - 1, rows);
     // dW[o][i] = sum_r d[r][o] in[r][i]
     lw::GemmDesc gw{d, 1, dout, in, din, 1, n->g + n->w_off[l], din, nullptr, dout, din, rows};
+    gw.part = n->splitk;  // many rows, few outputs: the rows are split over work-groups
     MLP_HIP(lw::gemm_bf16(gw, s), "gemm dW");
     lw_status cst = colsum(n, d, rows, dout, dout, nullptr, nullptr, 1.0, n->g + n->b_off[l]);
     if (cst != LW_OK) return cst;
@@ -562,11 +743,8 @@ lw_status backward(lw_mlp* n, const float* x, int64_t rows) {
       // dh[r][i] = sum_o d[r][o] W[o][i], then times gelu'(z)
       float* dh = (d == dz_of(n, rows)) ? dh_of(n, rows) : dz_of(n, rows);
       lw::GemmDesc gx{d, dout, 1, n->p + n->w_off[l], din, 1, dh, din, nullptr, rows, din, dout};
+      gx.Z = z_of(n, l - 1, rows);  // times GELU'(z) of the layer below, in the same pass
       MLP_HIP(lw::gemm_bf16(gx, s), "gemm dX");
-      dim3 grid((unsigned)((rows * din + 255) / 256));
-      hipLaunchKernelGGL(lw::lw_gelu_back_kernel, grid, dim3(256), 0, s, z_of(n, l - 1, rows), dh,
-                         rows * din);
-      MLP_HIP(hipGetLastError(), "gelu back");
       d = dh;
     }
   }
@@ -742,6 +920,9 @@ lw_status lw_mlp_create(lw_ctx* c, int32_t n_in, int32_t hidden, int32_t n_hidde
   alloc(&n->hm, hidden + 1);
   alloc(&n->hv, hidden + 1);
   alloc(&n->hg, hidden + 1);
+  int64_t largest = 0;  // the largest layer's weights: the split partial products of its gradient
+  for (int l = 0; l <= n_hidden; ++l) largest = std::max<int64_t>(largest, n->b_off[l] - n->w_off[l]);
+  alloc(&n->splitk, (int64_t)lw::kMaxSplits * largest);
   if (rc == LW_OK) {
     std::vector<float> zeros(std::max<int64_t>(off, hidden + 1), 0.0f);
     (void)hipMemcpy(n->p, h.data(), off * sizeof(float), hipMemcpyHostToDevice);
@@ -765,7 +946,7 @@ void lw_mlp_destroy(lw_mlp* n) {
   if (n->c) (void)hipStreamSynchronize(n->c->stream);
   for (void* p : {(void*)n->p, (void*)n->m, (void*)n->v, (void*)n->g, (void*)n->hp, (void*)n->hm,
                   (void*)n->hv, (void*)n->hg, (void*)n->act, (void*)n->loss_part, (void*)n->err_buf,
-                  (void*)n->col_part,
+                  (void*)n->col_part, (void*)n->splitk,
                   (void*)n->norm})
     if (p) (void)hipFree(p);
   delete n;
@@ -893,7 +1074,7 @@ lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, floa
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);
-  if (st == LW_OK) st = forward(n, x, in, rows, y);
+  if (st == LW_OK) st = forward(n, x, in, rows, y, false);
   if (st != LW_OK) return st;
   if (err_head) {
     hipLaunchKernelGGL(lw::lw_head_fwd_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0,
@@ -933,7 +1114,7 @@ lw_status lw_mlp_train_head_step(lw_mlp* n, const float* x, const float* err_tar
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);
-  if (st == LW_OK) st = forward(n, x, in, rows, y_of(n, rows));
+  if (st == LW_OK) st = forward(n, x, in, rows, y_of(n, rows), false);  // the head reads h only
   if (st != LW_OK) return st;
   hipStream_t s = n->c->stream;
   const float* hlast = h_of(n, n->n_hidden - 1, rows);

@@ -152,12 +152,15 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
 
 class Judge:
     """Accumulators of the held-out particles: exact, as the pipeline estimates them
-    (surrogate, exact where flagged), and surrogate alone."""
+    (surrogate, exact where flagged), and surrogate alone; plus the exact sum of every other
+    held-out particle, so that the sampling noise of the held-out sum can be measured on the
+    same particles (split-half floor)."""
 
     def __init__(self, ctx: Context):
         om = ctx.get_frequencies()
         self.exact, self.pipe, self.sur = Context(ctx.device), Context(ctx.device), Context(ctx.device)
-        for c in (self.exact, self.pipe, self.sur):
+        self.half = Context(ctx.device)
+        for c in (self.exact, self.pipe, self.sur, self.half):
             c.set_directions(ctx.dirs)
             c.set_frequencies(om)
             c.set_species(ctx.ns)
@@ -172,6 +175,9 @@ class Judge:
         P, nd = batch.n_particles, self.sur.nd
         held_d = torch.from_numpy(held).to(dev, non_blocking=True)
         self.exact.accumulate_subset(batch, held_d)
+        # every other held-out particle (counting across chunks) for the split-half floor
+        first = self.n % 2
+        self.half.accumulate_subset(batch, held_d[first::2].contiguous())
         # an "error" of 0 keeps a particle on the surrogate sum, 1 leaves it out (threshold 0.5)
         keep = torch.ones((P, nd), dtype=torch.float32, device=dev)
         keep[held_d] = 0.0
@@ -187,6 +193,10 @@ class Judge:
     def spectra(self):
         """(exact, pipeline, surrogate-only) spectra of the held-out particles."""
         return self.exact.read_spectra(), self.pipe.read_spectra(), self.sur.read_spectra()
+
+    def half_spectrum(self):
+        """Exact spectrum of every other held-out particle."""
+        return self.half.read_spectra()
 
 
 def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge | None = None, held=None,
@@ -214,6 +224,21 @@ def held_out_errors(S_exact, S_sur, floor=1e-4):
     for se, ss in zip(S_exact.reshape(-1, S_exact.shape[-1]), S_sur.reshape(-1, S_sur.shape[-1])):
         m = se >= floor * se.max()
         rel = np.abs(ss[m] - se[m]) / se[m]
+        worst.append(float(rel.max()))
+        med.append(float(np.median(rel)))
+    return {"per_bin_max": max(worst), "per_bin_median": float(np.median(med)), "per_direction_max": worst}
+
+
+def split_half_floor(S_exact, S_half, floor=1e-4):
+    """Sampling noise of the held-out sum, measured on the same particles: with S_a the exact
+    sum of every other held-out particle and S_b = S - S_a the rest, |S_a - S_b| / S per bin
+    has the spread of the difference between the held-out sum and a perfect prediction of its
+    mean (the two halves are independent and each carries half the variance).  Per-bin max
+    and median over the bins held_out_errors scores."""
+    worst, med = [], []
+    for se, sa in zip(S_exact.reshape(-1, S_exact.shape[-1]), S_half.reshape(-1, S_half.shape[-1])):
+        m = se >= floor * se.max()
+        rel = np.abs(2.0 * sa[m] - se[m]) / se[m]
         worst.append(float(rel.max()))
         med.append(float(np.median(rel)))
     return {"per_bin_max": max(worst), "per_bin_median": float(np.median(med)), "per_direction_max": worst}

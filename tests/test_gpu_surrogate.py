@@ -6,16 +6,17 @@ Tolerances.  Features are FP64 sums rounded once to FP32 (rtol 2e-5); counts
 of reversals and of in-cone samples are FP64 decisions on the same inputs on
 both sides (they may differ by at most one sample on an exact tie).  The
 network multiplies BF16-rounded operands (unit roundoff u = 2^-8) with FP32
-accumulation: each layer's output carries a normwise error of order 2u, the
-backward pass of a network with L hidden layers compounds about 2L + 1 such
-roundings, so the bars are 2e-2 normwise for outputs and 5e-2 for each layer's
-gradient block.  A purely linear layer on operands that are already BF16
-values is exact up to FP32 accumulation (bar 1e-5).
+accumulation: every output and gradient element is held to twice its first-order
+bound, the standard bound of a rounded dot product (2u + K u32) sum_k |a_ik| |b_kj|
+per product, propagated through the layers and GELU.  A purely linear layer on
+operands that are already BF16 values is exact up to FP32 accumulation (bar
+1e-5).
 """
 import time
 
 import numpy as np
 import pytest
+import scipy.special as sp
 
 import oracle
 import workloads
@@ -110,8 +111,74 @@ def test_linear_layer_is_exact_on_bf16_operands():
         np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-5)
 
 
-@pytest.mark.parametrize("rows", [64, 150])
+U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significant bits, round to nearest)
+U_FP32 = 2.0 ** -24
+GELU1 = 1.1289       # max |GELU'(z)| (at z = +-sqrt(2))
+GELU2 = 0.7979       # max |GELU''(z)| (at z = 0: 2 phi(0))
+
+
+def _layers(shape, p):
+    """Per-layer (W [out][in], b [out]) views of a flat parameter vector."""
+    n_in, hidden, n_hidden, n_out = shape
+    widths = [n_in] + [hidden] * n_hidden + [n_out]
+    out, off = [], 0
+    for l in range(n_hidden + 1):
+        din, dout = widths[l], widths[l + 1]
+        out.append((p[off:off + din * dout].reshape(dout, din), p[off + din * dout: off + din * dout + dout]))
+        off += din * dout + dout
+    return out
+
+
+def _elementwise_bounds(shape, p, x, t):
+    """First-order element-wise error bounds of the BF16 network against exact arithmetic.
+
+    Each product rounds both operands to BF16 and accumulates in FP32, so its own error is
+    at most (2 u + K u32) sum_k |a_ik| |b_kj| (the standard bound of a rounded dot product);
+    input errors propagate through |W| and through GELU with its Lipschitz constants.  The
+    intermediates (z, a, the back-propagated signals d) are formed here in FP64 from the
+    oracle's definition and checked against the oracle's own output and gradient, so that
+    the bounds belong to the values the oracle computes.
+    Returns (y, grad, bound_y, bound_grad) with grad laid out like the parameters."""
+    layers = _layers(shape, p)
+    L = len(layers) - 1
+    a, z, ea, ez = [x], [], [np.zeros_like(x)], []
+    for l, (W, b) in enumerate(layers):
+        K = W.shape[1]
+        zl = a[l] @ W.T + b
+        ezl = ea[l] @ np.abs(W).T + (2 * U_BF16 + K * U_FP32) * (np.abs(a[l]) @ np.abs(W).T)
+        z.append(zl)
+        ez.append(ezl)
+        if l < L:
+            a.append(oracle.mlp_gelu(zl))
+            ea.append(GELU1 * ezl)
+    y, ey = z[L], ez[L]
+    rows, n_out = y.shape
+    d = 2.0 * (y - t) / (rows * n_out)
+    ed = 2.0 * ey / (rows * n_out)
+    grads, bounds = [None] * (L + 1), [None] * (L + 1)
+    for l in range(L, -1, -1):
+        W, _ = layers[l]
+        dW = d.T @ a[l]
+        edW = ed.T @ np.abs(a[l]) + np.abs(d).T @ ea[l] + (2 * U_BF16 + rows * U_FP32) * (np.abs(d).T @ np.abs(a[l]))
+        db = d.sum(0)
+        edb = ed.sum(0) + rows * U_FP32 * np.abs(d).sum(0)
+        grads[l] = np.concatenate([dW.ravel(), db])
+        bounds[l] = np.concatenate([edW.ravel(), edb])
+        if l > 0:
+            K = W.shape[0]
+            back = d @ W
+            eback = ed @ np.abs(W) + (2 * U_BF16 + K * U_FP32) * (np.abs(d) @ np.abs(W))
+            zl = z[l - 1]
+            gp = 0.5 * (1.0 + sp.erf(zl / np.sqrt(2.0))) + zl * np.exp(-0.5 * zl * zl) / np.sqrt(2.0 * np.pi)
+            ed = eback * np.abs(gp) + np.abs(back) * GELU2 * ez[l - 1]
+            d = back * gp
+    return y, np.concatenate(grads), ey, np.concatenate(bounds)
+
+
+@pytest.mark.parametrize("rows", [64, 150, 4100])
 def test_forward_and_gradients_match_oracle(rows):
+    """Every output and every gradient element within twice its first-order bound (the
+    second-order terms and the rounding of the bound itself are covered by the factor 2)."""
     import torch
 
     c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
@@ -124,25 +191,22 @@ def test_forward_and_gradients_match_oracle(rows):
     x = rng.normal(size=(rows, 16)).astype(np.float32)
     t = rng.normal(size=(rows, 48)).astype(np.float32)
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
-    y = net.forward(xd).cpu().numpy()
+    y = net.forward(xd).cpu().numpy().astype(np.float64)
     loss, g = net.loss_grad(xd, td)
     ref = oracle.mlp_forward_backward(shape, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
                                       want_grad=True)
-    e_y = _rel(y, ref["y"])
-    print(f"[mlp] rows {rows}: output normwise {e_y:.2e}, loss {loss:.6f} vs {ref['loss']:.6f}", flush=True)
-    assert e_y < 2e-2
+    yb, gb, ey, eg = _elementwise_bounds(shape, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    # the bound's intermediates are the oracle's values
+    np.testing.assert_allclose(yb, ref["y"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(gb, ref["grad"], rtol=1e-9, atol=1e-15)
+    ry = np.abs(y - ref["y"]) / ey
+    rg = np.abs(g.astype(np.float64) - ref["grad"]) / np.maximum(eg, 1e-30)
+    print(f"[mlp] rows {rows}: output error / bound max {ry.max():.3f} (mean {ry.mean():.3f}); gradient "
+          f"error / bound max {rg.max():.3f} (mean {rg.mean():.3f}); loss {loss:.6f} vs {ref['loss']:.6f}",
+          flush=True)
+    assert ry.max() <= 2.0
+    assert rg.max() <= 2.0
     assert abs(loss - ref["loss"]) <= 2e-2 * ref["loss"]
-    # each layer's weight and bias blocks
-    widths = [16, 64, 64, 64, 48]
-    off = 0
-    for layer in range(4):
-        din, dout = widths[layer], widths[layer + 1]
-        for name, n in (("W", din * dout), ("b", dout)):
-            e = _rel(g[off:off + n], ref["grad"][off:off + n])
-            print(f"[mlp] layer {layer} d{name}: normwise {e:.2e}", flush=True)
-            assert e < 5e-2, (layer, name, e)
-            off += n
-    assert off == g.size
 
 
 def test_input_normalisation_matches_oracle_on_normalised_inputs():
@@ -309,6 +373,7 @@ def test_trained_surrogate_is_judged_and_gains_over_exact():
     t_pipe = time.perf_counter() - t0
     held_err = sg.held_out_errors(Se, Sp)
     sur_only = sg.held_out_errors(Se, Ss)
+    floor = sg.split_half_floor(Se, judge.half_spectrum())
     ens = sg.held_out_errors(S_exact, S_pipe)
     band = float(np.max(band_integrated_errors(Sp, Se, omega)))
     for d in range(c.nd):
@@ -323,11 +388,17 @@ def test_trained_surrogate_is_judged_and_gains_over_exact():
           f"{band:.3e}; whole chunk per-bin max {ens['per_bin_max']:.3e} median {ens['per_bin_median']:.3e}; "
           f"exact {t_exact * 1e3:.1f} ms, pipeline {t_pipe * 1e3:.1f} ms, gain {t_exact / t_pipe:.2f}x",
           flush=True)
+    print(f"[surrogate] held-out split-half floor: per-bin max {floor['per_bin_max']:.3e}, median "
+          f"{floor['per_bin_median']:.3e}", flush=True)
     assert r["fallback"] <= 0.15 * b.n_particles
-    # Two thousand held-out particles: in the perpendicular directions a few
-    # particles carry much of the power, and their spectra scatter about any
-    # prediction by tens of percent, so the held-out bar is on the median bin;
-    # the whole chunk (4e4 particles, 5 % of them exact) is held to 15 % per bin.
+    # The target is 5 % per bin of the summed held-out spectrum.  Two thousand held-out
+    # particles are too few for it in the perpendicular directions, where a few particles
+    # carry much of the power: even a perfect prediction of each particle's mean spectrum
+    # would miss their sum by the sampling noise, measured on the same particles as the
+    # split-half floor.  The per-bin maximum must meet the target or stay within twice
+    # that floor (the largest of several hundred noisy bins fluctuates by tens of percent
+    # between two samples); the median bin must meet the target outright.
+    assert held_err["per_bin_max"] <= max(0.05, 2.0 * floor["per_bin_max"])
     assert held_err["per_bin_median"] < 0.05
     assert ens["per_bin_max"] < 0.15
     assert ens["per_bin_median"] < 0.03
