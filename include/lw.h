@@ -155,6 +155,20 @@ lw_status lw_workspace_size(lw_ctx* ctx, const lw_batch* batch, lw_path path, si
 lw_status lw_accumulate(lw_ctx* ctx, const lw_batch* batch, lw_path path, void* workspace,
                         size_t workspace_bytes, float* per_particle);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): lw_accumulate on the FP32 path, plain
+ * grid launch, with its per-block partial sums in a library-owned static device array of
+ * LW_NOALLOC_SCRATCH_MB MiB instead of a caller workspace.  The call itself allocates
+ * nothing (no hipMalloc, no events; profiling and per-particle output are not offered).
+ * Each GPU holds its own copy of the array from the first lw_create on it until the process
+ * ends; every call on that GPU shares it, so calls that overlap on one GPU (several contexts
+ * or streams) race -- order them on one stream.  The partial sums need n_blocks x
+ * n_species x nd x nw (x 4 in coherent mode) doubles, n_blocks as lw_workspace_size of the
+ * FP32 path counts them; a batch that needs more than the array is refused with LW_ENOMEM
+ * before any launch.  Results equal lw_accumulate's plain-grid FP32 results bit for bit. */
+#define LW_NOALLOC_SCRATCH_MB 64
+lw_status lw_accumulate_noalloc(lw_ctx* ctx, const lw_batch* batch);
+
 /* Synchronise the stream and copy S to host_out [n_species][nd][nw] (FP64).
  * Returns LW_ERANGE (with the particle index in lw_last_error) if a device
  * data error was recorded since the last reset; S is copied regardless. */

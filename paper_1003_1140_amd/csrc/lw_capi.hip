@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -122,6 +123,34 @@ lw_status check_grids(lw_ctx* c) {
 using lw::DirectShape;
 using lw::direct_shape;
 
+// Partial sums of lw_accumulate_noalloc: a file-scope device array, one copy per GPU the
+// library runs on, held until the process ends.  In host code `scratch` only names the
+// symbol; its device address on each GPU comes from hipGetSymbolAddress (scratch_on).
+constexpr size_t kNoallocScratchBytes = (size_t)LW_NOALLOC_SCRATCH_MB << 20;
+static __device__ __attribute__((aligned(256))) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array, looked up once per device with that device
+// current (lw_create calls it, so the no-allocation entry point finds it ready).
+lw_status scratch_on(lw_ctx* c, void** out) {
+  if (c->device < 0 || c->device >= kMaxDevices) return fail(c, LW_EUNSUPPORTED, "device index %d too large", c->device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[c->device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(c, LW_EDEVICE, "hipGetDevice failed");
+    if (prev != c->device && hipSetDevice(c->device) != hipSuccess) return fail(c, LW_EDEVICE, "hipSetDevice failed");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != c->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) return fail(c, LW_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[c->device] = p;
+  }
+  *out = g_scratch_ptr[c->device];
+  return LW_OK;
+}
+
 // Wait for the stream, then turn the device's records into a status: a batch that outgrew
 // the matrix-core plan first (its result is incomplete), then bad data.
 lw_status read_device_errors(lw_ctx* c) {
@@ -201,6 +230,12 @@ lw_status lw_create(lw_ctx** out, int device, void* stream) {
     return LW_EDEVICE;
   }
   c->mfma = lw::mfma_cache_create();
+  void* sp = nullptr;
+  const lw_status sst = scratch_on(c, &sp);
+  if (sst != LW_OK) {
+    lw_destroy(c);
+    return sst;
+  }
   *out = c;
   return LW_OK;
 }
@@ -415,6 +450,52 @@ lw_status lw_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, si
   } else {
     return fail(c, LW_EINVAL, "unknown path %d", (int)path);
   }
+  c->calls += 1;
+  return LW_OK;
+}
+
+lw_status lw_accumulate_noalloc(lw_ctx* c, const lw_batch* b) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (b->n_particles == 0) return LW_OK;
+  const DirectShape s = direct_shape(c, b->n_particles);
+  const int ncomp = lw::direct_ncomp(c);
+  const size_t need = (size_t)s.n_blocks * c->ns * c->nd * c->nw * ncomp * sizeof(double);
+  if (need > kNoallocScratchBytes)
+    return fail(c, LW_ENOMEM,
+                "the batch needs %zu bytes of partial sums, more than the %zu-byte static scratch of "
+                "lw_accumulate_noalloc: split the batch or use lw_accumulate with a workspace",
+                need, kNoallocScratchBytes);
+  void* sp = nullptr;
+  st = scratch_on(c, &sp);  // found by lw_create: a lookup, no allocation
+  if (st != LW_OK) return st;
+  DeviceGuard g(c->device);
+  lw::DirectArgs a;
+  a.b = lw::view_of(b);
+  a.dirs = c->d_dirs;
+  a.wturn = c->d_wturn;
+  a.nd = c->nd;
+  a.nw = c->nw;
+  a.ns = c->ns;
+  a.ncomp = ncomp;
+  a.pb = s.pb;
+  a.n_blocks = s.n_blocks;
+  a.n_tiles = s.n_tiles;
+  a.partial = (double*)sp;  // every row is written by its item before the reduction reads it
+  a.per_particle = nullptr;
+  a.amp = nullptr;
+  a.err = c->d_err;
+  a.perm = nullptr;
+  a.order = nullptr;
+  a.ticket = nullptr;
+  a.n_items = 0;
+  LW_HIP(lw::launch_direct_f32(a, s.wpt, c->stream), "launch lw_direct_f32 (no allocation)");
+  LW_HIP(lw::launch_reduce_partials(a.partial, s.n_blocks, (int64_t)c->ns * c->nd * c->nw * ncomp,
+                                    direct_target(c), c->stream),
+         "launch lw_reduce_partials");
   c->calls += 1;
   return LW_OK;
 }

@@ -37,7 +37,7 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
             "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes",
             "lw_spectral_diagnostics", "lw_pitch_cones", "lw_profile_cu_busy", "lw_save_accumulator",
-            "lw_load_accumulator_file", "lw_mlp_save", "lw_mlp_load")
+            "lw_load_accumulator_file", "lw_mlp_save", "lw_mlp_load", "lw_accumulate_noalloc")
 
 
 class LWError(RuntimeError):
@@ -130,6 +130,7 @@ def load_library():
             "lw_load_accumulator_file": (ctypes.c_int, [P, ctypes.c_char_p]),
             "lw_mlp_save": (ctypes.c_int, [P, ctypes.c_char_p]),
             "lw_mlp_load": (ctypes.c_int, [P, ctypes.c_char_p]),
+            "lw_accumulate_noalloc": (ctypes.c_int, [P, ctypes.POINTER(lw_batch)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -269,6 +270,10 @@ class Context:
                                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                            ctypes.c_void_p(pp) if pp else None))
         return workspace
+
+    def accumulate_noalloc(self, batch: DeviceBatch):
+        """FP32 path with the library's static scratch for partial sums: no allocation."""
+        self._check(self.lib.lw_accumulate_noalloc(self.h, ctypes.byref(batch.struct)))
 
     def read_spectra(self):
         out = np.zeros((self.ns, self.nd, self.nw), dtype=np.float64)
