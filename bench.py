@@ -88,11 +88,18 @@ C3_TERMS = C3_PARTICLES * 2048 * 16 * 2048  # the full mixed-precision ensemble:
 
 def split_path(name):
     """'mfma_f16x3' -> ('mfma_f16', 3); 'fp32' -> ('fp32', 1)."""
-    if name.endswith("x3"):
-        return name[:-2], 3
-    if name.endswith("x1"):
-        return name[:-2], 1
+    for k in (1, 2, 3):
+        if name.endswith(f"x{k}"):
+            return name[:-2], k
     return name, 1
+
+
+def mfma_options(ctx, bands, path, products):
+    """Band count and product count of one matrix-core path (the other type keeps three)."""
+    if path == "mfma_bf16":
+        ctx.set_mfma_options(bands, 3, products)
+    else:
+        ctx.set_mfma_options(bands, products, 3)
 
 
 def parse():
@@ -114,8 +121,8 @@ def parse():
     ap.add_argument("--c2-particles", type=int, default=100_000, help="particles of the jitter (c2) leg")
     ap.add_argument("--c2-steps", type=int, default=3, help="timed steps of the FP32 path on the c2 leg")
     ap.add_argument("--chunk", type=int, default=8192, help="particles generated per host chunk")
-    ap.add_argument("--paths", default="mfma_f16x1,mfma_bf16x3,mfma_f16x3",
-                    help="comma list of fp32, mfma_f16[x1|x3], mfma_bf16[x1|x3]; the last one is the headline")
+    ap.add_argument("--paths", default="mfma_f16x1,mfma_f16x2,mfma_bf16x3,mfma_f16x3",
+                    help="comma list of fp32, mfma_f16[x1|x2|x3], mfma_bf16[x1|x3]; the last one is the headline")
     ap.add_argument("--bands", type=int, default=2,
                     help="frequency bands of the matrix-core paths (2 measured fastest on both workloads: "
                          "the upper band keeps the grid, the lower one is ~9x coarser)")
@@ -161,8 +168,9 @@ def band_integrated_error(S, ref, om, n_bands=16, floor=1e-4):
 
 TRAFFIC_PROFILES = {
     "c2": os.path.join(ROOT, "profiles", "lw_dft_mfma_r128__jitter_1e5x4096_4dir_1024w.md"),
-    "c3": os.path.join(ROOT, "profiles", "lw_mfma__c3_slice_1e5x2048_16dir_2048w.md"),
+    "c3": os.path.join(ROOT, "profiles", "lw_mfma__mixed_precision_1e6x2048_16dir_2048w.md"),
 }
+PROFILED_PARTICLES = {"c2": 100_000, "c3": 1_000_000}
 TRAFFIC_FIELDS = {"contraction": "traffic_bytes_per_launch", "spread": "spread_traffic_bytes_per_launch"}
 
 
@@ -181,7 +189,9 @@ def profiled_traffic(path, tile, particles, workload="c3", bands=2, kernel="cont
     counter profile of this exact configuration (the default launch of the workload), or None
     when there is no such profile or the kernel code or the band count differs from the
     profiled run."""
-    if path != "mfma_f16x3" or tile not in (0, 4) or particles != 100_000 or workload not in TRAFFIC_PROFILES:
+    if path != "mfma_f16x3" or tile not in (0, 4) or workload not in TRAFFIC_PROFILES:
+        return None
+    if particles != PROFILED_PARTICLES[workload]:
         return None
     try:
         text = open(TRAFFIC_PROFILES[workload]).read()
@@ -214,7 +224,7 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
     import torch
 
     path, products = split_path(name)
-    ctx.set_mfma_options(bands, products, products)
+    mfma_options(ctx, bands, path, products)
     ws = ctx.workspace(batch, path)
     for _ in range(warmup):
         ctx.accumulate(batch, path, workspace=ws)
@@ -333,7 +343,7 @@ def oracle_check(recipe, dirs, om, paths, bands, n_particles=8):
         c = Context(0)
         c.set_directions(dirs)
         c.set_frequencies(om)
-        c.set_mfma_options(bands, products, products)
+        mfma_options(c, bands, path, products)
         c.accumulate(dev, path, workspace=c.workspace(dev, path))
         S = c.read_spectra()
         c.close()
@@ -901,7 +911,7 @@ def main():
                     "ms_per_step": rf["ms_per_step"], "roofline": rf["roofline"]}
         for name in paths:
             path, products = split_path(name)
-            ctx.set_mfma_options(a.bands, products, products)
+            mfma_options(ctx, a.bands, path, products)
             ctx.reset()
             ctx.accumulate(sub, path, workspace=ctx.workspace(sub, path))
             fp32_cmp[name + "_band_integrated_err_vs_fp32"] = band_integrated_error(ctx.read_spectra(), sf, om)
@@ -920,6 +930,8 @@ def main():
                   "mfma_bf16": "bf16 hi/lo operands, f32 acc"}[split_path(head)[0]]
     if split_path(head)[1] == 1 and head != "fp32":
         path_dtype = path_dtype.replace(" hi/lo", "")
+    if split_path(head)[1] == 2:
+        path_dtype = "f16 operands (F hi/lo, table once), f32 acc"
     if a.workload == "c3":
         whole = a.particles == C3_PARTICLES
         config = {"workload": ("mixed-precision form: " + ("all of its" if whole else f"a slice of {a.particles} of its")

@@ -125,9 +125,13 @@ lw_status lw_set_species(lw_ctx* ctx, int32_t n_species);
  * of the frequency list, 1..16; default 1), each with its own retarded-time
  * grid.  More bands shrink the contraction (its rows per band) but every band
  * spreads every sample again.  products_f16 / products_bf16: 1 = operands rounded once to FP16/BF16;
- * 3 = each operand split into hi + lo parts and hi*hi + hi*lo + lo*hi summed
- * (defaults: 3 for both; one product keeps 11 (FP16) or 8 (BF16) mantissa
- * bits and is measured, not guaranteed, against the 1e-3 band target). */
+ * 3 = each operand split into hi + lo parts and hi*hi + hi*lo + lo*hi summed;
+ * 2 (FP16 only) = the phase table rounded once and F split, E_hi*F_hi +
+ * E_hi*F_lo summed.  Defaults: 3 for both.  One or two products keep 11 (FP16)
+ * or 8 (BF16) mantissa bits in at least one operand and are measured, not
+ * guaranteed, against the 1e-3 band target; they spread with the (W = 8,
+ * sigma = 2) kernel, three products with (W = 10, sigma = 1.6).  LW_EINVAL for
+ * other counts. */
 lw_status lw_set_mfma_options(lw_ctx* ctx, int32_t bands, int32_t products_f16,
                               int32_t products_bf16);
 
@@ -433,8 +437,11 @@ lw_status lw_profile_read(lw_ctx* ctx, double* host_out);
 /* Load balance of the last persistent FP32 launch made with profiling on (lw_plan_batch
  * plan in use): each work-group records the compute unit it ran on (XCC and hardware ids)
  * and its start and end on the device's real-time counter; a compute unit's busy time is
- * the sum over its work-groups of (end - start).  Synchronises.  host_out[4] = {compute
- * units seen, min, mean, max busy ms}.  LW_ESTATE if no such launch was made. */
+ * the sum over its work-groups of (end - start).  Several work-groups are resident on one
+ * compute unit at once, so a busy time is about that residency times the launch's duration;
+ * the spread of busy times across units is the load-balance figure.  Synchronises.
+ * host_out[4] = {compute units seen, min, mean, max busy ms}.  LW_ESTATE if no such launch
+ * was made. */
 lw_status lw_profile_cu_busy(lw_ctx* ctx, double* host_out);
 
 /* Number of successful lw_accumulate calls since creation. */

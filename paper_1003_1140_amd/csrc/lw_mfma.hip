@@ -25,7 +25,8 @@
 //        [C_im] = [E_im   E_re] [F_im]
 //    and runs on v_mfma_f32_32x32x16_{f16,bf16} with FP32 accumulation.
 //    Operands are rounded to FP16 (or BF16); optionally each is split into
-//    hi + lo parts and three products are summed (hi*hi + hi*lo + lo*hi).
+//    hi + lo parts and three products are summed (hi*hi + hi*lo + lo*hi), or
+//    (FP16) only F is split and two are summed (E_hi*F_hi + E_hi*F_lo).
 //    The F columns are scaled by a power of two so |F| <= 1 before rounding.
 //  * The epilogue squares the product, weights each column with
 //    w_p q_p^2 / scale^2, sums over columns and writes per-row partial sums;
@@ -57,7 +58,7 @@ struct KernelShape {
   double sigma, beta;
 };
 constexpr KernelShape kShapeSplit = {10, 1.6, 20.5};   // hi/lo operands, three products
-constexpr KernelShape kShapeSingle = {8, 2.0, 18.4};   // one product
+constexpr KernelShape kShapeSingle = {8, 2.0, 18.4};   // a table rounded once: one or two products
 constexpr int kWMax = 10;
 constexpr int kMaxBands = 16;
 constexpr int kTileM = 128;        // GEMM rows per work-group
@@ -336,6 +337,16 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
 
+// Work-groups go to the eight XCDs in turn (block b to XCD b mod 8).  This numbering gives
+// each XCD a contiguous run of n items instead, so that neighbouring items -- every (direction,
+// band) of one particle -- run on one XCD and read the particle's trajectory through one L2.
+// XCD x holds blocks x, x + 8, ...: m + (x < r) of them with n = 8 m + r, numbered from
+// x m + min(x, r); the map is a bijection of [0, n).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+  const int m = n / 8, r = n % 8, x = b % 8, j = b / 8;
+  return x * m + min(x, r) + j;
+}
+
 template <int kW>
 __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   __shared__ SpreadStage<kW> st;
@@ -345,10 +356,12 @@ __global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
   __shared__ float s_tap[kW / 2][kTapCoef];
 
   const int tid = threadIdx.x;
-  // block -> (particle, direction, band); bands fastest so one particle's work is adjacent
-  const int bi = blockIdx.x % a.nb;
-  const int d = (blockIdx.x / a.nb) % a.nd;
-  const int pl = blockIdx.x / (a.nb * a.nd);
+  // block -> item -> (particle, direction, band); bands fastest so one particle's work is
+  // adjacent, and each XCD takes a contiguous run of items
+  const int item = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+  const int bi = item % a.nb;
+  const int d = (item / a.nb) % a.nd;
+  const int pl = item / (a.nb * a.nd);
   const Band bd = a.band[bi];
   const int64_t p = a.p_begin + pl;
   const int64_t o = a.b.offsets[p], len = a.b.offsets[p + 1] - o;
@@ -649,6 +662,7 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
   constexpr int TM = 64 * WM;
   constexpr int NB = kTileN / (32 * WN);
   constexpr int LD = kTileK + kPad;
+  static_assert(PRODUCTS == 1 || PRODUCTS == 3, "one or three products");
   constexpr int NP = PRODUCTS > 1 ? 2 : 1;
   constexpr int A_VEC = TM * kTileK / 8 / NT;       // 8-element vectors of A per thread
   constexpr int B_VEC = kTileN * kTileK / 4 / NT;   // float4 of F per thread
@@ -969,7 +983,10 @@ __device__ __forceinline__ void coherent_epilogue(const GemmArgs& a, const f32x1
 template <typename T, int PRODUCTS, int WN, int MI, int NJ>
 __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_mfma_r128_kernel(GemmArgs a) {
   typedef typename MfmaOp<T>::vec vec;
-  constexpr int NT = 128 * WN, NW = 2 * WN, TN = 32 * NJ * WN, NP = PRODUCTS > 1 ? 2 : 1;
+  constexpr int NT = 128 * WN, NW = 2 * WN, TN = 32 * NJ * WN;
+  // operand parts: the table is split into hi + lo for three products, F for two or three
+  constexpr int NPA = PRODUCTS == 3 ? 2 : 1, NPB = PRODUCTS > 1 ? 2 : 1;
+  static_assert(PRODUCTS >= 1 && PRODUCTS <= 3, "one, two or three products");
   constexpr int TM = 64 * MI, WR = 32 * MI;  // tile rows, rows per wave
   typedef T t8 __attribute__((ext_vector_type(8)));
   typedef float f32x8 __attribute__((ext_vector_type(8)));
@@ -977,8 +994,8 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
   constexpr int BV = TN * 4 / NT;  // 8-float F chunks per thread and stage
   static_assert(kTileK == 32, "four 16-byte chunks per LDS row");
   static_assert(AV >= 1 && BV >= 1, "staging layout");
-  __shared__ __attribute__((aligned(16))) T sA[2][NP][TM * 32];
-  __shared__ __attribute__((aligned(16))) T sB[2][NP][TN * 32];
+  __shared__ __attribute__((aligned(16))) T sA[2][NPA][TM * 32];
+  __shared__ __attribute__((aligned(16))) T sB[2][NPB][TN * 32];
   __shared__ float s_scale[TN];
   __shared__ int s_q2[TN];
   __shared__ int s_fcol[TN];
@@ -1058,7 +1075,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
   // stage s of the inner dimension covers [32 s, 32 s + 32); LDS buffer s % 2
   const int nst = kend / kTileK;
   const int last = max(nst - 1, 0) * kTileK;
-  typedef u32x4 RegA[AV][NP];
+  typedef u32x4 RegA[AV][NPA];
   typedef f32x4 RegB[BV][2];
   // the thread's BV columns: F offset (column 0 stands in past the chunk, with length 0),
   // length and scale stay fixed over the inner loop
@@ -1079,7 +1096,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
     for (int v = 0; v < AV; ++v) {
       const size_t g = (size_t)(row0 + sr + (NT / 4) * v) * bd.kp + ke + sc4 * 8;
       ra[v][0] = *(const u32x4*)(E_hi + g);
-      if (NP > 1) ra[v][NP - 1] = *(const u32x4*)(E_lo + g);
+      if (NPA > 1) ra[v][NPA - 1] = *(const u32x4*)(E_lo + g);
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
@@ -1095,7 +1112,7 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
     for (int v = 0; v < AV; ++v) {
       const int r = sr + (NT / 4) * v;
       *(u32x4*)&sA[buf][0][swz(r, sc4)] = ra[v][0];
-      if (NP > 1) *(u32x4*)&sA[buf][NP - 1][swz(r, sc4)] = ra[v][NP - 1];
+      if (NPA > 1) *(u32x4*)&sA[buf][NPA - 1][swz(r, sc4)] = ra[v][NPA - 1];
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
@@ -1106,8 +1123,8 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
         // split x = hi + lo, both rounded to T, converting pairs of lanes at once
         const t8 hv = __builtin_convertvector(x, t8);
         *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
-        if (NP > 1)
-          *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = __builtin_convertvector(x - __builtin_convertvector(hv, f32x8), t8);
+        if (NPB > 1)
+          *(t8*)&sB[buf][NPB - 1][swz(r, sc4)] = __builtin_convertvector(x - __builtin_convertvector(hv, f32x8), t8);
       } else {  // BF16 in 128-row tiles: lane by lane schedules better (measured); in 256-row
                 // tiles it needs more than the 256 VGPRs available
         t8 hv, lv;
@@ -1115,10 +1132,10 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
         for (int e = 0; e < 8; ++e) {
           const float x = (e < 4 ? rb[v][0][e] : rb[v][1][e - 4]) * scl;
           hv[e] = (T)x;
-          if (NP > 1) lv[e] = (T)(x - (float)hv[e]);
+          if (NPB > 1) lv[e] = (T)(x - (float)hv[e]);
         }
         *(t8*)&sB[buf][0][swz(r, sc4)] = hv;
-        if (NP > 1) *(t8*)&sB[buf][NP - 1][swz(r, sc4)] = lv;
+        if (NPB > 1) *(t8*)&sB[buf][NPB - 1][swz(r, sc4)] = lv;
       }
     }
   };
@@ -1136,33 +1153,35 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int ch = 2 * ks + (lane >> 5);
-      vec fa[NP][MI], fb[NP][NJ];
+      vec fa[NPA][MI], fb[NPB][NJ];
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
         const int r = wr * WR + i * 32 + (lane & 31);
         fa[0][i] = *(const vec*)&sA[buf][0][swz(r, ch)];
-        if (NP > 1) fa[NP - 1][i] = *(const vec*)&sA[buf][NP - 1][swz(r, ch)];
+        if (NPA > 1) fa[NPA - 1][i] = *(const vec*)&sA[buf][NPA - 1][swz(r, ch)];
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int cc = wc * 32 * NJ + j * 32 + (lane & 31);
         fb[0][j] = *(const vec*)&sB[buf][0][swz(cc, ch)];
-        if (NP > 1) fb[NP - 1][j] = *(const vec*)&sB[buf][NP - 1][swz(cc, ch)];
+        if (NPB > 1) fb[NPB - 1][j] = *(const vec*)&sB[buf][NPB - 1][swz(cc, ch)];
       }
       // products outermost: consecutive MFMAs write different accumulators
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[0][j], acc[i][j]);
-      if (PRODUCTS > 1) {
+      if (PRODUCTS > 1) {  // table hi x F lo
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NP - 1][j], acc[i][j]);
+          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[0][i], fb[NPB - 1][j], acc[i][j]);
+      }
+      if (PRODUCTS > 2) {  // table lo x F hi
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NP - 1][i], fb[0][j], acc[i][j]);
+          for (int j = 0; j < NJ; ++j) acc[i][j] = MfmaOp<T>::mma(fa[NPA - 1][i], fb[0][j], acc[i][j]);
       }
     }
   };
@@ -1604,7 +1623,7 @@ lw_status ensure_plan(lw_ctx* c, const lw_batch* b, lw_path path, bool measure) 
   MfmaPlanCache* pc = c->mfma;
   const int dtype = path == LW_PATH_MFMA_BF16 ? 1 : 0;
   const int products = dtype ? pc->products_bf16 : pc->products_f16;
-  const KernelShape& ks = products > 1 ? kShapeSplit : kShapeSingle;
+  const KernelShape& ks = products == 3 ? kShapeSplit : kShapeSingle;
   const bool same = pc->valid && pc->dtype == dtype && pc->shape.w == ks.w;
   if (c->capturing) {
     if (same) return LW_OK;
@@ -1647,8 +1666,8 @@ void mfma_cache_invalidate(MfmaPlanCache* pc) {
 lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16) {
   MfmaPlanCache* pc = c->mfma;
   if (bands < 1 || bands > kMaxBands) return set_err(c, LW_EINVAL, "bands must be in [1, 16]");
-  if ((products_f16 != 1 && products_f16 != 3) || (products_bf16 != 1 && products_bf16 != 3))
-    return set_err(c, LW_EINVAL, "products must be 1 or 3");
+  if (products_f16 < 1 || products_f16 > 3 || (products_bf16 != 1 && products_bf16 != 3))
+    return set_err(c, LW_EINVAL, "products must be 1, 2 or 3 for FP16 and 1 or 3 for BF16");
   if (bands != pc->bands_req) free_tables(pc);
   pc->bands_req = bands;
   pc->products_f16 = products_f16;
@@ -1752,6 +1771,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   for (int i = 0; i < pc->nb; ++i)
     if (pc->band[i].m % 256 != 0) tile = tile == 2 ? 1 : tile == 4 ? 3 : tile;
   if (tile == 2 && (c->coherent || amp)) tile = 3;  // that kernel has no such epilogues
+  if (tile == 2 && products == 2) tile = 1;          // nor two products
   const int tm = tile == 2 || tile == 4 ? 256 : 128;
   const int tn = tile >= 3 ? 256 : 128;
   const bool bf = path == LW_PATH_MFMA_BF16;
@@ -1783,22 +1803,29 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     }
     ga.tiles_before[pc->nb] = tiles;
     MF_HIP(prof_begin(c, kProfGemm), "profile");
-#define LW_GEMM(T, P)                                                                            \
+#define LW_GEMM_R128(T, P)                                                                       \
   do {                                                                                           \
-    if (tile == 2)                                                                               \
-      hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
-    else if (tile == 4)                                                                          \
+    if (tile == 4)                                                                               \
       hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 4, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else if (tile == 3)                                                                          \
       hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 4, 2, 2>), dim3(tiles), dim3(512), 0, c->stream, ga); \
     else                                                                                         \
       hipLaunchKernelGGL((lw_dft_mfma_r128_kernel<T, P, 2, 2, 2>), dim3(tiles), dim3(256), 0, c->stream, ga); \
   } while (0)
+#define LW_GEMM(T, P)                                                                            \
+  do {                                                                                           \
+    if (tile == 2)                                                                               \
+      hipLaunchKernelGGL((lw_dft_mfma_kernel<T, P, 4>), dim3(tiles), dim3(512), 0, c->stream, ga); \
+    else                                                                                         \
+      LW_GEMM_R128(T, P);                                                                        \
+  } while (0)
     if (!bf && products == 1) LW_GEMM(_Float16, 1);
+    else if (!bf && products == 2) LW_GEMM_R128(_Float16, 2);
     else if (!bf) LW_GEMM(_Float16, 3);
     else if (products == 1) LW_GEMM(__bf16, 1);
     else LW_GEMM(__bf16, 3);
 #undef LW_GEMM
+#undef LW_GEMM_R128
     MF_HIP(hipGetLastError(), "launch dft_mfma");
     MF_HIP(prof_end(c), "profile");
     if (!amp) {

@@ -29,25 +29,26 @@ def test_traffic_is_reported_only_for_the_profiled_launch():
     b = _bench()
     src = open(os.path.join(ROOT, "paper_1003_1140_amd", "csrc", "lw_mfma.hip")).read()
     for workload, prof in b.TRAFFIC_PROFILES.items():
+        n = b.PROFILED_PARTICLES[workload]
         if not os.path.exists(prof):
-            assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, 2) is None
+            assert b.profiled_traffic("mfma_f16x3", 0, n, workload, 2) is None
             continue
         text = open(prof).read()
         fields = dict(line.split(":", 1) for line in text.splitlines() if ":" in line and not line.startswith(" "))
         profiled_bands = int(fields["bands"])
         if fields["kernel_code_sha256"].strip() != b.kernel_code_digest(src):
             # the kernel changed after the counters were taken: nothing may be reported
-            assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands) is None
+            assert b.profiled_traffic("mfma_f16x3", 0, n, workload, profiled_bands) is None
             continue
-        got = b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands)
+        got = b.profiled_traffic("mfma_f16x3", 0, n, workload, profiled_bands)
         assert got == float(fields["traffic_bytes_per_launch"])
-        got = b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands, "spread")
+        got = b.profiled_traffic("mfma_f16x3", 0, n, workload, profiled_bands, "spread")
         assert got == float(fields["spread_traffic_bytes_per_launch"])
         # any other launch gets none
-        assert b.profiled_traffic("mfma_f16x3", 0, 100_000, workload, profiled_bands + 1) is None
-        assert b.profiled_traffic("mfma_bf16x3", 0, 100_000, workload, profiled_bands) is None
-        assert b.profiled_traffic("mfma_f16x3", 1, 100_000, workload, profiled_bands) is None
-        assert b.profiled_traffic("mfma_f16x3", 0, 50_000, workload, profiled_bands) is None
+        assert b.profiled_traffic("mfma_f16x3", 0, n, workload, profiled_bands + 1) is None
+        assert b.profiled_traffic("mfma_bf16x3", 0, n, workload, profiled_bands) is None
+        assert b.profiled_traffic("mfma_f16x3", 1, n, workload, profiled_bands) is None
+        assert b.profiled_traffic("mfma_f16x3", 0, n // 2, workload, profiled_bands) is None
     assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "other", 2) is None
 
 

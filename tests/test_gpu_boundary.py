@@ -279,3 +279,17 @@ def test_persistent_launch_records_per_cu_busy_time():
     print(f"[cu busy] {r}", flush=True)
     assert 0 < r["cus"] <= 1024
     assert 0 < r["min_ms"] <= r["mean_ms"] <= r["max_ms"]
+
+
+def test_product_counts_accepted_and_refused():
+    """FP16 takes one, two or three products, BF16 one or three; anything else is refused."""
+    from paper_1003_1140_amd import LW_EINVAL, Context, LWError
+
+    c = Context(0)
+    for f16, bf16 in ((1, 1), (2, 3), (3, 1), (2, 1)):
+        c.set_mfma_options(2, f16, bf16)
+    for f16, bf16 in ((0, 3), (4, 3), (3, 2), (3, 0)):
+        with pytest.raises(LWError) as e:
+            c.set_mfma_options(2, f16, bf16)
+        assert e.value.status == LW_EINVAL
+    c.close()
