@@ -240,10 +240,13 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 //      written as zeros.
 // The next chunk starts with the sample that did not fit the ring, so every grid point
 // of a chunk lies within kRing of the oldest pending one.
-// Grid points held in LDS.  768 covers the grid points of a 256-sample chunk at the
-// oversamplings used, and keeps a work-group near 31 KB of LDS so that five share a CU
-// (1024 allowed four: measured 12 % slower).
-constexpr int kRing = 768;
+// Grid points held in LDS.  512 covers the grid points of a 256-sample chunk up to two
+// points per sample and keeps a work-group at 26 KB of LDS; with at most 80 VGPRs (the
+// launch bound below asks for six waves per SIMD) six work-groups share a CU.  Measured
+// against 768 (31 KB, five per CU): 4 % faster; 1024 (four per CU) was 12 % slower still.
+// Sparser columns take fewer samples per chunk.
+constexpr int kRing = 512;
+constexpr int kSpreadWavesPerSimd = 6;
 
 template <int kW>
 struct SpreadStage {
@@ -348,7 +351,7 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 }
 
 template <int kW>
-__global__ __launch_bounds__(kSpreadWin) void lw_spread_kernel(SpreadArgs a) {
+__global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_kernel(SpreadArgs a) {
   __shared__ SpreadStage<kW> st;
   __shared__ float s_wmax[kSpreadWin / 64];
   // the first W/2 tap polynomials, read at one address by all lanes (held as kernel

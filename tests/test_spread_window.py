@@ -9,7 +9,7 @@ table gives the first sample reaching each point of the chunk; a point below the
 first tap is final, is written and its slot cleared; points no sample reaches are written as
 zeros.  This module re-states that logic step by step, with the kernel's clamps and sizes, and
 checks on random first-tap sequences -- dense, sparse (3 to 7 points per sample), gapped,
-co-located -- at rings of 768 (the kernel's) and 1024 that
+co-located -- at rings of 512 (the kernel's), 768 and 1024 that
 
 * every index stays inside its buffer (first-sample table, ring, column),
 * no ring slot ever holds the running sums of two grid points at once,
@@ -121,7 +121,7 @@ SPACINGS = {
 
 
 @pytest.mark.parametrize("W", [8, 10])
-@pytest.mark.parametrize("k_ring", [768, 1024])
+@pytest.mark.parametrize("k_ring", [512, 768, 1024])
 @pytest.mark.parametrize("kind", sorted(SPACINGS))
 def test_every_point_written_once_and_equal_to_brute_force(kind, k_ring, W):
     rng = np.random.default_rng(sum(map(ord, kind)) * 7919 + k_ring * 31 + W)
@@ -142,7 +142,7 @@ def test_column_clipped_by_the_plan(W):
     qmax = int(lo[300])
     lo = np.minimum(lo, qmax + 1)
     vals = rng.normal(size=(600, W))
-    F, writes = emulate(lo, vals, qmax, W, 768)
+    F, writes = emulate(lo, vals, qmax, W, 512)
     assert np.all(writes == 1)
     np.testing.assert_allclose(F, brute(lo, vals, qmax, W), rtol=1e-12, atol=1e-12)
 
@@ -158,19 +158,20 @@ def test_disordered_data_ends_in_bounds(seed):
     lo[rng.random(700) < 0.3] = 1
     Q = 3000 + W + 1
     vals = rng.normal(size=(700, W))
-    emulate(lo, vals, Q, W, 768, strict=False)
+    emulate(lo, vals, Q, W, 512, strict=False)
 
 
 def test_sparse_first_chunk_spanning_the_ring():
     """The case the ring's origin rule exists for: spacings of 3 to 7 points, so that a first
-    chunk's taps reach past point kRing while point 0 is still unwritten."""
+    chunk's taps reach past point kRing while point 0 is still unwritten (rings of 512 and 768)."""
     rng = np.random.default_rng(12)
-    hit = 0
-    for _ in range(40):
-        lo, Q = ordered_case(rng, 600, SPACINGS["sparse_3_7"], 10)
-        hit += int(lo[min(254, len(lo) - 1)] + 9 >= 768)
-        vals = rng.normal(size=(600, 10))
-        F, writes = emulate(lo, vals, Q, 10, 768)
-        assert np.all(writes == 1)
-        np.testing.assert_allclose(F, brute(lo, vals, Q, 10), rtol=1e-12, atol=1e-12)
-    assert hit > 0
+    for k_ring in (512, 768):
+        hit = 0
+        for _ in range(40):
+            lo, Q = ordered_case(rng, 600, SPACINGS["sparse_3_7"], 10)
+            hit += int(lo[min(254, len(lo) - 1)] + 9 >= k_ring)
+            vals = rng.normal(size=(600, 10))
+            F, writes = emulate(lo, vals, Q, 10, k_ring)
+            assert np.all(writes == 1)
+            np.testing.assert_allclose(F, brute(lo, vals, Q, 10), rtol=1e-12, atol=1e-12)
+        assert hit > 0
