@@ -5,19 +5,21 @@ jitter generator (electrons of two gamma0 = 3 counter-streaming beams, kT = 0.01
 rest-frame spread, Boris-pushed through a static random-filament field, k^-2 over
 [0.5, 8], deflection parameter 0.3), 2048 samples each, seen from 16 directions
 (head-on, 15/30/45 degrees oblique at four azimuths, three perpendicular) on 2048
-log-spaced frequencies over [0.1, 1e3] omega_p.  The full ensemble has 1e6
-particles (6.87e16 terms, 123 GB of trajectories); one step is one lw_accumulate
-over a slice of it (1e5 particles by default) with the trajectories already
-resident in HBM, and the full-ensemble time is extrapolated linearly.
+log-spaced frequencies over [0.1, 1e3] omega_p.  The ensemble has 1e6 particles
+(6.71e13 terms, 123 GB of trajectories, generated on the device); one step is one
+lw_accumulate over all of it with the trajectories already resident in HBM
+(--particles takes a slice instead).
 
 metric: terms/s, a term being one (particle, sample, direction, frequency)
 product of the spectral sum.  The headline path is the matrix-core contraction
-with FP16 hi/lo operands; its band-integrated error against the FP64 oracle is
-measured on 8 particles of the same workload.
+with FP16 hi/lo operands and three products; the other matrix-core variants
+(one and two FP16 products, BF16 hi/lo) are timed on the same tensors, the FP32
+path on its first 5e4 particles, and every path's band-integrated error against
+the FP64 oracle is measured on 8 particles of the same workload.
 
-Legs (each its own JSON object): the FP32 path on the 1e5-particle, 4096-sample,
-4-direction, 1024-frequency jitter ensemble, with coherent, in-situ and coupled
-recording on it; the batched uneven three-species workload (64 directions) with
+Legs (each its own JSON object): the FP32 and FP16 hi/lo paths on the
+1e5-particle, 4096-sample, 4-direction, 1024-frequency jitter ensemble, with
+coherent, in-situ and coupled recording; the batched uneven three-species workload (64 directions) with
 per-CU busy spread; the learned surrogate (training on 1.25e5 particles' exact
 spectra, inference on 1e6 particles with fallback and a 1 % held-out judge); and
 the FP64 oracle on the host cores.
