@@ -28,8 +28,13 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 # matrix-core path: the band-integrated bars of its incoherent parity (FP16 hi/lo 1e-5,
 # BF16 hi/lo 1e-4) on the coherent power, and a per-bin sanity bar on the amplitude
-MFMA_BAND_TOL = {"mfma_f16": 1e-5, "mfma_bf16": 1e-4}
-MFMA_AMP_SANITY = 1e-3
+# Two FP16 products (the phase table rounded once) are measured here and bounded loosely:
+# in a coherent sum the table's rounding error multiplies the summed F of all particles, so
+# it does not average out as it does over an incoherent ensemble, and where the particles'
+# amplitudes cancel it is a larger share of the power (9.2e-4 on the jitter case, 4.2e-3 on
+# the uneven three-species case, above the path's 1e-3 incoherent target).
+MFMA_BAND_TOL = {"mfma_f16": 1e-5, "mfma_bf16": 1e-4, "mfma_f16x2": 1e-2}
+MFMA_AMP_SANITY = {"mfma_f16": 1e-3, "mfma_bf16": 1e-3, "mfma_f16x2": 2e-2}
 
 
 def _ctx(dirs, omega, ns=1, coherent=True):
@@ -210,7 +215,7 @@ def test_incoherent_amplitude_state_over_windows(path, tile):
         one.species = np.zeros(1, dtype=np.int32)
         _, a_ref = oracle.coherent_spectrum(one, dirs, om, n_species=1, with_amplitude=True)
         e = _amp_error(st[p][None], a_ref, np.sum(np.abs(a_ref) ** 2, axis=-1))
-        assert e <= (TOL if path == "fp32" else MFMA_AMP_SANITY), (p, e)
+        assert e <= (TOL if path == "fp32" else MFMA_AMP_SANITY[path]), (p, e)
     c.close()
 
 
@@ -260,7 +265,9 @@ def test_graph_replays_in_coherent_mode():
                                                   ("mfma_f16", "jitter", 4, 2),
                                                   ("mfma_f16", "uneven_species", 3, 1),
                                                   ("mfma_f16", "uneven_species", 4, 1),
-                                                  ("mfma_bf16", "jitter", 4, 1)])
+                                                  ("mfma_bf16", "jitter", 4, 1),
+                                                  ("mfma_f16x2", "jitter", 4, 2),
+                                                  ("mfma_f16x2", "uneven_species", 3, 2)])
 def test_coherent_matrix_core_path(path, case, tile, bands):
     """The matrix-core path keeps each column's phase e^{i w tau_0} in its epilogue (128- and
     256-row contraction tiles: 1024 and 640 frequencies give row counts that are multiples
@@ -277,8 +284,8 @@ def test_coherent_matrix_core_path(path, case, tile, bands):
     S_ref, A_ref = oracle.coherent_spectrum(b, dirs, om, n_species=ns, with_amplitude=True)
     c = _ctx(dirs, om, ns)
     c.set_tuning(tile=tile)
-    c.set_mfma_options(bands, 3, 3)
-    c.accumulate(DeviceBatch.from_host(b), path)
+    c.set_mfma_options(bands, 2 if path.endswith("x2") else 3, 3)
+    c.accumulate(DeviceBatch.from_host(b), path.replace("x2", ""))
     S = c.read_spectra()
     A = _xyz(c.read_amplitudes(), c.get_basis())
     c.close()
@@ -290,7 +297,7 @@ def test_coherent_matrix_core_path(path, case, tile, bands):
           f"band-integrated {band.max():.3e}",
           flush=True)
     assert band.max() <= MFMA_BAND_TOL[path]
-    assert e <= MFMA_AMP_SANITY
+    assert e <= MFMA_AMP_SANITY[path]
 
 
 def test_coherent_mode_errors_and_resume():

@@ -4,7 +4,8 @@ Accuracy statement of these paths: the power integrated over each of 16 equal
 log-frequency bands (per direction) is compared with the oracle for every band
 holding at least 1e-4 of the direction's strongest band.  Default operands
 (FP16 split into hi + lo parts, three products): within 1e-5.  BF16 hi + lo:
-within 1e-4.  Two FP16 products (table rounded once, F split): within 1e-3.
+within 1e-4.  Two FP16 products (table rounded once, F split): within 1e-3 on
+these incoherent cases (up to 7.1e-4 on 24 jitter particles with two bands).
 One FP16 product with 8 frequency bands: within 1e-3 on ensembles of 48
 particles (up to 2e-3 on six); one product with a single band and one BF16
 product are measured and printed only.  Per-bin errors are printed, not bounded.
@@ -136,6 +137,8 @@ def test_band_counts_jitter(bands):
     ref = oracle.spectrum(b, dirs, om, n_species=1)
     S = run(b, dirs, om, "mfma_f16", bands=bands, products_f16=3)
     assert report(f"mfma f16 x3, jitter 24 particles, {bands} bands", S, ref, om).max() <= 1e-5
+    S = run(b, dirs, om, "mfma_f16", bands=bands, products_f16=2)
+    assert report(f"mfma f16 x2, jitter 24 particles, {bands} bands", S, ref, om).max() <= 1e-3
 
 
 def test_synchrotron_workload():
@@ -146,6 +149,9 @@ def test_synchrotron_workload():
     assert report("mfma f16 x3, synchrotron", S, ref, cfg["omega"]).max() <= 1e-5
     S = run(b, cfg["dirs"], cfg["omega"], "mfma_f16", bands=8, products_f16=1)
     assert report("mfma f16 x1, 8 bands, synchrotron", S, ref, cfg["omega"]).max() <= 1e-3
+    for bands in (1, 2):
+        S = run(b, cfg["dirs"], cfg["omega"], "mfma_f16", bands=bands, products_f16=2)
+        assert report(f"mfma f16 x2, {bands} bands, synchrotron", S, ref, cfg["omega"]).max() <= 1e-3
 
 
 def test_uneven_species_ragged():
@@ -167,6 +173,8 @@ def test_uneven_species_ragged():
     ref = oracle.spectrum(b, dirs, om, n_species=3)
     S = run(b, dirs, om, "mfma_f16", products_f16=3, n_species=3)
     assert report("mfma f16 x3, uneven 14 particles, 3 species", S, ref, om).max() <= 1e-5
+    S = run(b, dirs, om, "mfma_f16", bands=2, products_f16=2, n_species=3)
+    assert report("mfma f16 x2, 2 bands, uneven 14 particles, 3 species", S, ref, om).max() <= 1e-3
 
 
 def test_sparse_sampling_first_chunk_fills_the_ring():
