@@ -403,7 +403,13 @@ lw_status lw_mlp_set_input_norm(lw_mlp* net, const float* shift, const float* sc
  * the network learns the outputs relative to that input; input_index = -1
  * removes it. */
 lw_status lw_mlp_set_output_skip(lw_mlp* net, int32_t input_index, float coeff);
-/* y: device [rows][n_out]; err_head (may be NULL): device [rows], the error head's output. */
+/* y: device [rows][n_out]; err_head (may be NULL): device [rows], the error head's output.
+ * Networks with a hidden width that is a multiple of 64, an output width a multiple of 32
+ * (both at most 256), an input width a multiple of 8 (at most 256), 1 to 8 hidden layers and
+ * a 16-byte aligned x run as one kernel per tile of 128 rows: activations stay on chip, the
+ * weights are rounded to BF16 once per call, and GELU's erf is a rational form within 1.5e-7
+ * of erf.  Other shapes run layer by layer, as the training calls do.  Both keep the
+ * roundings of the products (BF16 operands, FP32 accumulation). */
 lw_status lw_mlp_forward(lw_mlp* net, const float* x, int64_t rows, float* y, float* err_head);
 /* Loss and its gradient (copied to grad_host when not NULL), no update. */
 lw_status lw_mlp_loss_grad(lw_mlp* net, const float* x, const float* t, int64_t rows, float* grad_host,

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lw_internal.h"
@@ -22,6 +23,7 @@ constexpr int kFeat = 16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16v __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ features
 // One work-group per (particle, group of up to kDirGroup directions): the
@@ -599,6 +601,203 @@ __global__ void lw_log_targets_kernel(const float* pp, const float* charge, cons
   out[i] = (float)log10((double)pp[i] / (w * q * q) + floor_value);
 }
 
+// ------------------------------------------------------------------ fused inference forward
+// The whole network for a tile of 128 rows in one work-group of four waves.  Each wave owns 32
+// rows: it keeps a layer's 32 x (up to 256) outputs in MFMA accumulators and writes the
+// activation (GELU in FP32, rounded to BF16 as the layered products round their A operand)
+// back over its own rows of an LDS activation tile, which is the next layer's A operand.  No
+// wave reads another's rows, so the activations need no barrier.  The weights come from a
+// BF16 copy of the parameters (the rounding the layered products apply as they stage them)
+// in slabs of 64 inner indices through two LDS buffers shared by the four waves, the next
+// slab read from memory while the current one is multiplied.  Each layer's arithmetic is the
+// layered path's (bias, then the skip term; inner index ascending in steps of 16), except
+// that GELU's erf is the Abramowitz-Stegun rational form 7.1.26 (absolute error below
+// 1.5e-7, far under the BF16 rounding that follows) and the error head sums the hidden
+// units in another order.  Rows are read once and written once.
+constexpr int kFusedRows = 128;         // rows per work-group
+constexpr int kFusedMaxWidth = 256;     // widest layer (input tile padded to whole slabs)
+constexpr int kFusedLD = kFusedMaxWidth + 8;
+constexpr int kFusedSlab = 64;          // inner indices per weight slab
+constexpr int kFusedSlabLD = kFusedSlab + 8;
+constexpr int kFusedMaxLayers = 9;
+
+struct FusedMlp {
+  const float* x;       // [rows][n_in] raw inputs
+  const float* norm;    // [2][n_in] input shift and scale, or null
+  const float* p;       // parameters, FP32 (biases)
+  const __bf16* w;      // parameters rounded to BF16 (weights)
+  int64_t w_off[kFusedMaxLayers], b_off[kFusedMaxLayers];
+  int n_in, hidden, n_hidden, n_out;
+  int64_t rows;
+  float* y;             // [rows][n_out]
+  const float* head;    // error head [hidden + 1], or null
+  float* e;             // [rows] error head output, or null
+  int skip_index;       // raw input added (times skip_coeff) to every output, or -1
+  float skip_coeff;
+};
+
+__global__ void lw_round_bf16_kernel(const float* p, int64_t n, __bf16* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = (__bf16)p[i];
+}
+
+// GELU(z) = z Phi(z) with erf from Abramowitz & Stegun 7.1.26
+__device__ __forceinline__ float gelu_as(float z) {
+  const float x = fabsf(z) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float erf_abs = fmaf(-q * t, __expf(-x * x), 1.0f);
+  return 0.5f * z * (1.0f + copysignf(erf_abs, z));
+}
+
+__global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
+  __shared__ __attribute__((aligned(16))) __bf16 sH[kFusedRows * kFusedLD];
+  __shared__ __attribute__((aligned(16))) __bf16 sW[2][kFusedMaxWidth * kFusedSlabLD];  // [j][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = lane & 31, half = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * kFusedRows;
+  __bf16* myH = sH + (size_t)(wave * 32) * kFusedLD;
+
+  // input tile: normalised inputs rounded to BF16 (four at a time, several loads in flight),
+  // zero-padded to whole slabs
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  const int kin = (f.n_in + kFusedSlab - 1) / kFusedSlab * kFusedSlab;
+  const int q4 = f.n_in / 4;
+#pragma unroll 4
+  for (int idx = tid; idx < kFusedRows * q4; idx += 256) {
+    const int r = idx / q4, c = 4 * (idx - r * q4);
+    const int64_t ii = i0 + r;
+    f32x4 v = ii < f.rows ? *(const f32x4*)(f.x + ii * f.n_in + c) : f32x4{0.f, 0.f, 0.f, 0.f};
+    if (f.norm) v = (v - *(const f32x4*)(f.norm + c)) * *(const f32x4*)(f.norm + f.n_in + c);
+    *(bf16x4*)&sH[r * kFusedLD + c] = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+  }
+  for (int idx = tid; idx < kFusedRows * (kin - f.n_in); idx += 256) {
+    const int r = idx / (kin - f.n_in);
+    sH[r * kFusedLD + f.n_in + (idx - r * (kin - f.n_in))] = (__bf16)0.0f;
+  }
+
+  // weight slabs: thread t moves 16-byte pieces t + 256 v (column j = idx / 8, inner 8 (idx % 8))
+  u32x4 rw[8];
+  auto load_slab = [&](const __bf16* W, int din, int dout, int k0) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int idx = tid + 256 * v, j = idx >> 3, kq = (idx & 7) * 8;
+      rw[v] = (j < dout && k0 + kq < din) ? *(const u32x4*)(W + (int64_t)j * din + k0 + kq) : u32x4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store_slab = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int idx = tid + 256 * v, j = idx >> 3, kq = (idx & 7) * 8;
+      *(u32x4*)&sW[b][j * kFusedSlabLD + kq] = rw[v];
+    }
+  };
+
+  f32x16v acc[8];
+  const bool full = i0 + kFusedRows <= f.rows;  // a whole tile skips the per-row checks
+  const int64_t row0 = i0 + wave * 32 + 4 * half;  // row of accumulator register 0 of this lane
+  int buf = 0;
+  for (int l = 0; l <= f.n_hidden; ++l) {
+    const bool out_layer = l == f.n_hidden;
+    const int din = l == 0 ? f.n_in : f.hidden;
+    const int kdim = l == 0 ? kin : f.hidden;  // a multiple of the slab
+    const int dout = out_layer ? f.n_out : f.hidden;
+    const int nb = dout / 32;
+    const __bf16* W = f.w + f.w_off[l];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
+    // the buffer about to be filled was last read two barriers ago
+    load_slab(W, din, dout, 0);
+    store_slab(buf);
+    __syncthreads();  // slab stored (and, before the first layer, the input tile)
+    for (int k0 = 0; k0 < kdim; k0 += kFusedSlab) {
+      const bool more = k0 + kFusedSlab < kdim;
+      if (more) load_slab(W, din, dout, k0 + kFusedSlab);
+#pragma unroll
+      for (int q = 0; q < kFusedSlab; q += 32) {
+        // both inner halves' fragments are read before the products, and all eight column
+        // blocks are multiplied, also past a narrower layer's width (its slab columns there
+        // are zeros): a branch per block would make each product wait for its own read
+        bf16x8 fa[2], fb[2][8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          fa[h] = *(const bf16x8*)&myH[m * kFusedLD + k0 + q + 16 * h + 8 * half];
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+            fb[h][b] = *(const bf16x8*)&sW[buf][(32 * b + m) * kFusedSlabLD + q + 16 * h + 8 * half];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[h], fb[h][b], acc[b], 0, 0, 0);
+        // keep the 18 reads ahead of the 16 products (the scheduler otherwise reuses one
+        // register for every weight fragment and waits for each read in turn)
+        __builtin_amdgcn_sched_group_barrier(0x100, 18, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+      }
+      if (more) store_slab(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    const float* bias = f.p + f.b_off[l];
+    if (!out_layer) {
+      // activations over this wave's own rows (its reads of them are complete: the MFMAs
+      // above consumed them); the error head dots the last hidden layer in FP32
+      const bool head = f.head && l == f.n_hidden - 1;
+      float hs[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) hs[r] = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b < nb) {
+          const int j = 32 * b + m;
+          const float bj = bias[j];
+          const float hw = head ? f.head[j] : 0.0f;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int rr = 8 * (r / 4) + 4 * half + (r % 4);
+            const float h = gelu_as(acc[b][r] + bj);
+            myH[rr * kFusedLD + j] = (__bf16)h;
+            hs[r] = fmaf(hw, h, hs[r]);
+          }
+        }
+      }
+      if (head) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          for (int off = 16; off > 0; off >>= 1) hs[r] += __shfl_xor(hs[r], off);
+        if (m == 0 && f.e) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
+            if (full || ii < f.rows) f.e[ii] = hs[r] + f.head[f.hidden];
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (b < nb) {
+          const int j = 32 * b + m;
+          const float bj = bias[j];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
+            float v = acc[b][r] + bj;
+            if (f.skip_index >= 0) v += f.skip_coeff * f.x[min(ii, f.rows - 1) * f.n_in + f.skip_index];
+            if (full || ii < f.rows) f.y[ii * f.n_out + j] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 }  // namespace lw
 
 // ------------------------------------------------------------------ network object
@@ -618,6 +817,7 @@ struct lw_mlp {
   double* col_part = nullptr;  // stage-1 partial column sums [row blocks][max(n_out, hidden + 1)]
   float* err_buf = nullptr;
   float* splitk = nullptr;     // partial weight gradients [kMaxSplits][largest layer]
+  __bf16* wbf = nullptr;       // parameters rounded to BF16 for the fused inference kernel
   std::vector<int64_t> w_off, b_off;
 };
 
@@ -633,6 +833,20 @@ lw_status mlp_fail(lw_mlp* n, lw_status st, const std::string& msg) {
     hipError_t e_ = (call);                                                    \
     if (e_ != hipSuccess) return mlp_fail(n, LW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Shapes the fused inference kernel takes: hidden width a multiple of 64 (whole weight slabs)
+// and output width a multiple of 32, both up to 256; input width a multiple of 8 up to 256;
+// 1 to 8 hidden layers; every layer's weights at a multiple of 8 parameters (16-byte BF16
+// rows for the slab loads).
+bool fused_shape(const lw_mlp* n) {
+  if (n->hidden % lw::kFusedSlab != 0 || n->hidden > lw::kFusedMaxWidth || n->n_out % 32 != 0 ||
+      n->n_out > lw::kFusedMaxWidth || n->n_in % 8 != 0 || n->n_in <= 0 || n->n_in > lw::kFusedMaxWidth ||
+      n->n_hidden < 1 || n->n_hidden + 1 > lw::kFusedMaxLayers || !n->wbf)
+    return false;
+  for (int l = 0; l <= n->n_hidden; ++l)
+    if (n->w_off[l] % 8 != 0) return false;
+  return true;
+}
 
 int width(const lw_mlp* n, int l) {  // input width of layer l, l = 0..n_hidden (+1 = output)
   if (l == 0) return n->n_in;
@@ -923,6 +1137,7 @@ lw_status lw_mlp_create(lw_ctx* c, int32_t n_in, int32_t hidden, int32_t n_hidde
   int64_t largest = 0;  // the largest layer's weights: the split partial products of its gradient
   for (int l = 0; l <= n_hidden; ++l) largest = std::max<int64_t>(largest, n->b_off[l] - n->w_off[l]);
   alloc(&n->splitk, (int64_t)lw::kMaxSplits * largest);
+  if (rc == LW_OK && hipMalloc(&n->wbf, (size_t)off * sizeof(__bf16)) != hipSuccess) rc = LW_ENOMEM;
   if (rc == LW_OK) {
     std::vector<float> zeros(std::max<int64_t>(off, hidden + 1), 0.0f);
     (void)hipMemcpy(n->p, h.data(), off * sizeof(float), hipMemcpyHostToDevice);
@@ -946,7 +1161,7 @@ void lw_mlp_destroy(lw_mlp* n) {
   if (n->c) (void)hipStreamSynchronize(n->c->stream);
   for (void* p : {(void*)n->p, (void*)n->m, (void*)n->v, (void*)n->g, (void*)n->hp, (void*)n->hm,
                   (void*)n->hv, (void*)n->hg, (void*)n->act, (void*)n->loss_part, (void*)n->err_buf,
-                  (void*)n->col_part, (void*)n->splitk,
+                  (void*)n->col_part, (void*)n->splitk, (void*)n->wbf,
                   (void*)n->norm})
     if (p) (void)hipFree(p);
   delete n;
@@ -1071,6 +1286,35 @@ lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, floa
   if (!n || !x || !y || rows < 0) return LW_EINVAL;
   if (err_head && n->n_hidden < 1) return mlp_fail(n, LW_EINVAL, "the error head needs a hidden layer");
   if (rows == 0) return LW_OK;
+  if (fused_shape(n) && ((uintptr_t)x & 15) == 0) {
+    const int64_t np = n->n_params;
+    hipLaunchKernelGGL(lw::lw_round_bf16_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, n->c->stream,
+                       n->p, np, n->wbf);
+    MLP_HIP(hipGetLastError(), "round weights");
+    lw::FusedMlp f;
+    f.x = x;
+    f.norm = n->norm;
+    f.p = n->p;
+    f.w = n->wbf;
+    for (int l = 0; l <= n->n_hidden; ++l) {
+      f.w_off[l] = n->w_off[l];
+      f.b_off[l] = n->b_off[l];
+    }
+    f.n_in = n->n_in;
+    f.hidden = n->hidden;
+    f.n_hidden = n->n_hidden;
+    f.n_out = n->n_out;
+    f.rows = rows;
+    f.y = y;
+    f.head = err_head ? n->hp : nullptr;
+    f.e = err_head;
+    f.skip_index = n->skip_index;
+    f.skip_coeff = n->skip_coeff;
+    hipLaunchKernelGGL(lw::lw_mlp_fused_forward_kernel, dim3((unsigned)((rows + lw::kFusedRows - 1) / lw::kFusedRows)),
+                       dim3(256), 0, n->c->stream, f);
+    MLP_HIP(hipGetLastError(), "fused forward");
+    return LW_OK;
+  }
   lw_status st = ensure_rows(n, rows);
   const float* in = nullptr;
   if (st == LW_OK) st = input_of(n, x, rows, &in);

@@ -6,9 +6,12 @@ Tolerances.  Features are FP64 sums rounded once to FP32 (rtol 2e-5); counts
 of reversals and of in-cone samples are FP64 decisions on the same inputs on
 both sides (they may differ by at most one sample on an exact tie).  The
 network multiplies BF16-rounded operands (unit roundoff u = 2^-8) with FP32
-accumulation: every output and gradient element is held to twice its first-order
-bound, the standard bound of a rounded dot product (2u + K u32) sum_k |a_ik| |b_kj|
-per product, propagated through the layers and GELU.  A purely linear layer on
+accumulation: outputs and gradients are compared element by element with a
+reference that rounds the same operands to BF16 in FP64 (tests/_mlp_emul.py, pinned
+to the FP64 oracle), each element within its rigorous bound -- FP32 accumulation,
+BF16 rounding boundaries within reach, GELU evaluation -- on networks with one
+hidden layer, and within four BF16 units of the RMS (and 99.9 % within the bound)
+on deeper ones, where worst-case accumulation bounds outgrow the values.  A purely linear layer on
 operands that are already BF16 values is exact up to FP32 accumulation (bar
 1e-5).
 """
@@ -16,7 +19,6 @@ import time
 
 import numpy as np
 import pytest
-import scipy.special as sp
 
 import oracle
 import workloads
@@ -111,102 +113,87 @@ def test_linear_layer_is_exact_on_bf16_operands():
         np.testing.assert_allclose(y, ref, rtol=1e-5, atol=1e-5)
 
 
-U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significant bits, round to nearest)
-U_FP32 = 2.0 ** -24
-GELU1 = 1.1289       # max |GELU'(z)| (at z = +-sqrt(2))
-GELU2 = 0.7979       # max |GELU''(z)| (at z = 0: 2 phi(0))
+def _params(net, rng, head=False):
+    """The network's initial weights with small random biases (and an error head), as FP32."""
+    p0, _ = net.get_params()
+    p = p0 + rng.normal(scale=0.02, size=p0.size).astype(np.float32)
+    h = rng.normal(scale=0.05, size=net.shape[1] + 1).astype(np.float32) if head else None
+    net.set_params(p, h)
+    return p.astype(np.float64), (h.astype(np.float64) if head else None)
 
 
-def _layers(shape, p):
-    """Per-layer (W [out][in], b [out]) views of a flat parameter vector."""
-    n_in, hidden, n_hidden, n_out = shape
-    widths = [n_in] + [hidden] * n_hidden + [n_out]
-    out, off = [], 0
-    for l in range(n_hidden + 1):
-        din, dout = widths[l], widths[l + 1]
-        out.append((p[off:off + din * dout].reshape(dout, din), p[off + din * dout: off + din * dout + dout]))
-        off += din * dout + dout
-    return out
+def _check(name, got, ref, bound, rigorous):
+    """Element-wise comparison with the BF16 emulation.  Rigorous: every element within its
+    bound.  Otherwise (deep networks, where worst-case accumulation bounds grow past the
+    values): every element within 2^-6 of the tensor's RMS (four BF16 units) and at least
+    99.9 % of them within their bound."""
+    d = np.abs(got - ref)
+    r = d / np.maximum(bound, 1e-300)
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    inside = float(np.mean(d <= bound))
+    print(f"[mlp emul] {name}: max |diff| / bound {r.max():.3f}, within bound {inside * 100:.3f} %, "
+          f"max |diff| / rms {d.max() / rms:.2e}, median bound / |value| "
+          f"{np.median(bound / np.maximum(np.abs(ref), 1e-300)):.1e}", flush=True)
+    if rigorous:
+        assert r.max() <= 1.0, name
+    else:
+        assert d.max() <= 2.0 ** -6 * rms, name
+        assert inside >= 0.999, name
 
 
-def _elementwise_bounds(shape, p, x, t):
-    """First-order element-wise error bounds of the BF16 network against exact arithmetic.
-
-    Each product rounds both operands to BF16 and accumulates in FP32, so its own error is
-    at most (2 u + K u32) sum_k |a_ik| |b_kj| (the standard bound of a rounded dot product);
-    input errors propagate through |W| and through GELU with its Lipschitz constants.  The
-    intermediates (z, a, the back-propagated signals d) are formed here in FP64 from the
-    oracle's definition and checked against the oracle's own output and gradient, so that
-    the bounds belong to the values the oracle computes.
-    Returns (y, grad, bound_y, bound_grad) with grad laid out like the parameters."""
-    layers = _layers(shape, p)
-    L = len(layers) - 1
-    a, z, ea, ez = [x], [], [np.zeros_like(x)], []
-    for l, (W, b) in enumerate(layers):
-        K = W.shape[1]
-        zl = a[l] @ W.T + b
-        ezl = ea[l] @ np.abs(W).T + (2 * U_BF16 + K * U_FP32) * (np.abs(a[l]) @ np.abs(W).T)
-        z.append(zl)
-        ez.append(ezl)
-        if l < L:
-            a.append(oracle.mlp_gelu(zl))
-            ea.append(GELU1 * ezl)
-    y, ey = z[L], ez[L]
-    rows, n_out = y.shape
-    d = 2.0 * (y - t) / (rows * n_out)
-    ed = 2.0 * ey / (rows * n_out)
-    grads, bounds = [None] * (L + 1), [None] * (L + 1)
-    for l in range(L, -1, -1):
-        W, _ = layers[l]
-        dW = d.T @ a[l]
-        edW = ed.T @ np.abs(a[l]) + np.abs(d).T @ ea[l] + (2 * U_BF16 + rows * U_FP32) * (np.abs(d).T @ np.abs(a[l]))
-        db = d.sum(0)
-        edb = ed.sum(0) + rows * U_FP32 * np.abs(d).sum(0)
-        grads[l] = np.concatenate([dW.ravel(), db])
-        bounds[l] = np.concatenate([edW.ravel(), edb])
-        if l > 0:
-            K = W.shape[0]
-            back = d @ W
-            eback = ed @ np.abs(W) + (2 * U_BF16 + K * U_FP32) * (np.abs(d) @ np.abs(W))
-            zl = z[l - 1]
-            gp = 0.5 * (1.0 + sp.erf(zl / np.sqrt(2.0))) + zl * np.exp(-0.5 * zl * zl) / np.sqrt(2.0 * np.pi)
-            ed = eback * np.abs(gp) + np.abs(back) * GELU2 * ez[l - 1]
-            d = back * gp
-    return y, np.concatenate(grads), ey, np.concatenate(bounds)
-
-
-@pytest.mark.parametrize("rows", [64, 150, 4100])
-def test_forward_and_gradients_match_oracle(rows):
-    """Every output and every gradient element within twice its first-order bound (the
-    second-order terms and the rounding of the bound itself are covered by the factor 2)."""
+@pytest.mark.parametrize("shape,rows,rigorous", [((16, 64, 1, 32), 64, True), ((16, 64, 1, 32), 150, True),
+                                                 ((16, 64, 1, 32), 4100, True), ((16, 64, 3, 48), 4100, False),
+                                                 ((16, 256, 3, 256), 4100, False)])
+def test_training_path_matches_bf16_emulation(shape, rows, rigorous):
+    """The layered forward (z, GELU), the loss gradient and the backward products (split inner
+    dimension for the weight gradients) against the BF16-emulating reference of
+    tests/_mlp_emul.py, which is pinned to the FP64 oracle on the CPU."""
     import torch
 
+    import _mlp_emul as E
+
     c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
-    shape = (16, 64, 3, 48)
     net = _net(c, shape)
-    rng = np.random.default_rng(rows)
-    p0, _ = net.get_params()
-    p = p0 + rng.normal(scale=0.02, size=p0.size).astype(np.float32)  # non-zero biases
-    net.set_params(p)
-    x = rng.normal(size=(rows, 16)).astype(np.float32)
-    t = rng.normal(size=(rows, 48)).astype(np.float32)
+    rng = np.random.default_rng(rows + shape[1])
+    p, _ = _params(net, rng)
+    x = rng.normal(size=(rows, shape[0])).astype(np.float32)
+    t = rng.normal(size=(rows, shape[3])).astype(np.float32)
     xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
-    y = net.forward(xd).cpu().numpy().astype(np.float64)
     loss, g = net.loss_grad(xd, td)
-    ref = oracle.mlp_forward_backward(shape, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
-                                      want_grad=True)
-    yb, gb, ey, eg = _elementwise_bounds(shape, p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
-    # the bound's intermediates are the oracle's values
-    np.testing.assert_allclose(yb, ref["y"], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(gb, ref["grad"], rtol=1e-9, atol=1e-15)
-    ry = np.abs(y - ref["y"]) / ey
-    rg = np.abs(g.astype(np.float64) - ref["grad"]) / np.maximum(eg, 1e-30)
-    print(f"[mlp] rows {rows}: output error / bound max {ry.max():.3f} (mean {ry.mean():.3f}); gradient "
-          f"error / bound max {rg.max():.3f} (mean {rg.mean():.3f}); loss {loss:.6f} vs {ref['loss']:.6f}",
-          flush=True)
-    assert ry.max() <= 2.0
-    assert rg.max() <= 2.0
-    assert abs(loss - ref["loss"]) <= 2e-2 * ref["loss"]
+    ref = E.forward_backward(shape, p, x.astype(np.float64), t.astype(np.float64))
+    fp64 = oracle.mlp_forward_backward(shape, p, x.astype(np.float64), t.astype(np.float64), want_grad=True)
+    _check(f"gradient {shape} x {rows}", g.astype(np.float64), ref["grad"], ref["egrad"], rigorous)
+    assert abs(loss - fp64["loss"]) <= 2e-2 * fp64["loss"]
+
+
+@pytest.mark.parametrize("shape,rows,rigorous", [((16, 256, 1, 256), 4100, True), ((32, 128, 1, 32), 129, True),
+                                                 ((16, 64, 2, 96), 150, False), ((16, 256, 3, 256), 64, False),
+                                                 ((16, 256, 3, 256), 4100, False)])
+def test_inference_matches_bf16_emulation(shape, rows, rigorous):
+    """Inference (lw_mlp_forward) runs the whole network per tile of 128 rows in one kernel for
+    these shapes: one tile, a ragged last tile, many tiles; with an input normalisation, an
+    output skip and the error head.  Outputs and head against the BF16 emulation."""
+    import torch
+
+    import _mlp_emul as E
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    net = _net(c, shape, seed=rows)
+    rng = np.random.default_rng(rows + shape[1])
+    n_in = shape[0]
+    p, head = _params(net, rng, head=True)
+    shift = rng.normal(size=n_in).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, size=n_in).astype(np.float32)
+    net.set_input_norm(shift, scale)
+    skip, coeff = 3, 0.75
+    net.set_output_skip(skip, coeff)
+    x = (rng.normal(size=(rows, n_in)) * 2.0).astype(np.float32)
+    y, e = net.forward(torch.from_numpy(x).cuda(), with_error=True)
+    # the network's input as the kernel forms it: (x - shift) * scale in FP32
+    xn = ((x - shift) * scale).astype(np.float32).astype(np.float64)
+    ref = E.forward(shape, p, xn, skip=(x[:, skip].astype(np.float64), coeff), head=head)
+    _check(f"output {shape} x {rows}", y.cpu().numpy().astype(np.float64), ref["y"], ref["ey"], rigorous)
+    _check(f"error head {shape} x {rows}", e.cpu().numpy().astype(np.float64), ref["e"], ref["ee"], rigorous)
 
 
 def test_input_normalisation_matches_oracle_on_normalised_inputs():
