@@ -134,6 +134,15 @@ lw_status lw_set_species(lw_ctx* ctx, int32_t n_species);
  * other counts. */
 lw_status lw_set_mfma_options(lw_ctx* ctx, int32_t bands, int32_t products_f16,
                               int32_t products_bf16);
+/* Cap on the spread grids F (all directions and bands, FP32) held per chunk of particles,
+ * in bytes; 0 restores the default of 24 GiB.  The matrix-core path walks a batch in chunks
+ * of at least 64 particles that keep F under the cap (a smaller cap: a smaller workspace,
+ * more launches).  Query lw_workspace_size again after changing it. */
+lw_status lw_set_mfma_chunk_bytes(lw_ctx* ctx, int64_t bytes);
+/* Plans the batch for a matrix-core path as lw_workspace_size does (synchronises) and
+ * reports host_out[4] = {particles per chunk, chunks, frequency bands, workspace bytes}.
+ * LW_EINVAL for the FP32 path. */
+lw_status lw_mfma_plan_info(lw_ctx* ctx, const lw_batch* batch, lw_path path, int64_t* host_out);
 
 /* Device workspace (bytes) lw_accumulate needs for this batch and path.  For
  * the matrix-core paths this call plans the batch: it reads the batch on the

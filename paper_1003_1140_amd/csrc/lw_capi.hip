@@ -597,6 +597,24 @@ lw_status lw_set_mfma_options(lw_ctx* c, int32_t bands, int32_t products_f16,
   return lw::mfma_set_options(c, bands, products_f16, products_bf16);
 }
 
+lw_status lw_set_mfma_chunk_bytes(lw_ctx* c, int64_t bytes) {
+  if (!c) return LW_EINVAL;
+  return lw::mfma_set_chunk_bytes(c, bytes);
+}
+
+lw_status lw_mfma_plan_info(lw_ctx* c, const lw_batch* b, lw_path path, int64_t* host_out) {
+  if (!c || !host_out) return LW_EINVAL;
+  lw_status st = check_grids(c);
+  if (st != LW_OK) return st;
+  st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  path = resolve_path(c, path, false);
+  if (path != LW_PATH_MFMA_F16 && path != LW_PATH_MFMA_BF16)
+    return fail(c, LW_EINVAL, "plan information is for the matrix-core paths");
+  DeviceGuard g(c->device);
+  return lw::mfma_plan_info(c, b, path, host_out);
+}
+
 lw_status lw_set_profiling(lw_ctx* c, int32_t enable) {
   if (!c) return LW_EINVAL;
   DeviceGuard g(c->device);

@@ -12,6 +12,9 @@ uint64_t mfma_epoch(const MfmaPlanCache* c);
 lw_status mfma_set_options(lw_ctx* c, int bands, int products_f16, int products_bf16);
 lw_status mfma_set_bands(lw_ctx* c, int bands);
 lw_status mfma_set_tile(lw_ctx* c, int tile);
+lw_status mfma_set_chunk_bytes(lw_ctx* c, int64_t bytes);
+// Plans the batch and reports {particles per chunk, chunks, bands, workspace bytes}.
+lw_status mfma_plan_info(lw_ctx* c, const lw_batch* b, lw_path path, int64_t* out);
 // Plans the batch: measures its retarded-time span (synchronises), grows the tables if
 // needed and remembers the batch as planned.
 lw_status mfma_workspace_size(lw_ctx* c, const lw_batch* b, lw_path path, size_t* bytes);

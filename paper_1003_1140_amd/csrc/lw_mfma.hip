@@ -91,6 +91,7 @@ struct MfmaPlanCache {
   int bands_req = 1;
   int products_f16 = 3, products_bf16 = 3;
   int tile = 4;  // contraction tile: 1 = 128 x 128, 2 = 256 x 128, 3 = 128 x 256, 4 = 256 x 256
+  int64_t chunk_bytes = 24LL << 30;  // cap on F (all directions and bands) per chunk of particles
   KernelShape shape = kShapeSplit;  // spreading kernel the tables were built for
   uint64_t epoch = 0;               // bumped when the tables are freed
   int nb = 0;
@@ -1403,10 +1404,10 @@ int chunk_particles(const MfmaPlanCache* pc, int nd, int64_t P) {
   int64_t per = 0;
   for (int b = 0; b < pc->nb; ++b) per += 2 * (int64_t)pc->band[b].kp * sizeof(float);
   per *= nd;
-  int64_t n = per > 0 ? (int64_t)(24LL << 30) / per : 8192;
+  int64_t n = per > 0 ? pc->chunk_bytes / per : 8192;
   // column indices (direction, band, 2 x particle) stay within int32
   n = std::min<int64_t>(n, ((int64_t)1 << 30) / ((int64_t)nd * pc->nb));
-  n = std::max<int64_t>(64, n);
+  n = std::max<int64_t>(64, n);  // at least one tile of columns, whatever the cap
   n = (n / 64) * 64;
   return (int)std::min<int64_t>(n, ((P + 63) / 64) * 64);
 }
@@ -1686,6 +1687,26 @@ lw_status mfma_set_bands(lw_ctx* c, int bands) {
 lw_status mfma_set_tile(lw_ctx* c, int tile) {
   if (tile < 1 || tile > 4) return set_err(c, LW_EINVAL, "tile shape must be 1, 2, 3 or 4");
   c->mfma->tile = tile;
+  return LW_OK;
+}
+
+lw_status mfma_set_chunk_bytes(lw_ctx* c, int64_t bytes) {
+  if (bytes < 0) return set_err(c, LW_EINVAL, "chunk cap must be >= 0 bytes (0: the default)");
+  c->mfma->chunk_bytes = bytes ? bytes : (24LL << 30);
+  return LW_OK;
+}
+
+lw_status mfma_plan_info(lw_ctx* c, const lw_batch* b, lw_path path, int64_t* out) {
+  size_t bytes = 0;
+  lw_status st = mfma_workspace_size(c, b, path, &bytes);  // plans the batch
+  if (st != LW_OK) return st;
+  const MfmaPlanCache* pc = c->mfma;
+  const int64_t P = b->n_particles;
+  const WsLayout L = ws_layout(c, pc, std::max<int64_t>(P, 1));
+  out[0] = P > 0 ? L.chunk : 0;
+  out[1] = P > 0 ? (P + L.chunk - 1) / L.chunk : 0;
+  out[2] = pc->nb;
+  out[3] = (int64_t)bytes;
   return LW_OK;
 }
 

@@ -27,7 +27,8 @@ LW_AUTO_MIN_FREQUENCIES = 256
 EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set_directions",
             "lw_set_frequencies", "lw_set_log_frequencies", "lw_get_frequencies", "lw_set_species",
             "lw_workspace_size", "lw_accumulate", "lw_read_spectra", "lw_reset",
-            "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_profiling",
+            "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_mfma_chunk_bytes",
+            "lw_mfma_plan_info", "lw_set_profiling",
             "lw_profile_read", "lw_plan_batch", "lw_set_tuning", "lw_tune", "lw_graph_capture",
             "lw_graph_launch", "lw_graph_destroy", "lw_accumulate_subset", "lw_features",
             "lw_mlp_create", "lw_mlp_destroy", "lw_mlp_num_params", "lw_mlp_get_params",
@@ -89,6 +90,8 @@ def load_library():
             "lw_load_accumulator": (ctypes.c_int, [P, P]),
             "lw_stats": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
             "lw_set_mfma_options": (ctypes.c_int, [P, I32, I32, I32]),
+            "lw_set_mfma_chunk_bytes": (ctypes.c_int, [P, I64]),
+            "lw_mfma_plan_info": (ctypes.c_int, [P, P, ctypes.c_int, P]),
             "lw_set_profiling": (ctypes.c_int, [P, I32]),
             "lw_plan_batch": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), ctypes.c_int]),
             "lw_set_tuning": (ctypes.c_int, [P, I32, I32, I32, I32, I32]),
@@ -407,6 +410,17 @@ class Context:
 
     def set_mfma_options(self, bands=1, products_f16=3, products_bf16=3):
         self._check(self.lib.lw_set_mfma_options(self.h, bands, products_f16, products_bf16))
+
+    def set_mfma_chunk_bytes(self, nbytes=0):
+        self._check(self.lib.lw_set_mfma_chunk_bytes(self.h, int(nbytes)))
+
+    def mfma_plan_info(self, batch, path="mfma_f16"):
+        """{particles_per_chunk, chunks, bands, workspace_bytes} of the batch (plans it)."""
+        out = np.zeros(4, dtype=np.int64)
+        self._check(self.lib.lw_mfma_plan_info(self.h, ctypes.byref(batch.struct), PATHS.get(path, path),
+                                               _np_ptr(out)))
+        return {"particles_per_chunk": int(out[0]), "chunks": int(out[1]), "bands": int(out[2]),
+                "workspace_bytes": int(out[3])}
 
     def set_profiling(self, enable=True):
         self._check(self.lib.lw_set_profiling(self.h, 1 if enable else 0))

@@ -192,6 +192,36 @@ def test_sparse_sampling_first_chunk_fills_the_ring():
     assert report("mfma f16 x3, sparse sampling", S, ref, om).max() <= 2e-6
 
 
+def test_several_chunks_against_the_oracle():
+    """A cap on the grids per chunk splits 200 particles into chunks of 64 (the smallest) and a
+    ragged last one: each chunk spreads, sorts, contracts and reduces on its own into S.
+    Against the oracle at the path's bar, and against the one-chunk launch at the FP32 level
+    (each contraction tile sums its columns' squared amplitudes in FP32, and the chunks group
+    the particles into other tiles; measured 1.4e-7)."""
+    from paper_1003_1140_amd import Context, DeviceBatch
+
+    b = workloads.generate(configs.jitter_recipe(steps=1024), 0, 200)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 1024)
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    db = DeviceBatch.from_host(b)
+    out = {}
+    for cap in (0, 1):
+        c = Context(0)
+        c.set_directions(dirs)
+        c.set_frequencies(om)
+        c.set_mfma_options(2, 3, 3)
+        c.set_mfma_chunk_bytes(cap)
+        info = c.mfma_plan_info(db, "mfma_f16")
+        print(f"[chunks] cap {cap}: {info}", flush=True)
+        assert info["chunks"] == (1 if cap == 0 else 4) and info["particles_per_chunk"] == (256 if cap == 0 else 64)
+        c.accumulate(db, "mfma_f16", workspace=c.workspace(db, "mfma_f16"))
+        out[cap] = c.read_spectra()
+        c.close()
+    assert report("mfma f16 x3, 200 particles in 4 chunks", out[1], ref, om).max() <= 1e-5
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-6, atol=1e-12 * out[0].max())
+
+
 def test_straight_motion_is_exactly_zero():
     b = Batch.concat([orbits.straight([0.9, 0.1, 0], [1, 2, 3], 700, 0.01, accel_dtype=np.float32),
                       orbits.straight([-0.3, 0.5, 0.6], [0, 0, 0], 300, 0.02, accel_dtype=np.float32)])
@@ -219,11 +249,23 @@ def test_chunk_sorted_in_several_blocks():
     """40000 short trajectories fit one chunk, whose columns are ordered by grid length in
     three blocks of particles (16384, 16384 and a ragged 7232), each sorted on its own: a
     wrong block offset would drop or repeat columns.  The FP32 path judges."""
+    from paper_1003_1140_amd import Context, DeviceBatch
+
     b = workloads.generate(workloads.make_recipe(11, steps=128), 0, 40_000)
     dirs = configs.dirs_jitter()
     om = configs.log_grid(0.1, 1e3, 256)
     S32 = gpu_spectrum(b, dirs, om, path="fp32")
+    db = DeviceBatch.from_host(b)
     for bands in (1, 2):
+        c = Context(0)
+        c.set_directions(dirs)
+        c.set_frequencies(om)
+        c.set_mfma_options(bands, 3, 3)
+        info = c.mfma_plan_info(db, "mfma_f16")
+        print(f"[plan] {bands} band(s): {info}", flush=True)
+        # one chunk holding the whole batch, sorted in three blocks
+        assert info["chunks"] == 1 and info["particles_per_chunk"] >= 40_000 > 2 * 16384
+        c.close()
         S16 = run(b, dirs, om, "mfma_f16", bands=bands)
         assert report(f"mfma f16 x3 vs fp32, 40000 particles in one chunk, {bands} band(s)",
                       S16, S32, om).max() <= 1e-5
