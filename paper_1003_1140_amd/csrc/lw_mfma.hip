@@ -247,16 +247,19 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 // against 768 (31 KB, five per CU): 4 % faster; 1024 (four per CU) was 12 % slower still.
 // Sparser columns take fewer samples per chunk.
 constexpr int kRing = 512;
+static_assert((kRing & (kRing - 1)) == 0, "ring slots are taken modulo a power of two");
 constexpr int kSpreadWavesPerSimd = 6;
 
 template <int kW>
 struct SpreadStage {
   static_assert(kW % 2 == 0 && kW <= kWMax, "even widths: the tap window must not depend on frac(u)");
-  int lo[kSpreadWin];             // first grid point of each sample's taps
-  float w[kW][kSpreadWin];        // tap weights
-  float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2)
-  int first[kRing + kW];          // first sample reaching grid point base + x
   float4 acc[kRing];              // running grid sums, slot q mod kRing
+  float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2)
+  // tap i of sample s at w[i + 1][s]; rows 0 and kW + 1 stay zero, so that a pair of
+  // adjacent grid points reads taps i and i + 1 of any sample reaching either of them
+  float w[kW + 2][kSpreadWin];
+  int lo[kSpreadWin];             // first grid point of each sample's taps
+  short first[kRing + kW + 1];    // first sample reaching grid point base + x
 };
 
 // One sample's trajectory data, loaded a chunk ahead of its use.
@@ -334,8 +337,8 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
     for (int c = kTapCoef - 3; c >= 0; c -= 2) e = fmaf(e, z2, tap[i][c]);
 #pragma unroll
     for (int c = kTapCoef - 4; c >= 1; c -= 2) o = fmaf(o, z2, tap[i][c]);
-    st.w[i][tid] = fmaf(z, o, e);
-    st.w[kW - 1 - i][tid] = fmaf(-z, o, e);
+    st.w[i + 1][tid] = fmaf(z, o, e);
+    st.w[kW - i][tid] = fmaf(-z, o, e);
   }
   const float G1 = ok ? g1 : 0.f, G2 = ok ? g2 : 0.f;
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
@@ -349,6 +352,38 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
 __device__ __forceinline__ int xcd_contiguous(int b, int n) {
   const int m = n / 8, r = n % 8, x = b % 8, j = b / 8;
   return x * m + min(x, r) + j;
+}
+
+// Sum N values over each aligned group of S consecutive lanes (S a power of two up to 64),
+// leaving the sum in every lane of the group.  Within a row of 16 lanes the partners come
+// from DPP lane permutations (after the xor-1 and xor-2 steps all lanes of a quad agree, so
+// the half-row and row mirrors pair equal-valued groups); wider groups use shuffles.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_partner(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, false));
+}
+
+template <int N>
+__device__ __forceinline__ void group_sum(float* v, int S) {
+  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_partner<kXor1>(v[j]);
+  if (S >= 4) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += dpp_partner<kXor2>(v[j]);
+  }
+  if (S >= 8) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += dpp_partner<kHalfMirror>(v[j]);
+  }
+  if (S >= 16) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += dpp_partner<kMirror>(v[j]);
+  }
+  for (int off = 16; off < S; off <<= 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] += __shfl_xor(v[j], off);
+  }
 }
 
 template <int kW>
@@ -375,6 +410,8 @@ __global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_ker
   float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
   float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
   float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
+  char* const c0b = (char*)c0;
+  char* const c1b = (char*)c1;
   double n[3];
   float nf[3], e1f[3], e2f[3];
 #pragma unroll
@@ -406,6 +443,8 @@ __global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_ker
   // no tap may pass the grid allotment (samples beyond it only add to unwritten points)
   const double umax = (double)bd.qmax + 0.5 * kW;
   for (int x = tid; x < kRing; x += kSpreadWin) st.acc[x] = make_float4(0.f, 0.f, 0.f, 0.f);
+  st.w[0][tid] = 0.f;
+  st.w[kW + 1][tid] = 0.f;
   if (tid < (kW / 2) * kTapCoef) s_tap[tid / kTapCoef][tid % kTapCoef] = a.tapc[tid / kTapCoef][tid % kTapCoef];
   float wmax = 0.0f;
   int qdone = 0;  // grid points [0, qdone) are written
@@ -443,54 +482,66 @@ __global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_ker
     if (tid < take) {
       const int prev = tid == 0 ? base - 1 : st.lo[tid - 1] + kW - 1;
       const int mine = st.lo[tid] + kW - 1;
-      for (int x = max(prev + 1, base) - base; x <= min(mine - base, G - 1); ++x) st.first[x] = tid;
+      for (int x = max(prev + 1, base) - base; x <= min(mine - base, G - 1); ++x) st.first[x] = (short)tid;
     }
-    if (tid < kW) st.first[max(G, 0) + tid] = take;  // past the last point: no sample
+    if (tid <= kW) st.first[max(G, 0) + tid] = (short)take;  // past the last point: no sample
     __syncthreads();
+    // Each lane group sums a pair of adjacent grid points x0 = 2 y, x0 + 1 over the samples
+    // reaching either (first[x0] .. first[x0 + 1 + W] - 1, tap x0 - lo in [-1, W - 1]); S
+    // lanes split a pair's samples when the chunk has few points for its samples.
+    const int G2 = (G + 1) >> 1;
     int S = 1;
-    while (S < 64 && 2 * S * G <= kSpreadWin) S *= 2;
+    while (S < 64 && 2 * S * G2 <= kSpreadWin) S *= 2;
     const int per_pass = kSpreadWin / S;
-    const int ring0 = base % kRing;  // slot of grid point base (base >= 1)
-    for (int xb = 0; xb < G; xb += per_pass) {
-      const int x = xb + tid / S, sl = tid % S;
-      float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, acc3 = 0.f;
-      if (x < G) {
-        const int q = base + x;
-        // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale)
-        const int s_begin = min(max(st.first[x], 0), take);
-        const int s_end = min(max(st.first[x + kW], s_begin), take);
-        // two samples per trip: half the loop control (2 % of the kernel; 4 gained less)
-#pragma unroll 2
-        for (int s = s_begin + sl; s < s_end; s += S) {
-          const int i = min(max(q - st.lo[s], 0), kW - 1);
-          const float w = st.w[i][s];
-          const float4 gv = st.g[s];
-          acc0 = fmaf(w, gv.x, acc0);
-          acc1 = fmaf(w, gv.y, acc1);
-          acc2 = fmaf(w, gv.z, acc2);
-          acc3 = fmaf(w, gv.w, acc3);
-        }
+    const int ring0 = base & (kRing - 1);  // slot of grid point base
+    for (int yb = 0; yb < G2; yb += per_pass) {
+      const int y = yb + tid / S, sl = tid % S;
+      const bool live = y < G2;
+      const int x0 = live ? 2 * y : 0;
+      // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale);
+      // lanes past the last pair get an empty range
+      const int s_begin = min(max((int)st.first[x0], 0), take);
+      const int s_end = live ? min(max((int)st.first[x0 + 1 + kW], s_begin), take) : s_begin;
+      float a[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] = 0.f;
+      const int q0 = base + x0;
+#pragma unroll 1
+      for (int s = s_begin + sl; s < s_end; s += S) {
+        const int r = min(max(q0 - st.lo[s], -1), kW - 1) + 1;  // row of tap x0 - lo
+        const float w0 = st.w[r][s], w1 = st.w[r + 1][s];
+        const float4 gv = st.g[s];
+        a[0] = fmaf(w0, gv.x, a[0]);
+        a[1] = fmaf(w0, gv.y, a[1]);
+        a[2] = fmaf(w0, gv.z, a[2]);
+        a[3] = fmaf(w0, gv.w, a[3]);
+        a[4] = fmaf(w1, gv.x, a[4]);
+        a[5] = fmaf(w1, gv.y, a[5]);
+        a[6] = fmaf(w1, gv.z, a[6]);
+        a[7] = fmaf(w1, gv.w, a[7]);
       }
-      for (int off = S >> 1; off > 0; off >>= 1) {
-        acc0 += __shfl_xor(acc0, off);
-        acc1 += __shfl_xor(acc1, off);
-        acc2 += __shfl_xor(acc2, off);
-        acc3 += __shfl_xor(acc3, off);
-      }
-      if (x < G && sl == 0) {
-        const int slot = ring0 + x < kRing ? ring0 + x : ring0 + x - kRing;  // x < G <= kRing
-        float4& r = st.acc[slot];
-        const float4 v = make_float4(r.x + acc0, r.y + acc1, r.z + acc2, r.w + acc3);
-        // q >= qdone on valid data (the chunk starts at or after the oldest pending point); on
-        // invalid data, which is reported, a point may be rewritten, still within [1, Q)
-        const int q = base + x;
-        if (q < qfin) {
-          *(float2*)(c0 + 2 * q) = make_float2(v.x, v.y);
-          *(float2*)(c1 + 2 * q) = make_float2(v.z, v.w);
-          wmax = fmaxf(wmax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-          r = make_float4(0.f, 0.f, 0.f, 0.f);
-        } else {
-          r = v;
+      if (S > 1) group_sum<8>(a, S);
+      if (live && sl == 0) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int x = x0 + j;
+          if (x < G) {
+            float4& rs = st.acc[(ring0 + x) & (kRing - 1)];  // x < G <= kRing
+            const float4 v = make_float4(rs.x + a[4 * j], rs.y + a[4 * j + 1], rs.z + a[4 * j + 2],
+                                         rs.w + a[4 * j + 3]);
+            // q >= qdone on valid data (the chunk starts at or after the oldest pending point);
+            // on invalid data, which is reported, a point may be rewritten, still within [1, Q)
+            const int q = base + x;
+            if (q < qfin) {
+              const uint32_t off = (uint32_t)q * 8u;  // byte offset of point q in a column
+              *(float2*)(c0b + off) = make_float2(v.x, v.y);
+              *(float2*)(c1b + off) = make_float2(v.z, v.w);
+              wmax = fmaxf(fmaxf(fmaxf(fmaxf(wmax, fabsf(v.x)), fabsf(v.y)), fabsf(v.z)), fabsf(v.w));
+              rs = make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+              rs = v;
+            }
+          }
         }
       }
     }

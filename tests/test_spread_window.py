@@ -5,13 +5,14 @@ grid: sample s adds its W tap values to grid points lo_s .. lo_s + W - 1.  The k
 samples in chunks of up to 256 and keeps running sums in a ring of kRing grid points (slot
 q mod kRing).  A chunk takes the samples whose taps stay within kRing of the oldest unwritten
 point (and leaves its last sample to the next chunk, so that the next first tap is known); a
-table gives the first sample reaching each point of the chunk; a point below the next chunk's
-first tap is final, is written and its slot cleared; points no sample reaches are written as
-zeros.  This module re-states that logic step by step, with the kernel's clamps and sizes, and
+table gives the first sample reaching each point of the chunk; each pair of adjacent points
+(x0 = 2 y, x0 + 1) is summed over the samples reaching either, reading taps x0 - lo and
+x0 + 1 - lo from rows padded with a zero tap on each side; a point below the next chunk's first
+tap is final, is written and its slot cleared; points no sample reaches are written as zeros.  This module re-states that logic step by step, with the kernel's clamps and sizes, and
 checks on random first-tap sequences -- dense, sparse (3 to 7 points per sample), gapped,
 co-located -- at rings of 512 (the kernel's), 768 and 1024 that
 
-* every index stays inside its buffer (first-sample table, ring, column),
+* every index stays inside its buffer (first-sample table, padded tap rows, ring, column),
 * no ring slot ever holds the running sums of two grid points at once,
 * every grid point below Q is written exactly once and equals the brute-force sum of the taps
   that land on it,
@@ -37,6 +38,9 @@ def emulate(lo_all, vals, Q, W, k_ring, strict=True):
     def clamp(v, a, b):
         return min(max(v, a), b)
 
+    # tap rows as the kernel keeps them: a zero before tap 0 and after tap W - 1
+    wpad = np.zeros((n, W + 2))
+    wpad[:, 1:W + 1] = vals
     qdone, kc, guard = 0, 0, 0
     while kc < n:
         guard += 1
@@ -52,36 +56,47 @@ def emulate(lo_all, vals, Q, W, k_ring, strict=True):
         qfin = Q
         if kc + take < n:
             qfin = min(Q, lo[take] if take < cnt else top + 1)
-        first = np.full(k_ring + W, -12345)
+        first = np.full(k_ring + W + 1, -12345)
         for t in range(take):
             prev = base - 1 if t == 0 else lo[t - 1] + W - 1
             mine = lo[t] + W - 1
             for x in range(max(prev + 1, base) - base, min(mine - base, G - 1) + 1):
                 assert 0 <= x < len(first)
                 first[x] = t
-        for t in range(W):
+        for t in range(W + 1):
             assert 0 <= max(G, 0) + t < len(first)
             first[max(G, 0) + t] = take
         ring0 = base % k_ring
-        for x in range(G):
-            q = base + x
-            sb = clamp(first[x], 0, take)
-            se = clamp(first[x + W], sb, take)
-            acc = 0.0
+        for y in range((G + 1) // 2):
+            x0 = 2 * y
+            q0 = base + x0
+            assert 0 <= x0 + 1 + W < len(first)
+            sb = clamp(first[x0], 0, take)
+            se = clamp(first[x0 + 1 + W], sb, take)
+            acc = [0.0, 0.0]
             for s in range(sb, se):
-                acc += vals[kc + s, clamp(q - lo[s], 0, W - 1)]
-            slot = ring0 + x if ring0 + x < k_ring else ring0 + x - k_ring
-            assert 0 <= slot < k_ring
-            if strict:
-                assert owner[slot] in (-1, q), f"slot {slot} holds point {owner[slot]} and {q}"
-            v = ring[slot] + acc
-            if q < qfin:
-                assert 0 <= q < Q
-                F[q] = v
-                writes[q] += 1
-                ring[slot], owner[slot] = 0.0, -1
-            else:
-                ring[slot], owner[slot] = v, q
+                assert 0 <= s < CHUNK
+                r = clamp(q0 - lo[s], -1, W - 1) + 1
+                assert 0 <= r and r + 1 <= W + 1
+                acc[0] += wpad[kc + s, r]
+                acc[1] += wpad[kc + s, r + 1]
+            for j in range(2):
+                x = x0 + j
+                if x >= G:
+                    continue
+                q = base + x
+                slot = ring0 + x if ring0 + x < k_ring else ring0 + x - k_ring
+                assert 0 <= slot < k_ring
+                if strict:
+                    assert owner[slot] in (-1, q), f"slot {slot} holds point {owner[slot]} and {q}"
+                v = ring[slot] + acc[j]
+                if q < qfin:
+                    assert 0 <= q < Q
+                    F[q] = v
+                    writes[q] += 1
+                    ring[slot], owner[slot] = 0.0, -1
+                else:
+                    ring[slot], owner[slot] = v, q
         for q in range(qdone, min(base, qfin)):
             F[q] = 0.0
             writes[q] += 1
