@@ -225,41 +225,42 @@ __global__ void lw_etable_kernel(T* hi, T* lo, const double* omega, Band bd) {
 }
 
 // ------------------------------------------------------------------ spreading
-// One work-group per (particle of the chunk, direction, band).  Samples are sorted in
-// tau because dtau/dt = kappa > 0, so each sample's W taps (W even) cover grid points
-// lo_s .. lo_s + W - 1 with lo_s = floor(u_s) - W/2 + 1 nondecreasing in s.  The trajectory
-// is walked in chunks of 256 samples, each staged once:
-//   1. one thread per sample: prepass, demodulation, grid coordinate and its W tap
-//      weights phi(lo_s + i - u_s), kept in LDS;
-//   2. first[x] = the first sample of the chunk whose taps reach grid point base + x
-//      (built by the samples themselves, no search); the samples reaching q are then
-//      exactly first[x] .. first[x + W] - 1, since each covers W consecutive points;
-//   3. one thread (or S threads taking every S-th sample, summed with shuffles) per grid
-//      point adds w g over its samples to the point's running sum, held in a ring in LDS;
-//   4. a point below the next chunk's first tap is then final: that thread writes it to F
-//      (FP32) and clears its ring slot; the chunk's points that no sample reached are
-//      written as zeros.
-// The next chunk starts with the sample that did not fit the ring, so every grid point
-// of a chunk lies within kRing of the oldest pending one.
-// Grid points held in LDS.  512 covers the grid points of a 256-sample chunk up to two
-// points per sample and keeps a work-group at 26 KB of LDS; with at most 80 VGPRs (the
-// launch bound below asks for six waves per SIMD) six work-groups share a CU.  Measured
-// against 768 (31 KB, five per CU): 4 % faster; 1024 (four per CU) was 12 % slower still.
-// Sparser columns take fewer samples per chunk.
-constexpr int kRing = 512;
-static_assert((kRing & (kRing - 1)) == 0, "ring slots are taken modulo a power of two");
+// One work-group per (particle of the chunk, direction, group of up to two bands).
+// Samples are sorted in tau because dtau/dt = kappa > 0, so each sample's W taps (W even)
+// cover grid points lo_s .. lo_s + W - 1 with lo_s = floor(u_s) - W/2 + 1 nondecreasing in
+// s, in every band.  The trajectory is walked in chunks of 256 samples, each loaded once:
+//   1. one thread per sample: the prepass (retarded time, integrand) shared by the bands,
+//      and each band's grid coordinate;
+//   2. per band in turn: the demodulated integrand and the W tap weights
+//      phi(lo_s + i - u_s) go to LDS, and first[x] = the first sample of the chunk whose
+//      taps reach grid point base + x (built by the samples themselves, no search); the
+//      samples reaching q are then exactly first[x] .. first[x + W] - 1;
+//   3. per band, one lane (or S lanes taking every S-th sample, summed across lanes) per
+//      pair of adjacent grid points adds w g over the samples reaching either point;
+//   4. a point below the next chunk's first tap is final and is written to F (FP32); the
+//      points at or above it (fewer than W: the next chunk starts with the sample whose
+//      taps reach that tap) are carried to the next chunk in a small LDS buffer; the
+//      chunk's points that no sample reached are written as zeros.
+// A chunk takes the samples whose taps stay within kWin points of the oldest unwritten
+// point in every band; the next chunk starts with the first sample it did not take.
+// kWin = 512 covers a 256-sample chunk up to two grid points per sample; the work-group
+// keeps 19 KB of LDS, and with at most 80 VGPRs (the launch bound below asks for six waves
+// per SIMD) six work-groups share a CU.
+constexpr int kWin = 512;
 constexpr int kSpreadWavesPerSimd = 6;
+constexpr int kBandGroup = 2;  // bands per work-group
 
 template <int kW>
 struct SpreadStage {
   static_assert(kW % 2 == 0 && kW <= kWMax, "even widths: the tap window must not depend on frac(u)");
-  float4 acc[kRing];              // running grid sums, slot q mod kRing
-  float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2)
+  float4 g[kSpreadWin];           // demodulated integrand (re1, im1, re2, im2) of the band
   // tap i of sample s at w[i + 1][s]; rows 0 and kW + 1 stay zero, so that a pair of
   // adjacent grid points reads taps i and i + 1 of any sample reaching either of them
   float w[kW + 2][kSpreadWin];
   int lo[kSpreadWin];             // first grid point of each sample's taps
-  short first[kRing + kW + 1];    // first sample reaching grid point base + x
+  short first[kWin + kW + 1];     // first sample reaching grid point base + x
+  // grid sums still open at a chunk boundary, per band, read and written in turn
+  float4 carry[kBandGroup][2][kW];
 };
 
 // One sample's trajectory data, loaded a chunk ahead of its use.
@@ -294,17 +295,20 @@ __device__ __forceinline__ float dot3f(const float a[3], float x, float y, float
   return fmaf(a[0], x, fmaf(a[1], y, a[2] * z));
 }
 
-template <int kW>
-__device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& bd, SpreadStage<kW>& st,
-                                              const RawSample& r, const double* n, const float* nf,
-                                              const float* e1f, const float* e2f,
-                                              const float (*tap)[kTapCoef], int64_t p, int64_t len,
-                                              int64_t kc,
-                                              double t0, double dtp, double tau0, double inv_h,
-                                              double umax) {
-  const int tid = threadIdx.x;
-  const int64_t k = kc + tid;
-  if (k >= len) return;
+// The band-independent part of a sample: retarded time from the first sample (FP64) and
+// the integrand's two polarisation components (FP32); invalid samples are reported.
+struct Prepass {
+  double taup;
+  float g1, g2;
+  bool ok;
+};
+
+__device__ __forceinline__ Prepass prepass(const SpreadArgs& a, const RawSample& r, const double* n,
+                                           const float* frame, int64_t p, int64_t k, double t0, double dtp,
+                                           double tau0) {
+  const float* nf = frame;
+  const float* e1f = frame + 3;
+  const float* e2f = frame + 6;
   const double bx = r.bx, by = r.by, bz = r.bz;
   // kappa = 1 - n.beta cancels as |beta| -> 1 and stays FP64; the integrand is used in FP32
   // and is formed in FP32 from it (e.(n x ((n - beta) x a)) = -(e.beta)(n.a) - kappa (e.a))
@@ -312,20 +316,35 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
   const float kf = (float)kap, bxf = (float)bx, byf = (float)by, bzf = (float)bz;
   const float na = dot3f(nf, r.ax, r.ay, r.az);
   const float sc = (float)dtp * __builtin_amdgcn_rcpf(kf * kf);
-  const float g1 = -(na * dot3f(e1f, bxf, byf, bzf) + kf * dot3f(e1f, r.ax, r.ay, r.az)) * sc;
-  const float g2 = -(na * dot3f(e2f, bxf, byf, bzf) + kf * dot3f(e2f, r.ax, r.ay, r.az)) * sc;
-  const double taup = (t0 + (double)k * dtp - dot3(n, r.x, r.y, r.z)) - tau0;
-  const bool ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(taup) && isfinite(g1) && isfinite(g2);
-  if (!ok) atomicMin(a.err, (unsigned long long)p);
-  const double x = bd.wc_turn * taup;
+  Prepass q;
+  q.g1 = -(na * dot3f(e1f, bxf, byf, bzf) + kf * dot3f(e1f, r.ax, r.ay, r.az)) * sc;
+  q.g2 = -(na * dot3f(e2f, bxf, byf, bzf) + kf * dot3f(e2f, r.ax, r.ay, r.az)) * sc;
+  q.taup = (t0 + (double)k * dtp - dot3(n, r.x, r.y, r.z)) - tau0;
+  q.ok = (bx * bx + by * by + bz * bz < 1.0) && isfinite(q.taup) && isfinite(q.g1) && isfinite(q.g2);
+  if (!q.ok) atomicMin(a.err, (unsigned long long)p);
+  return q;
+}
+
+// Grid coordinate of a sample in one band, kept within the grid even for invalid samples
+// (those add nothing): the first tap's grid point and the fraction of u.
+template <int kW>
+__device__ __forceinline__ void grid_coord(const Prepass& q, double inv_h, double umax, int& lo, float& fu) {
+  double u = q.taup * inv_h + 0.5 * kW;
+  u = q.ok ? fmin(fmax(u, 0.5 * kW), umax) : 0.5 * kW;
+  const double iu = floor(u);
+  fu = (float)(u - iu);
+  lo = (int)iu - (kW / 2 - 1);
+}
+
+// One band's stage of a sample: demodulated integrand and the W tap weights.
+template <int kW>
+__device__ __forceinline__ void stage_band(SpreadStage<kW>& st, const Prepass& q, double wc_turn, int lo,
+                                           float fu, const float (*tap)[kTapCoef]) {
+  const int tid = threadIdx.x;
+  const double x = wc_turn * q.taup;
   const float fr = (float)(x - rint(x));
   const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
-  // grid coordinate, kept within the grid even for invalid samples (those add nothing)
-  double u = taup * inv_h + 0.5 * kW;
-  u = ok ? fmin(fmax(u, 0.5 * kW), umax) : 0.5 * kW;
-  const double iu = floor(u);
-  const float fu = (float)(u - iu);
-  st.lo[tid] = (int)iu - (kW / 2 - 1);
+  st.lo[tid] = lo;
   const float z = 2.0f * fu - 1.0f, z2 = z * z;
   // phi(q - u) for q = lo + i: tap i is E(z^2) + z O(z^2) and tap W - 1 - i is E - z O, with
   // E and O the even and odd parts of tap i's polynomial, each by Horner in z^2
@@ -340,15 +359,15 @@ __device__ __forceinline__ void stage_samples(const SpreadArgs& a, const Band& b
     st.w[i + 1][tid] = fmaf(z, o, e);
     st.w[kW - i][tid] = fmaf(-z, o, e);
   }
-  const float G1 = ok ? g1 : 0.f, G2 = ok ? g2 : 0.f;
+  const float G1 = q.ok ? q.g1 : 0.f, G2 = q.ok ? q.g2 : 0.f;
   st.g[tid] = make_float4(G1 * cs, G1 * sn, G2 * cs, G2 * sn);
 }
 
 // Work-groups go to the eight XCDs in turn (block b to XCD b mod 8).  This numbering gives
 // each XCD a contiguous run of n items instead, so that neighbouring items -- every (direction,
-// band) of one particle -- run on one XCD and read the particle's trajectory through one L2.
-// XCD x holds blocks x, x + 8, ...: m + (x < r) of them with n = 8 m + r, numbered from
-// x m + min(x, r); the map is a bijection of [0, n).
+// band group) of one particle -- run on one XCD and read the particle's trajectory through
+// one L2.  XCD x holds blocks x, x + 8, ...: m + (x < r) of them with n = 8 m + r, numbered
+// from x m + min(x, r); the map is a bijection of [0, n).
 __device__ __forceinline__ int xcd_contiguous(int b, int n) {
   const int m = n / 8, r = n % 8, x = b % 8, j = b / 8;
   return x * m + min(x, r) + j;
@@ -386,68 +405,187 @@ __device__ __forceinline__ void group_sum(float* v, int S) {
   }
 }
 
+// A band's walk along the trajectory, shared by the work-group in LDS.
+struct BandWalk {
+  int Q;      // grid points of the column
+  int qdone;  // grid points [0, qdone) are written
+  int cbase;  // first grid point of the open sums carried in from the previous chunk
+  int par;    // carry buffer read by this chunk
+};
+
+// Gather of one band over the staged chunk: pairs of grid points, final points to the
+// band's two F columns (byte pointers c0, c1), the open ones to the carry buffer.  Every
+// thread reads the walk state before the first barrier here; thread 0 writes it back after,
+// to be read after the next chunk's first barrier.  Returns the band's new qdone.
+template <int kW>
+__device__ __forceinline__ int gather_band(SpreadStage<kW>& st, BandWalk& bws, int k, int take, int cnt,
+                                           bool last, char* c0, char* c1, float& wmax) {
+  const int tid = threadIdx.x;
+  const BandWalk bw = bws;
+  const int base = st.lo[0];
+  const int top = st.lo[take - 1] + kW - 1;  // highest grid point touched
+  const int G = min(top - base + 1, kWin);
+  // grid points below the next chunk's first tap are final after this chunk
+  int qfin = bw.Q;
+  if (!last) qfin = min(bw.Q, take < cnt ? st.lo[take] : top + 1);
+  // first sample reaching each grid point of the chunk
+  if (tid < take) {
+    const int prev = tid == 0 ? base - 1 : st.lo[tid - 1] + kW - 1;
+    const int mine = st.lo[tid] + kW - 1;
+    for (int x = max(prev + 1, base) - base; x <= min(mine - base, G - 1); ++x) st.first[x] = (short)tid;
+  }
+  if (tid <= kW) st.first[max(G, 0) + tid] = (short)take;  // past the last point: no sample
+  float4* const cin = st.carry[k][bw.par];
+  float4* const cout = st.carry[k][bw.par ^ 1];
+  __syncthreads();
+  const int G2 = (G + 1) >> 1;
+  int S = 1;
+  while (S < 64 && 2 * S * G2 <= kSpreadWin) S *= 2;
+  const int per_pass = kSpreadWin / S;
+  for (int yb = 0; yb < G2; yb += per_pass) {
+    const int y = yb + tid / S, sl = tid % S;
+    const bool live = y < G2;
+    const int x0 = live ? 2 * y : 0;
+    // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale);
+    // lanes past the last pair get an empty range
+    const int s_begin = min(max((int)st.first[x0], 0), take);
+    const int s_end = live ? min(max((int)st.first[x0 + 1 + kW], s_begin), take) : s_begin;
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.f;
+    const int q0 = base + x0;
+#pragma unroll 1
+    for (int s = s_begin + sl; s < s_end; s += S) {
+      const int r = min(max(q0 - st.lo[s], -1), kW - 1) + 1;  // row of tap x0 - lo
+      const float w0 = st.w[r][s], w1 = st.w[r + 1][s];
+      const float4 gv = st.g[s];
+      acc[0] = fmaf(w0, gv.x, acc[0]);
+      acc[1] = fmaf(w0, gv.y, acc[1]);
+      acc[2] = fmaf(w0, gv.z, acc[2]);
+      acc[3] = fmaf(w0, gv.w, acc[3]);
+      acc[4] = fmaf(w1, gv.x, acc[4]);
+      acc[5] = fmaf(w1, gv.y, acc[5]);
+      acc[6] = fmaf(w1, gv.z, acc[6]);
+      acc[7] = fmaf(w1, gv.w, acc[7]);
+    }
+    if (S > 1) group_sum<8>(acc, S);
+    if (live && sl == 0) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int x = x0 + j;
+        if (x < G) {
+          const int q = base + x;
+          float4 v = make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
+          // sums opened by the previous chunk (its last W points at most; the carry window
+          // is checked, so that stale entries of invalid data stay unread)
+          const unsigned ci = (unsigned)(q - bw.cbase);
+          if (ci < (unsigned)kW) {
+            const float4 c = cin[ci];
+            v.x += c.x;
+            v.y += c.y;
+            v.z += c.z;
+            v.w += c.w;
+          }
+          // q >= qdone on valid data (the chunk starts at or after the oldest pending point);
+          // on invalid data, which is reported, a point may be rewritten, still within [1, Q)
+          if (q < qfin) {
+            const uint32_t off = (uint32_t)q * 8u;  // byte offset of point q (q < Q <= 4e6)
+            *(float2*)(c0 + off) = make_float2(v.x, v.y);
+            *(float2*)(c1 + off) = make_float2(v.z, v.w);
+            wmax = fmaxf(fmaxf(fmaxf(fmaxf(wmax, fabsf(v.x)), fabsf(v.y)), fabsf(v.z)), fabsf(v.w));
+          } else {
+            const unsigned co = (unsigned)(q - qfin);  // < W on valid data
+            if (co < (unsigned)kW) cout[co] = v;
+          }
+        }
+      }
+    }
+  }
+  // final points outside [base, base + G) were reached by no sample: below the first
+  // chunk's first tap, in a gap between two samples wider than the kernel, or past the
+  // last tap of the trajectory
+  for (int q = bw.qdone + tid; q < min(base, qfin); q += kSpreadWin) {
+    *(float2*)(c0 + (uint32_t)q * 8u) = make_float2(0.f, 0.f);
+    *(float2*)(c1 + (uint32_t)q * 8u) = make_float2(0.f, 0.f);
+  }
+  for (int q = max(base + G, bw.qdone) + tid; q < qfin; q += kSpreadWin) {
+    *(float2*)(c0 + (uint32_t)q * 8u) = make_float2(0.f, 0.f);
+    *(float2*)(c1 + (uint32_t)q * 8u) = make_float2(0.f, 0.f);
+  }
+  if (tid == 0) bws = BandWalk{bw.Q, max(bw.qdone, qfin), qfin, bw.par ^ 1};
+  return max(bw.qdone, qfin);
+}
+
+// The particle's two F columns of band bi for direction d, as byte pointers.
+__device__ __forceinline__ void band_columns(const SpreadArgs& a, int bi, int d, int pl, char*& c0, char*& c1) {
+  const Band& bd = a.band[bi];
+  float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
+  c0 = (char*)(Fb + (size_t)(2 * pl) * bd.kp);
+  c1 = (char*)(Fb + (size_t)(2 * pl + 1) * bd.kp);
+}
+
 template <int kW>
 __global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_kernel(SpreadArgs a) {
   __shared__ SpreadStage<kW> st;
-  __shared__ float s_wmax[kSpreadWin / 64];
+  __shared__ BandWalk s_walk[kBandGroup];
+  __shared__ float s_wmax[kBandGroup][kSpreadWin / 64];
   // the first W/2 tap polynomials, read at one address by all lanes (held as kernel
   // arguments they would crowd the scalar registers)
   __shared__ float s_tap[kW / 2][kTapCoef];
+  // the direction and its polarisation axes in FP32 (read at one address by all lanes)
+  __shared__ float s_frame[9];
+  __shared__ double s_n[3];
 
   const int tid = threadIdx.x;
-  // block -> item -> (particle, direction, band); bands fastest so one particle's work is
-  // adjacent, and each XCD takes a contiguous run of items
+  // block -> item -> (particle, direction, band group); groups fastest so one particle's
+  // work is adjacent, and each XCD takes a contiguous run of items
+  const int ng = (a.nb + kBandGroup - 1) / kBandGroup;
   const int item = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
-  const int bi = item % a.nb;
-  const int d = (item / a.nb) % a.nd;
-  const int pl = item / (a.nb * a.nd);
-  const Band bd = a.band[bi];
+  const int gi = item % ng;
+  const int d = (item / ng) % a.nd;
+  const int pl = item / (ng * a.nd);
+  const int b0 = gi * kBandGroup;
+  const int nbg = min(kBandGroup, a.nb - b0);  // bands of this group (1 or 2)
   const int64_t p = a.p_begin + pl;
   const int64_t o = a.b.offsets[p], len = a.b.offsets[p + 1] - o;
   const double t0 = a.b.t0[p], dtp = a.b.dt[p];
   const int ncol = 2 * a.n_local;
-  const int db = d * a.nb + bi;
-  float* Fb = a.F + (size_t)d * a.f_dir + bd.f_off;
-  float* c0 = Fb + (size_t)(2 * pl) * bd.kp;
-  float* c1 = Fb + (size_t)(2 * pl + 1) * bd.kp;
-  char* const c0b = (char*)c0;
-  char* const c1b = (char*)c1;
   double n[3];
-  float nf[3], e1f[3], e2f[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    n[c] = a.dirs[kDirStride * d + c];
-    nf[c] = (float)n[c];
-    e1f[c] = (float)a.dirs[kDirStride * d + 3 + c];
-    e2f[c] = (float)a.dirs[kDirStride * d + 6 + c];
-  }
+  for (int c = 0; c < 3; ++c) n[c] = a.dirs[kDirStride * d + c];
+  if (tid < 9) s_frame[tid] = (float)a.dirs[kDirStride * d + tid];
+  if (tid < 3) s_n[tid] = a.dirs[kDirStride * d + tid];
 
-  if (tid == 0 && bi == 0 && d == 0 && a.b.species) {
+  if (tid == 0 && gi == 0 && d == 0 && a.b.species) {
     const int sp = a.b.species[p];
     if (sp < 0 || sp >= a.ns) atomicMin(a.err, (unsigned long long)p);
   }
-  if (tid == 0 && bi == 0 && d == 0 && len < 0) atomicMin(a.err, (unsigned long long)p);
-  int Q = 0;
+  if (tid == 0 && gi == 0 && d == 0 && len < 0) atomicMin(a.err, (unsigned long long)p);
   double tau0 = 0.0;
-  if (len > 0) {
-    tau0 = retarded_time(a.b, o, t0, n);
-    const double taul = retarded_time(a.b, o + len - 1, t0 + (double)(len - 1) * dtp, n);
-    double span = taul - tau0;
-    if (!(span >= 0.0) || !isfinite(span)) span = 0.0;
-    const double qneed = ceil(span / bd.h) + kW + 1;
-    // a batch that outgrew the plan is reported, not silently clipped
-    if (tid == 0 && qneed > (double)bd.qmax) atomicMin(a.overflow, (unsigned long long)p);
-    Q = (int)fmin(qneed, (double)bd.qmax);
+  if (len > 0) tau0 = retarded_time(a.b, o, t0, n);
+  if (tid < nbg) {
+    const Band& bd = a.band[b0 + tid];
+    int Q = 0;
+    if (len > 0) {
+      const double taul = retarded_time(a.b, o + len - 1, t0 + (double)(len - 1) * dtp, n);
+      double span = taul - tau0;
+      if (!(span >= 0.0) || !isfinite(span)) span = 0.0;
+      const double qneed = ceil(span / bd.h) + kW + 1;
+      // a batch that outgrew the plan is reported, not silently clipped
+      if (qneed > (double)bd.qmax) atomicMin(a.overflow, (unsigned long long)p);
+      Q = (int)fmin(qneed, (double)bd.qmax);
+    }
+    s_walk[tid] = BandWalk{Q, 0, 0, 0};
   }
-  const double inv_h = 1.0 / bd.h;
-  // no tap may pass the grid allotment (samples beyond it only add to unwritten points)
-  const double umax = (double)bd.qmax + 0.5 * kW;
-  for (int x = tid; x < kRing; x += kSpreadWin) st.acc[x] = make_float4(0.f, 0.f, 0.f, 0.f);
   st.w[0][tid] = 0.f;
   st.w[kW + 1][tid] = 0.f;
+  if (tid < kBandGroup * 2 * kW) (&st.carry[0][0][0])[tid] = make_float4(0.f, 0.f, 0.f, 0.f);
   if (tid < (kW / 2) * kTapCoef) s_tap[tid / kTapCoef][tid % kTapCoef] = a.tapc[tid / kTapCoef][tid % kTapCoef];
-  float wmax = 0.0f;
-  int qdone = 0;  // grid points [0, qdone) are written
+  __syncthreads();
+  float wmax0 = 0.0f, wmax1 = 0.0f;  // this thread's largest |F| written, per band
+  // each thread's copy of the bands' qdone, for the chunk's fit test (which precedes the
+  // chunk's first barrier, so it cannot read the shared walk state)
+  int qd0 = 0, qd1 = 0;
   int64_t kc = 0;
   // the chunk after this one usually starts one sample before this one ends: its data
   // is requested while this chunk is processed
@@ -459,125 +597,84 @@ __global__ __launch_bounds__(kSpreadWin, kSpreadWavesPerSimd) void lw_spread_ker
     raw = next;
     const int cnt = (int)min((int64_t)kSpreadWin, len - kc);
     k_next = kc + (kc + cnt < len ? cnt - 1 : cnt);
-    if (k_next < len) load_raw(a.b, o, len, k_next, next);
-    __syncthreads();  // the previous chunk's LDS is no longer read
-    stage_samples(a, bd, st, raw, n, nf, e1f, e2f, s_tap, p, len, kc, t0, dtp, tau0, inv_h, umax);
-    __syncthreads();
-    const int base = st.lo[0];
-    // samples whose taps fit the ring; the chunk's last sample waits for the next chunk
-    // unless it ends the trajectory, so that the next chunk's first tap is known here
+    Prepass pq = {0.0, 0.f, 0.f, false};
+    if (tid < cnt) pq = prepass(a, raw, s_n, s_frame, p, kc + tid, t0, dtp, tau0);
+    if (k_next < len) load_raw(a.b, o, len, k_next, next);  // after the prepass: raw is dead
+    // each band's grid coordinate; a chunk takes the samples whose taps stay within kWin
+    // of the oldest unwritten point in every band; its last sample waits for the next
+    // chunk unless it ends the trajectory, so that the next chunk's first tap is known here
+    // (the count also orders the previous chunk's reads of the stage before this chunk's
+    // writes)
+    int lo0, lo1 = 0;
+    float fu0, fu1 = 0.f;
+    {
+      const Band& bd = a.band[b0];
+      grid_coord<kW>(pq, 1.0 / bd.h, (double)bd.qmax + 0.5 * kW, lo0, fu0);
+    }
+    bool fit = tid < cnt && lo0 - qd0 <= kWin - kW;
+    if (nbg > 1) {
+      const Band& bd = a.band[b0 + 1];
+      grid_coord<kW>(pq, 1.0 / bd.h, (double)bd.qmax + 0.5 * kW, lo1, fu1);
+      fit = fit && lo1 - qd1 <= kWin - kW;
+    }
     const bool more = kc + cnt < len;
-    // The ring holds every grid point from the oldest unwritten one (qdone) to the highest
-    // one touched.  qdone is this chunk's first tap except in the first chunk, where it is 0
-    // while the first tap is 1: measuring from it keeps point qdone + kRing out of qdone's slot.
-    const int fits = __syncthreads_count(tid < cnt && st.lo[tid] - qdone <= kRing - kW);
+    const int fits = __syncthreads_count(fit);
     int take = min(fits, more ? cnt - 1 : cnt);
     take = max(take, 1);
-    const int top = st.lo[take - 1] + kW - 1;  // highest grid point touched
-    const int G = min(top - base + 1, kRing);
-    // grid points below the next chunk's first tap are final after this chunk
-    int qfin = Q;
-    if (kc + take < len) qfin = min(Q, take < cnt ? st.lo[take] : top + 1);
-    // first sample reaching each grid point of the chunk
-    if (tid < take) {
-      const int prev = tid == 0 ? base - 1 : st.lo[tid - 1] + kW - 1;
-      const int mine = st.lo[tid] + kW - 1;
-      for (int x = max(prev + 1, base) - base; x <= min(mine - base, G - 1); ++x) st.first[x] = (short)tid;
-    }
-    if (tid <= kW) st.first[max(G, 0) + tid] = (short)take;  // past the last point: no sample
-    __syncthreads();
-    // Each lane group sums a pair of adjacent grid points x0 = 2 y, x0 + 1 over the samples
-    // reaching either (first[x0] .. first[x0 + 1 + W] - 1, tap x0 - lo in [-1, W - 1]); S
-    // lanes split a pair's samples when the chunk has few points for its samples.
-    const int G2 = (G + 1) >> 1;
-    int S = 1;
-    while (S < 64 && 2 * S * G2 <= kSpreadWin) S *= 2;
-    const int per_pass = kSpreadWin / S;
-    const int ring0 = base & (kRing - 1);  // slot of grid point base
-    for (int yb = 0; yb < G2; yb += per_pass) {
-      const int y = yb + tid / S, sl = tid % S;
-      const bool live = y < G2;
-      const int x0 = live ? 2 * y : 0;
-      // (clamped, and the tap index too: on invalid, unsorted data an entry may be stale);
-      // lanes past the last pair get an empty range
-      const int s_begin = min(max((int)st.first[x0], 0), take);
-      const int s_end = live ? min(max((int)st.first[x0 + 1 + kW], s_begin), take) : s_begin;
-      float a[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) a[j] = 0.f;
-      const int q0 = base + x0;
+    const bool last = kc + take >= len;
 #pragma unroll 1
-      for (int s = s_begin + sl; s < s_end; s += S) {
-        const int r = min(max(q0 - st.lo[s], -1), kW - 1) + 1;  // row of tap x0 - lo
-        const float w0 = st.w[r][s], w1 = st.w[r + 1][s];
-        const float4 gv = st.g[s];
-        a[0] = fmaf(w0, gv.x, a[0]);
-        a[1] = fmaf(w0, gv.y, a[1]);
-        a[2] = fmaf(w0, gv.z, a[2]);
-        a[3] = fmaf(w0, gv.w, a[3]);
-        a[4] = fmaf(w1, gv.x, a[4]);
-        a[5] = fmaf(w1, gv.y, a[5]);
-        a[6] = fmaf(w1, gv.z, a[6]);
-        a[7] = fmaf(w1, gv.w, a[7]);
-      }
-      if (S > 1) group_sum<8>(a, S);
-      if (live && sl == 0) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int x = x0 + j;
-          if (x < G) {
-            float4& rs = st.acc[(ring0 + x) & (kRing - 1)];  // x < G <= kRing
-            const float4 v = make_float4(rs.x + a[4 * j], rs.y + a[4 * j + 1], rs.z + a[4 * j + 2],
-                                         rs.w + a[4 * j + 3]);
-            // q >= qdone on valid data (the chunk starts at or after the oldest pending point);
-            // on invalid data, which is reported, a point may be rewritten, still within [1, Q)
-            const int q = base + x;
-            if (q < qfin) {
-              const uint32_t off = (uint32_t)q * 8u;  // byte offset of point q in a column
-              *(float2*)(c0b + off) = make_float2(v.x, v.y);
-              *(float2*)(c1b + off) = make_float2(v.z, v.w);
-              wmax = fmaxf(fmaxf(fmaxf(fmaxf(wmax, fabsf(v.x)), fabsf(v.y)), fabsf(v.z)), fabsf(v.w));
-              rs = make_float4(0.f, 0.f, 0.f, 0.f);
-            } else {
-              rs = v;
-            }
-          }
-        }
+    for (int k = 0; k < nbg; ++k) {
+      if (k > 0) __syncthreads();  // the previous band's gather no longer reads the stage
+      const Band& bd = a.band[b0 + k];
+      if (tid < cnt) stage_band<kW>(st, pq, bd.wc_turn, k ? lo1 : lo0, k ? fu1 : fu0, s_tap);
+      if (tid < kW) st.carry[k][s_walk[k].par ^ 1][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+      __syncthreads();
+      char *c0, *c1;
+      band_columns(a, b0 + k, d, pl, c0, c1);
+      float wm = k ? wmax1 : wmax0;
+      const int qd = gather_band<kW>(st, s_walk[k], k, take, cnt, last, c0, c1, wm);
+      if (k) {
+        wmax1 = wm;
+        qd1 = qd;
+      } else {
+        wmax0 = wm;
+        qd0 = qd;
       }
     }
-    // final points outside [base, base + G) were reached by no sample: below the first
-    // chunk's first tap, in a gap between two samples wider than the kernel, or past the
-    // last tap of the trajectory
-    for (int q = qdone + tid; q < min(base, qfin); q += kSpreadWin) {
-      *(float2*)(c0 + 2 * q) = make_float2(0.f, 0.f);
-      *(float2*)(c1 + 2 * q) = make_float2(0.f, 0.f);
-    }
-    for (int q = max(base + G, qdone) + tid; q < qfin; q += kSpreadWin) {
-      *(float2*)(c0 + 2 * q) = make_float2(0.f, 0.f);
-      *(float2*)(c1 + 2 * q) = make_float2(0.f, 0.f);
-    }
-    qdone = max(qdone, qfin);
     kc += take;
   }
-  // The inner dimension is read in groups of eight floats: clear the rest of the column's
-  // last group (at most three grid points, within kp), so that the contraction loads whole
-  // groups and needs no mask.
-  if (tid < ((2 * Q + 7) / 8 * 8 - 2 * Q) / 2) {
-    *(float2*)(c0 + 2 * (Q + tid)) = make_float2(0.f, 0.f);
-    *(float2*)(c1 + 2 * (Q + tid)) = make_float2(0.f, 0.f);
-  }
   // column maximum (one value for both polarisation columns keeps them on one scale)
-  for (int off = 32; off > 0; off >>= 1) wmax = fmaxf(wmax, __shfl_xor(wmax, off));
-  if ((tid & 63) == 0) s_wmax[tid >> 6] = wmax;
+  for (int off = 32; off > 0; off >>= 1) {
+    wmax0 = fmaxf(wmax0, __shfl_xor(wmax0, off));
+    wmax1 = fmaxf(wmax1, __shfl_xor(wmax1, off));
+  }
+  if ((tid & 63) == 0) {
+    s_wmax[0][tid >> 6] = wmax0;
+    s_wmax[1][tid >> 6] = wmax1;
+  }
   __syncthreads();
-  if (tid == 0) {
-    float m = 0.f;
-    for (int w = 0; w < kSpreadWin / 64; ++w) m = fmaxf(m, s_wmax[w]);
-    a.colmax[db * ncol + 2 * pl] = __float_as_uint(m);
-    a.colmax[db * ncol + 2 * pl + 1] = __float_as_uint(m);
-    a.colq[db * a.n_local + pl] = Q;
-    // rows (2 nj) x columns (2 polarisations) x inner (2 Q) multiply-adds of one product
-    if (a.flops) atomicAdd(a.flops, 2ull * (2ull * bd.nj) * 2ull * (2ull * Q));
+#pragma unroll 1
+  for (int k = 0; k < nbg; ++k) {
+    const int Q = s_walk[k].Q;
+    char *c0, *c1;
+    band_columns(a, b0 + k, d, pl, c0, c1);
+    // The inner dimension is read in groups of eight floats: clear the rest of the
+    // column's last group (at most three grid points, within kp), so that the contraction
+    // loads whole groups and needs no mask.
+    if (tid < ((2 * Q + 7) / 8 * 8 - 2 * Q) / 2) {
+      *(float2*)(c0 + (uint32_t)(Q + tid) * 8u) = make_float2(0.f, 0.f);
+      *(float2*)(c1 + (uint32_t)(Q + tid) * 8u) = make_float2(0.f, 0.f);
+    }
+    if (tid == 0) {
+      const int bi = b0 + k, db = d * a.nb + bi;
+      float m = 0.f;
+      for (int w = 0; w < kSpreadWin / 64; ++w) m = fmaxf(m, s_wmax[k][w]);
+      a.colmax[db * ncol + 2 * pl] = __float_as_uint(m);
+      a.colmax[db * ncol + 2 * pl + 1] = __float_as_uint(m);
+      a.colq[db * a.n_local + pl] = Q;
+      // rows (2 nj) x columns (2 polarisations) x inner (2 Q) multiply-adds of one product
+      if (a.flops) atomicAdd(a.flops, 2ull * (2ull * a.band[bi].nj) * 2ull * (2ull * Q));
+    }
   }
 }
 
@@ -1851,6 +1948,7 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
   const int tn = tile >= 3 ? 256 : 128;
   const bool bf = path == LW_PATH_MFMA_BF16;
 
+  const int ngroups = (pc->nb + kBandGroup - 1) / kBandGroup;  // spreading work-groups per column
   for (int64_t p0 = 0; p0 < b->n_particles; p0 += L.chunk) {
     const int nl = (int)std::min<int64_t>(L.chunk, b->n_particles - p0);
     const int nft = (2 * nl + tn - 1) / tn;
@@ -1859,10 +1957,10 @@ lw_status mfma_accumulate(lw_ctx* c, const lw_batch* b, lw_path path, void* ws, 
     sa.n_ftile = ga.n_ftile = nft;
     MF_HIP(prof_begin(c, kProfSpread), "profile");
     if (pc->shape.w == kShapeSplit.w)
-      hipLaunchKernelGGL(lw_spread_kernel<kShapeSplit.w>, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)),
+      hipLaunchKernelGGL(lw_spread_kernel<kShapeSplit.w>, dim3((unsigned)((int64_t)nl * c->nd * ngroups)),
                          dim3(kSpreadWin), 0, c->stream, sa);
     else
-      hipLaunchKernelGGL(lw_spread_kernel<kShapeSingle.w>, dim3((unsigned)((int64_t)nl * c->nd * pc->nb)),
+      hipLaunchKernelGGL(lw_spread_kernel<kShapeSingle.w>, dim3((unsigned)((int64_t)nl * c->nd * ngroups)),
                          dim3(kSpreadWin), 0, c->stream, sa);
     MF_HIP(hipGetLastError(), "launch spread");
     MF_HIP(prof_end(c), "profile");
