@@ -405,6 +405,17 @@ __device__ __forceinline__ void group_sum(float* v, int S) {
   }
 }
 
+// Sum over each half-wave (lanes 0-31 and 32-63) without LDS traffic: the four in-row DPP
+// steps of group_sum leave every lane of a row of 16 with its row's sum, and the row
+// broadcast (lane 15 of a row to the next row, rows 1 and 3 written) adds row 0's sum into
+// row 1 and row 2's into row 3, so lanes 31 and 63 hold their half-wave's sum.
+__device__ __forceinline__ float half_wave_sum(float v) {
+  constexpr int kRowBcast15 = 0x142;
+  float t[1] = {v};
+  group_sum<1>(t, 16);
+  return t[0] + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t[0]), kRowBcast15, 0xA, 0xF, false));
+}
+
 // A band's walk along the trajectory, shared by the work-group in LDS.
 struct BandWalk {
   int Q;      // grid points of the column
@@ -970,8 +981,8 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
           v = fmaf(c * c, s_colw[s][cc], v);
         }
         // sum over the 32 columns held by lanes with the same lane / 32
-        for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if ((lane & 31) == 0) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
+        v = half_wave_sum(v);
+        if ((lane & 31) == 31) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
       }
     __syncthreads();
     if (tid < TM) {
@@ -1389,8 +1400,8 @@ __global__ __launch_bounds__(128 * WN, WN == 2 && MI == 2 ? 2 : 1) void lw_dft_m
           const float c = acc[i][j][r];
           v = fmaf(c * c, s_colw[s][cc], v);
         }
-        for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if ((lane & 31) == 0) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
+        v = half_wave_sum(v);
+        if ((lane & 31) == 31) s_rows[wave][i * 32 + 8 * (r / 4) + 4 * (lane >> 5) + (r % 4)] = (double)v;
       }
     __syncthreads();
     for (int t = tid; t < TM; t += NT) {
