@@ -64,20 +64,23 @@ def spread_width(products):
     return 10 if products == 3 else 8
 
 
-def spread_flops_per_unit(w):
+def spread_flops_per_unit(w, bands=1):
     """Counted arithmetic of the spreading step for one (sample, direction, band) with W taps.
 
-    FP32: the W tap weights times the demodulated integrand into 2 polarisations x
+    Per band, FP32: the W tap weights times the demodulated integrand into 2 polarisations x
     (re, im), 4W FMAs = 8W; the tap weights, W/2 mirrored pairs of degree-8 polynomials in
     z = 2 frac(u) - 1 evaluated as even and odd parts in z^2 (4 + 3 Horner FMAs and 2 FMAs
-    to combine), 9W, plus 3 for z and z^2; the integrand e.(n x ((n - beta) x a)) / kappa^2
-    for both polarisations, 35; the demodulation of both by (cos, sin), 4.
-    FP64: kappa 6, retarded time 9, the turn fraction of w_c tau 2, the grid coordinate
-    and its fraction 4.
-    Sine, cosine and reciprocal are not counted.  Total 17 W + 63 (233 at W = 10).  This
-    is instruction work, reported beside the algorithmic figure below.
+    to combine), 9W, plus 3 for z and z^2; the demodulation of both polarisations by (cos,
+    sin), 4.  FP64: the turn fraction of w_c tau 2, the grid coordinate and its fraction 4.
+    Per sample and direction, shared by the (at most two) bands one work-group spreads:
+    the integrand e.(n x ((n - beta) x a)) / kappa^2 for both polarisations, 35 (FP32), kappa
+    6 and the retarded time 9 (FP64).  Sine, cosine and reciprocal are not counted.  Total
+    17 W + 13 + 50 / g with g the mean bands per work-group (208 at W = 10 with two bands).
+    This is instruction work, reported beside the algorithmic figure below.
     """
-    return 17 * w + 63
+    nb = max(1, bands)
+    groups = (nb + 1) // 2
+    return 17 * w + 13 + 50.0 * groups / nb
 
 
 # Algorithmic work of the spread per (sample, direction, band): 8 taps x 2 polarisations
@@ -272,14 +275,14 @@ def time_path(ctx, batch, name, steps, warmup, terms_per_step, bands, tile=0):
         units = float(batch.n_samples_host) * ctx.nd * nb * steps
         sec = prof["spread_ms"] * 1e-3
         ach = units * SPREAD_ALGO_FLOPS / sec / 1e12
-        counted = units * spread_flops_per_unit(w) / sec / 1e12
+        counted = units * spread_flops_per_unit(w, nb) / sec / 1e12
         spread = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                   "frac": ach / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": SPREAD_KERNEL(w),
                   "avg_launch_ms": prof["spread_ms"] / max(prof["spread_launches"], 1),
                   "launches_per_step": prof["spread_launches"] / steps,
                   "algorithmic_flops_per_sample_direction_band": SPREAD_ALGO_FLOPS,
                   "units_per_step": units / steps,
-                  "counted_flops_per_sample_direction_band": spread_flops_per_unit(w),
+                  "counted_flops_per_sample_direction_band": spread_flops_per_unit(w, nb),
                   "counted_tflops": counted, "counted_frac": counted / PEAK_FP32_VECTOR_TFLOPS}
         res["roofline_contraction"] = contraction
         res["roofline_spread"] = spread

@@ -61,12 +61,23 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   #pragma unroll
   for (int g = 0; g < kDirGroup; ++g)
     for (int c = 0; c < 3; ++c) n[g][c] = g < ng ? dirs[kDirStride * (d0 + g) + c] : 0.0;
+  // the two polarisation axes e1, e2 normal to each direction, read at one address by all
+  // lanes
+  __shared__ double s_e[kDirGroup][6];
+  if (tid < kDirGroup * 6) {
+    const int g = tid / 6;
+    s_e[g][tid % 6] = g < ng ? dirs[kDirStride * (d0 + g) + 3 + tid % 6] : 0.0;
+  }
+  __syncthreads();
   const int64_t o = b.offsets[p], len = b.offsets[p + 1] - o;
   double q[NQ];
   #pragma unroll
   for (int i = 0; i < NQ; ++i) q[i] = 0.0;
   #pragma unroll
   for (int g = 0; g < kDirGroup; ++g) q[NI + 4 * g + 1] = 1.0e300;
+  // Precision: 1 - beta^2, kappa = 1 - n.beta, e.beta, the unit velocity and the cone test
+  // are FP64 (they cancel as |beta| -> 1, or decide a count); gamma, |a_perp| and the
+  // integrand's projections are FP32 values (relative error ~1e-7) summed in FP64.
   for (int64_t k = tid; k < len; k += 256) {
     const int64_t i = o + k;
     const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
@@ -77,45 +88,71 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
       atomicMin(err, (unsigned long long)p);
       continue;
     }
-    const double gam = 1.0 / sqrt(1.0 - b2);
-    const double bn = sqrt(b2);
-    const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
+    const double y = 1.0 - b2;  // 1 / gamma^2
+    const float gam = __builtin_amdgcn_rsqf((float)y);
+    // 1 / |beta|: an FP32 reciprocal square root refined by one Newton step (relative
+    // error ~1e-14); a particle at rest has u = 0
+    double inv = 0.0;
+    if (b2 > 0.0) {
+      const double r0 = (double)__builtin_amdgcn_rsqf((float)b2);
+      inv = r0 * (1.5 - 0.5 * b2 * r0 * r0);
+    }
     const double ux = bx * inv, uy = by * inv, uz = bz * inv;
-    const double apar = ax * ux + ay * uy + az * uz;
-    const double px = ax - apar * ux, py = ay - apar * uy, pz = az - apar * uz;
-    const double ap = sqrt(px * px + py * py + pz * pz);
-    q[0] += gam;
-    q[1] += gam * gam;
-    q[2] += ap;
-    q[3] += ap * ap;
-    q[4] += ap * ap * ap * ap;
+    const float axf = (float)ax, ayf = (float)ay, azf = (float)az;
+    const float uxf = (float)ux, uyf = (float)uy, uzf = (float)uz;
+    const float apar = axf * uxf + ayf * uyf + azf * uzf;
+    const float px = axf - apar * uxf, py = ayf - apar * uyf, pz = azf - apar * uzf;
+    const float ap2 = px * px + py * py + pz * pz;
+    const float ap = __builtin_amdgcn_sqrtf(ap2);
+    q[0] += (double)gam;
+    q[1] += (double)gam * (double)gam;
+    q[2] += (double)ap;
+    q[3] += (double)ap2;
+    q[4] += (double)ap2 * (double)ap2;
     if (k > 0) {
       double px0, py0, pz0;
       lw::load_accel(b, i - 1, px0, py0, pz0);
       const double dot = ax * px0 + ay * py0 + az * pz0;
       if (dot < 0.0) q[5] += 1.0;
     }
-    q[6] = fmax(q[6], ap);
+    q[6] = fmax(q[6], (double)ap);
     q[7] += ux;
     q[8] += uy;
     q[9] += uz;
     // inside the 1/gamma cone around the velocity: the angle to n is below 1/gamma
-    // (<= 1 rad), i.e. the cosine u.n exceeds cos(1/gamma); a particle at rest has
-    // angle 0 by convention
-    const double cos_cone = cos(1.0 / gam);
+    // (<= 1 rad), i.e. the cosine u.n exceeds cos(1/gamma) = sum_k (-1)^k y^k / (2k)! with
+    // y = 1/gamma^2 <= 1 (the series through y^9 is within 1/20! < 5e-19); a particle at
+    // rest has angle 0 by convention
+    double cos_cone = 0.0;
+    #pragma unroll
+    for (int m = 9; m >= 0; --m) {
+      double f = 1.0;  // (2m)!
+      for (int j = 2; j <= 2 * m; ++j) f *= (double)j;
+      cos_cone = cos_cone * y + ((m & 1) ? -1.0 : 1.0) / f;
+    }
     #pragma unroll
     for (int g = 0; g < kDirGroup; ++g) {
       const double* m = n[g];
       const double kap = 1.0 - (m[0] * bx + m[1] * by + m[2] * bz);
       q[NI + 4 * g] += kap;
       q[NI + 4 * g + 1] = fmin(q[NI + 4 * g + 1], kap);
-      if (bn == 0.0 || ux * m[0] + uy * m[1] + uz * m[2] > cos_cone) q[NI + 4 * g + 2] += 1.0;
-      // w = (n - beta) x betadot, v = n x w
-      const double dx = m[0] - bx, dy = m[1] - by, dz = m[2] - bz;
-      const double wx = dy * az - dz * ay, wy = dz * ax - dx * az, wz = dx * ay - dy * ax;
-      const double vx = m[1] * wz - m[2] * wy, vy = m[2] * wx - m[0] * wz, vz = m[0] * wy - m[1] * wx;
-      const double ik = 1.0 / kap, ik2 = ik * ik;
-      q[NI + 4 * g + 3] += (vx * vx + vy * vy + vz * vz) * (ik2 * ik2 * ik);
+      if (b2 == 0.0 || ux * m[0] + uy * m[1] + uz * m[2] > cos_cone) q[NI + 4 * g + 2] += 1.0;
+      // |n x ((n - beta) x a)|^2 from its components on e1, e2 (normal to n):
+      // e.(n x ((n - beta) x a)) = -(e.beta)(n.a) - kappa (e.a)
+      const double* e1 = s_e[g];
+      const double* e2 = s_e[g] + 3;
+      const float na = (float)m[0] * axf + (float)m[1] * ayf + (float)m[2] * azf;
+      const float e1b = (float)(e1[0] * bx + e1[1] * by + e1[2] * bz);
+      const float e2b = (float)(e2[0] * bx + e2[1] * by + e2[2] * bz);
+      const float e1a = (float)e1[0] * axf + (float)e1[1] * ayf + (float)e1[2] * azf;
+      const float e2a = (float)e2[0] * axf + (float)e2[1] * ayf + (float)e2[2] * azf;
+      const float kf = (float)kap;
+      const float g1 = e1b * na + kf * e1a, g2 = e2b * na + kf * e2a;
+      // 1 / kappa in FP64 (kappa^-5 leaves the FP32 range as gamma grows): FP32 reciprocal
+      // and one Newton step
+      const double r0 = (double)__builtin_amdgcn_rcpf(kf);
+      const double ik = r0 * (2.0 - kap * r0), ik2 = ik * ik;
+      q[NI + 4 * g + 3] += (double)(g1 * g1 + g2 * g2) * (ik2 * ik2 * ik);
     }
   }
   auto is_max = [](int i) { return i == 6; };
@@ -140,25 +177,28 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   ex *= ie;
   ey *= ie;
   ez *= ie;
-  // pass 2: deflection of the unit velocity from the mean direction
-  double th2 = 0.0, thmax = 0.0;
+  // pass 2: deflection of the unit velocity from the mean direction (FP32 angles, relative
+  // error ~1e-7 against the angles' spread)
+  const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
+  double th2 = 0.0;
+  float thmax = 0.0f;
   for (int64_t k = tid; k < len; k += 256) {
     const int64_t i = o + k;
-    const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
-    const double bn = sqrt(bx * bx + by * by + bz * bz);
-    const double inv = bn > 0.0 ? 1.0 / bn : 0.0;
-    const double ux = bx * inv, uy = by * inv, uz = bz * inv;
-    const double cx = uy * ez - uz * ey, cy = uz * ex - ux * ez, cz = ux * ey - uy * ex;
-    const double th = atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * ex + uy * ey + uz * ez);
-    th2 += th * th;
-    thmax = fmax(thmax, th);
+    const float bx = (float)b.bx[i], by = (float)b.by[i], bz = (float)b.bz[i];
+    const float bb = bx * bx + by * by + bz * bz;
+    const float inv = bb > 0.0f ? __builtin_amdgcn_rsqf(bb) : 0.0f;
+    const float ux = bx * inv, uy = by * inv, uz = bz * inv;
+    const float cx = uy * ezf - uz * eyf, cy = uz * exf - ux * ezf, cz = ux * eyf - uy * exf;
+    const float th = atan2f(__builtin_amdgcn_sqrtf(cx * cx + cy * cy + cz * cz), ux * exf + uy * eyf + uz * ezf);
+    th2 += (double)th * (double)th;
+    thmax = fmaxf(thmax, th);
   }
   th2 = wave_sum(th2);
-  thmax = wave_max(thmax);
+  const double thm = wave_max((double)thmax);
   __syncthreads();
   if (lane == 0) {
     s_part[wave][0] = th2;
-    s_part[wave][1] = thmax;
+    s_part[wave][1] = thm;
   }
   __syncthreads();
   if (tid < ng) {

@@ -54,10 +54,16 @@ def test_traffic_is_reported_only_for_the_profiled_launch():
 
 def test_spread_flop_model():
     b = _bench()
-    # 8W accumulation + 9W tap polynomials + 3 (z, z^2) + 35 integrand + 4 demodulation
-    # + 21 FP64 prepass
+    # per band: 8W accumulation + 9W tap polynomials + 3 (z, z^2) + 4 demodulation + 6 FP64
+    # (turn fraction, grid coordinate); per sample and direction, shared by a work-group's
+    # bands: 35 integrand + 15 FP64 (kappa, retarded time)
     for w in (8, 10):
-        assert b.spread_flops_per_unit(w) == 8 * w + 9 * w + 3 + 35 + 4 + 21
+        per_band = 8 * w + 9 * w + 3 + 4 + 6
+        assert b.spread_flops_per_unit(w) == per_band + 50  # one band: nothing shared
+        assert b.spread_flops_per_unit(w, 2) == per_band + 25  # one work-group, two bands
+        assert b.spread_flops_per_unit(w, 3) == per_band + 50 * 2 / 3  # groups of 2 and 1
+        assert b.spread_flops_per_unit(w, 16) == per_band + 25
+    assert b.spread_flops_per_unit(10, 2) == 208
     assert b.spread_width(3) == 10 and b.spread_width(1) == 8
 
 
