@@ -29,30 +29,57 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // One work-group per (particle, group of up to kDirGroup directions): the
 // trajectory is read twice (moments, then deflections from the mean velocity)
 // and the direction-dependent sums of the group ride along with the first pass.
-// Sums in FP64, wave shuffles + LDS.
+// Sums in FP64, reduced across the wave by DPP.
 constexpr int kDirGroup = 4;
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  return v;
+constexpr int kFeatThreads = 64;  // one wave per (particle, direction group)
+
+// Wave reductions of FP64 values without LDS traffic: DPP lane permutations of the two
+// 32-bit halves.  The four in-row steps give every lane of a row of 16 its row's value; the
+// row broadcasts then fold row 0 into row 1 (and row 2 into row 3), and rows 0-1 into row 3,
+// so lane 63 holds the result, which is read out to every lane.  Lanes a row mask leaves out
+// keep their own value (so a sum holds partial garbage there, in rows never read).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp64(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = (int)u, hi = (int)(u >> 32);
+  const int plo = __builtin_amdgcn_update_dpp(lo, lo, kCtrl, kRowMask, 0xF, false);
+  const int phi = __builtin_amdgcn_update_dpp(hi, hi, kCtrl, kRowMask, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)phi << 32) | (unsigned)plo));
 }
 
-__global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const double* dirs, int nd,
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+  constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  v = op(v, dpp64<kXor1, 0xF>(v));
+  v = op(v, dpp64<kXor2, 0xF>(v));
+  v = op(v, dpp64<kHalfMirror, 0xF>(v));
+  v = op(v, dpp64<kMirror, 0xF>(v));
+  v = op(v, dpp64<kRowBcast15, 0xA>(v));
+  v = op(v, dpp64<kRowBcast31, 0xC>(v));
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, 63), hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+struct OpSum {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct OpMin {
+  __device__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+  __device__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+__global__ __launch_bounds__(kFeatThreads) void lw_features_kernel(BatchView b, const double* dirs, int nd,
                                                           float* feats, unsigned long long* err) {
   // direction-independent sums 0..9, then per direction g: kappa sum, kappa min, cone count,
   // radiated energy sum |n x ((n - beta) x betadot)|^2 / kappa^5
   constexpr int NI = 10, NQ = NI + 4 * kDirGroup;
-  __shared__ double s_part[4][NQ];
   __shared__ double s_tot[NQ];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int n_groups = (nd + kDirGroup - 1) / kDirGroup;
   const int64_t p = blockIdx.x / n_groups;
   const int d0 = (int)(blockIdx.x % n_groups) * kDirGroup;
@@ -78,7 +105,7 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   // Precision: 1 - beta^2, kappa = 1 - n.beta, e.beta, the unit velocity and the cone test
   // are FP64 (they cancel as |beta| -> 1, or decide a count); gamma, |a_perp| and the
   // integrand's projections are FP32 values (relative error ~1e-7) summed in FP64.
-  for (int64_t k = tid; k < len; k += 256) {
+  for (int64_t k = tid; k < len; k += kFeatThreads) {
     const int64_t i = o + k;
     const double bx = b.bx[i], by = b.by[i], bz = b.bz[i];
     double ax, ay, az;
@@ -155,19 +182,12 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
       q[NI + 4 * g + 3] += (double)(g1 * g1 + g2 * g2) * (ik2 * ik2 * ik);
     }
   }
-  auto is_max = [](int i) { return i == 6; };
-  auto is_min = [](int i) { return i >= NI && (i - NI) % 4 == 1; };
+  // index 6 is a maximum, the kappa minima of the directions are minima, the rest sums
   #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const double v = is_max(i) ? wave_max(q[i]) : (is_min(i) ? wave_min(q[i]) : wave_sum(q[i]));
-    if (lane == 0) s_part[wave][i] = v;
-  }
-  __syncthreads();
-  if (tid < NQ) {
-    double v = s_part[0][tid];
-    for (int w = 1; w < 4; ++w)
-      v = is_max(tid) ? fmax(v, s_part[w][tid]) : (is_min(tid) ? fmin(v, s_part[w][tid]) : v + s_part[w][tid]);
-    s_tot[tid] = v;
+    const double v = i == 6 ? wave_reduce(q[i], OpMax()) :
+                     (i >= NI && (i - NI) % 4 == 1 ? wave_reduce(q[i], OpMin()) : wave_reduce(q[i], OpSum()));
+    if (tid == 0) s_tot[i] = v;
   }
   __syncthreads();
   const double N = (double)max(len, (int64_t)1);
@@ -182,7 +202,7 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
   const float exf = (float)ex, eyf = (float)ey, ezf = (float)ez;
   double th2 = 0.0;
   float thmax = 0.0f;
-  for (int64_t k = tid; k < len; k += 256) {
+  for (int64_t k = tid; k < len; k += kFeatThreads) {
     const int64_t i = o + k;
     const float bx = (float)b.bx[i], by = (float)b.by[i], bz = (float)b.bz[i];
     const float bb = bx * bx + by * by + bz * bz;
@@ -193,21 +213,10 @@ __global__ __launch_bounds__(256) void lw_features_kernel(BatchView b, const dou
     th2 += (double)th * (double)th;
     thmax = fmaxf(thmax, th);
   }
-  th2 = wave_sum(th2);
-  const double thm = wave_max((double)thmax);
-  __syncthreads();
-  if (lane == 0) {
-    s_part[wave][0] = th2;
-    s_part[wave][1] = thm;
-  }
-  __syncthreads();
+  const double t2 = wave_reduce(th2, OpSum());
+  const double tm = wave_reduce((double)thmax, OpMax());
   if (tid < ng) {
     const int g = tid;
-    double t2 = 0.0, tm = 0.0;
-    for (int w = 0; w < 4; ++w) {
-      t2 += s_part[w][0];
-      tm = fmax(tm, s_part[w][1]);
-    }
     const double eps = 1e-12;
     const double gm = s_tot[0] / N;
     const double gvar = fmax(s_tot[1] / N - gm * gm, 0.0);
@@ -510,7 +519,7 @@ __global__ void lw_mse_kernel(const float* y, const float* t, float* dy, int64_t
     e2 = e * e;
     dy[i] = (float)(2.0 * e * scale);
   }
-  e2 = wave_sum(e2);
+  e2 = wave_reduce(e2, OpSum());
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = e2;
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
@@ -1054,7 +1063,7 @@ lw_status lw_features(lw_ctx* c, const lw_batch* b, float* feats) {
     c->err = "too many particles for one feature launch";
     return LW_ERANGE;
   }
-  hipLaunchKernelGGL(lw::lw_features_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream, v,
+  hipLaunchKernelGGL(lw::lw_features_kernel, dim3((unsigned)blocks), dim3(lw::kFeatThreads), 0, c->stream, v,
                      c->d_dirs, c->nd, feats, c->d_err);
   if (hipGetLastError() != hipSuccess) {
     c->err = "launch lw_features";
