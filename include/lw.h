@@ -388,6 +388,44 @@ lw_status lw_surrogate_accumulate(lw_ctx* ctx, const lw_batch* batch, const floa
 lw_status lw_surrogate_targets(lw_ctx* ctx, const lw_batch* batch, const float* per_particle,
                                double floor_value, float* out);
 
+/* Calibration statistics of the surrogate, on the device (the training set-up of the
+ * learned surrogate: input normalisation, the per-direction mean spectrum, the error-head
+ * targets, the fallback threshold and the per-bin calibration).
+ *
+ * lw_column_stats: x = device FP32 [rows][cols], row r = p groups + g of particle p and
+ * group g (rows a multiple of groups, groups <= 65535, rows / groups <= 65535 x 256).  For
+ * each group and column, out (device double [groups][cols][2]) = mean and mean square of
+ * v = x[r][j] + row_add_coeff row_add[r row_add_stride] (row_add may be NULL), or of 10^v
+ * when exp10 != 0, over the kept particles: all of them when err is NULL, else those whose
+ * largest err[p][g'] (device FP32 [rows]) is <= threshold (zeros when none is kept).  FP64
+ * sums in a fixed order.  Workspace: ceil(P / 256) x groups x cols x 3 doubles
+ * (LW_ENOMEM if smaller; the needed size is in the error text). */
+lw_status lw_column_stats(lw_ctx* ctx, const float* x, int64_t rows, int32_t cols, int32_t groups,
+                          const float* row_add, int64_t row_add_stride, double row_add_coeff, int32_t exp10,
+                          const float* err, float threshold, double* out, void* workspace,
+                          size_t workspace_bytes);
+
+/* Error-head target of each row (surrogate pair): share[r] = log10(mean_j |10^pred[r][j] -
+ * 10^y[r][j]| / smean[((r mod groups) cols + j) smean_stride] + floor_value), the pair's
+ * share in the error of the summed spectrum.  pred, y = device FP32 [rows][cols]; smean =
+ * device double (e.g. the means of lw_column_stats with stride 2); share = device FP32 [rows]. */
+lw_status lw_error_share(lw_ctx* ctx, const float* pred, const float* y, int64_t rows, int32_t cols,
+                         int32_t groups, const double* smean, int64_t smean_stride, double floor_value,
+                         float* share);
+
+/* q-quantile (0 <= q <= 1; linear interpolation between the order statistics around
+ * q (n - 1)) of the per-particle maxima max_g v[p][g] of v = device FP32 [n][groups]; NaN
+ * counts as the largest value.  Exact: the order statistics are selected by four byte-wise
+ * histogram passes over order-preserving keys (each pass synchronises the stream).  Result
+ * in *host_out.  Workspace: ceil(4 n / 256) x 256 + 1280 bytes. */
+lw_status lw_quantile_of_maxima(lw_ctx* ctx, const float* v, int64_t n, int32_t groups, double q,
+                                double* host_out, void* workspace, size_t workspace_bytes);
+
+/* out[i] = log10(num[i num_stride] / den[i den_stride]) in FP32 where both are positive,
+ * else 0, for i < n (device arrays): the per-bin calibration from two means. */
+lw_status lw_log_ratio(lw_ctx* ctx, const double* num, int64_t num_stride, const double* den,
+                       int64_t den_stride, int64_t n, float* out);
+
 /* MLP n_in -> [Linear, GELU] x n_hidden -> Linear -> n_out, FP32 master weights,
  * products in BF16 on the matrix cores with FP32 accumulation, AdamW updates,
  * plus an error head (Linear on the last hidden layer -> 1).  Parameter layout:

@@ -847,6 +847,127 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
   }
 }
 
+
+// ------------------------------------------------------------------ calibration statistics
+// Column statistics of x [rows][cols] with rows grouped by row index modulo `groups` (row
+// r = p groups + g belongs to particle p and group g): over the kept particles of a slice of
+// kStatSlice particles, the sum of v, of v^2 and the count, with v = x[r][j] + coeff
+// row_add[r stride] (row_add optional) or 10 to that power.  A particle is kept when err is
+// null or its largest err[p][g'] over the groups is <= threshold.  Stage 1: one work-group
+// per (64 columns, slice, group), four row lanes summed in a fixed order; stage 2 adds the
+// slices in order.
+constexpr int kStatSlice = 256;
+
+__global__ __launch_bounds__(256) void lw_column_stats_stage1_kernel(
+    const float* x, int64_t P, int cols, int groups, const float* row_add, int64_t stride, double coeff,
+    int exp10, const float* err, float threshold, double* partial) {
+  __shared__ double s[3][4][64];
+  const int jl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
+  const int64_t slice = blockIdx.y;
+  const int g = blockIdx.z;
+  const int64_t p0 = slice * kStatSlice, p1 = min(P, p0 + kStatSlice);
+  double s1 = 0.0, s2 = 0.0, cnt = 0.0;
+  for (int64_t p = p0 + rl; p < p1; p += 4) {
+    bool keep = true;
+    if (err)
+      for (int h = 0; h < groups; ++h) keep = keep && err[p * groups + h] <= threshold;
+    if (!keep || j >= cols) continue;
+    const int64_t r = p * groups + g;
+    double v = (double)x[r * cols + j];
+    if (row_add) v += coeff * (double)row_add[r * stride];
+    if (exp10) v = pow(10.0, v);
+    s1 += v;
+    s2 += v * v;
+    cnt += 1.0;
+  }
+  s[0][rl][jl] = s1;
+  s[1][rl][jl] = s2;
+  s[2][rl][jl] = cnt;
+  __syncthreads();
+  if (rl == 0 && j < cols) {
+    double* o = partial + ((slice * groups + g) * (int64_t)cols + j) * 3;
+    for (int k = 0; k < 3; ++k) o[k] = s[k][0][jl] + s[k][1][jl] + s[k][2][jl] + s[k][3][jl];
+  }
+}
+
+// out[g][j] = (mean, mean square) over the kept particles (zeros when none is kept)
+__global__ void lw_column_stats_stage2_kernel(const double* partial, int64_t slices, int groups, int cols,
+                                              double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)groups * cols) return;
+  double s1 = 0.0, s2 = 0.0, cnt = 0.0;
+  for (int64_t t = 0; t < slices; ++t) {
+    const double* q = partial + (t * groups * (int64_t)cols + i) * 3;
+    s1 += q[0];
+    s2 += q[1];
+    cnt += q[2];
+  }
+  out[2 * i] = cnt > 0.0 ? s1 / cnt : 0.0;
+  out[2 * i + 1] = cnt > 0.0 ? s2 / cnt : 0.0;
+}
+
+// share[r] = log10(mean_j |10^pred[r][j] - 10^y[r][j]| / smean[r mod groups][j] + floor):
+// one wave per row, lanes over the columns, a DPP sum.
+__global__ __launch_bounds__(64) void lw_error_share_kernel(const float* pred, const float* y, int64_t rows,
+                                                            int cols, int groups, const double* smean,
+                                                            int64_t smean_stride, double floor_value,
+                                                            float* share) {
+  const int64_t r = blockIdx.x;
+  if (r >= rows) return;
+  const int g = (int)(r % groups);
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < cols; j += 64) {
+    const double d = fabs(pow(10.0, (double)pred[r * cols + j]) - pow(10.0, (double)y[r * cols + j]));
+    acc += d / smean[((int64_t)g * cols + j) * smean_stride];
+  }
+  acc = wave_reduce(acc, OpSum());
+  if (threadIdx.x == 0) share[r] = (float)log10(acc / cols + floor_value);
+}
+
+// Order-preserving 32-bit keys of the per-particle maxima max_g v[p][g] (NaN as the largest).
+__device__ __forceinline__ uint32_t order_key(float f) {
+  if (f != f) return 0xFFFFFFFFu;
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float key_value(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+__global__ void lw_max_keys_kernel(const float* v, int64_t n, int groups, uint32_t* keys) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint32_t k = 0;
+  for (int g = 0; g < groups; ++g) k = max(k, order_key(v[p * groups + g]));
+  keys[p] = k;
+}
+
+// hist[b] += number of keys with (key & mask) == prefix and byte (key >> shift) & 255 == b
+__global__ __launch_bounds__(256) void lw_radix_hist_kernel(const uint32_t* keys, int64_t n, uint32_t prefix,
+                                                            uint32_t mask, int shift, unsigned* hist) {
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void lw_key_to_value_kernel(const uint32_t* key, double* out) { *out = (double)key_value(*key); }
+
+// out[i] = log10(num[i s_num] / den[i s_den]) where both are positive, else 0
+__global__ void lw_log_ratio_kernel(const double* num, int64_t s_num, const double* den, int64_t s_den,
+                                    int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = num[i * s_num], b = den[i * s_den];
+  out[i] = (a > 0.0 && b > 0.0) ? (float)log10(a / b) : 0.0f;
+}
+
 }  // namespace lw
 
 // ------------------------------------------------------------------ network object
@@ -1424,5 +1545,135 @@ lw_status lw_mlp_train_head_step(lw_mlp* n, const float* x, const float* err_tar
   n->head_step += 1;
   return adamw(n, n->hp, n->hm, n->hv, n->hg, n->hidden + 1, n->head_step, lr, 0.0f);
 }
+
+lw_status lw_column_stats(lw_ctx* c, const float* x, int64_t rows, int32_t cols, int32_t groups,
+                          const float* row_add, int64_t row_add_stride, double row_add_coeff, int32_t exp10,
+                          const float* err, float threshold, double* out, void* ws, size_t ws_bytes) {
+  if (!c || !x || !out || cols <= 0 || groups <= 0 || rows < 0) return LW_EINVAL;
+  if (rows % groups != 0) {
+    c->err = "column statistics: rows must be a multiple of groups";
+    return LW_EINVAL;
+  }
+  if (groups > 65535) {
+    c->err = "column statistics: at most 65535 groups";
+    return LW_ERANGE;
+  }
+  const int64_t P = rows / groups;
+  const int64_t slices = std::max<int64_t>(1, (P + lw::kStatSlice - 1) / lw::kStatSlice);
+  if (slices > 65535) {
+    c->err = "column statistics: at most 65535 x 256 particles per call";
+    return LW_ERANGE;
+  }
+  const size_t need = (size_t)slices * groups * cols * 3 * sizeof(double);
+  if (!ws || ws_bytes < need) {
+    c->err = "workspace too small for the column statistics (" + std::to_string(need) + " bytes)";
+    return LW_ENOMEM;
+  }
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(lw::lw_column_stats_stage1_kernel, dim3((unsigned)((cols + 63) / 64), (unsigned)slices,
+                     (unsigned)groups), dim3(256), 0, s, x, P, cols, groups, row_add, row_add_stride,
+                     row_add_coeff, exp10, err, threshold, (double*)ws);
+  const int64_t n = (int64_t)groups * cols;
+  hipLaunchKernelGGL(lw::lw_column_stats_stage2_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     (const double*)ws, slices, groups, cols, out);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "launch column statistics";
+    return LW_EDEVICE;
+  }
+  return LW_OK;
+}
+
+lw_status lw_error_share(lw_ctx* c, const float* pred, const float* y, int64_t rows, int32_t cols, int32_t groups,
+                         const double* smean, int64_t smean_stride, double floor_value, float* share) {
+  if (!c || !pred || !y || !smean || !share || rows < 0 || cols <= 0 || groups <= 0 || smean_stride <= 0 ||
+      !(floor_value >= 0.0))
+    return LW_EINVAL;
+  if (rows == 0) return LW_OK;
+  if (rows > 0x7FFFFFFFLL) {
+    c->err = "error share: at most 2^31 - 1 rows per call";
+    return LW_ERANGE;
+  }
+  hipLaunchKernelGGL(lw::lw_error_share_kernel, dim3((unsigned)rows), dim3(64), 0, c->stream, pred, y, rows, cols,
+                     groups, smean, smean_stride, floor_value, share);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "launch error share";
+    return LW_EDEVICE;
+  }
+  return LW_OK;
+}
+
+lw_status lw_quantile_of_maxima(lw_ctx* c, const float* v, int64_t n, int32_t groups, double q, double* host_out,
+                                void* ws, size_t ws_bytes) {
+  if (!c || !v || !host_out || n <= 0 || groups <= 0 || !(q >= 0.0 && q <= 1.0)) return LW_EINVAL;
+  const size_t need = ((size_t)n * sizeof(uint32_t) + 255) / 256 * 256 + 256 * sizeof(unsigned) + 256;
+  if (!ws || ws_bytes < need) {
+    c->err = "workspace too small for the quantile (" + std::to_string(need) + " bytes)";
+    return LW_ENOMEM;
+  }
+  uint32_t* keys = (uint32_t*)ws;
+  unsigned* hist = (unsigned*)((char*)ws + ((size_t)n * sizeof(uint32_t) + 255) / 256 * 256);
+  double* dval = (double*)(hist + 256);
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(lw::lw_max_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, n, groups, keys);
+  // the k-th smallest key by four byte-wise histogram passes
+  auto select = [&](int64_t k, double* value) -> lw_status {
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+      if (lw::launch_fill_u32(hist, 256, 0u, s) != hipSuccess) {
+        c->err = "quantile histogram clear";
+        return LW_EDEVICE;
+      }
+      const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+      hipLaunchKernelGGL(lw::lw_radix_hist_kernel, dim3(blocks), dim3(256), 0, s, keys, n, prefix, mask, shift, hist);
+      unsigned h[256];
+      if (hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        c->err = "quantile histogram";
+        return LW_EDEVICE;
+      }
+      int b = 0;
+      while (b < 255 && (int64_t)h[b] <= k) k -= h[b++];
+      prefix |= (uint32_t)b << shift;
+      mask |= 255u << shift;
+    }
+    // the selected key's value, converted on the device
+    uint32_t* kd = (uint32_t*)(dval + 1);
+    if (hipMemcpyAsync(kd, &prefix, sizeof(prefix), hipMemcpyHostToDevice, s) != hipSuccess) {
+      c->err = "quantile key";
+      return LW_EDEVICE;
+    }
+    hipLaunchKernelGGL(lw::lw_key_to_value_kernel, dim3(1), dim3(1), 0, s, kd, dval);
+    if (hipMemcpyAsync(value, dval, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      c->err = "quantile value";
+      return LW_EDEVICE;
+    }
+    return LW_OK;
+  };
+  // linear interpolation between the order statistics around q (n - 1)
+  const double pos = q * (double)(n - 1);
+  const int64_t lo = (int64_t)floor(pos), hi = std::min<int64_t>(lo + 1, n - 1);
+  double a = 0.0, b = 0.0;
+  lw_status st = select(lo, &a);
+  if (st == LW_OK) st = hi == lo ? (b = a, LW_OK) : select(hi, &b);
+  if (st != LW_OK) return st;
+  const double t = pos - (double)lo;
+  *host_out = t == 0.0 ? a : a + (b - a) * t;
+  return LW_OK;
+}
+
+lw_status lw_log_ratio(lw_ctx* c, const double* num, int64_t num_stride, const double* den, int64_t den_stride,
+                       int64_t n, float* out) {
+  if (!c || !num || !den || !out || n < 0 || num_stride <= 0 || den_stride <= 0) return LW_EINVAL;
+  if (n == 0) return LW_OK;
+  hipLaunchKernelGGL(lw::lw_log_ratio_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, num,
+                     num_stride, den, den_stride, n, out);
+  if (hipGetLastError() != hipSuccess) {
+    c->err = "launch log ratio";
+    return LW_EDEVICE;
+  }
+  return LW_OK;
+}
+
 
 }  // extern "C"

@@ -38,7 +38,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_set_coherent", "lw_get_basis", "lw_read_amplitudes", "lw_load_amplitudes",
             "lw_accumulate_amplitudes", "lw_amplitude_workspace_size", "lw_spectrum_from_amplitudes",
             "lw_spectral_diagnostics", "lw_pitch_cones", "lw_profile_cu_busy", "lw_save_accumulator",
-            "lw_load_accumulator_file", "lw_mlp_save", "lw_mlp_load", "lw_accumulate_noalloc")
+            "lw_load_accumulator_file", "lw_mlp_save", "lw_mlp_load", "lw_accumulate_noalloc",
+            "lw_column_stats", "lw_error_share", "lw_quantile_of_maxima", "lw_log_ratio")
 
 
 class LWError(RuntimeError):
@@ -106,6 +107,11 @@ def load_library():
             "lw_surrogate_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, P, ctypes.c_float,
                                                        P, P, P, P, SZ]),
             "lw_surrogate_targets": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, D, P]),
+            "lw_column_stats": (ctypes.c_int, [P, P, I64, I32, I32, P, I64, D, I32, P, ctypes.c_float, P, P,
+                                               SZ]),
+            "lw_error_share": (ctypes.c_int, [P, P, P, I64, I32, I32, P, I64, D, P]),
+            "lw_quantile_of_maxima": (ctypes.c_int, [P, P, I64, I32, D, ctypes.POINTER(D), P, SZ]),
+            "lw_log_ratio": (ctypes.c_int, [P, P, I64, P, I64, I64, P]),
             "lw_mlp_create": (ctypes.c_int, [P, I32, I32, I32, I32, ctypes.c_uint64, ctypes.POINTER(P)]),
             "lw_mlp_destroy": (None, [P]),
             "lw_mlp_num_params": (ctypes.c_int, [P, ctypes.POINTER(I64)]),
@@ -518,6 +524,52 @@ class Context:
         self._check(self.lib.lw_features(self.h, ctypes.byref(batch.struct), ctypes.c_void_p(out.data_ptr())))
         return out
 
+
+    def column_stats(self, x, groups=1, row_add=None, row_add_stride=1, row_add_coeff=0.0, exp10=False,
+                     err=None, threshold=0.0):
+        """Device double [groups][cols][2]: mean and mean square per group and column of x
+        (device float [rows][cols], row r = p groups + g), of x + coeff row_add or of 10 to that,
+        over the particles whose largest err (device float [rows]) is <= threshold."""
+        rows, cols = int(x.shape[0]), int(x.shape[1])
+        P = rows // groups
+        slices = max(1, (P + 255) // 256)
+        ws = torch.empty(max(slices * groups * cols * 3 * 8, 256), dtype=torch.uint8, device=x.device)
+        out = torch.empty((groups, cols, 2), dtype=torch.float64, device=x.device)
+        ra = ctypes.c_void_p(row_add.data_ptr()) if row_add is not None else None
+        ep = ctypes.c_void_p(err.data_ptr()) if err is not None else None
+        self._check(self.lib.lw_column_stats(self.h, ctypes.c_void_p(x.data_ptr()), rows, cols, groups, ra,
+                                             row_add_stride, float(row_add_coeff), int(bool(exp10)), ep,
+                                             float(threshold), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return out
+
+    def error_share(self, pred, y, groups, smean, floor):
+        """Device float [rows]: log10 of each row's mean |10^pred - 10^y| / smean[r mod groups]
+        plus floor; smean = device double [groups][cols][2] (the means are used)."""
+        rows, cols = int(pred.shape[0]), int(pred.shape[1])
+        share = torch.empty(rows, dtype=torch.float32, device=pred.device)
+        self._check(self.lib.lw_error_share(self.h, ctypes.c_void_p(pred.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                            rows, cols, groups, ctypes.c_void_p(smean.data_ptr()), 2,
+                                            float(floor), ctypes.c_void_p(share.data_ptr())))
+        return share
+
+    def quantile_of_maxima(self, v, groups, q):
+        """q-quantile of the per-particle maxima of v (device float [n][groups])."""
+        n = int(v.numel()) // groups
+        ws = torch.empty(((4 * n + 255) // 256) * 256 + 1280, dtype=torch.uint8, device=v.device)
+        out = ctypes.c_double()
+        self._check(self.lib.lw_quantile_of_maxima(self.h, ctypes.c_void_p(v.data_ptr()), n, groups, float(q),
+                                                   ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), ws.numel()))
+        return out.value
+
+    def log_ratio(self, num, den, stride=2):
+        """Device float [n]: log10(num / den) of the strided device doubles where both are positive."""
+        n = int(num.numel()) // stride
+        out = torch.empty(n, dtype=torch.float32, device=num.device)
+        self._check(self.lib.lw_log_ratio(self.h, ctypes.c_void_p(num.data_ptr()), stride,
+                                          ctypes.c_void_p(den.data_ptr()), stride, n,
+                                          ctypes.c_void_p(out.data_ptr())))
+        return out
     def stats(self) -> int:
         calls = ctypes.c_int64()
         self._check(self.lib.lw_stats(self.h, ctypes.byref(calls)))

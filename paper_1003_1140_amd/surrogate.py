@@ -81,12 +81,18 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
     y = exact_log_spectra(ctx, batch)
     torch.cuda.synchronize(dev)
     t_targets = time.perf_counter() - t_start
-    xh, yh = _host(x), _host(y)
-    s_mean = (10.0 ** yh).reshape(-1, ctx.nd, ctx.nw).mean(0)  # <S>_d per bin
-    mu_x, sd_x = xh.mean(0), xh.std(0)
+    # statistics on the device: feature moments, <S>_d per (direction, bin), and the moments of
+    # the spectral shape (targets minus the Parseval skip); the host only sets the network's
+    # normalisation parameters from them
+    fx = _host(ctx.column_stats(x))[0]
+    mu_x = fx[:, 0]
+    sd_x = np.sqrt(np.maximum(fx[:, 1] - mu_x * mu_x, 0.0))
     scale_x = np.where(sd_x > 1e-6 * (np.abs(mu_x) + 1.0), 1.0 / np.maximum(sd_x, 1e-300), 0.0)
-    shape_h = yh - LOG10E * xh[:, ENERGY_FEATURE:ENERGY_FEATURE + 1]
-    mu_y, sd_y = shape_h.mean(0), np.maximum(shape_h.std(0), 1e-3)
+    s_mean = ctx.column_stats(y, groups=ctx.nd, exp10=True)
+    fy = _host(ctx.column_stats(y, row_add=x[:, ENERGY_FEATURE], row_add_stride=x.shape[1],
+                                row_add_coeff=-LOG10E))[0]
+    mu_y = fy[:, 0]
+    sd_y = np.maximum(np.sqrt(np.maximum(fy[:, 1] - mu_y * mu_y, 0.0)), 1e-3)
     net = MLP(ctx, 16, 256, 3, ctx.nw, seed=seed)
     net.set_input_norm(mu_x, scale_x)
     net.set_output_skip(ENERGY_FEATURE, LOG10E)
@@ -114,14 +120,12 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
     xc = ctx.features(calib).view(-1, 16).contiguous()
     yc = exact_log_spectra(ctx, calib)
     pred = net.forward(xc)
-    ph, ych = _host(pred), _host(yc)
-    rms = np.sqrt(np.mean((ph - ych) ** 2, axis=1))
-    sm = np.tile(s_mean, (ph.shape[0] // ctx.nd, 1))
-    share = np.log10(np.mean(np.abs(10.0 ** ph - 10.0 ** ych) / sm, axis=1) + FLOOR)
-    share_d = torch.from_numpy(share.astype(np.float32)).to(dev)
+    rms = np.sqrt(np.mean((_host(pred) - _host(yc)) ** 2, axis=1))  # reported only
+    # error-head targets: each pair's share in the error of the summed spectrum
+    share_d = ctx.error_share(pred, yc, ctx.nd, s_mean, FLOOR)
     p, head = net.get_params()
     head[:] = 0.0
-    head[-1] = share.mean()
+    head[-1] = float(_host(ctx.column_stats(share_d.view(-1, 1)))[0, 0, 0])
     net.set_params(p, head)
     head_losses = []
     for step in range(head_steps):
@@ -129,14 +133,13 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
         lr_t = head_lr * 0.5 * (1.0 + np.cos(np.pi * step / head_steps))
         head_losses.append(net.train_head_step(xc[idx].contiguous(), share_d[idx].contiguous(), lr=float(lr_t)))
     _, err = net.forward(xc, with_error=True)
-    per_particle = _host(err).reshape(-1, ctx.nd).max(1)
-    thr = float(np.quantile(per_particle, 1.0 - fallback_fraction)) if fallback_fraction > 0 else float("inf")
-    kept = per_particle <= thr
-    sh = (10.0 ** ych).reshape(-1, ctx.nd, ctx.nw)[kept].sum(0)
-    sp = (10.0 ** ph).reshape(-1, ctx.nd, ctx.nw)[kept].sum(0)
-    ratio = np.where(sp > 0, sh / np.where(sp > 0, sp, 1.0), 1.0)
-    ratio = np.where(ratio > 0, ratio, 1.0)
-    calib_d = torch.from_numpy(np.log10(ratio).astype(np.float32).ravel()).to(dev)
+    # fallback threshold: the quantile of the per-particle largest predicted error; then the
+    # per-bin calibration 10^<log S> -> <S> over the particles the threshold keeps
+    thr = ctx.quantile_of_maxima(err, ctx.nd, 1.0 - fallback_fraction) if fallback_fraction > 0 else float("inf")
+    sh = ctx.column_stats(yc, groups=ctx.nd, exp10=True, err=err, threshold=thr)
+    sp = ctx.column_stats(pred, groups=ctx.nd, exp10=True, err=err, threshold=thr)
+    calib_d = ctx.log_ratio(sh, sp)
+    ratio = 10.0 ** _host(calib_d).reshape(ctx.nd, ctx.nw)  # reported only
     stats = {"train_pairs": int(rows), "calib_pairs": int(xc.shape[0]), "steps": steps,
              "final_train_loss": float(np.mean(losses[-50:])) if losses else None,
              "calib_rms_log10_median": float(np.median(rms)), "calib_rms_log10_p90": float(np.quantile(rms, 0.9)),

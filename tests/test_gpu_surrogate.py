@@ -86,6 +86,81 @@ def test_features_of_uneven_lengths():
     np.testing.assert_allclose(f[..., keep], ref[..., keep], rtol=2e-5, atol=1e-6)
 
 
+# ---------------------------------------------------------------- calibration statistics
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_column_stats_match_numpy():
+    """Grouped column moments of x, of x + c row_add and of 10^(...), over all particles and
+    over those whose largest err is within a threshold: 700 particles (slices of 256 and a
+    ragged one), 4 groups, 37 columns (part of one 64-column block), against NumPy in FP64."""
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    rng = np.random.default_rng(17)
+    P, G, C = 700, 4, 37
+    x = rng.normal(size=(P * G, C)).astype(np.float32)
+    ra = rng.normal(size=(P * G, 5)).astype(np.float32)
+    err = rng.normal(size=P * G).astype(np.float32)
+    x64 = x.astype(np.float64)
+    out = c.column_stats(_dev(x)).cpu().numpy()
+    np.testing.assert_allclose(out[0, :, 0], x64.mean(0), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(out[0, :, 1], (x64 ** 2).mean(0), rtol=1e-12)
+    pmax = err.reshape(P, G).max(1)
+    thr = float(np.sort(pmax)[int(0.8 * P)])  # a value the maxima take exactly
+    keep = pmax <= thr
+    out = c.column_stats(_dev(x), groups=G, row_add=_dev(ra)[:, 2], row_add_stride=5, row_add_coeff=-0.4,
+                         exp10=True, err=_dev(err), threshold=thr).cpu().numpy()
+    v = (10.0 ** (x64 - 0.4 * ra[:, 2:3].astype(np.float64))).reshape(P, G, C)[keep]
+    np.testing.assert_allclose(out[:, :, 0], v.mean(0), rtol=1e-12)
+    np.testing.assert_allclose(out[:, :, 1], (v ** 2).mean(0), rtol=1e-12)
+    # no particle kept: zeros
+    out = c.column_stats(_dev(x), groups=G, err=_dev(err), threshold=float(pmax.min()) - 1.0).cpu().numpy()
+    assert np.all(out == 0.0)
+
+
+def test_quantile_of_maxima_is_exact():
+    """The q-quantile of per-particle maxima (linear interpolation, as NumPy's default) on
+    values with negatives and many ties (rounded to 1/8), against np.quantile in FP64."""
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    rng = np.random.default_rng(23)
+    for P, G in ((1, 1), (2, 3), (999, 4), (25000, 4)):
+        v = (np.round(rng.normal(size=(P, G)) * 8) / 8).astype(np.float32)
+        pmax = v.max(1).astype(np.float64)
+        for q in (0.0, 0.05, 0.37, 0.5, 0.95, 1.0):
+            got = c.quantile_of_maxima(_dev(v), G, q)
+            ref = float(np.quantile(pmax, q))
+            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (P, G, q, got, ref)
+
+
+def test_error_share_and_log_ratio_match_numpy():
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    rng = np.random.default_rng(29)
+    P, G, C = 300, 4, 130
+    y = rng.normal(scale=0.7, size=(P * G, C)).astype(np.float32)
+    pr = (y + rng.normal(scale=0.2, size=y.shape)).astype(np.float32)
+    y64, p64 = y.astype(np.float64), pr.astype(np.float64)
+    smean = c.column_stats(_dev(y), groups=G, exp10=True)
+    share = c.error_share(_dev(pr), _dev(y), G, smean, 1e-3).cpu().numpy()
+    sm = (10.0 ** y64).reshape(P, G, C).mean(0)
+    ref = np.log10(np.mean(np.abs(10.0 ** p64 - 10.0 ** y64) / np.tile(sm, (P, 1)), axis=1) + 1e-3)
+    np.testing.assert_allclose(share, ref, rtol=1e-6, atol=1e-6)
+    sp = c.column_stats(_dev(pr), groups=G, exp10=True)
+    lr = c.log_ratio(smean, sp).cpu().numpy()
+    a, b = smean.cpu().numpy()[..., 0].ravel(), sp.cpu().numpy()[..., 0].ravel()
+    np.testing.assert_allclose(lr, np.log10(a / b), rtol=1e-6, atol=1e-7)
+
+
+def test_column_stats_refuses_rows_not_a_multiple_of_groups():
+    from paper_1003_1140_amd.lw import LWError
+
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    x = np.zeros((10, 3), dtype=np.float32)
+    with pytest.raises(LWError):
+        c.column_stats(_dev(x), groups=4)
+
+
 # ---------------------------------------------------------------- network vs oracle
 def _net(c, shape, seed=3):
     from paper_1003_1140_amd import MLP
