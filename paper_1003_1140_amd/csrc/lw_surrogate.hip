@@ -651,24 +651,26 @@ __global__ void lw_log_targets_kernel(const float* pp, const float* charge, cons
 }
 
 // ------------------------------------------------------------------ fused inference forward
-// The whole network for a tile of 128 rows in one work-group of four waves.  Each wave owns 32
-// rows: it keeps a layer's 32 x (up to 256) outputs in MFMA accumulators and writes the
-// activation (GELU in FP32, rounded to BF16 as the layered products round their A operand)
-// back over its own rows of an LDS activation tile, which is the next layer's A operand.  No
-// wave reads another's rows, so the activations need no barrier.  The weights come from a
-// BF16 copy of the parameters (the rounding the layered products apply as they stage them)
-// in slabs of 64 inner indices through two LDS buffers shared by the four waves, the next
-// slab read from memory while the current one is multiplied.  Each layer's arithmetic is the
-// layered path's (bias, then the skip term; inner index ascending in steps of 16), except
-// that GELU's erf is the Abramowitz-Stegun rational form 7.1.26 (absolute error below
-// 1.5e-7, far under the BF16 rounding that follows) and the error head sums the hidden
-// units in another order.  Rows are read once and written once.
+// The whole network for a tile of 128 rows in one work-group of eight waves, two per SIMD, so
+// that one wave's activation arithmetic overlaps the other's products.  Wave (r, c) owns rows
+// 32 r .. 32 r + 31 and output columns 128 c .. 128 c + 127: it keeps a layer's 32 x 128
+// outputs in MFMA accumulators and writes the activation (GELU in FP32, rounded to BF16 as the
+// layered products round their A operand) over its part of an LDS activation tile, which is
+// the next layer's A operand; a layer's last barrier orders every wave's reads of the tile
+// before the rewrite.  The weights come from a BF16 copy of the parameters (the rounding the
+// layered products apply as they stage them) in slabs of 64 inner indices through two LDS
+// buffers shared by the eight waves, the next slab read from memory while the current one is
+// multiplied.  Each layer's arithmetic is the layered path's (bias, then the skip term; inner
+// index ascending in steps of 16), except that GELU's erf is the Abramowitz-Stegun rational
+// form 7.1.26 (absolute error below 1.5e-7, far under the BF16 rounding that follows) and the
+// error head sums the hidden units in another order.  Rows are read once and written once.
 constexpr int kFusedRows = 128;         // rows per work-group
 constexpr int kFusedMaxWidth = 256;     // widest layer (input tile padded to whole slabs)
 constexpr int kFusedLD = kFusedMaxWidth + 8;
 constexpr int kFusedSlab = 64;          // inner indices per weight slab
 constexpr int kFusedSlabLD = kFusedSlab + 8;
 constexpr int kFusedMaxLayers = 9;
+constexpr int kFusedThreads = 512;      // eight waves: four row blocks x two column halves
 
 struct FusedMlp {
   const float* x;       // [rows][n_in] raw inputs
@@ -702,13 +704,15 @@ __device__ __forceinline__ float gelu_as(float z) {
   return 0.5f * z * (1.0f + copysignf(erf_abs, z));
 }
 
-__global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
+__global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(FusedMlp f) {
   __shared__ __attribute__((aligned(16))) __bf16 sH[kFusedRows * kFusedLD];
   __shared__ __attribute__((aligned(16))) __bf16 sW[2][kFusedMaxWidth * kFusedSlabLD];  // [j][k]
+  __shared__ float s_head[2][kFusedRows];  // error-head partial sums of the two column halves
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 3, wc = wave >> 2;  // row block, column half
   const int m = lane & 31, half = lane >> 5;
   const int64_t i0 = (int64_t)blockIdx.x * kFusedRows;
-  __bf16* myH = sH + (size_t)(wave * 32) * kFusedLD;
+  __bf16* myH = sH + (size_t)(wr * 32) * kFusedLD;
 
   // input tile: normalised inputs rounded to BF16 (four at a time, several loads in flight),
   // zero-padded to whole slabs
@@ -716,38 +720,40 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
   const int kin = (f.n_in + kFusedSlab - 1) / kFusedSlab * kFusedSlab;
   const int q4 = f.n_in / 4;
 #pragma unroll 4
-  for (int idx = tid; idx < kFusedRows * q4; idx += 256) {
+  for (int idx = tid; idx < kFusedRows * q4; idx += kFusedThreads) {
     const int r = idx / q4, c = 4 * (idx - r * q4);
     const int64_t ii = i0 + r;
     f32x4 v = ii < f.rows ? *(const f32x4*)(f.x + ii * f.n_in + c) : f32x4{0.f, 0.f, 0.f, 0.f};
     if (f.norm) v = (v - *(const f32x4*)(f.norm + c)) * *(const f32x4*)(f.norm + f.n_in + c);
     *(bf16x4*)&sH[r * kFusedLD + c] = bf16x4{(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
   }
-  for (int idx = tid; idx < kFusedRows * (kin - f.n_in); idx += 256) {
+  for (int idx = tid; idx < kFusedRows * (kin - f.n_in); idx += kFusedThreads) {
     const int r = idx / (kin - f.n_in);
     sH[r * kFusedLD + f.n_in + (idx - r * (kin - f.n_in))] = (__bf16)0.0f;
   }
 
-  // weight slabs: thread t moves 16-byte pieces t + 256 v (column j = idx / 8, inner 8 (idx % 8))
-  u32x4 rw[8];
+  // weight slabs: thread t moves 16-byte pieces t + 512 v (column j = idx / 8, inner 8 (idx % 8))
+  constexpr int kPieces = kFusedMaxWidth * kFusedSlab / 8 / kFusedThreads;
+  // two register sets: a slab's loads are issued two slabs ahead of its products
+  u32x4 rw[kPieces];
   auto load_slab = [&](const __bf16* W, int din, int dout, int k0) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int idx = tid + 256 * v, j = idx >> 3, kq = (idx & 7) * 8;
+    for (int v = 0; v < kPieces; ++v) {
+      const int idx = tid + kFusedThreads * v, j = idx >> 3, kq = (idx & 7) * 8;
       rw[v] = (j < dout && k0 + kq < din) ? *(const u32x4*)(W + (int64_t)j * din + k0 + kq) : u32x4{0u, 0u, 0u, 0u};
     }
   };
   auto store_slab = [&](int b) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      const int idx = tid + 256 * v, j = idx >> 3, kq = (idx & 7) * 8;
+    for (int v = 0; v < kPieces; ++v) {
+      const int idx = tid + kFusedThreads * v, j = idx >> 3, kq = (idx & 7) * 8;
       *(u32x4*)&sW[b][j * kFusedSlabLD + kq] = rw[v];
     }
   };
 
-  f32x16v acc[8];
+  f32x16v acc[4];
   const bool full = i0 + kFusedRows <= f.rows;  // a whole tile skips the per-row checks
-  const int64_t row0 = i0 + wave * 32 + 4 * half;  // row of accumulator register 0 of this lane
+  const int64_t row0 = i0 + wr * 32 + 4 * half;  // row of accumulator register 0 of this lane
   int buf = 0;
   for (int l = 0; l <= f.n_hidden; ++l) {
     const bool out_layer = l == f.n_hidden;
@@ -757,7 +763,7 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
     const int nb = dout / 32;
     const __bf16* W = f.w + f.w_off[l];
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
     // the buffer about to be filled was last read two barriers ago
@@ -769,25 +775,25 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
       if (more) load_slab(W, din, dout, k0 + kFusedSlab);
 #pragma unroll
       for (int q = 0; q < kFusedSlab; q += 32) {
-        // both inner halves' fragments are read before the products, and all eight column
+        // both inner halves' fragments are read before the products, and all four column
         // blocks are multiplied, also past a narrower layer's width (its slab columns there
         // are zeros): a branch per block would make each product wait for its own read
-        bf16x8 fa[2], fb[2][8];
+        bf16x8 fa[2], fb[2][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           fa[h] = *(const bf16x8*)&myH[m * kFusedLD + k0 + q + 16 * h + 8 * half];
 #pragma unroll
-          for (int b = 0; b < 8; ++b)
-            fb[h][b] = *(const bf16x8*)&sW[buf][(32 * b + m) * kFusedSlabLD + q + 16 * h + 8 * half];
+          for (int b = 0; b < 4; ++b)
+            fb[h][b] = *(const bf16x8*)&sW[buf][(32 * (4 * wc + b) + m) * kFusedSlabLD + q + 16 * h + 8 * half];
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int b = 0; b < 8; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[h], fb[h][b], acc[b], 0, 0, 0);
-        // keep the 18 reads ahead of the 16 products (the scheduler otherwise reuses one
+          for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[h], fb[h][b], acc[b], 0, 0, 0);
+        // keep the 10 reads ahead of the 8 products (the scheduler otherwise reuses one
         // register for every weight fragment and waits for each read in turn)
-        __builtin_amdgcn_sched_group_barrier(0x100, 18, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
       }
       if (more) store_slab(buf ^ 1);
       __syncthreads();
@@ -795,16 +801,16 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
     }
     const float* bias = f.p + f.b_off[l];
     if (!out_layer) {
-      // activations over this wave's own rows (its reads of them are complete: the MFMAs
-      // above consumed them); the error head dots the last hidden layer in FP32
+      // activations over this wave's rows and columns (every wave's reads of the tile ended
+      // at the layer's last barrier); the error head dots the last hidden layer in FP32
       const bool head = f.head && l == f.n_hidden - 1;
       float hs[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) hs[r] = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        if (b < nb) {
-          const int j = 32 * b + m;
+      for (int b = 0; b < 4; ++b) {
+        if (4 * wc + b < nb) {
+          const int j = 32 * (4 * wc + b) + m;
           const float bj = bias[j];
           const float hw = head ? f.head[j] : 0.0f;
 #pragma unroll
@@ -815,33 +821,48 @@ __global__ __launch_bounds__(256) void lw_mlp_fused_forward_kernel(FusedMlp f) {
             hs[r] = fmaf(hw, h, hs[r]);
           }
         }
+        // one column block at a time: interleaving the blocks' activations would hold
+        // their temporaries all at once
+        __builtin_amdgcn_sched_barrier(0);
       }
       if (head) {
+        // this half's sum over its columns, kept for the output layer's epilogue (after the
+        // output layer's barriers) to add the two halves
 #pragma unroll
         for (int r = 0; r < 16; ++r)
           for (int off = 16; off > 0; off >>= 1) hs[r] += __shfl_xor(hs[r], off);
-        if (m == 0 && f.e) {
+        if (m == 0) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
-            if (full || ii < f.rows) f.e[ii] = hs[r] + f.head[f.hidden];
-          }
+          for (int r = 0; r < 16; ++r) s_head[wc][wr * 32 + 8 * (r / 4) + 4 * half + (r % 4)] = hs[r];
         }
       }
-    } else {
+    }
+  }
+  // output layer epilogue, after the loop (inside it, the compiler would hoist the rows'
+  // addresses out of the loop and hold them through every layer)
+  {
+    const int nb = f.n_out / 32;
+    const float* bias = f.p + f.b_off[f.n_hidden];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        if (b < nb) {
-          const int j = 32 * b + m;
-          const float bj = bias[j];
+    for (int b = 0; b < 4; ++b) {
+      if (4 * wc + b < nb) {
+        const int j = 32 * (4 * wc + b) + m;
+        const float bj = bias[j];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
-            float v = acc[b][r] + bj;
-            if (f.skip_index >= 0) v += f.skip_coeff * f.x[min(ii, f.rows - 1) * f.n_in + f.skip_index];
-            if (full || ii < f.rows) f.y[ii * f.n_out + j] = v;
-          }
+        for (int r = 0; r < 16; ++r) {
+          const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
+          float v = acc[b][r] + bj;
+          if (f.skip_index >= 0) v += f.skip_coeff * f.x[min(ii, f.rows - 1) * f.n_in + f.skip_index];
+          if (full || ii < f.rows) f.y[ii * f.n_out + j] = v;
         }
+      }
+    }
+    if (f.head && f.e && f.n_hidden >= 1 && wc == 0 && m == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rl = wr * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        const int64_t ii = i0 + rl;
+        if (full || ii < f.rows) f.e[ii] = s_head[0][rl] + s_head[1][rl] + f.head[f.hidden];
       }
     }
   }
@@ -1481,7 +1502,7 @@ lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, floa
     f.skip_index = n->skip_index;
     f.skip_coeff = n->skip_coeff;
     hipLaunchKernelGGL(lw::lw_mlp_fused_forward_kernel, dim3((unsigned)((rows + lw::kFusedRows - 1) / lw::kFusedRows)),
-                       dim3(256), 0, n->c->stream, f);
+                       dim3(lw::kFusedThreads), 0, n->c->stream, f);
     MLP_HIP(hipGetLastError(), "fused forward");
     return LW_OK;
   }
