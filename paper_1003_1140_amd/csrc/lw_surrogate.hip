@@ -654,10 +654,11 @@ __global__ void lw_log_targets_kernel(const float* pp, const float* charge, cons
 // The whole network for a tile of 128 rows in one work-group of eight waves, two per SIMD, so
 // that one wave's activation arithmetic overlaps the other's products.  Wave (r, c) owns rows
 // 32 r .. 32 r + 31 and output columns 128 c .. 128 c + 127: it keeps a layer's 32 x 128
-// outputs in MFMA accumulators and writes the activation (GELU in FP32, rounded to BF16 as the
-// layered products round their A operand) over its part of an LDS activation tile, which is
-// the next layer's A operand; a layer's last barrier orders every wave's reads of the tile
-// before the rewrite.  The weights come from a BF16 copy of the parameters (the rounding the
+// outputs transposed in MFMA accumulators (the weights are the products' first operand, so
+// that a lane holds four consecutive units of one row) and writes the activation (GELU in
+// FP32, rounded to BF16 as the layered products round their A operand) over its part of an
+// LDS activation tile, 8 bytes per four units, which is the next layer's second operand; a
+// layer's last barrier orders every wave's reads of the tile before the rewrite.  The weights come from a BF16 copy of the parameters (the rounding the
 // layered products apply as they stage them) in slabs of 64 inner indices through two LDS
 // buffers shared by the eight waves, the next slab read from memory while the current one is
 // multiplied.  Each layer's arithmetic is the layered path's (bias, then the skip term; inner
@@ -692,16 +693,18 @@ __global__ void lw_round_bf16_kernel(const float* p, int64_t n, __bf16* w) {
   if (i < n) w[i] = (__bf16)p[i];
 }
 
-// GELU(z) = z Phi(z) with erf from Abramowitz & Stegun 7.1.26
+// GELU(z) = z Phi(z) = max(z, 0) - |z| erfc(|z| / sqrt 2) / 2, with erfc(x) = P(t) exp(-x^2),
+// t = 1 / (1 + p x), from Abramowitz & Stegun 7.1.26 (P's coefficients halved here, exactly)
 __device__ __forceinline__ float gelu_as(float z) {
-  const float x = fabsf(z) * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-  float q = fmaf(1.061405429f, t, -1.453152027f);
-  q = fmaf(q, t, 1.421413741f);
-  q = fmaf(q, t, -0.284496736f);
-  q = fmaf(q, t, 0.254829592f);
-  const float erf_abs = fmaf(-q * t, __expf(-x * x), 1.0f);
-  return 0.5f * z * (1.0f + copysignf(erf_abs, z));
+  const float az = fabsf(z);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+  float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+  q = fmaf(q, t, 0.5f * 1.421413741f);
+  q = fmaf(q, t, 0.5f * -0.284496736f);
+  q = fmaf(q, t, 0.5f * 0.254829592f);
+  // exp(-z^2 / 2) = 2^(-z^2 log2(e) / 2)
+  const float e = __builtin_amdgcn_exp2f(z * (z * -0.72134752044448170f));
+  return fmaf(-az, q * t * e, fmaxf(z, 0.0f));
 }
 
 __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(FusedMlp f) {
@@ -753,7 +756,6 @@ __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(Fus
 
   f32x16v acc[4];
   const bool full = i0 + kFusedRows <= f.rows;  // a whole tile skips the per-row checks
-  const int64_t row0 = i0 + wr * 32 + 4 * half;  // row of accumulator register 0 of this lane
   int buf = 0;
   for (int l = 0; l <= f.n_hidden; ++l) {
     const bool out_layer = l == f.n_hidden;
@@ -789,7 +791,7 @@ __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(Fus
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[h], fb[h][b], acc[b], 0, 0, 0);
+          for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb[h][b], fa[h], acc[b], 0, 0, 0);
         // keep the 10 reads ahead of the 8 products (the scheduler otherwise reuses one
         // register for every weight fragment and waits for each read in turn)
         __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
@@ -804,21 +806,23 @@ __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(Fus
       // activations over this wave's rows and columns (every wave's reads of the tile ended
       // at the layer's last barrier); the error head dots the last hidden layer in FP32
       const bool head = f.head && l == f.n_hidden - 1;
-      float hs[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) hs[r] = 0.0f;
+      float hs = 0.0f;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         if (4 * wc + b < nb) {
-          const int j = 32 * (4 * wc + b) + m;
-          const float bj = bias[j];
-          const float hw = head ? f.head[j] : 0.0f;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int rr = 8 * (r / 4) + 4 * half + (r % 4);
-            const float h = gelu_as(acc[b][r] + bj);
-            myH[rr * kFusedLD + j] = (__bf16)h;
-            hs[r] = fmaf(hw, h, hs[r]);
+          for (int g = 0; g < 4; ++g) {
+            const int j = 32 * (4 * wc + b) + 8 * g + 4 * half;  // this lane's four units
+            const f32x4 bj = *(const f32x4*)(bias + j);
+            f32x4 h;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = gelu_as(acc[b][4 * g + i] + bj[i]);
+            *(bf16x4*)&myH[m * kFusedLD + j] = bf16x4{(__bf16)h[0], (__bf16)h[1], (__bf16)h[2], (__bf16)h[3]};
+            if (head) {
+              const f32x4 hw = *(const f32x4*)(f.head + j);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) hs = fmaf(hw[i], h[i], hs);
+            }
           }
         }
         // one column block at a time: interleaving the blocks' activations would hold
@@ -826,15 +830,10 @@ __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(Fus
         __builtin_amdgcn_sched_barrier(0);
       }
       if (head) {
-        // this half's sum over its columns, kept for the output layer's epilogue (after the
+        // this column half's sum for the row, kept for the output layer's epilogue (after the
         // output layer's barriers) to add the two halves
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          for (int off = 16; off > 0; off >>= 1) hs[r] += __shfl_xor(hs[r], off);
-        if (m == 0) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) s_head[wc][wr * 32 + 8 * (r / 4) + 4 * half + (r % 4)] = hs[r];
-        }
+        hs += __shfl_xor(hs, 32);
+        if (half == 0) s_head[wc][wr * 32 + m] = hs;
       }
     }
   }
@@ -843,28 +842,28 @@ __global__ __launch_bounds__(kFusedThreads) void lw_mlp_fused_forward_kernel(Fus
   {
     const int nb = f.n_out / 32;
     const float* bias = f.p + f.b_off[f.n_hidden];
+    const int64_t ii = i0 + wr * 32 + m;  // this lane's row
+    const bool ok = full || ii < f.rows;
+    const float xs = f.skip_index >= 0 ? f.x[min(ii, f.rows - 1) * f.n_in + f.skip_index] : 0.0f;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       if (4 * wc + b < nb) {
-        const int j = 32 * (4 * wc + b) + m;
-        const float bj = bias[j];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t ii = row0 + 8 * (r / 4) + (r % 4);
-          float v = acc[b][r] + bj;
-          if (f.skip_index >= 0) v += f.skip_coeff * f.x[min(ii, f.rows - 1) * f.n_in + f.skip_index];
-          if (full || ii < f.rows) f.y[ii * f.n_out + j] = v;
+        for (int g = 0; g < 4; ++g) {
+          const int j = 32 * (4 * wc + b) + 8 * g + 4 * half;
+          const f32x4 bj = *(const f32x4*)(bias + j);
+          f32x4 v;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            v[i] = acc[b][4 * g + i] + bj[i];
+            if (f.skip_index >= 0) v[i] += f.skip_coeff * xs;
+          }
+          if (ok) *(f32x4*)(f.y + ii * f.n_out + j) = v;
         }
       }
     }
-    if (f.head && f.e && f.n_hidden >= 1 && wc == 0 && m == 0) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int rl = wr * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        const int64_t ii = i0 + rl;
-        if (full || ii < f.rows) f.e[ii] = s_head[0][rl] + s_head[1][rl] + f.head[f.hidden];
-      }
-    }
+    if (f.head && f.e && f.n_hidden >= 1 && wc == 0 && half == 0 && ok)
+      f.e[ii] = s_head[0][wr * 32 + m] + s_head[1][wr * 32 + m] + f.head[f.hidden];
   }
 }
 
@@ -1477,7 +1476,7 @@ lw_status lw_mlp_forward(lw_mlp* n, const float* x, int64_t rows, float* y, floa
   if (!n || !x || !y || rows < 0) return LW_EINVAL;
   if (err_head && n->n_hidden < 1) return mlp_fail(n, LW_EINVAL, "the error head needs a hidden layer");
   if (rows == 0) return LW_OK;
-  if (fused_shape(n) && ((uintptr_t)x & 15) == 0) {
+  if (fused_shape(n) && ((uintptr_t)x & 15) == 0 && ((uintptr_t)y & 15) == 0) {
     const int64_t np = n->n_params;
     hipLaunchKernelGGL(lw::lw_round_bf16_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, n->c->stream,
                        n->p, np, n->wbf);
