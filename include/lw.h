@@ -453,7 +453,7 @@ lw_status lw_mlp_set_output_skip(lw_mlp* net, int32_t input_index, float coeff);
 /* y: device [rows][n_out]; err_head (may be NULL): device [rows], the error head's output.
  * Networks with a hidden width that is a multiple of 64, an output width a multiple of 32
  * (both at most 256), an input width a multiple of 8 (at most 256), 1 to 8 hidden layers and
- * a 16-byte aligned x run as one kernel per tile of 128 rows: activations stay on chip, the
+ * 16-byte aligned x and y run as one kernel per tile of 128 rows: activations stay on chip, the
  * weights are rounded to BF16 once per call, and GELU's erf is a rational form within 1.5e-7
  * of erf.  Other shapes run layer by layer, as the training calls do.  Both keep the
  * roundings of the products (BF16 operands, FP32 accumulation). */
