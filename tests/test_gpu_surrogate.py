@@ -271,6 +271,42 @@ def test_inference_matches_bf16_emulation(shape, rows, rigorous):
     _check(f"error head {shape} x {rows}", e.cpu().numpy().astype(np.float64), ref["e"], ref["ee"], rigorous)
 
 
+@pytest.mark.parametrize("which", ["x", "y"])
+def test_inference_with_unaligned_rows_runs_layer_by_layer(which):
+    """An input or output array that is not 16-byte aligned takes the layered path instead of
+    the single kernel (which reads and writes rows 16 bytes at a time); its outputs and error
+    head meet the same emulation bars, with the normalisation and the output skip."""
+    import torch
+
+    import _mlp_emul as E
+
+    shape, rows = (16, 64, 2, 96), 150
+    c = _ctx(configs.dirs_jitter(), configs.log_grid(0.1, 1e3, 8))
+    net = _net(c, shape, seed=11)
+    rng = np.random.default_rng(11)
+    n_in, n_out = shape[0], shape[3]
+    p, head = _params(net, rng, head=True)
+    shift = rng.normal(size=n_in).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, size=n_in).astype(np.float32)
+    net.set_input_norm(shift, scale)
+    net.set_output_skip(3, 0.75)
+    x = (rng.normal(size=(rows, n_in)) * 2.0).astype(np.float32)
+    xb = torch.zeros(rows * n_in + 4, device="cuda")
+    yb = torch.zeros(rows * n_out + 4, device="cuda")
+    k = 1 if which == "x" else 0
+    xd = xb[k:k + rows * n_in].view(rows, n_in)
+    xd.copy_(torch.from_numpy(x))
+    k = 1 if which == "y" else 0
+    yd = yb[k:k + rows * n_out].view(rows, n_out)
+    e = torch.zeros(rows, device="cuda")
+    assert (xd.data_ptr() % 16 != 0) == (which == "x") and (yd.data_ptr() % 16 != 0) == (which == "y")
+    c._check(c.lib.lw_mlp_forward(net.h, net._ptr(xd), rows, net._ptr(yd), net._ptr(e)))
+    xn = ((x - shift) * scale).astype(np.float32).astype(np.float64)
+    ref = E.forward(shape, p, xn, skip=(x[:, 3].astype(np.float64), 0.75), head=head)
+    _check(f"unaligned {which} output", yd.cpu().numpy().astype(np.float64), ref["y"], ref["ey"], False)
+    _check(f"unaligned {which} error head", e.cpu().numpy().astype(np.float64), ref["e"], ref["ee"], False)
+
+
 def test_input_normalisation_matches_oracle_on_normalised_inputs():
     import torch
 
