@@ -214,6 +214,14 @@ def profiled_traffic(path, tile, particles, workload="c3", bands=2, kernel="cont
     return float(value) if value is not None else None
 
 
+def attach_traffic(r, path, tile, particles, workload, bands):
+    """Profiled HBM bytes per launch on both kernels' rooflines of a timed matrix-core path, and
+    its `roofline` again the dominant kernel's (copied before the traffic was known)."""
+    for kernel in ("contraction", "spread"):
+        r["roofline_" + kernel]["traffic"] = profiled_traffic(path, tile, particles, workload, bands, kernel)
+    r["roofline"] = dict(r["roofline_spread" if r["roofline"]["bound"] == "alu" else "roofline_contraction"])
+
+
 def SPREAD_KERNEL(w):
     return f"lw_spread_kernel<{w}>"
 
@@ -844,9 +852,7 @@ def c2_leg(a, log):
     spec.update(spec2)
     res["mfma_f16x3"]["band_integrated_err_vs_fp32"] = band_integrated_error(spec["mfma_f16x3"], spec["fp32"], om)
     res["mfma_f16x3"]["speedup_vs_fp32"] = res["mfma_f16x3"]["terms_per_s"] / res["fp32"]["terms_per_s"]
-    for kernel in ("contraction", "spread"):
-        res["mfma_f16x3"]["roofline_" + kernel]["traffic"] = profiled_traffic(
-            "mfma_f16x3", a.tile, a.c2_particles, "c2", a.bands, kernel)
+    attach_traffic(res["mfma_f16x3"], "mfma_f16x3", a.tile, a.c2_particles, "c2", a.bands)
     out["paths"] = res
     ctx.close()
     if not a.no_insitu:
@@ -924,10 +930,7 @@ def main():
         log(f"[bench] fp32 on {sub.n_particles} particles of the same workload: {rf['terms_per_s']:.3e} terms/s")
         del sub
     if "roofline_contraction" in r:
-        for kernel in ("contraction", "spread"):
-            r["roofline_" + kernel]["traffic"] = profiled_traffic(head, a.tile, a.particles, a.workload,
-                                                                  a.bands, kernel)
-        r["roofline"] = dict(r["roofline_spread" if r["roofline"]["bound"] == "alu" else "roofline_contraction"])
+        attach_traffic(r, head, a.tile, a.particles, a.workload, a.bands)
     ctx.close()
     del batch
     torch.cuda.empty_cache()

@@ -52,6 +52,21 @@ def test_traffic_is_reported_only_for_the_profiled_launch():
     assert b.profiled_traffic("mfma_f16x3", 0, 100_000, "other", 2) is None
 
 
+def test_roofline_carries_the_dominant_kernels_traffic():
+    """Both legs' `roofline` is re-copied from the dominant kernel after the traffic is
+    attached, so it carries the same bytes as that kernel's own roofline."""
+    b = _bench()
+    for workload, bound, dominant in (("c2", "alu", "spread"), ("c3", "mfma", "contraction")):
+        r = {"roofline_contraction": {"bound": "mfma", "traffic": None},
+             "roofline_spread": {"bound": "alu", "traffic": None}}
+        r["roofline"] = dict(r["roofline_" + dominant])
+        b.attach_traffic(r, "mfma_f16x3", 0, b.PROFILED_PARTICLES[workload], workload, 2)
+        assert r["roofline"]["bound"] == bound
+        assert r["roofline"]["traffic"] == r["roofline_" + dominant]["traffic"]
+        assert r["roofline"]["traffic"] == b.profiled_traffic("mfma_f16x3", 0, b.PROFILED_PARTICLES[workload],
+                                                              workload, 2, dominant)
+
+
 def test_spread_flop_model():
     b = _bench()
     # per band: 8W accumulation + 9W tap polynomials + 3 (z, z^2) + 4 demodulation + 6 FP64
