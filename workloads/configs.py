@@ -124,7 +124,7 @@ WORKLOADS = {
     "jitter_wide": dict(n_particles=1_000_000, steps=2048, dirs=dirs_wide, omega=(0.1, 1e3, 2048)),
     "uneven": dict(n_particles=400_000, steps=None, dirs=dirs_equal_area, omega=(0.1, 1e3, 1024),
                    n_species=3),
-    "surrogate": dict(n_train=125_000, n_calib=25_000, n_infer=1_000_000, infer_first_id=1 << 20,
+    "surrogate": dict(n_train=125_000, n_calib=200_000, n_infer=1_000_000, infer_first_id=1 << 20,
                       steps=4096, dirs=dirs_jitter, omega=(0.1, 1e3, 256), held_out=0.01,
                       fallback=0.05),
 }
