@@ -871,7 +871,6 @@ __global__ __launch_bounds__(512) void lw_dft_mfma_kernel(GemmArgs a) {
     const int c = col0 + tid;
     float sc = 1.0f;
     int q2 = 0, fc = -1;
-    double tau0 = 0.0;
     for (int s = 0; s < a.ns; ++s) s_colw[s][tid] = 0.0f;
     if (c < ncol) {
       const int pl = a.perm[db * a.n_local + c / 2];  // columns in decreasing-length order
