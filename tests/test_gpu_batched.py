@@ -179,3 +179,60 @@ def test_stale_graphs_are_refused(uneven_small):
     np.testing.assert_allclose(c.read_spectra(), first, rtol=1e-12, atol=0)
     g.close()
     c.close()
+
+
+def test_uneven_bench_slice_sampled_bins():
+    """The benchmark's batched launch at its size: 5e4 particles of the uneven workload
+    (device-generated as the benchmark does, lengths 256..8192, three species), 64 equal-area
+    directions, 1024 log frequencies; the persistent FP32 launch on its planned ticket queue,
+    then the matrix-core path.  The oracle recomputes two sampled (direction, frequency) bins
+    per species over all 5e4 particles from host copies of the same trajectories.  Bars: the
+    FP32 path's 1e-5 per bin, 1e-4 per sampled bin for the matrix-core path."""
+    from types import SimpleNamespace
+
+    from paper_1003_1140_amd import DeviceBatch
+    from workloads.gpu import generate_device
+
+    n = 50_000
+    t, _ = generate_device(configs.uneven_recipe(), 0, n)
+    b = DeviceBatch(t, n)
+    dirs, om = configs.dirs_equal_area(), configs.log_grid(0.1, 1e3, 1024)
+    c = ctx_for(dirs, om)
+    c.set_tuning(persistent=1)
+    c.plan_batch(b, "fp32")
+    c.accumulate(b, "fp32")
+    S32 = c.read_spectra()
+    c.reset()
+    c.accumulate(b, "mfma_f16")
+    S16 = c.read_spectra()
+    # per species a forward and an oblique direction, a low and a high frequency, each moved
+    # down to the nearest bin holding at least 1e-3 of its (species, direction) peak (chosen
+    # from the FP32 spectrum; the expected values come from the oracle alone)
+    picks = []
+    for s in range(3):
+        for d, j in ((0, 200), (37, 900)):
+            peak = S32[s, d].max()
+            while j > 0 and S32[s, d, j] < 1e-3 * peak:
+                j -= 1
+            picks.append((s, d, j))
+    ref = np.zeros(len(picks))
+    offs = t["offsets"].cpu().numpy()
+    per_sample = ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az")
+    per_particle = ("t0", "dt", "charge", "weight", "species")
+    step = 8192
+    for p0 in range(0, n, step):
+        p1 = min(n, p0 + step)
+        s0, s1 = int(offs[p0]), int(offs[p1])
+        h = SimpleNamespace(n_particles=p1 - p0, offsets=offs[p0:p1 + 1],
+                            **{k: t[k][s0:s1].cpu().numpy() for k in per_sample},
+                            **{k: t[k][p0:p1].cpu().numpy() for k in per_particle})
+        for s in range(3):
+            idx = [i for i, (sp, _, _) in enumerate(picks) if sp == s]
+            ref[idx] += oracle.sampled_bins(h, dirs[[picks[i][1] for i in idx]], om[[picks[i][2] for i in idx]],
+                                            species=s)
+    r32 = np.array([abs(S32[s, d, j] / ref[i] - 1.0) for i, (s, d, j) in enumerate(picks)])
+    r16 = np.array([abs(S16[s, d, j] / ref[i] - 1.0) for i, (s, d, j) in enumerate(picks)])
+    print(f"[parity] uneven workload, 5e4 particles, sampled bins: fp32 persistent "
+          f"{[f'{x:.2e}' for x in r32]}, mfma f16 x3 {[f'{x:.2e}' for x in r16]}", flush=True)
+    assert r32.max() <= TOL
+    assert r16.max() <= 1e-4
