@@ -287,6 +287,32 @@ def test_straight_motion_is_exactly_zero():
     assert np.all(S == 0.0)
 
 
+def test_span_too_long_for_the_grid_is_refused():
+    """A retarded-time span needing more than 4e6 grid points in a band (samples 1e5 apart,
+    frequencies up to 1e3: ~5e7 points) is refused by the matrix-core planner with
+    LW_EUNSUPPORTED before any launch.  The context stays usable: the FP32 path sums the
+    same particle, against the oracle at its 1e-5 bar."""
+    from paper_1003_1140_amd import LW_EUNSUPPORTED, Context, DeviceBatch, LWError
+
+    k = np.arange(3, dtype=np.float64)
+    b = workloads.single_particle(x=0.5e5 * k, y=0 * k, z=0 * k, bx=0.5 + 0 * k, by=0 * k, bz=0 * k,
+                                  ax=0 * k, ay=np.array([0.01, 0.02, -0.01]), az=0 * k, dt=1e5)
+    dirs = configs.dirs_jitter()
+    om = configs.log_grid(0.1, 1e3, 64)
+    c = Context(0)
+    c.set_directions(dirs)
+    c.set_frequencies(om)
+    db = DeviceBatch.from_host(b)
+    with pytest.raises(LWError) as e:
+        c.accumulate(db, "mfma_f16")
+    assert e.value.status == LW_EUNSUPPORTED and "too long" in str(e.value)
+    c.reset()
+    c.accumulate(db, "fp32")
+    S = c.read_spectra()
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    assert band_relative_error(S, ref) <= 1e-5
+
+
 def test_agrees_with_fp32_path_on_a_large_batch():
     """4096 jitter particles: the FP32 path (itself parity-checked) judges the matrix-core path."""
     r = configs.jitter_recipe()
