@@ -152,6 +152,11 @@ def parse():
                     help="the first particles of the batched leg the autotuner times its candidates on")
     ap.add_argument("--surrogate-infer", type=int, default=1_000_000)
     ap.add_argument("--surrogate-chunk", type=int, default=100_000)
+    ap.add_argument("--surrogate-fallback-path", choices=("fp32", "mfma_f16"), default="mfma_f16",
+                    help="exact path of the surrogate's fallback (mfma_f16: FP16 hi/lo, three products, on a "
+                         "gathered copy of the flagged particles)")
+    ap.add_argument("--surrogate-judge-path", choices=("fp32", "mfma_f16"), default="fp32",
+                    help="exact path of the held-out judge")
     ap.add_argument("--surrogate-steps", type=int, default=1500)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (scales HBM byte counters)")
@@ -742,7 +747,7 @@ def surrogate_leg(a, log):
     del tt, tc
     torch.cuda.empty_cache()
     ctx.reset()
-    judge = sg.Judge(ctx)
+    judge = sg.Judge(ctx, exact_path=a.surrogate_judge_path)
     n, chunk, first = a.surrogate_infer, min(a.surrogate_chunk, a.surrogate_infer), cfg["infer_first_id"]
     t_exact = t_pipe = t_mfma = 0.0
     fallback = 0
@@ -761,7 +766,7 @@ def surrogate_leg(a, log):
         exact.accumulate(b, "fp32")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = sg.infer_chunk(ctx, sur, b, judge=judge, held=held)
+        r = sg.infer_chunk(ctx, sur, b, judge=judge, held=held, exact_path=a.surrogate_fallback_path)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         ws_m = exact_m.workspace(b, "mfma_f16")  # plans the grids (synchronises) before timing
@@ -794,7 +799,8 @@ def surrogate_leg(a, log):
         "gain_vs_exact": t_exact / t_pipe, "seconds_pipeline": t_pipe, "seconds_exact": t_exact,
         "exact_mfma_f16x3_terms_per_s": terms / t_mfma, "gain_vs_exact_mfma": t_mfma / t_pipe,
         "exact_mfma_vs_fp32_band_integrated": band_integrated_error(S_mfma, S_exact, om),
-        "fallback_fraction": fallback / n, "held_out_particles": judge.n,
+        "fallback_fraction": fallback / n, "fallback_path": a.surrogate_fallback_path,
+        "judge_path": a.surrogate_judge_path, "held_out_particles": judge.n,
         "held_out_per_bin_max": held_err["per_bin_max"], "held_out_per_bin_median": held_err["per_bin_median"],
         "held_out_split_half_floor_per_bin_max": floor["per_bin_max"],
         "held_out_split_half_floor_per_bin_median": floor["per_bin_median"],

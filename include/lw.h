@@ -344,6 +344,26 @@ lw_status lw_graph_capture(lw_ctx* ctx, const lw_batch* batch, lw_path path, voi
 lw_status lw_graph_launch(lw_graph* graph);
 void lw_graph_destroy(lw_graph* graph);
 
+/* Particle subsets as batches of their own, so that any path (the matrix-core one
+ * included) can sum a list of particles, e.g. the ones a surrogate defers to the exact
+ * method (Section 2.2: the spectrum is a sum over particles, so any subset's sum is a
+ * partial sum of the whole).
+ * lw_subset_offsets: dst_offsets (device int64 [n + 1]) gets 0 and the running sums of the
+ * lengths of the particles listed in `indices` (device int64 [n], each in [0, n_particles)
+ * of `batch`); *host_total receives dst_offsets[n], the gathered batch's sample count.  An
+ * index outside the batch (or a particle of negative length) is LW_EINVAL.  Synchronous;
+ * LW_ESTATE inside graph capture.
+ * lw_gather_particles: copies the listed particles' samples and per-particle values into
+ * `dst`, a batch of n particles whose offsets hold lw_subset_offsets' result and whose
+ * arrays (caller-owned, written here) hold that many samples; d(beta)/dt in the same
+ * precision as `batch` (LW_BATCH_F64_ACCEL on both or neither); dst.species, when given,
+ * gets the source's species (0 when the source has none).  Stream-ordered, no allocation;
+ * n <= 2^31 - 1. */
+lw_status lw_subset_offsets(lw_ctx* ctx, const lw_batch* batch, const int64_t* indices, int64_t n,
+                            int64_t* dst_offsets, int64_t* host_total);
+lw_status lw_gather_particles(lw_ctx* ctx, const lw_batch* batch, const int64_t* indices, int64_t n,
+                              const lw_batch* dst);
+
 /* Exact FP32 accumulation of the particles listed in `indices` (device int64
  * [n_indices], each in [0, n_particles)) of `batch`: as lw_accumulate on the
  * FP32 path restricted to those particles; per_particle (optional) keeps the

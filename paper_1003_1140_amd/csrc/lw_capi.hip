@@ -249,6 +249,7 @@ void lw_destroy(lw_ctx* c) {
   free_dev(c->plan.d_order);
   free_dev(c->d_ticket);
   free_dev(c->d_wgtime);
+  free_dev(c->d_flag);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   free_dev(c->d_flops);
   free_dev(c->d_dirs);
@@ -769,6 +770,176 @@ lw_status lw_plan_batch(lw_ctx* c, const lw_batch* b, lw_path path) {
   pl.n_blocks = s.n_blocks;
   pl.n_items = n_items;
   pl.valid = true;
+  return LW_OK;
+}
+
+// ------------------------------------------------------------------ particle subsets as batches
+namespace {
+
+constexpr int kScanThreads = 1024;
+
+// dst[0] = 0 and dst[i + 1] = the summed lengths of particles idx[0] .. idx[i]: one work-group
+// walks the list in runs of 1024, an inclusive scan per wave by shuffles and one lane adding
+// the sixteen wave totals in order.  An index outside [0, P), or a particle with a negative
+// length, counts as empty and sets *bad.
+__global__ __launch_bounds__(kScanThreads) void subset_offsets_kernel(const int64_t* offsets, int64_t P,
+                                                                      const int64_t* idx, int64_t n,
+                                                                      int64_t* dst, unsigned* bad) {
+  __shared__ int64_t s_wave[kScanThreads / 64];
+  __shared__ int64_t s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) {
+    s_carry = 0;
+    dst[0] = 0;
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += kScanThreads) {
+    const int64_t i = base + tid;
+    int64_t len = 0;
+    if (i < n) {
+      const int64_t p = idx[i];
+      if (p >= 0 && p < P) len = offsets[p + 1] - offsets[p];
+      if (p < 0 || p >= P || len < 0) {
+        len = 0;
+        atomicOr(bad, 1u);
+      }
+    }
+    int64_t v = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t u = __shfl_up(v, off);
+      if (lane >= off) v += u;
+    }
+    if (lane == 63) s_wave[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t run = s_carry;
+      for (int w = 0; w < kScanThreads / 64; ++w) {
+        const int64_t t = s_wave[w];
+        s_wave[w] = run;
+        run += t;
+      }
+      s_carry = run;
+    }
+    __syncthreads();
+    if (i < n) dst[i + 1] = s_wave[wave] + v;
+    __syncthreads();  // the next run rewrites s_wave
+  }
+}
+
+struct GatherArgs {
+  lw::BatchView src;
+  const int64_t* idx;
+  const int64_t* dst_offsets;
+  double *x, *y, *z, *bx, *by, *bz;
+  float *ax, *ay, *az;      // FP32 d(beta)/dt, or null
+  double *adx, *ady, *adz;  // FP64 d(beta)/dt, or null
+  double *t0, *dt;
+  float *charge, *weight;
+  int32_t* species;         // null when the destination has none
+};
+
+// One work-group per listed particle copies its samples (the shorter of its length in the
+// source and its slot in the destination, so that both stay in bounds) and its per-particle
+// values; an index outside the source is skipped.
+__global__ __launch_bounds__(256) void gather_particles_kernel(GatherArgs a) {
+  const int64_t i = blockIdx.x;
+  const int64_t p = a.idx[i];
+  if (p < 0 || p >= a.src.n_particles) return;
+  const int64_t so = a.src.offsets[p], d0 = a.dst_offsets[i];
+  const int64_t len = min(a.src.offsets[p + 1] - so, a.dst_offsets[i + 1] - d0);
+  for (int64_t k = threadIdx.x; k < len; k += blockDim.x) {
+    a.x[d0 + k] = a.src.x[so + k];
+    a.y[d0 + k] = a.src.y[so + k];
+    a.z[d0 + k] = a.src.z[so + k];
+    a.bx[d0 + k] = a.src.bx[so + k];
+    a.by[d0 + k] = a.src.by[so + k];
+    a.bz[d0 + k] = a.src.bz[so + k];
+    if (a.adx) {
+      a.adx[d0 + k] = a.src.adx[so + k];
+      a.ady[d0 + k] = a.src.ady[so + k];
+      a.adz[d0 + k] = a.src.adz[so + k];
+    } else {
+      a.ax[d0 + k] = a.src.ax[so + k];
+      a.ay[d0 + k] = a.src.ay[so + k];
+      a.az[d0 + k] = a.src.az[so + k];
+    }
+  }
+  if (threadIdx.x == 0) {
+    a.t0[i] = a.src.t0[p];
+    a.dt[i] = a.src.dt[p];
+    a.charge[i] = a.src.charge[p];
+    a.weight[i] = a.src.weight[p];
+    if (a.species) a.species[i] = a.src.species ? a.src.species[p] : 0;
+  }
+}
+
+}  // namespace
+
+lw_status lw_subset_offsets(lw_ctx* c, const lw_batch* b, const int64_t* indices, int64_t n,
+                            int64_t* dst_offsets, int64_t* host_total) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (n < 0 || (n > 0 && !indices) || !dst_offsets || !host_total) return fail(c, LW_EINVAL, "bad index list");
+  if (c->capturing) return fail(c, LW_ESTATE, "lw_subset_offsets synchronises: not inside graph capture");
+  DeviceGuard g(c->device);
+  if (!c->d_flag) LW_HIP(hipMalloc(&c->d_flag, sizeof(unsigned)), "hipMalloc(flag)");
+  LW_HIP(lw::launch_fill_u32(c->d_flag, 1, 0u, c->stream), "clear flag");
+  hipLaunchKernelGGL(subset_offsets_kernel, dim3(1), dim3(kScanThreads), 0, c->stream, b->offsets,
+                     b->n_particles, indices, n, dst_offsets, c->d_flag);
+  LW_HIP(hipGetLastError(), "launch subset_offsets");
+  int64_t total = 0;
+  unsigned bad = 0;
+  LW_HIP(hipMemcpyAsync(&total, dst_offsets + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream), "read total");
+  LW_HIP(hipMemcpyAsync(&bad, c->d_flag, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream), "read flag");
+  LW_HIP(hipStreamSynchronize(c->stream), "synchronise");
+  if (bad) return fail(c, LW_EINVAL, "index outside the batch, or a particle of negative length");
+  *host_total = total;
+  return LW_OK;
+}
+
+lw_status lw_gather_particles(lw_ctx* c, const lw_batch* b, const int64_t* indices, int64_t n,
+                              const lw_batch* dst) {
+  if (!c) return LW_EINVAL;
+  lw_status st = check_batch(c, b);
+  if (st != LW_OK) return st;
+  if (n < 0 || (n > 0 && !indices) || !dst) return fail(c, LW_EINVAL, "bad index list or destination");
+  if (n == 0) return LW_OK;
+  if (dst->n_particles != n) return fail(c, LW_EINVAL, "destination holds %lld particles, not %lld",
+                                         (long long)dst->n_particles, (long long)n);
+  st = check_batch(c, dst);
+  if (st != LW_OK) return st;
+  if ((dst->flags & LW_BATCH_F64_ACCEL) != (b->flags & LW_BATCH_F64_ACCEL))
+    return fail(c, LW_EINVAL, "source and destination differ in the precision of d(beta)/dt");
+  if (n > 0x7fffffffLL) return fail(c, LW_EINVAL, "at most 2^31 - 1 particles per gather");
+  DeviceGuard g(c->device);
+  GatherArgs a;
+  a.src = lw::view_of(b);
+  a.idx = indices;
+  a.dst_offsets = dst->offsets;
+  // the destination's arrays are the caller's, written here (lw_batch declares them const
+  // for the calls that only read)
+  a.x = const_cast<double*>(dst->x);
+  a.y = const_cast<double*>(dst->y);
+  a.z = const_cast<double*>(dst->z);
+  a.bx = const_cast<double*>(dst->bx);
+  a.by = const_cast<double*>(dst->by);
+  a.bz = const_cast<double*>(dst->bz);
+  const lw::BatchView dv = lw::view_of(dst);
+  a.ax = const_cast<float*>(dv.ax);
+  a.ay = const_cast<float*>(dv.ay);
+  a.az = const_cast<float*>(dv.az);
+  a.adx = const_cast<double*>(dv.adx);
+  a.ady = const_cast<double*>(dv.ady);
+  a.adz = const_cast<double*>(dv.adz);
+  a.t0 = const_cast<double*>(dst->t0);
+  a.dt = const_cast<double*>(dst->dt);
+  a.charge = const_cast<float*>(dst->charge);
+  a.weight = const_cast<float*>(dst->weight);
+  a.species = const_cast<int32_t*>(dst->species);
+  hipLaunchKernelGGL(gather_particles_kernel, dim3((unsigned)n), dim3(256), 0, c->stream, a);
+  LW_HIP(hipGetLastError(), "launch gather_particles");
   return LW_OK;
 }
 

@@ -252,6 +252,7 @@ struct lw_ctx {
   // per work-group timing of the last persistent FP32 launch made with profiling on
   unsigned long long* d_wgtime = nullptr;
   int wgtime_cap = 0, wgtime_n = 0;
+  unsigned* d_flag = nullptr;  // invalid-index flag of lw_subset_offsets
   bool capturing = false;  // inside lw_graph_capture: no synchronisation allowed
   // bumped whenever a device buffer that captured work refers to is freed, moved or refilled
   // for another batch (accumulators, grids, persistent plan); a graph records it at capture

@@ -30,7 +30,8 @@ EXPORTED = ("lw_create", "lw_destroy", "lw_last_error", "lw_set_stream", "lw_set
             "lw_load_accumulator", "lw_stats", "lw_set_mfma_options", "lw_set_mfma_chunk_bytes",
             "lw_mfma_plan_info", "lw_set_profiling",
             "lw_profile_read", "lw_plan_batch", "lw_set_tuning", "lw_tune", "lw_graph_capture",
-            "lw_graph_launch", "lw_graph_destroy", "lw_accumulate_subset", "lw_features",
+            "lw_graph_launch", "lw_graph_destroy", "lw_accumulate_subset", "lw_subset_offsets",
+            "lw_gather_particles", "lw_features",
             "lw_mlp_create", "lw_mlp_destroy", "lw_mlp_num_params", "lw_mlp_get_params",
             "lw_mlp_set_params", "lw_mlp_set_input_norm", "lw_mlp_set_output_skip",
             "lw_mlp_forward", "lw_mlp_loss_grad", "lw_mlp_train_step",
@@ -103,6 +104,8 @@ def load_library():
             "lw_graph_launch": (ctypes.c_int, [P]),
             "lw_graph_destroy": (None, [P]),
             "lw_accumulate_subset": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, I64, P, SZ, P]),
+            "lw_subset_offsets": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, I64, P, ctypes.POINTER(I64)]),
+            "lw_gather_particles": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, I64, ctypes.POINTER(lw_batch)]),
             "lw_features": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P]),
             "lw_surrogate_accumulate": (ctypes.c_int, [P, ctypes.POINTER(lw_batch), P, P, P, ctypes.c_float,
                                                        P, P, P, P, SZ]),
@@ -190,6 +193,28 @@ class DeviceBatch:
         if with_species:
             t["species"] = torch.from_numpy(np.ascontiguousarray(host.species, dtype=np.int32)).to(dev)
         return cls(t, len(host.offsets) - 1)
+
+    def gather(self, ctx: "Context", indices) -> "DeviceBatch":
+        """The particles listed in `indices` (device int64) as a batch of their own, copied by
+        lw_subset_offsets and lw_gather_particles (ctx's stream; synchronises once)."""
+        idx = indices.contiguous()
+        n = int(idx.numel())
+        dev = self.t["offsets"].device
+        offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        total = ctypes.c_int64()
+        ctx._check(ctx.lib.lw_subset_offsets(ctx.h, ctypes.byref(self.struct), ctypes.c_void_p(idx.data_ptr()), n,
+                                             ctypes.c_void_p(offs.data_ptr()), ctypes.byref(total)))
+        t = {"offsets": offs}
+        for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
+            t[k] = torch.empty(total.value, dtype=self.t[k].dtype, device=dev)
+        for k in ("t0", "dt", "charge", "weight"):
+            t[k] = torch.empty(n, dtype=self.t[k].dtype, device=dev)
+        if self.t.get("species") is not None:
+            t["species"] = torch.empty(n, dtype=torch.int32, device=dev)
+        out = DeviceBatch(t, n)
+        ctx._check(ctx.lib.lw_gather_particles(ctx.h, ctypes.byref(self.struct), ctypes.c_void_p(idx.data_ptr()), n,
+                                               ctypes.byref(out.struct)))
+        return out
 
     def head(self, n: int) -> "DeviceBatch":
         """The first n particles (a view sharing the arrays)."""

@@ -153,14 +153,25 @@ def train(ctx: Context, batch: DeviceBatch, calib: DeviceBatch, steps=1500, batc
     return sur
 
 
+def exact_subset(ctx: Context, batch: DeviceBatch, idx, path="fp32"):
+    """Exact sum of the particles listed in idx (device int64) into ctx's S: the FP32 kernel
+    walking the list, or another exact path ("mfma_f16": FP16 hi/lo operands, three products)
+    on a copy of those particles gathered into a batch of their own."""
+    if path == "fp32":
+        ctx.accumulate_subset(batch, idx)
+    else:
+        ctx.accumulate(batch.gather(ctx, idx), path)
+
+
 class Judge:
     """Accumulators of the held-out particles: exact, as the pipeline estimates them
     (surrogate, exact where flagged), and surrogate alone; plus the exact sum of every other
     held-out particle, so that the sampling noise of the held-out sum can be measured on the
     same particles (split-half floor)."""
 
-    def __init__(self, ctx: Context):
+    def __init__(self, ctx: Context, exact_path="fp32"):
         om = ctx.get_frequencies()
+        self.exact_path = exact_path
         self.exact, self.pipe, self.sur = Context(ctx.device), Context(ctx.device), Context(ctx.device)
         self.half = Context(ctx.device)
         for c in (self.exact, self.pipe, self.sur, self.half):
@@ -177,10 +188,10 @@ class Judge:
         dev = ylog.device
         P, nd = batch.n_particles, self.sur.nd
         held_d = torch.from_numpy(held).to(dev, non_blocking=True)
-        self.exact.accumulate_subset(batch, held_d)
+        exact_subset(self.exact, batch, held_d, self.exact_path)
         # every other held-out particle (counting across chunks) for the split-half floor
         first = self.n % 2
-        self.half.accumulate_subset(batch, held_d[first::2].contiguous())
+        exact_subset(self.half, batch, held_d[first::2].contiguous(), self.exact_path)
         # an "error" of 0 keeps a particle on the surrogate sum, 1 leaves it out (threshold 0.5)
         keep = torch.ones((P, nd), dtype=torch.float32, device=dev)
         keep[held_d] = 0.0
@@ -189,7 +200,7 @@ class Judge:
         if held_flagged.size:
             hf = torch.from_numpy(held_flagged).to(dev, non_blocking=True)
             keep[hf] = 1.0
-            self.pipe.accumulate_subset(batch, hf)
+            exact_subset(self.pipe, batch, hf, self.exact_path)
         self.pipe.surrogate_accumulate(batch, ylog, keep, 0.5, calib=calib)
         self.n += int(held.size)
 
@@ -203,8 +214,9 @@ class Judge:
 
 
 def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge | None = None, held=None,
-                threshold=None) -> dict:
-    """Add the surrogate estimate of one chunk to ctx's S (exact for flagged particles).
+                threshold=None, exact_path="fp32") -> dict:
+    """Add the surrogate estimate of one chunk to ctx's S (exact for flagged particles, on
+    exact_path: see exact_subset).
 
     held: host int64 indices (increasing) of the chunk's held-out particles, judged when
     a Judge is given."""
@@ -214,7 +226,7 @@ def infer_chunk(ctx: Context, sur: Surrogate, batch: DeviceBatch, judge: Judge |
     _, idx, cnt = ctx.surrogate_accumulate(batch, ylog, err, thr, compact=True, calib=sur.calib)
     n_flag = int(cnt.item())
     if n_flag:
-        ctx.accumulate_subset(batch, idx[:n_flag])
+        exact_subset(ctx, batch, idx[:n_flag], exact_path)
     if judge is not None and held is not None:
         flagged = idx[:n_flag].cpu().numpy() if n_flag else np.zeros(0, dtype=np.int64)
         judge.add(batch, ylog, np.asarray(held, dtype=np.int64), flagged, calib=sur.calib)

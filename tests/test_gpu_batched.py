@@ -236,3 +236,52 @@ def test_uneven_bench_slice_sampled_bins():
           f"{[f'{x:.2e}' for x in r32]}, mfma f16 x3 {[f'{x:.2e}' for x in r16]}", flush=True)
     assert r32.max() <= TOL
     assert r16.max() <= 1e-4
+
+
+@pytest.mark.parametrize("f64_accel", [False, True])
+def test_gathered_subset_is_a_batch_of_its_own(f64_accel):
+    """lw_subset_offsets and lw_gather_particles: an unsorted list of 300 of 800 uneven
+    particles (three species, lengths 256..8192, d(beta)/dt in FP32 or FP64) gathered into a
+    batch of its own equals the host selection bit for bit; the FP32 sum of it equals
+    lw_accumulate_subset on the same list bit for bit (same particles, same positions); the
+    matrix-core path on it meets its 1e-5 band-integrated bar against that sum.  An empty
+    list gathers nothing; an index outside the batch is refused."""
+    import torch
+
+    from paper_1003_1140_amd import LW_EINVAL, DeviceBatch, LWError
+
+    host = workloads.generate(configs.uneven_recipe(), 300, 800)
+    db = DeviceBatch.from_host(host, f64_accel=f64_accel)
+    dirs = configs.dirs_equal_area()[::8]
+    om = configs.log_grid(0.1, 1e3, 512)
+    c = ctx_for(dirs, om)
+    rng = np.random.default_rng(17)
+    pick = rng.choice(800, 300, replace=False)  # unsorted
+    idx = torch.from_numpy(pick.astype(np.int64)).cuda()
+    sub = db.gather(c, idx)
+    assert sub.n_particles == 300
+    sel = host.select(pick)
+    np.testing.assert_array_equal(sub.t["offsets"].cpu().numpy(), sel.offsets - sel.offsets[0])
+    for k in ("x", "y", "z", "bx", "by", "bz", "t0", "dt", "charge", "weight", "species"):
+        np.testing.assert_array_equal(sub.t[k].cpu().numpy(), getattr(sel, k), err_msg=k)
+    for k in ("ax", "ay", "az"):
+        want = getattr(sel, k).astype(np.float64 if f64_accel else np.float32)
+        np.testing.assert_array_equal(sub.t[k].cpu().numpy(), want, err_msg=k)
+    c.set_tuning(persistent=0)
+    c.accumulate(sub, "fp32")
+    S_gather = c.read_spectra()
+    c.reset()
+    c.accumulate_subset(db, idx)
+    S_list = c.read_spectra()
+    np.testing.assert_array_equal(S_gather, S_list)
+    c.reset()
+    c.accumulate(sub, "mfma_f16")
+    S16 = c.read_spectra()
+    assert band_integrated_errors(S16, S_list, om).max() <= 1e-5
+    empty = db.gather(c, idx[:0])
+    assert empty.n_particles == 0 and empty.t["offsets"].cpu().tolist() == [0]
+    bad = torch.tensor([3, 800, 5], dtype=torch.int64, device="cuda")
+    with pytest.raises(LWError) as e:
+        db.gather(c, bad)
+    assert e.value.status == LW_EINVAL
+    torch.cuda.synchronize()

@@ -419,6 +419,16 @@ def test_fallback_extremes_reduce_to_exact_and_to_surrogate():
     r = sg.infer_chunk(c, sur, b, threshold=float("-inf"))
     assert r["fallback"] == b.n_particles
     np.testing.assert_allclose(c.read_spectra(), S_exact, rtol=1e-12)
+    # the same on the matrix-core exact path (a gathered copy of the flagged particles): the
+    # matrix-core sum of the whole chunk, exactly (the same particles in the same order)
+    c.reset()
+    c.accumulate(b, "mfma_f16")
+    S_mfma = c.read_spectra()
+    c.reset()
+    r = sg.infer_chunk(c, sur, b, threshold=float("-inf"), exact_path="mfma_f16")
+    assert r["fallback"] == b.n_particles
+    np.testing.assert_array_equal(c.read_spectra(), S_mfma)
+    assert float(np.max(band_integrated_errors(S_mfma[0], S_exact[0], omega))) <= 1e-5
     # threshold +inf: nothing falls back; S is the plain surrogate sum
     c.reset()
     r = sg.infer_chunk(c, sur, b, threshold=float("inf"))
