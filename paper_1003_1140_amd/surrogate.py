@@ -165,16 +165,17 @@ def exact_subset(ctx: Context, batch: DeviceBatch, idx, path="fp32"):
 
 class Judge:
     """Accumulators of the held-out particles: exact, as the pipeline estimates them
-    (surrogate, exact where flagged), and surrogate alone; plus the exact sum of every other
-    held-out particle, so that the sampling noise of the held-out sum can be measured on the
-    same particles (split-half floor)."""
+    (surrogate, exact where flagged), and surrogate alone.  The exact sum is kept as two
+    halves (every other held-out particle, counting across chunks, and the rest), so that the
+    sampling noise of the held-out sum can be measured on the same particles (split-half
+    floor) without summing any particle twice."""
 
     def __init__(self, ctx: Context, exact_path="fp32"):
         om = ctx.get_frequencies()
         self.exact_path = exact_path
-        self.exact, self.pipe, self.sur = Context(ctx.device), Context(ctx.device), Context(ctx.device)
-        self.half = Context(ctx.device)
-        for c in (self.exact, self.pipe, self.sur, self.half):
+        self.half, self.rest = Context(ctx.device), Context(ctx.device)
+        self.pipe, self.sur = Context(ctx.device), Context(ctx.device)
+        for c in (self.half, self.rest, self.pipe, self.sur):
             c.set_directions(ctx.dirs)
             c.set_frequencies(om)
             c.set_species(ctx.ns)
@@ -188,10 +189,12 @@ class Judge:
         dev = ylog.device
         P, nd = batch.n_particles, self.sur.nd
         held_d = torch.from_numpy(held).to(dev, non_blocking=True)
-        exact_subset(self.exact, batch, held_d, self.exact_path)
-        # every other held-out particle (counting across chunks) for the split-half floor
+        # every other held-out particle (counting across chunks), and the rest
         first = self.n % 2
         exact_subset(self.half, batch, held_d[first::2].contiguous(), self.exact_path)
+        rest = held_d[1 - first::2].contiguous()
+        if rest.numel():
+            exact_subset(self.rest, batch, rest, self.exact_path)
         # an "error" of 0 keeps a particle on the surrogate sum, 1 leaves it out (threshold 0.5)
         keep = torch.ones((P, nd), dtype=torch.float32, device=dev)
         keep[held_d] = 0.0
@@ -206,7 +209,8 @@ class Judge:
 
     def spectra(self):
         """(exact, pipeline, surrogate-only) spectra of the held-out particles."""
-        return self.exact.read_spectra(), self.pipe.read_spectra(), self.sur.read_spectra()
+        return (self.half.read_spectra() + self.rest.read_spectra(), self.pipe.read_spectra(),
+                self.sur.read_spectra())
 
     def half_spectrum(self):
         """Exact spectrum of every other held-out particle."""
