@@ -395,8 +395,8 @@ lw_status lw_features(lw_ctx* ctx, const lw_batch* batch, float* feats);
  * others add w_p q_p^2 10^(ylog + calib) to their species.  Fixed-order reduction.
  * flagged, n_flagged (device int64 [n_particles] and [1], both or neither): the
  * flagged particle indices in increasing order and their count.  Workspace:
- * ceil(n_particles / 1024) x n_species x nd x nw doubles; at most 65535 x 1024
- * particles per call (LW_ERANGE beyond). */
+ * ceil(n_particles / 128) x n_species x nd x nw doubles; at most 65535 x 256
+ * (direction, frequency) columns per call (LW_ERANGE beyond). */
 lw_status lw_surrogate_accumulate(lw_ctx* ctx, const lw_batch* batch, const float* ylog,
                                   const float* calib, const float* err, float threshold, int32_t* flags,
                                   int64_t* flagged, int64_t* n_flagged, void* workspace,

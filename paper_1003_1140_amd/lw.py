@@ -519,7 +519,7 @@ class Context:
         int64 list of flagged particles (increasing) and its device count [1]."""
         P = batch.n_particles
         flags = torch.empty(P, dtype=torch.int32, device=ylog.device)
-        need = ((P + 1023) // 1024) * self.ns * self.nd * self.nw * 8
+        need = ((P + 127) // 128) * self.ns * self.nd * self.nw * 8
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=ylog.device)
         ep = ctypes.c_void_p(err.data_ptr()) if err is not None else None
         idx = cnt = None
