@@ -205,8 +205,9 @@ class DeviceBatch:
         ctx._check(ctx.lib.lw_subset_offsets(ctx.h, ctypes.byref(self.struct), ctypes.c_void_p(idx.data_ptr()), n,
                                              ctypes.c_void_p(offs.data_ptr()), ctypes.byref(total)))
         t = {"offsets": offs}
+        # at least one element, so that a list of empty particles still has arrays to point at
         for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
-            t[k] = torch.empty(total.value, dtype=self.t[k].dtype, device=dev)
+            t[k] = torch.empty(max(total.value, 1), dtype=self.t[k].dtype, device=dev)
         for k in ("t0", "dt", "charge", "weight"):
             t[k] = torch.empty(n, dtype=self.t[k].dtype, device=dev)
         if self.t.get("species") is not None:

@@ -280,6 +280,15 @@ def test_gathered_subset_is_a_batch_of_its_own(f64_accel):
     assert band_integrated_errors(S16, S_list, om).max() <= 1e-5
     empty = db.gather(c, idx[:0])
     assert empty.n_particles == 0 and empty.t["offsets"].cpu().tolist() == [0]
+    # particles without samples: lengths 0 in the gathered offsets, and a list of only those
+    t0 = dict(db.t)
+    t0["offsets"] = torch.tensor([0, 0, 3, 3, 5], dtype=torch.int64, device="cuda")
+    db0 = DeviceBatch(t0, 4)
+    g0 = db0.gather(c, torch.tensor([3, 0, 1, 2], dtype=torch.int64, device="cuda"))
+    assert g0.t["offsets"].cpu().tolist() == [0, 2, 2, 5, 5]
+    np.testing.assert_array_equal(g0.t["x"][:5].cpu().numpy(), db.t["x"][[3, 4, 0, 1, 2]].cpu().numpy())
+    g1 = db0.gather(c, torch.tensor([0, 2], dtype=torch.int64, device="cuda"))
+    assert g1.t["offsets"].cpu().tolist() == [0, 0, 0]
     bad = torch.tensor([3, 800, 5], dtype=torch.int64, device="cuda")
     with pytest.raises(LWError) as e:
         db.gather(c, bad)
