@@ -177,6 +177,32 @@ def test_uneven_species_ragged():
     assert report("mfma f16 x2, 2 bands, uneven 14 particles, 3 species", S, ref, om).max() <= 1e-3
 
 
+@pytest.mark.parametrize("bands", [1, 2])
+def test_lengths_at_the_spreading_chunk_boundaries(bands):
+    """Trajectory lengths at and around the spreading kernel's chunks of 256 samples (a
+    chunk's last sample waits for the next chunk unless it ends the trajectory, so lengths
+    256 k and 256 k + 1 end a walk differently), plus 0, 1 and 2 samples; FP16 hi/lo, three
+    products, against the oracle at the path's 1e-5 band-integrated bar."""
+    r = configs.uneven_recipe()
+    full = workloads.generate(r, 60, 16)
+    long_enough = [i for i in range(16) if full.lengths()[i] >= 800][:10]
+    lens = [255, 256, 257, 511, 512, 513, 1, 2, 0, 767]
+    assert len(long_enough) == len(lens)
+    parts = []
+    for i, L in zip(long_enough, lens):
+        one = full.select([i])
+        one.offsets = np.array([0, L], dtype=np.int64)
+        for k in ("x", "y", "z", "bx", "by", "bz", "ax", "ay", "az"):
+            setattr(one, k, getattr(one, k)[:L])
+        parts.append(one)
+    b = Batch.concat(parts)
+    dirs = configs.dirs_equal_area()[::16]
+    om = configs.log_grid(0.1, 1e3, 512)
+    ref = oracle.spectrum(b, dirs, om, n_species=3)
+    S = run(b, dirs, om, "mfma_f16", bands=bands, n_species=3)
+    assert report(f"mfma f16 x3, lengths at chunk boundaries, {bands} band(s)", S, ref, om).max() <= 1e-5
+
+
 def test_sparse_sampling_first_chunk_fills_the_ring():
     """Samples ~6 grid points apart (dt = 0.025 seen from y and z, frequencies up to 1e3):
     a 256-sample chunk spans more grid points than the spreading kernel's ring of running
