@@ -203,6 +203,20 @@ def test_lengths_at_the_spreading_chunk_boundaries(bands):
     assert report(f"mfma f16 x3, lengths at chunk boundaries, {bands} band(s)", S, ref, om).max() <= 1e-5
 
 
+@pytest.mark.parametrize("om", [np.array([5.0]), np.array([2.0, 2.0001]), np.array([0.5, 300.0])])
+def test_one_or_two_frequencies(om):
+    """Degenerate frequency lists: one frequency (a band of zero width, its half-width
+    floored at 1e-6 of its centre), two almost equal ones, two far apart (two bands).  FP16
+    hi/lo, three products, per bin against the oracle at the 1e-5 bar."""
+    b = workloads.generate(configs.jitter_recipe(steps=1024), 0, 12)
+    dirs = configs.dirs_jitter()
+    ref = oracle.spectrum(b, dirs, om, n_species=1)
+    S = run(b, dirs, om, "mfma_f16", bands=min(2, om.size))
+    rel = float(np.max(np.abs(S / ref - 1.0)))
+    print(f"[parity] mfma f16 x3, {om.size} frequencies {om.tolist()}: per-bin max {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
 def test_sparse_sampling_first_chunk_fills_the_ring():
     """Samples ~6 grid points apart (dt = 0.025 seen from y and z, frequencies up to 1e3):
     a 256-sample chunk spans more grid points than the spreading kernel's ring of running
