@@ -873,7 +873,7 @@ def c2_leg(a, log):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (no multi-GPU path); --gpus must be 1"}))
         sys.exit(2)
     import torch
 
