@@ -152,6 +152,15 @@ def load_library():
     return _lib
 
 
+def _checked_indices(indices):
+    """Index lists go to the device as pointers: a device int64 tensor, made contiguous (a
+    copy stays valid for the stream-ordered call: torch reuses its memory only for later work
+    on the same stream)."""
+    if not isinstance(indices, torch.Tensor) or not indices.is_cuda or indices.dtype != torch.int64:
+        raise TypeError("indices must be a device (cuda) int64 tensor")
+    return indices.contiguous()
+
+
 def _np_ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -197,7 +206,7 @@ class DeviceBatch:
     def gather(self, ctx: "Context", indices) -> "DeviceBatch":
         """The particles listed in `indices` (device int64) as a batch of their own, copied by
         lw_subset_offsets and lw_gather_particles (ctx's stream; synchronises once)."""
-        idx = indices.contiguous()
+        idx = _checked_indices(indices)
         n = int(idx.numel())
         dev = self.t["offsets"].device
         offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
@@ -498,6 +507,7 @@ class Context:
 
     def accumulate_subset(self, batch: DeviceBatch, indices, workspace=None, per_particle=None):
         """Exact FP32 accumulation of the particles in `indices` (device int64 tensor)."""
+        indices = _checked_indices(indices)
         n = int(indices.numel())
         if workspace is None:
             sub = lw_batch()
