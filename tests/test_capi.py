@@ -48,3 +48,17 @@ def test_binding_refuses_to_run_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lw, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         lw.load_library()
+
+
+def test_binding_refuses_host_index_lists():
+    """Index lists reach the kernels as device pointers: a host tensor, a numpy array or an
+    int32 tensor is refused before any library call."""
+    import numpy as np
+    import torch
+
+    from paper_1003_1140_amd.lw import _checked_indices
+
+    for bad in (torch.arange(3, dtype=torch.int64), np.arange(3, dtype=np.int64), [0, 1, 2],
+                torch.arange(3, dtype=torch.int32)):
+        with pytest.raises(TypeError):
+            _checked_indices(bad)
